@@ -1,0 +1,258 @@
+/*
+ * kdefft — FFT-based integrated density-derivative functionals psi_r and the
+ * smoothed cross-validation (SCV) bandwidth objective, for full (unconstrained)
+ * d x d bandwidth matrices, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Gramacki & Gramacki, "FFT-based fast bandwidth selector for
+ * multivariate kernel density estimation".  The quantity computed is
+ *
+ *     psi_r(G) = n^-2 sum_i sum_j D^{(x)r} phi_G(X_i - X_j)          (Eq. (13))
+ *
+ * by the paper's four steps (Sec. 4): linear binning onto an M_1 x ... x M_d
+ * grid (Eq. (14)), the kernel on the full symmetric lag grid (Eq. (17)-(18)),
+ * a zero-padded FFT convolution (Eq. (19)-(23)) and the count-weighted sum
+ * (Eq. (24)).  Sec. 5 extends the route to derivative functionals of any even
+ * order r and to the double sums of the PI and SCV selectors.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Return value   int: KDEFFT_OK (0) or a negative KDEFFT_E_* code.  On error a
+ *                human-readable reason is available from
+ *                kdefft_last_error_detail() (per calling thread).  Argument
+ *                errors are detected on the host before anything is launched.
+ * Pointers       Arrays are DEVICE pointers unless the name ends in _host.
+ * Ownership      The caller owns all memory.  The library never allocates
+ *                device memory: functions that need scratch space take a
+ *                workspace (ws, ws_bytes) whose size is obtained first from
+ *                kdefft_ws_bytes(); a too-small workspace is KDEFFT_E_WORKSPACE.
+ * Streams        `stream` is a hipStream_t passed as void* (NULL = the default
+ *                stream).  All device work is enqueued on it and the call
+ *                returns without waiting, except kdefft_grid_auto() (reads the
+ *                data bounds back) and kdefft_autotune().
+ * Layouts        X: row-major [n, d] float64.  G, H: d x d row-major float64.
+ *                Grid counts: row-major [M_0, ..., M_{d-1}], last axis fastest.
+ *                vechL: [B, q], q = d(d+1)/2, lower Cholesky factor L of
+ *                H = L L^T with the columns of the lower triangle stacked:
+ *                (L11, L21, ..., Ld1, L22, ..., Ldd).
+ *                psi: the C(d+r-1, r) unique entries of D^{(x)r} (Sec. 5) in
+ *                canonical order: index tuples i_1 <= ... <= i_r, sorted
+ *                lexicographically (d=2, r=4: 1111,1112,1122,1222,2222).
+ * Limits         1 <= d <= 4; r even, 0 <= r <= 8, and the number of
+ *                multi-indices of order <= r, C(d+r, r), at most 84 (so d=3
+ *                allows r <= 6 and d=4 allows r <= 4); 2 <= M_k; P_k a power of
+ *                two with 2 M_k - 1 <= P_k <= 4096; 1 <= n < 2^23 per dataset.
+ * Determinism    Counts are bit-exact (integer atomics).  Every floating-point
+ *                reduction has a fixed order, so repeated calls with the same
+ *                inputs and launch configuration give identical bits.
+ */
+#ifndef KDEFFT_H
+#define KDEFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KDEFFT_OK 0
+#define KDEFFT_E_ARG (-1)          /* invalid argument (null pointer, bad size, bad layout) */
+#define KDEFFT_E_NOT_SPD (-2)      /* a bandwidth matrix is not symmetric positive definite */
+#define KDEFFT_E_ODD_R (-3)        /* derivative order r is odd (the functional is 0) */
+#define KDEFFT_E_OUT_OF_GRID (-4)  /* data outside the grid (reported by kdefft_check_binning) */
+#define KDEFFT_E_OVERFLOW (-5)     /* n >= 2^23: an int64 bin could overflow */
+#define KDEFFT_E_WORKSPACE (-6)    /* workspace or dataset buffer too small / misaligned */
+#define KDEFFT_E_HIP (-7)          /* a HIP runtime call failed */
+#define KDEFFT_E_UNSUPPORTED (-8)  /* (d, r, P) outside the compiled limits */
+
+#define KDEFFT_MAX_D 4
+#define KDEFFT_MAX_R 8
+#define KDEFFT_MAX_P 4096
+#define KDEFFT_MAX_N (((int64_t)1) << 23)
+#define KDEFFT_QBITS 40            /* binning quantum 2^-40 of a unit point mass */
+
+/* Grid descriptor (Sec. 4, Eq. (15)-(16)): node j of axis k is lo[k] + j*delta[k],
+ * j = 0..M[k]-1.  P[k] is the length of the zero-padded circular transform. */
+typedef struct kdefft_grid {
+    int32_t d;
+    int32_t M[4];
+    int32_t P[4];
+    double lo[4];
+    double delta[4];
+} kdefft_grid;
+
+/* A binned, transformed dataset, filled by kdefft_dataset_prepare().  The
+ * device arrays live inside one caller buffer (see kdefft_dataset_bytes):
+ *   counts  int64 [prod M]                  grid counts, 2^-40 quanta
+ *   spec    complex [prod_{k<d-1} P_k][Q]   C = R2C(counts), Q = P_{d-1}/2+1,
+ *                                           interleaved (re, im) float64
+ *   wmix    complex [prod_{k<d-1} P_k][Q]   |C|^2 transformed forward along
+ *                                           axes 0..d-2 (mixed-domain spectrum)
+ *   scal    float64 [4]                     scal[0] = n^-2 sum sum phi_{2G} (binned)
+ *   n_out   int32 [1]                       number of points outside the grid
+ *   rec     opaque device record (pointers, n, spacing, pilot) read by the
+ *           batched kernels, so batch calls need no host-to-device copies */
+typedef struct kdefft_dataset {
+    kdefft_grid grid;
+    int64_t n;
+    double G[16];            /* pilot bandwidth, row-major d x d (host copy) */
+    int64_t* counts;
+    double* spec;
+    double* wmix;
+    double* scal;
+    int32_t* n_out;
+    void* rec;
+} kdefft_dataset;
+
+/* Datasets per batched call: kdefft_scv_batch / kdefft_scv_adjoint accept up
+ * to KDEFFT_MAX_BATCH_DS datasets per call, kdefft_psi_batch up to
+ * KDEFFT_MAX_PSI_DS (their record pointers travel as kernel arguments). */
+#define KDEFFT_MAX_BATCH_DS 64
+#define KDEFFT_MAX_PSI_DS 32
+
+/* Operation selectors for kdefft_ws_bytes(). */
+#define KDEFFT_OP_GRID_AUTO 1   /* kdefft_grid_auto: batch = n (points) */
+#define KDEFFT_OP_PSI_PLAIN 2   /* kdefft_psi(mode = PLAIN) */
+#define KDEFFT_OP_PSI_FUSED 3   /* kdefft_psi(mode = FUSED) */
+#define KDEFFT_OP_PREPARE 4     /* kdefft_dataset_prepare */
+#define KDEFFT_OP_PSI_BATCH 5   /* kdefft_psi_batch: batch = number of datasets */
+#define KDEFFT_OP_SCV_BATCH 6   /* kdefft_scv_batch / kdefft_scv_adjoint: batch = total H */
+#define KDEFFT_OP_SCV_PLAIN 7   /* kdefft_scv_plain */
+#define KDEFFT_OP_AUTOTUNE 8    /* kdefft_autotune */
+
+/* psi modes */
+#define KDEFFT_PSI_PLAIN 0  /* the paper's steps literally: per entry, kernel grid ->
+                               R2C -> multiply by C -> C2R -> scale 1/prod P ->
+                               contract with the counts (Eq. (22)-(24)) */
+#define KDEFFT_PSI_FUSED 1  /* Parseval form: one fused launch for all entries */
+
+/* Human-readable name of an error code (static string). */
+const char* kdefft_strerror(int code);
+
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char* kdefft_last_error_detail(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int kdefft_version(void);
+
+/* Number of unique entries C(d+r-1, r) of D^{(x)r} (Sec. 5), or a negative code. */
+int kdefft_unique_count(int d, int r);
+
+/* The unique index tuples in canonical order, 0-based: tuples_host[k*r + m] is
+ * the m-th index of entry k; tuples_host must hold kdefft_unique_count(d,r)*r
+ * int32 (nothing is written for r = 0). Host only. */
+int kdefft_unique_index(int d, int r, int32_t* tuples_host);
+
+/* Grid from explicit bounds (Sec. 4, Eq. (16)): delta_k = (hi_k - lo_k)/(M_k - 1),
+ * one float64 subtraction and one division.  P_host may be NULL (then P_k is the
+ * smallest power of two >= max(4, 2 M_k - 1); P_k = 2 M_k when M_k is a power
+ * of two) or give the padded lengths.  Host only. */
+int kdefft_grid_plan(int d, const int32_t* M_host, const int32_t* P_host,
+                     const double* lo_host, const double* hi_host, kdefft_grid* out);
+
+/* Grid spanning the data padded by pad_sd kernel standard deviations:
+ * lo_k = min_i X_ik - pad_sd*sqrt(G_kk), hi_k = max_i X_ik + pad_sd*sqrt(G_kk)
+ * (the paper leaves the span open; Sec. 4 only asks that it contain the data).
+ * Reads the bounds back, so it synchronizes `stream`.  Workspace:
+ * KDEFFT_OP_GRID_AUTO with batch = n. */
+int kdefft_grid_auto(const double* X, int64_t n, int d, const double* G_host,
+                     const int32_t* M_host, double pad_sd, kdefft_grid* out,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for operation `op` on grid g with derivative order r and
+ * batch size `batch` (meaning per op above); written to *out. Host only. */
+int kdefft_ws_bytes(const kdefft_grid* g, int op, int r, int64_t batch, size_t* out);
+
+/* Step 1 of Sec. 4: linear binning of X [n,d] onto g into int64 counts
+ * [prod M] (zeroed first), fixed-point quanta of 2^-40 per unit mass; the
+ * corner with the largest quantum absorbs the rounding so each point adds
+ * exactly 2^40.  Points with (X_ik - lo_k)/delta_k outside [0, M_k - 1] are
+ * skipped and counted into *n_out_dev (device int32, may be NULL). */
+int kdefft_linbin(const double* X, int64_t n, const kdefft_grid* g,
+                  int64_t* counts, int32_t* n_out_dev, void* stream);
+
+/* psi_r(G) (Eq. (13)) of X on grid g by the binned FFT route (Eq. (14)-(24)).
+ * psi: device float64 [kdefft_unique_count(d, r)].  mode: KDEFFT_PSI_PLAIN or
+ * KDEFFT_PSI_FUSED.  Workspace: KDEFFT_OP_PSI_PLAIN / KDEFFT_OP_PSI_FUSED.
+ * Out-of-grid points are dropped (see kdefft_check_binning on the workspace). */
+int kdefft_psi(const double* X, int64_t n, const kdefft_grid* g, const double* G_host,
+               int r, double* psi, int mode, void* ws, size_t ws_bytes, void* stream);
+
+/* Synchronize `stream` and return KDEFFT_E_OUT_OF_GRID if the int32 counter
+ * n_out_dev is non-zero (its value is stored in *n_out_host if not NULL). */
+int kdefft_check_binning(const int32_t* n_out_dev, int32_t* n_out_host, void* stream);
+
+/* Device bytes of the buffer that holds one prepared dataset on grid g. */
+int kdefft_dataset_bytes(const kdefft_grid* g, size_t* out);
+
+/* Bin X onto g, transform the counts once (C = R2C(counts), then |C|^2 and its
+ * transform along the leading axes) and evaluate the constant SCV term with
+ * the pilot Gpilot_host.  ds_mem: device buffer of kdefft_dataset_bytes(g)
+ * bytes, 256-byte aligned; *out receives the descriptor.  Workspace:
+ * KDEFFT_OP_PREPARE. */
+int kdefft_dataset_prepare(const double* X, int64_t n, const kdefft_grid* g,
+                           const double* Gpilot_host, void* ds_mem, size_t ds_bytes,
+                           kdefft_dataset* out, void* ws, size_t ws_bytes, void* stream);
+
+/* psi_r at bandwidth G_host + 16*j (row-major d x d) for each of n_ds prepared
+ * datasets, one launch (Parseval form against the prepared spectra; Sec. 5).
+ * psi: device float64 [n_ds, kdefft_unique_count(d, r)].  All datasets must
+ * share d and the grid lengths P. Workspace: KDEFFT_OP_PSI_BATCH, batch = n_ds. */
+int kdefft_psi_batch(const kdefft_dataset* ds_host, int n_ds, const double* G_host,
+                     int r, double* psi, void* ws, size_t ws_bytes, void* stream);
+
+/* SCV objective for B = h_offsets_host[n_ds] candidate bandwidths, candidate b
+ * belonging to dataset j when h_offsets_host[j] <= b < h_offsets_host[j+1]:
+ *   SCV(H) = n^-1 (4 pi)^{-d/2} |H|^{-1/2}
+ *          + n^-2 sum sum [phi_{2H+2G} - 2 phi_{H+2G} + phi_{2G}](X_i - X_j)
+ * with the double sum binned and evaluated by the FFT route (the SCV selector
+ * of Sec. 3 and Sec. 5, V-statistic form).  vechL [B, q] parametrises H = L L^T.
+ * obj: device [B].  grad: device [B, q] or NULL; if given it receives
+ * d SCV / d vechL.  status: device int32 [B] or NULL; 0 = ok, 1 = H singular
+ * (a zero diagonal entry of L; obj and grad are NaN for that entry).  One
+ * persistent launch covers all datasets and candidates.  All datasets must
+ * share d and P.  Workspace: KDEFFT_OP_SCV_BATCH with batch = B. */
+int kdefft_scv_batch(const kdefft_dataset* ds_host, int n_ds, const int64_t* h_offsets_host,
+                     const double* vechL, double* obj, double* grad, int32_t* status,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of kdefft_scv_batch's objective: grad_vechL[b, :] = grad_out[b] *
+ * d SCV(H_b) / d vechL_b, recomputing the Hessian kernel grids (never stored).
+ * grad_out: device [B]; grad_vechL: device [B, q].  Same workspace as
+ * kdefft_scv_batch. */
+int kdefft_scv_adjoint(const kdefft_dataset* ds_host, int n_ds, const int64_t* h_offsets_host,
+                       const double* vechL, const double* grad_out, double* grad_vechL,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* One candidate H at a time by the paper's literal steps: for the objective
+ * grid and each of the q Hessian grids, kernel grid -> R2C -> multiply by the
+ * prepared count spectrum -> C2R -> scale -> contract with the counts, each a
+ * separate launch.  out: device [1 + q] = (SCV(H), d SCV / d vechL).
+ * H_host: d x d row-major.  Workspace: KDEFFT_OP_SCV_PLAIN. */
+int kdefft_scv_plain(const kdefft_dataset* ds_host, const double* H_host, double* out,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* Pin the launch of the batched row kernels for one kernel family (kind: 0 psi,
+ * 1 SCV objective, 2 SCV objective+gradient, 3 SCV gradient), dimension d,
+ * order r (2 for the SCV families) and last-axis length N for the rest of the
+ * process: variant = compiled variant in [0, 3) (0: ~32 KiB of LDS pencils per
+ * block, radix-8 first; 1: ~64 KiB; 2: ~32 KiB, radix-4 first); grid_blocks =
+ * persistent grid size, 0 = resident blocks per CU x CUs, -1 = one block per
+ * work item.  Used by kdefft_autotune and by tests that cover every variant.
+ * Host only. */
+int kdefft_set_row_launch(int kind, int d, int r, int N, int variant, int grid_blocks);
+
+/* Time the compiled launch variants of the batched kernels (rows per block
+ * iteration / LDS footprint, radix schedule of the row transforms, persistent
+ * grid size) for this dataset's grid shape on the current device, keep the
+ * fastest for the rest of the process, and append the choice to cache_path
+ * (one JSON object per line; NULL = no file).  Workspace: KDEFFT_OP_AUTOTUNE.
+ * Synchronizes `stream`. */
+int kdefft_autotune(const kdefft_dataset* ds_host, void* ws, size_t ws_bytes,
+                    const char* cache_path, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KDEFFT_H */

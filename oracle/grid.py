@@ -10,8 +10,9 @@ span contains the data, with binwidth delta_k = (g_{kM_k} - g_{k1})/(M_k - 1)
 
 each step one IEEE float64 operation in that order, so that the HIP library
 (which plans the grid on the host with the same operations) produces the
-same bits.  The zero-padded transform length used by the wrap layout is
-P_k = 2 M_k (any P_k >= 2M_k - 1 gives the exact circular result).
+same bits.  The zero-padded transform length of the circular layout is the
+smallest power of two P_k >= max(4, 2 M_k - 1) (any P_k >= 2M_k - 1 gives the
+exact circular result; P_k = 2 M_k when M_k is a power of two).
 """
 from __future__ import annotations
 
@@ -25,7 +26,8 @@ def plan(lo, hi, M):
     hi = np.asarray(hi, dtype=np.float64)
     M = np.asarray(M, dtype=np.int64)
     delta = (hi - lo) / (M - 1).astype(np.float64)
-    return {"d": len(lo), "M": M, "P": 2 * M, "lo": lo.copy(), "delta": delta}
+    P = np.array([max(4, 1 << int(2 * m - 2).bit_length()) for m in M], dtype=np.int64)
+    return {"d": len(lo), "M": M, "P": P, "lo": lo.copy(), "delta": delta}
 
 
 def plan_auto(X, G, M, pad_sd=4.0):

@@ -1,0 +1,319 @@
+"""FFT-based psi_r and SCV bandwidth-selector hot path on MI355X (HIP, gfx950).
+
+Python face of libkdefft (include/kdefft.h): every step runs in the library's
+HIP kernels; this module only allocates device memory through torch, passes
+pointers and the current stream, and raises on error codes.  It refuses to
+work without the built library.
+
+    import paper_1511_07482_amd as kf
+    g   = kf.grid_auto(X, G, M=256)                     # X: cuda float64 [n, d]
+    psi = kf.psi(X, G, r=4, grid=g)                     # unique entries of psi_4
+    ds  = kf.Dataset(X, G_pilot, M=256)                 # binned + transformed once
+    obj, grad = kf.scv([ds], vechL)                     # many H in one launch
+    obj = kf.SCV.apply(vechL, ds)                       # autograd: backward = adjoint
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import FUN_PSI, FUN_SCV_GRAD, FUN_SCV_OBJ, FUN_SCV_OBJGRAD, Grid, KdefftError  # noqa: F401
+
+__all__ = ["Grid", "Dataset", "KdefftError", "grid_plan", "grid_auto", "linbin", "psi", "psi_batch", "scv",
+           "scv_adjoint", "scv_plain", "SCV", "unique_tuples", "autotune", "set_row_launch", "library_path"]
+
+
+def library_path():
+    return _lib.LIB_PATH
+
+
+def _L():
+    return _lib.load()
+
+
+def _stream(device=None):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _as_X(X):
+    if not isinstance(X, torch.Tensor) or not X.is_cuda:
+        raise TypeError("X must be a CUDA (HIP) tensor")
+    if X.dtype != torch.float64 or X.dim() != 2:
+        raise TypeError("X must be float64 [n, d]")
+    return X.contiguous()
+
+
+def _mat(A, d, name):
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
+    if A.shape != (d, d):
+        raise ValueError(f"{name} must be {d}x{d}")
+    return A
+
+
+def _ws(grid: Grid, op, r, batch, device):
+    n = C.c_size_t()
+    _lib.check(_L().kdefft_ws_bytes(C.byref(grid), op, r, int(batch), C.byref(n)), "kdefft_ws_bytes")
+    return torch.empty(max(int(n.value), 256), dtype=torch.uint8, device=device)
+
+
+def unique_tuples(d: int, r: int):
+    cnt = _L().kdefft_unique_count(d, r)
+    if cnt < 0:
+        _lib.check(cnt, "kdefft_unique_count")
+    if r == 0:
+        return [()]
+    buf = (C.c_int32 * (cnt * r))()
+    _lib.check(_L().kdefft_unique_index(d, r, buf), "kdefft_unique_index")
+    return [tuple(buf[k * r:(k + 1) * r]) for k in range(cnt)]
+
+
+def grid_plan(M, lo, hi, P=None) -> Grid:
+    lo = np.asarray(lo, dtype=np.float64)
+    d = len(lo)
+    M = np.broadcast_to(np.asarray(M, dtype=np.int32), (d,)).copy()
+    hi = np.asarray(hi, dtype=np.float64)
+    Pa = None if P is None else np.broadcast_to(np.asarray(P, dtype=np.int32), (d,)).copy()
+    g = Grid()
+    _lib.check(_L().kdefft_grid_plan(d, M.ctypes.data, None if Pa is None else Pa.ctypes.data,
+                                     lo.ctypes.data, hi.ctypes.data, C.byref(g)), "kdefft_grid_plan")
+    return g
+
+
+def grid_auto(X: torch.Tensor, G, M, pad_sd: float = 4.0) -> Grid:
+    X = _as_X(X)
+    n, d = X.shape
+    Gm = _mat(G, d, "G")
+    Ma = np.broadcast_to(np.asarray(M, dtype=np.int32), (d,)).copy()
+    probe = Grid()
+    probe.d = d
+    for k in range(d):
+        probe.M[k], probe.P[k], probe.delta[k] = 2, 4, 1.0
+    ws = _ws(probe, _lib.OP_GRID_AUTO, 0, n, X.device)
+    g = Grid()
+    _lib.check(_L().kdefft_grid_auto(_ptr(X), n, d, Gm.ctypes.data, Ma.ctypes.data, float(pad_sd), C.byref(g),
+                                     _ptr(ws), ws.numel(), _stream(X.device)), "kdefft_grid_auto")
+    return g
+
+
+def linbin(X: torch.Tensor, grid: Grid):
+    """Int64 fixed-point counts [M_0, ..., M_{d-1}] (2^-40 quanta) and the out-of-grid count."""
+    X = _as_X(X)
+    n, d = X.shape
+    shape = tuple(grid.M[:grid.d])
+    counts = torch.empty(shape, dtype=torch.int64, device=X.device)
+    nout = torch.zeros(2, dtype=torch.int32, device=X.device)
+    _lib.check(_L().kdefft_linbin(_ptr(X), n, C.byref(grid), _ptr(counts), _ptr(nout), _stream(X.device)),
+               "kdefft_linbin")
+    return counts, nout[:1]
+
+
+def psi(X: torch.Tensor, G, r: int, M=None, grid: Optional[Grid] = None, mode: str = "plain",
+        pad_sd: float = 4.0) -> torch.Tensor:
+    """Unique entries of psi_r(G) of the sample X by the binned FFT route.
+    With an explicit grid, points outside it are dropped (see linbin)."""
+    X = _as_X(X)
+    n, d = X.shape
+    Gm = _mat(G, d, "G")
+    if grid is None:
+        if M is None:
+            raise ValueError("give M or grid")
+        grid = grid_auto(X, Gm, M, pad_sd)
+    m = {"plain": _lib.PSI_PLAIN, "fused": _lib.PSI_FUSED}[mode]
+    ws = _ws(grid, _lib.OP_PSI_PLAIN if m == _lib.PSI_PLAIN else _lib.OP_PSI_FUSED, r, 1, X.device)
+    cnt = _L().kdefft_unique_count(d, r)
+    out = torch.empty(max(cnt, 1), dtype=torch.float64, device=X.device)
+    _lib.check(_L().kdefft_psi(_ptr(X), n, C.byref(grid), Gm.ctypes.data, r, _ptr(out), m, _ptr(ws), ws.numel(),
+                               _stream(X.device)), "kdefft_psi")
+    return out
+
+
+class Dataset:
+    """A sample binned on a grid and transformed once (counts, spectra, constant SCV term)."""
+
+    def __init__(self, X: torch.Tensor, G_pilot, M=None, grid: Optional[Grid] = None, pad_sd: float = 4.0):
+        X = _as_X(X)
+        n, d = X.shape
+        self.G_pilot = _mat(G_pilot, d, "G_pilot")
+        self.grid = grid if grid is not None else grid_auto(X, self.G_pilot, M, pad_sd)
+        self.device = X.device
+        nb = C.c_size_t()
+        _lib.check(_L().kdefft_dataset_bytes(C.byref(self.grid), C.byref(nb)), "kdefft_dataset_bytes")
+        self.mem = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=X.device)
+        base = self.mem.data_ptr()
+        off = (-base) % 256
+        ws = _ws(self.grid, _lib.OP_PREPARE, 0, 1, X.device)
+        self.desc = _lib.Dataset()
+        _lib.check(_L().kdefft_dataset_prepare(_ptr(X), n, C.byref(self.grid), self.G_pilot.ctypes.data,
+                                               C.c_void_p(base + off), int(nb.value), C.byref(self.desc),
+                                               _ptr(ws), ws.numel(), _stream(X.device)), "kdefft_dataset_prepare")
+        self.n = n
+        self.d = d
+
+    @property
+    def q(self):
+        return self.d * (self.d + 1) // 2
+
+    def out_of_grid(self) -> int:
+        v = C.c_int32()
+        rc = _L().kdefft_check_binning(C.c_void_p(self.desc.n_out), C.byref(v), _stream(self.device))
+        if rc not in (_lib.OK, _lib.E_OUT_OF_GRID):
+            _lib.check(rc, "kdefft_check_binning")
+        return int(v.value)
+
+    def counts(self) -> torch.Tensor:
+        """Copy of the int64 grid counts."""
+        shape = tuple(self.grid.M[:self.d])
+        numel = int(np.prod(shape))
+        base = self.mem.data_ptr()
+        start = self.desc.counts - base
+        return self.mem[start:start + 8 * numel].view(torch.int64).view(shape).clone()
+
+
+def _ds_array(datasets: Sequence[Dataset]):
+    arr = (_lib.Dataset * len(datasets))()
+    for j, ds in enumerate(datasets):
+        arr[j] = ds.desc
+    return arr
+
+
+def psi_batch(datasets: Sequence[Dataset], Gs, r: int) -> torch.Tensor:
+    """psi_r at Gs[j] for each prepared dataset j, one launch (up to 32 datasets per call)."""
+    datasets = list(datasets)
+    d = datasets[0].d
+    dev = datasets[0].device
+    cnt = _L().kdefft_unique_count(d, r)
+    out = torch.empty((len(datasets), max(cnt, 1)), dtype=torch.float64, device=dev)
+    for s in range(0, len(datasets), _lib.MAX_PSI_DS):
+        part = datasets[s:s + _lib.MAX_PSI_DS]
+        Gh = np.zeros((len(part), 16))
+        for j in range(len(part)):
+            Gh[j, :d * d] = _mat(Gs[s + j], d, "G").ravel()
+        ws = _ws(part[0].grid, _lib.OP_PSI_BATCH, r, len(part), dev)
+        arr = _ds_array(part)
+        _lib.check(_L().kdefft_psi_batch(arr, len(part), Gh.ctypes.data, r, _ptr(out[s:s + len(part)]), _ptr(ws),
+                                         ws.numel(), _stream(dev)), "kdefft_psi_batch")
+    return out
+
+
+def _offsets(datasets, counts):
+    off = np.zeros(len(datasets) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(counts)
+    return off
+
+
+def _split_counts(datasets, vechL, per_ds):
+    if per_ds is None:
+        if len(datasets) != 1:
+            raise ValueError("give per_ds (candidates per dataset) for several datasets")
+        per_ds = [vechL.shape[0]]
+    per_ds = [int(c) for c in per_ds]
+    if sum(per_ds) != vechL.shape[0]:
+        raise ValueError("per_ds must add up to the number of candidates")
+    return per_ds
+
+
+def scv(datasets: Sequence[Dataset], vechL: torch.Tensor, per_ds=None, grad: bool = True, status: bool = False):
+    """SCV objective (and d/d vechL) for candidates vechL [B, q]; candidates are
+    grouped by dataset in order, per_ds[j] of them for dataset j."""
+    datasets = list(datasets)
+    dev = datasets[0].device
+    vechL = vechL.to(device=dev, dtype=torch.float64).contiguous()
+    B, q = vechL.shape
+    per_ds = _split_counts(datasets, vechL, per_ds)
+    obj = torch.empty(B, dtype=torch.float64, device=dev)
+    g = torch.empty((B, q), dtype=torch.float64, device=dev) if grad else None
+    st = torch.empty(B, dtype=torch.int32, device=dev)
+    start = 0
+    for s in range(0, len(datasets), _lib.MAX_BATCH_DS):
+        part = datasets[s:s + _lib.MAX_BATCH_DS]
+        cnts = per_ds[s:s + _lib.MAX_BATCH_DS]
+        nb = sum(cnts)
+        if nb == 0:
+            continue
+        off = _offsets(part, cnts)
+        ws = _ws(part[0].grid, _lib.OP_SCV_BATCH, 2, nb, dev)
+        arr = _ds_array(part)
+        sl = slice(start, start + nb)
+        _lib.check(_L().kdefft_scv_batch(arr, len(part), off.ctypes.data, _ptr(vechL[sl]), _ptr(obj[sl]),
+                                         _ptr(g[sl]) if grad else None, _ptr(st[sl]), _ptr(ws), ws.numel(),
+                                         _stream(dev)), "kdefft_scv_batch")
+        start += nb
+    if status:
+        return obj, g, st
+    return (obj, g) if grad else obj
+
+
+def scv_adjoint(datasets: Sequence[Dataset], vechL: torch.Tensor, grad_out: torch.Tensor, per_ds=None):
+    datasets = list(datasets)
+    dev = datasets[0].device
+    vechL = vechL.to(device=dev, dtype=torch.float64).contiguous()
+    grad_out = grad_out.to(device=dev, dtype=torch.float64).contiguous()
+    B, q = vechL.shape
+    per_ds = _split_counts(datasets, vechL, per_ds)
+    out = torch.empty((B, q), dtype=torch.float64, device=dev)
+    start = 0
+    for s in range(0, len(datasets), _lib.MAX_BATCH_DS):
+        part = datasets[s:s + _lib.MAX_BATCH_DS]
+        cnts = per_ds[s:s + _lib.MAX_BATCH_DS]
+        nb = sum(cnts)
+        if nb == 0:
+            continue
+        off = _offsets(part, cnts)
+        ws = _ws(part[0].grid, _lib.OP_SCV_BATCH, 2, nb, dev)
+        arr = _ds_array(part)
+        sl = slice(start, start + nb)
+        _lib.check(_L().kdefft_scv_adjoint(arr, len(part), off.ctypes.data, _ptr(vechL[sl]), _ptr(grad_out[sl]),
+                                           _ptr(out[sl]), _ptr(ws), ws.numel(), _stream(dev)), "kdefft_scv_adjoint")
+        start += nb
+    return out
+
+
+def scv_plain(dataset: Dataset, H) -> torch.Tensor:
+    """[SCV(H), d SCV / d vechL] for one H by the paper's literal steps."""
+    Hm = _mat(H, dataset.d, "H")
+    ws = _ws(dataset.grid, _lib.OP_SCV_PLAIN, 2, 1, dataset.device)
+    out = torch.empty(1 + dataset.q, dtype=torch.float64, device=dataset.device)
+    arr = _ds_array([dataset])
+    _lib.check(_L().kdefft_scv_plain(arr, Hm.ctypes.data, _ptr(out), _ptr(ws), ws.numel(), _stream(dataset.device)),
+               "kdefft_scv_plain")
+    return out
+
+
+class SCV(torch.autograd.Function):
+    """obj[b] = SCV(H_b), H_b = L_b L_b^T from vechL [B, q]; backward runs the
+    adjoint kernel (Hessian grids recomputed, never stored)."""
+
+    @staticmethod
+    def forward(ctx, vechL, dataset, per_ds=None):
+        datasets = dataset if isinstance(dataset, (list, tuple)) else [dataset]
+        obj = scv(datasets, vechL.detach(), per_ds=per_ds, grad=False)
+        ctx.datasets = datasets
+        ctx.per_ds = per_ds
+        ctx.save_for_backward(vechL.detach())
+        return obj
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (vechL,) = ctx.saved_tensors
+        g = scv_adjoint(ctx.datasets, vechL, grad_out.detach(), per_ds=ctx.per_ds)
+        return g, None, None
+
+
+def set_row_launch(kind: int, d: int, r: int, N: int, variant: int, grid_blocks: int = 0):
+    _lib.check(_L().kdefft_set_row_launch(kind, d, r, N, variant, grid_blocks), "kdefft_set_row_launch")
+
+
+def autotune(dataset: Dataset, cache_path: Optional[str] = None) -> str:
+    ws = _ws(dataset.grid, _lib.OP_AUTOTUNE, 2, 64, dataset.device)
+    arr = _ds_array([dataset])
+    _lib.check(_L().kdefft_autotune(arr, _ptr(ws), ws.numel(), cache_path.encode() if cache_path else None,
+                                    _stream(dataset.device)), "kdefft_autotune")
+    return _L().kdefft_last_error_detail().decode()

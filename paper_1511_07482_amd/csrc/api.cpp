@@ -1,0 +1,960 @@
+// C-ABI entry points of libkdefft: argument validation, grid planning,
+// workspace layout, and the order of launches for each operation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "internal.h"
+
+using namespace kdefft;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(KDEFFT_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(expr, what)                          \
+    do {                                            \
+        hipError_t _e = (expr);                     \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+int64_t binom(int n, int k) {
+    if (k < 0 || k > n) return 0;
+    int64_t r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int check_d_r(int d, int r) {
+    if (d < 1 || d > KDEFFT_MAX_D) return fail(KDEFFT_E_ARG, "d=%d outside [1,%d]", d, KDEFFT_MAX_D);
+    if (r < 0 || r > KDEFFT_MAX_R) return fail(KDEFFT_E_UNSUPPORTED, "r=%d outside [0,%d]", r, KDEFFT_MAX_R);
+    if (r % 2) return fail(KDEFFT_E_ODD_R, "r=%d is odd: the double sum vanishes", r);
+    if (binom(d + r, r) > 84)
+        return fail(KDEFFT_E_UNSUPPORTED, "d=%d, r=%d needs %lld multi-indices (limit 84)", d, r,
+                    (long long)binom(d + r, r));
+    return KDEFFT_OK;
+}
+
+int check_grid(const kdefft_grid* g) {
+    if (!g) return fail(KDEFFT_E_ARG, "grid is NULL");
+    if (g->d < 1 || g->d > KDEFFT_MAX_D) return fail(KDEFFT_E_ARG, "grid d=%d outside [1,4]", g->d);
+    double total = 1.0;
+    for (int k = 0; k < g->d; ++k) {
+        if (g->M[k] < 2) return fail(KDEFFT_E_ARG, "M[%d]=%d < 2", k, g->M[k]);
+        if (!is_pow2(g->P[k]) || g->P[k] > KDEFFT_MAX_P || g->P[k] < 2 * g->M[k] - 1 || g->P[k] < 4)
+            return fail(KDEFFT_E_ARG, "P[%d]=%d must be a power of two in [max(4, 2M-1), %d]", k, g->P[k],
+                        KDEFFT_MAX_P);
+        if (!(g->delta[k] > 0.0) || !std::isfinite(g->delta[k]) || !std::isfinite(g->lo[k]))
+            return fail(KDEFFT_E_ARG, "grid spacing/origin of axis %d not finite and positive", k);
+        total *= g->P[k];
+    }
+    if (total > (double)(1LL << 30)) return fail(KDEFFT_E_UNSUPPORTED, "prod P = %.0f exceeds 2^30", total);
+    return KDEFFT_OK;
+}
+
+int check_n(int64_t n) {
+    if (n < 1) return fail(KDEFFT_E_ARG, "n=%lld < 1", (long long)n);
+    if (n >= KDEFFT_MAX_N) return fail(KDEFFT_E_OVERFLOW, "n=%lld >= 2^23 could overflow an int64 bin", (long long)n);
+    return KDEFFT_OK;
+}
+
+// Cholesky of a host d x d row-major matrix (row stride ld); 0 if not SPD.
+bool chol_host(const double* A, int ld, int d, double* L /*[16], stride 4*/) {
+    for (int i = 0; i < 16; ++i) L[i] = 0.0;
+    for (int j = 0; j < d; ++j) {
+        double s = A[j * ld + j];
+        for (int k = 0; k < j; ++k) s -= L[j * 4 + k] * L[j * 4 + k];
+        if (!(s > 0.0) || !std::isfinite(s)) return false;
+        const double ljj = std::sqrt(s);
+        L[j * 4 + j] = ljj;
+        for (int i = j + 1; i < d; ++i) {
+            double t = A[i * ld + j];
+            for (int k = 0; k < j; ++k) t -= L[i * 4 + k] * L[j * 4 + k];
+            L[i * 4 + j] = t / ljj;
+        }
+    }
+    return true;
+}
+
+void chol_inv_host(const double* L, int d, double* Ainv /*stride 4*/) {
+    double Li[16] = {0};
+    for (int j = 0; j < d; ++j) {
+        Li[j * 4 + j] = 1.0 / L[j * 4 + j];
+        for (int i = j + 1; i < d; ++i) {
+            double s = 0.0;
+            for (int k = j; k < i; ++k) s -= L[i * 4 + k] * Li[k * 4 + j];
+            Li[i * 4 + j] = s / L[i * 4 + i];
+        }
+    }
+    for (int i = 0; i < 16; ++i) Ainv[i] = 0.0;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double s = 0.0;
+            for (int k = std::max(i, j); k < d; ++k) s += Li[k * 4 + i] * Li[k * 4 + j];
+            Ainv[i * 4 + j] = s;
+        }
+}
+
+// Validate a symmetric positive definite d x d row-major matrix.
+int check_spd(const double* A, int d, const char* name, double* L) {
+    if (!A) return fail(KDEFFT_E_ARG, "%s is NULL", name);
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < i; ++j) {
+            const double a = A[i * d + j], b = A[j * d + i];
+            if (!(std::fabs(a - b) <= 1e-12 * (std::fabs(a) + std::fabs(b)) + 1e-300))
+                return fail(KDEFFT_E_NOT_SPD, "%s is not symmetric (%g vs %g)", name, a, b);
+        }
+    if (!chol_host(A, d, d, L)) return fail(KDEFFT_E_NOT_SPD, "%s is not positive definite", name);
+    return KDEFFT_OK;
+}
+
+const double kInvSqrt2Pi = 0.39894228040143267794;
+
+double normal_const(const double* L, int d) {  // (2 pi)^{-d/2} / prod L_kk
+    double c = 1.0;
+    for (int k = 0; k < d; ++k) c *= kInvSqrt2Pi / L[k * 4 + k];
+    return c;
+}
+
+struct Arena {
+    char* base;
+    size_t cap;
+    size_t off = 0;
+    bool dry;
+    Arena(void* b, size_t c, bool d) : base(static_cast<char*>(b)), cap(c), dry(d) {}
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = dry ? nullptr : reinterpret_cast<T*>(base + off);
+        off += count * sizeof(T);
+        return p;
+    }
+    bool fits() const { return dry || off <= cap; }
+};
+
+struct Sizes {
+    int64_t prodM = 1, prodP = 1, lead = 1, Q = 0, spec = 0;
+};
+Sizes sizes_of(const kdefft_grid& g) {
+    Sizes s;
+    for (int k = 0; k < g.d; ++k) {
+        s.prodM *= g.M[k];
+        s.prodP *= g.P[k];
+        if (k + 1 < g.d) s.lead *= g.P[k];
+    }
+    s.Q = g.P[g.d - 1] / 2 + 1;
+    s.spec = s.lead * s.Q;
+    return s;
+}
+
+int nblk_dot(const kdefft_grid& g) {
+    const int64_t b = (sizes_of(g).prodM + 255) / 256;
+    return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 1024);
+}
+
+int64_t max_nchunks(const kdefft_grid& g, int kind, int r, int64_t ncand) {
+    int64_t m = 1;
+    for (int v = 0; v < ROW_VARIANTS; ++v) m = std::max(m, make_geom(g, kind, r, ncand, v).nchunks);
+    return m;
+}
+
+// ---------------------------------------------------------------- launch choices
+struct LaunchKey {
+    int dev, kind, d, r, N;
+    bool operator<(const LaunchKey& o) const {
+        return std::tie(dev, kind, d, r, N) < std::tie(o.dev, o.kind, o.d, o.r, o.N);
+    }
+};
+std::mutex g_launch_mu;
+std::map<LaunchKey, RowLaunch> g_launch;
+bool g_cache_loaded = false;
+
+std::string arch_name(int dev) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::string a = p.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+int json_int(const std::string& line, const char* key, int dflt) {
+    const std::string k = std::string("\"") + key + "\":";
+    size_t p = line.find(k);
+    if (p == std::string::npos) return dflt;
+    p += k.size();
+    while (p < line.size() && line[p] == ' ') ++p;
+    return std::atoi(line.c_str() + p);
+}
+
+void load_cache_locked(int dev) {
+    if (g_cache_loaded) return;
+    g_cache_loaded = true;
+    const char* path = std::getenv("KDEFFT_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    const std::string arch = arch_name(dev);
+    char buf[1024];
+    while (std::fgets(buf, sizeof(buf), f)) {
+        std::string line(buf);
+        if (line.find("\"arch\": \"" + arch + "\"") == std::string::npos) continue;
+        LaunchKey k{dev, json_int(line, "kind", -1), json_int(line, "d", 0), json_int(line, "r", 0),
+                    json_int(line, "N", 0)};
+        RowLaunch rl{json_int(line, "variant", 0), json_int(line, "grid", 0)};
+        if (k.kind >= 0 && rl.variant >= 0 && rl.variant < ROW_VARIANTS) g_launch[k] = rl;
+    }
+    std::fclose(f);
+}
+
+RowLaunch launch_for(int kind, int d, int r, int N) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_launch_mu);
+    load_cache_locked(dev);
+    auto it = g_launch.find(LaunchKey{dev, kind, d, r, N});
+    if (it != g_launch.end()) return it->second;
+    return RowLaunch{0, 0};
+}
+
+void set_launch(int kind, int d, int r, int N, RowLaunch rl) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_launch_mu);
+    g_launch[LaunchKey{dev, kind, d, r, N}] = rl;
+}
+
+// ---------------------------------------------------------------- workspace plans
+struct DsLayout {
+    int64_t* counts;
+    double2* spec;
+    double2* wmix;
+    double* scal;
+    int32_t* n_out;
+    DsDev* rec;
+};
+DsLayout carve_dataset(Arena& a, const kdefft_grid& g) {
+    const Sizes s = sizes_of(g);
+    DsLayout L;
+    L.counts = a.take<int64_t>(s.prodM);
+    L.spec = a.take<double2>(s.spec);
+    L.wmix = a.take<double2>(s.spec);
+    L.scal = a.take<double>(4);
+    L.n_out = a.take<int32_t>(1);
+    L.rec = a.take<DsDev>(1);
+    return L;
+}
+
+struct PrepScratch {
+    double* czp;
+    double* prm;
+    double* partial;
+};
+PrepScratch carve_prepare(Arena& a, const kdefft_grid& g) {
+    PrepScratch p;
+    p.czp = a.take<double>(sizes_of(g).prodP);
+    p.prm = a.take<double>(PRM);
+    p.partial = a.take<double>(max_nchunks(g, FUN_PSI, 0, 1));
+    return p;
+}
+
+struct PlainScratch {
+    int64_t* counts;
+    int32_t* n_out;
+    double* czp;
+    double2* C;
+    double* kreal;
+    double2* K;
+    double* partial;
+    double* sums;
+};
+PlainScratch carve_plain(Arena& a, const kdefft_grid& g, bool with_counts) {
+    const Sizes s = sizes_of(g);
+    PlainScratch p{};
+    if (with_counts) {
+        p.counts = a.take<int64_t>(s.prodM);
+        p.n_out = a.take<int32_t>(1);
+        p.czp = a.take<double>(s.prodP);
+        p.C = a.take<double2>(s.spec);
+    }
+    p.kreal = a.take<double>(s.prodP);
+    p.K = a.take<double2>(s.spec);
+    p.partial = a.take<double>(nblk_dot(g));
+    p.sums = a.take<double>(16);
+    return p;
+}
+
+struct BatchScratch {
+    double* prm;
+    double* partial;
+};
+// Partial sums of the row kernels: sized for every family that may run in
+// this workspace (the SCV families differ in grids per item and chunking).
+BatchScratch carve_batch(Arena& a, const kdefft_grid& g, int kind, int r, int64_t ncand) {
+    BatchScratch b;
+    b.prm = a.take<double>(ncand * PRM);
+    int64_t need = 0;
+    if (kind == FUN_PSI) {
+        need = max_nchunks(g, kind, r, ncand) * ng_of(kind, g.d, r);
+    } else {
+        for (int k = FUN_SCV_OBJ; k <= FUN_SCV_GRAD; ++k)
+            need = std::max<int64_t>(need, max_nchunks(g, k, 2, ncand) * ng_of(k, g.d, 2));
+    }
+    b.partial = a.take<double>(ncand * need);
+    return b;
+}
+
+int plan_bytes(const kdefft_grid& g, int op, int r, int64_t batch, Arena& a) {
+    switch (op) {
+        case KDEFFT_OP_GRID_AUTO: {
+            const int64_t nb = std::min<int64_t>(std::max<int64_t>((batch + 255) / 256, 1), 1024);
+            a.take<double>(nb * 8);
+            a.take<double>(8);
+            return KDEFFT_OK;
+        }
+        case KDEFFT_OP_PSI_PLAIN: carve_plain(a, g, true); return KDEFFT_OK;
+        case KDEFFT_OP_PSI_FUSED:
+            carve_dataset(a, g);
+            carve_prepare(a, g);
+            carve_batch(a, g, FUN_PSI, r, 1);
+            return KDEFFT_OK;
+        case KDEFFT_OP_PREPARE: carve_prepare(a, g); return KDEFFT_OK;
+        case KDEFFT_OP_PSI_BATCH: carve_batch(a, g, FUN_PSI, r, std::max<int64_t>(batch, 1)); return KDEFFT_OK;
+        case KDEFFT_OP_SCV_BATCH:
+            carve_batch(a, g, FUN_SCV_OBJGRAD, 2, std::max<int64_t>(batch, 1));
+            return KDEFFT_OK;
+        case KDEFFT_OP_SCV_PLAIN: carve_plain(a, g, false); return KDEFFT_OK;
+        case KDEFFT_OP_AUTOTUNE: {
+            carve_batch(a, g, FUN_SCV_OBJGRAD, 2, 64);
+            const int q = g.d * (g.d + 1) / 2;
+            a.take<double>(64 * q);
+            a.take<double>(64);
+            a.take<double>(64 * q);
+            return KDEFFT_OK;
+        }
+        default: return fail(KDEFFT_E_ARG, "unknown op %d", op);
+    }
+}
+
+hipStream_t S(void* stream) { return static_cast<hipStream_t>(stream); }
+
+// Bin X into counts (zeroed first) and build the circular real count array.
+int bin_and_fill(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts, int32_t* n_out, double* czp,
+                 hipStream_t s) {
+    const Sizes sz = sizes_of(g);
+    HIPCHK(launch_zero(counts, sz.prodM * sizeof(int64_t), s), "zero counts");
+    if (n_out) HIPCHK(launch_zero(n_out, sizeof(int32_t), s), "zero n_out");
+    HIPCHK(launch_linbin(X, n, g, counts, n_out, s), "linbin");
+    if (czp) HIPCHK(launch_fill_czp(counts, g, czp, s), "fill czp");
+    return KDEFFT_OK;
+}
+
+PsiBatchArgs psi_args(const kdefft_grid& g, int r, int n_ds, const DsDev* const* recs, const double* Gs /*d*d each*/) {
+    PsiBatchArgs a{};
+    a.n_ds = n_ds;
+    a.d = g.d;
+    a.r = r;
+    a.prodP = (double)sizes_of(g).prodP;
+    for (int j = 0; j < n_ds; ++j) {
+        a.rec[j] = recs[j];
+        int t = 0;
+        for (int c = 0; c < g.d; ++c)
+            for (int i = c; i < g.d; ++i) a.Gv[j][t++] = Gs[j * g.d * g.d + i * g.d + c];
+    }
+    return a;
+}
+
+// Prepare a dataset whose buffers are described by L (in a caller buffer or workspace).
+int prepare_into(const double* X, int64_t n, const kdefft_grid& g, const double* Gpilot, const DsLayout& L,
+                 const PrepScratch& p, bool with_const, hipStream_t s) {
+    int rc = bin_and_fill(X, n, g, L.counts, L.n_out, p.czp, s);
+    if (rc) return rc;
+    HIPCHK(fft_prepare_nd(p.czp, L.spec, L.wmix, g, s), "count transform");
+    DsDev rec{};
+    rec.wmix = L.wmix;
+    rec.scal = L.scal;
+    rec.n = (double)n;
+    for (int k = 0; k < g.d; ++k) rec.delta[k] = g.delta[k];
+    if (Gpilot)
+        for (int i = 0; i < g.d; ++i)
+            for (int j = 0; j < g.d; ++j) rec.G[i * 4 + j] = Gpilot[i * g.d + j];
+    HIPCHK(launch_write_rec(L.rec, rec, s), "dataset record");
+    HIPCHK(launch_zero(L.scal, 4 * sizeof(double), s), "zero scal");
+    if (with_const) {
+        // constant SCV term: n^-2 sum sum phi_{2G}, the psi_0 functional at 2G
+        std::vector<double> G2(g.d * g.d);
+        for (int i = 0; i < g.d * g.d; ++i) G2[i] = 2.0 * Gpilot[i];
+        const DsDev* recs[1] = {L.rec};
+        const PsiBatchArgs a = psi_args(g, 0, 1, recs, G2.data());
+        HIPCHK(launch_psi_setup(a, p.prm, s), "const-term setup");
+        const RowLaunch rl = launch_for(FUN_PSI, g.d, 0, g.P[g.d - 1]);
+        const RowGeom geo = make_geom(g, FUN_PSI, 0, 1, rl.variant);
+        HIPCHK(launch_rows(FUN_PSI, g.d, 0, geo, p.prm, 1, p.partial, rl, s), "const-term rows");
+        HIPCHK(launch_psi_final(p.partial, geo, 1, p.prm, 1, nullptr, L.scal, s), "const-term final");
+    }
+    return KDEFFT_OK;
+}
+
+// The batched row kernels are compiled for last-axis lengths up to 2048, 1024,
+// 256, 128 (d = 1..4) and enough LDS for the family's grids.
+int check_rows(int kind, int d, int r, int N) {
+    if (rows_per_iter(kind, d, r, N, 0) < 1)
+        return fail(KDEFFT_E_UNSUPPORTED,
+                    "no batched row kernel for d=%d, r=%d, last-axis P=%d (family %d); use the plain path", d, r, N,
+                    kind);
+    return KDEFFT_OK;
+}
+
+int check_ws(const Arena& a, size_t have) {
+    if (!a.fits()) return fail(KDEFFT_E_WORKSPACE, "workspace of %zu bytes, need %zu", have, a.off);
+    return KDEFFT_OK;
+}
+
+int check_ptr_align(const void* p, const char* name) {
+    if (!p) return fail(KDEFFT_E_ARG, "%s is NULL", name);
+    if (reinterpret_cast<uintptr_t>(p) % 256) return fail(KDEFFT_E_WORKSPACE, "%s is not 256-byte aligned", name);
+    return KDEFFT_OK;
+}
+
+int check_batch_ds(const kdefft_dataset* ds, int n_ds, int max_ds) {
+    if (!ds) return fail(KDEFFT_E_ARG, "dataset array is NULL");
+    if (n_ds < 1 || n_ds > max_ds) return fail(KDEFFT_E_ARG, "n_ds=%d outside [1,%d]", n_ds, max_ds);
+    int rc = check_grid(&ds[0].grid);
+    if (rc) return rc;
+    for (int j = 0; j < n_ds; ++j) {
+        if (!ds[j].rec || !ds[j].wmix || !ds[j].scal)
+            return fail(KDEFFT_E_ARG, "dataset %d is not prepared", j);
+        rc = check_grid(&ds[j].grid);
+        if (rc) return rc;
+        if (ds[j].grid.d != ds[0].grid.d) return fail(KDEFFT_E_ARG, "datasets differ in d");
+        for (int k = 0; k < ds[0].grid.d; ++k)
+            if (ds[j].grid.M[k] != ds[0].grid.M[k] || ds[j].grid.P[k] != ds[0].grid.P[k])
+                return fail(KDEFFT_E_ARG, "datasets in one batch must share M and P (dataset %d)", j);
+        rc = check_n(ds[j].n);
+        if (rc) return rc;
+    }
+    return KDEFFT_OK;
+}
+
+}  // namespace
+
+// ==================================================================== exports
+extern "C" {
+
+const char* kdefft_strerror(int code) {
+    switch (code) {
+        case KDEFFT_OK: return "ok";
+        case KDEFFT_E_ARG: return "invalid argument";
+        case KDEFFT_E_NOT_SPD: return "bandwidth matrix not symmetric positive definite";
+        case KDEFFT_E_ODD_R: return "odd derivative order";
+        case KDEFFT_E_OUT_OF_GRID: return "data outside the grid";
+        case KDEFFT_E_OVERFLOW: return "sample too large for int64 fixed-point bins";
+        case KDEFFT_E_WORKSPACE: return "workspace too small or misaligned";
+        case KDEFFT_E_HIP: return "HIP runtime error";
+        case KDEFFT_E_UNSUPPORTED: return "configuration outside the compiled limits";
+        default: return "unknown error";
+    }
+}
+
+const char* kdefft_last_error_detail(void) { return g_err.c_str(); }
+
+int kdefft_version(void) { return 10000; }
+
+int kdefft_unique_count(int d, int r) {
+    if (d < 1 || d > KDEFFT_MAX_D) return fail(KDEFFT_E_ARG, "d=%d outside [1,4]", d);
+    if (r < 0 || r > KDEFFT_MAX_R) return fail(KDEFFT_E_ARG, "r=%d outside [0,8]", r);
+    return (int)binom(d + r - 1, r);
+}
+
+int kdefft_unique_index(int d, int r, int32_t* tuples_host) {
+    const int cnt = kdefft_unique_count(d, r);
+    if (cnt < 0) return cnt;
+    if (r == 0) return KDEFFT_OK;
+    if (!tuples_host) return fail(KDEFFT_E_ARG, "tuples_host is NULL");
+    std::vector<int> idx(r, 0);
+    int e = 0;
+    while (true) {
+        for (int m = 0; m < r; ++m) tuples_host[e * r + m] = idx[m];
+        ++e;
+        int m = r - 1;
+        while (m >= 0 && idx[m] == d - 1) --m;
+        if (m < 0) break;
+        idx[m] += 1;
+        for (int q = m + 1; q < r; ++q) idx[q] = idx[m];
+    }
+    return e == cnt ? KDEFFT_OK : fail(KDEFFT_E_ARG, "internal enumeration mismatch");
+}
+
+int kdefft_grid_plan(int d, const int32_t* M_host, const int32_t* P_host, const double* lo_host,
+                     const double* hi_host, kdefft_grid* out) {
+    if (!M_host || !lo_host || !hi_host || !out) return fail(KDEFFT_E_ARG, "NULL argument to kdefft_grid_plan");
+    if (d < 1 || d > KDEFFT_MAX_D) return fail(KDEFFT_E_ARG, "d=%d outside [1,4]", d);
+    kdefft_grid g;
+    std::memset(&g, 0, sizeof(g));
+    g.d = d;
+    for (int k = 0; k < d; ++k) {
+        g.M[k] = M_host[k];
+        if (P_host) {
+            g.P[k] = P_host[k];
+        } else {  // smallest power of two >= 2M - 1 (circular layout without wrap-around)
+            int p = 4;
+            while (p < 2 * M_host[k] - 1 && p < (1 << 30)) p <<= 1;
+            g.P[k] = p;
+        }
+        g.lo[k] = lo_host[k];
+        if (!(hi_host[k] > lo_host[k])) return fail(KDEFFT_E_ARG, "hi[%d] <= lo[%d]", k, k);
+        volatile double span = hi_host[k] - lo_host[k];  // one rounding, then one division
+        g.delta[k] = span / (double)(M_host[k] - 1);
+    }
+    const int rc = check_grid(&g);
+    if (rc) return rc;
+    *out = g;
+    return KDEFFT_OK;
+}
+
+int kdefft_ws_bytes(const kdefft_grid* g, int op, int r, int64_t batch, size_t* out) {
+    if (!out) return fail(KDEFFT_E_ARG, "out is NULL");
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (op == KDEFFT_OP_PSI_PLAIN || op == KDEFFT_OP_PSI_FUSED || op == KDEFFT_OP_PSI_BATCH) {
+        rc = check_d_r(g->d, r);
+        if (rc) return rc;
+    }
+    Arena a(nullptr, 0, true);
+    rc = plan_bytes(*g, op, r, batch, a);
+    if (rc) return rc;
+    *out = a.off + 256;
+    return KDEFFT_OK;
+}
+
+int kdefft_grid_auto(const double* X, int64_t n, int d, const double* G_host, const int32_t* M_host,
+                     double pad_sd, kdefft_grid* out, void* ws, size_t ws_bytes, void* stream) {
+    if (!X || !G_host || !M_host || !out) return fail(KDEFFT_E_ARG, "NULL argument to kdefft_grid_auto");
+    int rc = check_n(n);
+    if (rc) return rc;
+    if (d < 1 || d > KDEFFT_MAX_D) return fail(KDEFFT_E_ARG, "d=%d outside [1,4]", d);
+    if (!(pad_sd >= 0.0) || !std::isfinite(pad_sd)) return fail(KDEFFT_E_ARG, "pad_sd must be finite and >= 0");
+    double Lg[16];
+    rc = check_spd(G_host, d, "G", Lg);
+    if (rc) return rc;
+    kdefft_grid probe;
+    std::memset(&probe, 0, sizeof(probe));
+    probe.d = d;
+    for (int k = 0; k < d; ++k) { probe.M[k] = 2; probe.P[k] = 4; probe.delta[k] = 1.0; }
+    Arena a(ws, ws_bytes, false);
+    const int64_t nb = std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 1024);
+    double* partial = a.take<double>(nb * 8);
+    double* dout = a.take<double>(8);
+    if (!ws) return fail(KDEFFT_E_ARG, "workspace is NULL");
+    rc = check_ws(a, ws_bytes);
+    if (rc) return rc;
+    hipStream_t s = S(stream);
+    HIPCHK(launch_bounds(X, n, d, partial, (int)nb, dout, s), "bounds");
+    double host[8];
+    HIPCHK(hipMemcpyAsync(host, dout, sizeof(host), hipMemcpyDeviceToHost, s), "bounds readback");
+    HIPCHK(hipStreamSynchronize(s), "bounds sync");
+    double lo[4], hi[4];
+    for (int k = 0; k < d; ++k) {
+        const double sd = std::sqrt(G_host[k * d + k]);
+        volatile double pad = pad_sd * sd;
+        lo[k] = host[k] - pad;
+        hi[k] = host[4 + k] + pad;
+        if (!std::isfinite(lo[k]) || !std::isfinite(hi[k])) return fail(KDEFFT_E_ARG, "data not finite");
+        if (!(hi[k] > lo[k])) hi[k] = lo[k] + 1.0;  // degenerate axis: unit span
+    }
+    return kdefft_grid_plan(d, M_host, nullptr, lo, hi, out);
+}
+
+int kdefft_linbin(const double* X, int64_t n, const kdefft_grid* g, int64_t* counts, int32_t* n_out_dev,
+                  void* stream) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    rc = check_n(n);
+    if (rc) return rc;
+    if (!X || !counts) return fail(KDEFFT_E_ARG, "NULL X or counts");
+    return bin_and_fill(X, n, *g, counts, n_out_dev, nullptr, S(stream));
+}
+
+int kdefft_check_binning(const int32_t* n_out_dev, int32_t* n_out_host, void* stream) {
+    if (!n_out_dev) return fail(KDEFFT_E_ARG, "n_out_dev is NULL");
+    int32_t v = 0;
+    HIPCHK(hipMemcpyAsync(&v, n_out_dev, sizeof(v), hipMemcpyDeviceToHost, S(stream)), "n_out readback");
+    HIPCHK(hipStreamSynchronize(S(stream)), "n_out sync");
+    if (n_out_host) *n_out_host = v;
+    if (v) return fail(KDEFFT_E_OUT_OF_GRID, "%d points outside the grid were skipped", v);
+    return KDEFFT_OK;
+}
+
+int kdefft_psi(const double* X, int64_t n, const kdefft_grid* g, const double* G_host, int r, double* psi,
+               int mode, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    rc = check_d_r(g->d, r);
+    if (rc) return rc;
+    rc = check_n(n);
+    if (rc) return rc;
+    if (!X || !psi) return fail(KDEFFT_E_ARG, "NULL X or psi");
+    if (mode != KDEFFT_PSI_PLAIN && mode != KDEFFT_PSI_FUSED) return fail(KDEFFT_E_ARG, "mode=%d", mode);
+    double L[16];
+    rc = check_spd(G_host, g->d, "G", L);
+    if (rc) return rc;
+    if (!ws) return fail(KDEFFT_E_ARG, "workspace is NULL");
+    const int d = g->d;
+    const Sizes sz = sizes_of(*g);
+    const double scale = 1.0 / ((double)n * (double)n * (double)sz.prodP);
+    const int nu = (int)binom(d + r - 1, r);
+    hipStream_t s = S(stream);
+    Arena a(ws, ws_bytes, false);
+    if (mode == KDEFFT_PSI_PLAIN) {
+        const PlainScratch p = carve_plain(a, *g, true);
+        rc = check_ws(a, ws_bytes);
+        if (rc) return rc;
+        ParamBlock prm{};
+        chol_inv_host(L, d, prm.v + S_P1);
+        prm.v[S_C] = normal_const(L, d);
+        rc = bin_and_fill(X, n, *g, p.counts, p.n_out, p.czp, s);
+        if (rc) return rc;
+        HIPCHK(fft_r2c_nd(p.czp, p.C, *g, s), "R2C counts");
+        const int nb = nblk_dot(*g);
+        for (int u = 0; u < nu; ++u) {
+            HIPCHK(launch_kgrid_psi(p.kreal, *g, r, prm, u, s), "kernel grid");
+            HIPCHK(fft_r2c_nd(p.kreal, p.K, *g, s), "R2C kernel");
+            HIPCHK(launch_cmul(p.K, p.C, sz.spec, s), "spectrum product");
+            HIPCHK(fft_c2r_nd(p.K, p.kreal, *g, s), "C2R");
+            HIPCHK(launch_dot_counts(p.counts, p.kreal, *g, p.partial, nb, s), "count contraction");
+            HIPCHK(launch_sum_scale(p.partial, nb, scale, psi + u, s), "final sum");
+        }
+        return KDEFFT_OK;
+    }
+    rc = check_rows(FUN_PSI, d, r, g->P[d - 1]);
+    if (!rc) rc = check_rows(FUN_PSI, d, 0, g->P[d - 1]);
+    if (rc) return rc;
+    const DsLayout L2 = carve_dataset(a, *g);
+    const PrepScratch pp = carve_prepare(a, *g);
+    const BatchScratch b = carve_batch(a, *g, FUN_PSI, r, 1);
+    rc = check_ws(a, ws_bytes);
+    if (rc) return rc;
+    rc = prepare_into(X, n, *g, G_host, L2, pp, false, s);
+    if (rc) return rc;
+    const DsDev* recs[1] = {L2.rec};
+    const PsiBatchArgs args = psi_args(*g, r, 1, recs, G_host);
+    HIPCHK(launch_psi_setup(args, b.prm, s), "psi setup");
+    const RowLaunch rl = launch_for(FUN_PSI, d, r, g->P[d - 1]);
+    const RowGeom geo = make_geom(*g, FUN_PSI, r, 1, rl.variant);
+    HIPCHK(launch_rows(FUN_PSI, d, r, geo, b.prm, 1, b.partial, rl, s), "psi rows");
+    HIPCHK(launch_psi_final(b.partial, geo, nu, b.prm, 1, psi, nullptr, s), "psi final");
+    return KDEFFT_OK;
+}
+
+int kdefft_dataset_bytes(const kdefft_grid* g, size_t* out) {
+    if (!out) return fail(KDEFFT_E_ARG, "out is NULL");
+    const int rc = check_grid(g);
+    if (rc) return rc;
+    Arena a(nullptr, 0, true);
+    carve_dataset(a, *g);
+    *out = a.off;
+    return KDEFFT_OK;
+}
+
+int kdefft_dataset_prepare(const double* X, int64_t n, const kdefft_grid* g, const double* Gpilot_host,
+                           void* ds_mem, size_t ds_bytes, kdefft_dataset* out, void* ws, size_t ws_bytes,
+                           void* stream) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    rc = check_n(n);
+    if (rc) return rc;
+    if (!X || !out) return fail(KDEFFT_E_ARG, "NULL X or out");
+    double L[16];
+    rc = check_spd(Gpilot_host, g->d, "Gpilot", L);
+    if (rc) return rc;
+    rc = check_rows(FUN_PSI, g->d, 0, g->P[g->d - 1]);
+    if (rc) return rc;
+    rc = check_ptr_align(ds_mem, "ds_mem");
+    if (rc) return rc;
+    if (!ws) return fail(KDEFFT_E_ARG, "workspace is NULL");
+    Arena da(ds_mem, ds_bytes, false);
+    const DsLayout dl = carve_dataset(da, *g);
+    if (!da.fits()) return fail(KDEFFT_E_WORKSPACE, "dataset buffer of %zu bytes, need %zu", ds_bytes, da.off);
+    Arena a(ws, ws_bytes, false);
+    const PrepScratch p = carve_prepare(a, *g);
+    rc = check_ws(a, ws_bytes);
+    if (rc) return rc;
+    rc = prepare_into(X, n, *g, Gpilot_host, dl, p, true, S(stream));
+    if (rc) return rc;
+    kdefft_dataset o;
+    std::memset(&o, 0, sizeof(o));
+    o.grid = *g;
+    o.n = n;
+    for (int i = 0; i < g->d * g->d; ++i) o.G[i] = Gpilot_host[i];
+    o.counts = dl.counts;
+    o.spec = reinterpret_cast<double*>(dl.spec);
+    o.wmix = reinterpret_cast<double*>(dl.wmix);
+    o.scal = dl.scal;
+    o.n_out = dl.n_out;
+    o.rec = dl.rec;
+    *out = o;
+    return KDEFFT_OK;
+}
+
+int kdefft_psi_batch(const kdefft_dataset* ds, int n_ds, const double* G_host, int r, double* psi, void* ws,
+                     size_t ws_bytes, void* stream) {
+    int rc = check_batch_ds(ds, n_ds, KDEFFT_MAX_PSI_DS);
+    if (rc) return rc;
+    const kdefft_grid& g = ds[0].grid;
+    rc = check_d_r(g.d, r);
+    if (rc) return rc;
+    rc = check_rows(FUN_PSI, g.d, r, g.P[g.d - 1]);
+    if (rc) return rc;
+    if (!G_host || !psi) return fail(KDEFFT_E_ARG, "NULL G_host or psi");
+    const int d = g.d, dd = d * d;
+    std::vector<double> Gs(n_ds * dd);
+    for (int j = 0; j < n_ds; ++j) {
+        double L[16];
+        rc = check_spd(G_host + 16 * j, d, "G", L);
+        if (rc) return rc;
+        for (int i = 0; i < dd; ++i) Gs[j * dd + i] = G_host[16 * j + i];
+    }
+    if (!ws) return fail(KDEFFT_E_ARG, "workspace is NULL");
+    Arena a(ws, ws_bytes, false);
+    const BatchScratch b = carve_batch(a, g, FUN_PSI, r, n_ds);
+    rc = check_ws(a, ws_bytes);
+    if (rc) return rc;
+    std::vector<const DsDev*> recs(n_ds);
+    for (int j = 0; j < n_ds; ++j) recs[j] = static_cast<const DsDev*>(ds[j].rec);
+    const PsiBatchArgs args = psi_args(g, r, n_ds, recs.data(), Gs.data());
+    hipStream_t s = S(stream);
+    HIPCHK(launch_psi_setup(args, b.prm, s), "psi setup");
+    const RowLaunch rl = launch_for(FUN_PSI, d, r, g.P[d - 1]);
+    const RowGeom geo = make_geom(g, FUN_PSI, r, n_ds, rl.variant);
+    HIPCHK(launch_rows(FUN_PSI, d, r, geo, b.prm, n_ds, b.partial, rl, s), "psi rows");
+    HIPCHK(launch_psi_final(b.partial, geo, (int)binom(d + r - 1, r), b.prm, n_ds, psi, nullptr, s), "psi final");
+    return KDEFFT_OK;
+}
+
+static int scv_common(const kdefft_dataset* ds, int n_ds, const int64_t* off, const double* vechL, int kind,
+                      const double* grad_out, double* obj, double* grad, int32_t* status, void* ws,
+                      size_t ws_bytes, void* stream, const RowLaunch* force) {
+    int rc = check_batch_ds(ds, n_ds, KDEFFT_MAX_BATCH_DS);
+    if (rc) return rc;
+    if (!off || !vechL) return fail(KDEFFT_E_ARG, "NULL h_offsets or vechL");
+    if (off[0] != 0) return fail(KDEFFT_E_ARG, "h_offsets[0] must be 0");
+    for (int j = 0; j < n_ds; ++j)
+        if (off[j + 1] < off[j]) return fail(KDEFFT_E_ARG, "h_offsets must be non-decreasing");
+    const int64_t B = off[n_ds];
+    if (B < 1) return fail(KDEFFT_E_ARG, "no candidate bandwidths");
+    if (B > (1LL << 24)) return fail(KDEFFT_E_ARG, "too many candidates in one call");
+    const kdefft_grid& g = ds[0].grid;
+    rc = check_rows(kind, g.d, 2, g.P[g.d - 1]);
+    if (rc) return rc;
+    ScvBatchArgs a{};
+    a.n_ds = n_ds;
+    a.d = g.d;
+    a.prodP = (double)sizes_of(g).prodP;
+    for (int j = 0; j < n_ds; ++j) a.rec[j] = static_cast<const DsDev*>(ds[j].rec);
+    for (int j = 0; j <= n_ds; ++j) a.off[j] = off[j];
+    if (!ws) return fail(KDEFFT_E_ARG, "workspace is NULL");
+    Arena ar(ws, ws_bytes, false);
+    const BatchScratch b = carve_batch(ar, g, FUN_SCV_OBJGRAD, 2, B);
+    rc = check_ws(ar, ws_bytes);
+    if (rc) return rc;
+    hipStream_t s = S(stream);
+    const RowLaunch rl = force ? *force : launch_for(kind, g.d, 2, g.P[g.d - 1]);
+    const RowGeom geo = make_geom(g, kind, 2, B, rl.variant);
+    HIPCHK(launch_scv_setup(vechL, a, B, b.prm, status, s), "scv setup");
+    HIPCHK(launch_rows(kind, g.d, 2, geo, b.prm, B, b.partial, rl, s), "scv rows");
+    HIPCHK(launch_scv_final(kind, b.partial, geo, b.prm, B, grad_out, obj, grad, s), "scv final");
+    return KDEFFT_OK;
+}
+
+int kdefft_scv_batch(const kdefft_dataset* ds, int n_ds, const int64_t* h_offsets_host, const double* vechL,
+                     double* obj, double* grad, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+    if (!obj) return fail(KDEFFT_E_ARG, "obj is NULL");
+    return scv_common(ds, n_ds, h_offsets_host, vechL, grad ? FUN_SCV_OBJGRAD : FUN_SCV_OBJ, nullptr, obj, grad,
+                      status, ws, ws_bytes, stream, nullptr);
+}
+
+int kdefft_scv_adjoint(const kdefft_dataset* ds, int n_ds, const int64_t* h_offsets_host, const double* vechL,
+                       const double* grad_out, double* grad_vechL, void* ws, size_t ws_bytes, void* stream) {
+    if (!grad_out || !grad_vechL) return fail(KDEFFT_E_ARG, "NULL grad_out or grad_vechL");
+    return scv_common(ds, n_ds, h_offsets_host, vechL, FUN_SCV_GRAD, grad_out, nullptr, grad_vechL, nullptr, ws,
+                      ws_bytes, stream, nullptr);
+}
+
+int kdefft_scv_plain(const kdefft_dataset* ds, const double* H_host, double* out, void* ws, size_t ws_bytes,
+                     void* stream) {
+    if (!ds || !out) return fail(KDEFFT_E_ARG, "NULL dataset or out");
+    int rc = check_batch_ds(ds, 1, 1);
+    if (rc) return rc;
+    if (!ds->counts || !ds->spec) return fail(KDEFFT_E_ARG, "dataset is not prepared");
+    const kdefft_grid& g = ds->grid;
+    const int d = g.d, q = d * (d + 1) / 2;
+    double LH[16];
+    rc = check_spd(H_host, d, "H", LH);
+    if (rc) return rc;
+    double S1[16] = {0}, S2[16] = {0}, S3[16] = {0};
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            const double h = H_host[i * d + j], gp = ds->G[i * d + j];
+            S1[i * 4 + j] = 2.0 * h + 2.0 * gp;
+            S2[i * 4 + j] = h + 2.0 * gp;
+            S3[i * 4 + j] = 2.0 * gp;
+        }
+    double L1[16], L2[16], L3[16];
+    if (!chol_host(S1, 4, d, L1) || !chol_host(S2, 4, d, L2) || !chol_host(S3, 4, d, L3))
+        return fail(KDEFFT_E_NOT_SPD, "2H+2G, H+2G or 2G not positive definite");
+    ParamBlock kp{};
+    chol_inv_host(L1, d, kp.v + S_P1);
+    chol_inv_host(L2, d, kp.v + S_P2);
+    chol_inv_host(L3, d, kp.v + S_L);
+    kp.v[S_C1] = normal_const(L1, d);
+    kp.v[S_C2] = normal_const(L2, d);
+    kp.v[S_CONST] = normal_const(L3, d);
+    ParamBlock fin{};
+    chol_inv_host(LH, d, fin.v);
+    for (int i = 0; i < 16; ++i) fin.v[16 + i] = LH[i];
+    double c4 = 1.0;
+    for (int k = 0; k < d; ++k) c4 *= 0.28209479177387814347 / LH[k * 4 + k];  // (4 pi)^{-1/2} / L_kk
+    fin.v[32] = c4 / (double)ds->n;
+    if (!ws) return fail(KDEFFT_E_ARG, "workspace is NULL");
+    Arena a(ws, ws_bytes, false);
+    const PlainScratch p = carve_plain(a, g, false);
+    rc = check_ws(a, ws_bytes);
+    if (rc) return rc;
+    const Sizes sz = sizes_of(g);
+    const double scale = 1.0 / ((double)ds->n * (double)ds->n * (double)sz.prodP);
+    const int nb = nblk_dot(g);
+    hipStream_t s = S(stream);
+    const double2* C = reinterpret_cast<const double2*>(ds->spec);
+    for (int e = 0; e <= q; ++e) {
+        HIPCHK(launch_kgrid_scv(p.kreal, g, kp, e, s), "kernel grid");
+        HIPCHK(fft_r2c_nd(p.kreal, p.K, g, s), "R2C kernel");
+        HIPCHK(launch_cmul(p.K, C, sz.spec, s), "spectrum product");
+        HIPCHK(fft_c2r_nd(p.K, p.kreal, g, s), "C2R");
+        HIPCHK(launch_dot_counts(ds->counts, p.kreal, g, p.partial, nb, s), "count contraction");
+        HIPCHK(launch_sum_scale(p.partial, nb, scale, p.sums + e, s), "final sum");
+    }
+    HIPCHK(launch_scv_plain_final(p.sums, fin, d, out, s), "scv assembly");
+    return KDEFFT_OK;
+}
+
+int kdefft_set_row_launch(int kind, int d, int r, int N, int variant, int grid_blocks) {
+    if (kind < 0 || kind > 3) return fail(KDEFFT_E_ARG, "kind=%d", kind);
+    if (variant < 0 || variant >= ROW_VARIANTS) return fail(KDEFFT_E_ARG, "variant=%d", variant);
+    if (grid_blocks < -1) return fail(KDEFFT_E_ARG, "grid_blocks=%d", grid_blocks);
+    if (rows_per_iter(kind, d, r, N, variant) < 1)
+        return fail(KDEFFT_E_UNSUPPORTED, "no compiled row kernel for kind=%d d=%d r=%d N=%d", kind, d, r, N);
+    set_launch(kind, d, r, N, RowLaunch{variant, grid_blocks});
+    return KDEFFT_OK;
+}
+
+int kdefft_autotune(const kdefft_dataset* ds, void* ws, size_t ws_bytes, const char* cache_path, void* stream) {
+    int rc = check_batch_ds(ds, 1, 1);
+    if (rc) return rc;
+    const kdefft_grid& g = ds->grid;
+    const int d = g.d, q = d * (d + 1) / 2, N = g.P[d - 1];
+    if (!ws) return fail(KDEFFT_E_ARG, "workspace is NULL");
+    Arena a(ws, ws_bytes, false);
+    carve_batch(a, g, FUN_SCV_OBJGRAD, 2, 64);
+    double* vech = a.take<double>(64 * q);
+    double* obj = a.take<double>(64);
+    double* grad = a.take<double>(64 * q);
+    rc = check_ws(a, ws_bytes);
+    if (rc) return rc;
+    // 64 candidates H_b = s_b * Gpilot with s_b spread over [0.5, 8]
+    double LG[16];
+    rc = check_spd(ds->G, d, "Gpilot", LG);
+    if (rc) return rc;
+    std::vector<double> hv(64 * q);
+    for (int b = 0; b < 64; ++b) {
+        const double sc = std::sqrt(0.5 * std::pow(16.0, b / 63.0));
+        int t = 0;
+        for (int j = 0; j < d; ++j)
+            for (int i = j; i < d; ++i) hv[b * q + t++] = sc * LG[i * 4 + j];
+    }
+    hipStream_t s = S(stream);
+    HIPCHK(hipMemcpyAsync(vech, hv.data(), hv.size() * sizeof(double), hipMemcpyHostToDevice, s), "tuner upload");
+    int64_t off[2] = {0, 64};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0), "event");
+    HIPCHK(hipEventCreate(&e1), "event");
+    const int grids[2] = {0, -1};
+    RowLaunch best{0, 0};
+    float best_ms = 1e30f;
+    std::string lines;
+    const std::string arch = [] {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        return arch_name(dev);
+    }();
+    for (int v = 0; v < ROW_VARIANTS; ++v) {
+        if (rows_per_iter(FUN_SCV_OBJGRAD, d, 2, N, v) < 1) continue;
+        for (int gi = 0; gi < 2; ++gi) {
+            const RowLaunch rl{v, grids[gi]};
+            rc = scv_common(ds, 1, off, vech, FUN_SCV_OBJGRAD, nullptr, obj, grad, nullptr, ws, ws_bytes, stream, &rl);
+            if (rc) break;
+            HIPCHK(hipEventRecord(e0, s), "event");
+            for (int rep = 0; rep < 3; ++rep) {
+                rc = scv_common(ds, 1, off, vech, FUN_SCV_OBJGRAD, nullptr, obj, grad, nullptr, ws, ws_bytes, stream,
+                                &rl);
+                if (rc) break;
+            }
+            HIPCHK(hipEventRecord(e1, s), "event");
+            HIPCHK(hipEventSynchronize(e1), "event sync");
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+            ms /= 3.f;
+            char buf[256];
+            snprintf(buf, sizeof(buf), "variant %d grid %d: %.1f us\n", v, rl.grid_blocks, ms * 1000.0);
+            lines += buf;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = rl;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    for (int kind = FUN_SCV_OBJ; kind <= FUN_SCV_GRAD; ++kind)
+        if (rows_per_iter(kind, d, 2, N, best.variant) >= 1) set_launch(kind, d, 2, N, best);
+    if (cache_path && *cache_path) {
+        FILE* f = std::fopen(cache_path, "a");
+        if (f) {
+            for (int kind = FUN_SCV_OBJ; kind <= FUN_SCV_GRAD; ++kind)
+                std::fprintf(f,
+                             "{\"arch\": \"%s\", \"kind\": %d, \"d\": %d, \"r\": 2, \"N\": %d, \"variant\": %d, "
+                             "\"grid\": %d, \"us\": %.2f}\n",
+                             arch.c_str(), kind, d, N, best.variant, best.grid_blocks, best_ms * 1000.0);
+            std::fclose(f);
+        }
+    }
+    g_err = lines;
+    return KDEFFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,356 @@
+// Multi-dimensional real FFT for the zero-padded grids (Sec. 4, Eq. (19)-(23)):
+// LDS-staged Stockham passes along one axis at a time.
+//
+//  * last axis (contiguous): real-to-complex through a half-length complex
+//    transform of the even/odd pairs plus the standard split step, and the
+//    inverse complex-to-real;
+//  * leading axes (strided): each block loads a tile of T adjacent columns for
+//    the full axis length (T * 16 contiguous bytes per row: coalesced), runs T
+//    pencils in LDS and writes the tile back in place.  The axis-0 pass of the
+//    count transform also forms |C|^2 and transforms it forward again while the
+//    tile is still in LDS.
+//
+// Transforms are unnormalised: forward uses e^{-2 pi i jk/N}, inverse e^{+...}.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <mutex>
+
+#include "dev_common.h"
+#include "internal.h"
+
+namespace kdefft {
+
+// ------------------------------------------------------------------ twiddles
+// One table per device; kernels receive its device address as an argument.
+static __device__ double2 g_twiddle[TWN];
+
+hipError_t twiddles(const double2** out) {
+    static std::mutex mu;
+    static const double2* ptr[64] = {nullptr};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        // cos/sin of 2 pi m / TWN from the first octant in long double, so that
+        // symmetric entries are exactly symmetric and each value is rounded once.
+        static double2 host[TWN];
+        const long double pi = 3.141592653589793238462643383279502884L;
+        for (int m = 0; m < TWN; ++m) {
+            int q = m / (TWN / 4), rr = m % (TWN / 4);  // quadrant, remainder
+            long double cs, sn;
+            if (rr <= TWN / 8) {
+                long double a = 2.0L * pi * rr / TWN;
+                cs = cosl(a);
+                sn = sinl(a);
+            } else {
+                long double a = 2.0L * pi * (TWN / 4 - rr) / TWN;
+                cs = sinl(a);
+                sn = cosl(a);
+            }
+            long double c2, s2;  // rotate by q quarter turns
+            switch (q) {
+                case 0: c2 = cs; s2 = sn; break;
+                case 1: c2 = -sn; s2 = cs; break;
+                case 2: c2 = -cs; s2 = -sn; break;
+                default: c2 = sn; s2 = -cs; break;
+            }
+            host[m] = make_double2((double)c2, -(double)s2);  // e^{-i theta}
+        }
+        e = hipMemcpyToSymbol(HIP_SYMBOL(g_twiddle), host, sizeof(host), 0, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return e;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_twiddle));
+        if (e != hipSuccess) return e;
+        ptr[dev] = static_cast<const double2*>(p);
+    }
+    *out = ptr[dev];
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------------ last axis
+// Rows per block for a last-axis pass of real length N.
+template <int N>
+constexpr int last_rows() { return (N / 2) >= 2048 ? 1 : 2048 / (N / 2); }
+
+template <int N, int NT>
+__global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, double2* __restrict__ out,
+                                                 int64_t rows, const double2* __restrict__ tw) {
+    constexpr int H = N / 2, Q = H + 1, ROWS = last_rows<N>();
+    constexpr int PS = H + 1;
+    __shared__ double2 buf[ROWS * PS];
+    const int64_t r0 = (int64_t)blockIdx.x * ROWS;
+    const double2* src = reinterpret_cast<const double2*>(in);
+    for (int e = threadIdx.x; e < ROWS * H; e += NT) {
+        const int rr = e / H, m = e - rr * H;
+        const int64_t row = r0 + rr;
+        buf[rr * PS + m] = row < rows ? src[row * H + m] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    fft_lds<H, ROWS, NT, -1>(buf, PS, tw);
+    for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
+        const int rr = e / Q, k = e - rr * Q;
+        const int64_t row = r0 + rr;
+        if (row >= rows) continue;
+        const double2 zk = buf[rr * PS + (k == H ? 0 : k)];
+        const double2 zc = c_conj(buf[rr * PS + (k == 0 ? 0 : H - k)]);
+        const double2 E = c_scale(c_add(zk, zc), 0.5);
+        const double2 O = c_rot<-1>(c_scale(c_sub(zk, zc), 0.5));  // (zk - zc)/(2i)
+        const double2 w = tw[k * (TWN / N)];
+        out[row * Q + k] = c_add(E, c_mul(w, O));
+    }
+}
+
+template <int N, int NT>
+__global__ __launch_bounds__(NT) void k_c2r_last(const double2* __restrict__ in, double* __restrict__ out,
+                                                 int64_t rows, const double2* __restrict__ tw) {
+    constexpr int H = N / 2, Q = H + 1, ROWS = last_rows<N>();
+    constexpr int PS = H + 1;
+    __shared__ double2 buf[ROWS * PS];
+    const int64_t r0 = (int64_t)blockIdx.x * ROWS;
+    for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
+        const int rr = e / Q, k = e - rr * Q;
+        const int64_t row = r0 + rr;
+        buf[rr * PS + k] = row < rows ? in[row * Q + k] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    constexpr int PER = (ROWS * H + NT - 1) / NT;
+    double2 z[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int e = threadIdx.x + u * NT;
+        if (e < ROWS * H) {
+            const int rr = e / H, k = e - rr * H;
+            const double2 xk = buf[rr * PS + k];
+            const double2 xc = c_conj(buf[rr * PS + H - k]);
+            const double2 E = c_scale(c_add(xk, xc), 0.5);
+            const double2 O = c_scale(c_mulc(c_sub(xk, xc), tw[k * (TWN / N)]), 0.5);  // * e^{+i..}
+            z[u] = c_add(E, c_rot<1>(O));
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int e = threadIdx.x + u * NT;
+        if (e < ROWS * H) {
+            const int rr = e / H, k = e - rr * H;
+            buf[rr * PS + k] = z[u];
+        }
+    }
+    __syncthreads();
+    fft_lds<H, ROWS, NT, 1>(buf, PS, tw);
+    double2* dst = reinterpret_cast<double2*>(out);
+    for (int e = threadIdx.x; e < ROWS * H; e += NT) {
+        const int rr = e / H, m = e - rr * H;
+        const int64_t row = r0 + rr;
+        if (row < rows) dst[row * H + m] = c_scale(buf[rr * PS + m], 2.0);
+    }
+}
+
+// ------------------------------------------------------------------ strided axes
+// Columns per tile: the largest power of two <= 16 whose padded tile fits 64 KiB.
+template <int N>
+constexpr int tile_cols() {
+    return 4096 / (N + 1) >= 16 ? 16 : 4096 / (N + 1) >= 8 ? 8 : 4096 / (N + 1) >= 4 ? 4
+         : 4096 / (N + 1) >= 2 ? 2 : 1;
+}
+
+// MODE 0: in-place transform.  MODE 1: forward transform stored in place
+// (the finished count spectrum C), then |C|^2 transformed forward again and
+// stored to out2.
+template <int N, int NT, int DIR, int MODE>
+__global__ __launch_bounds__(NT) void k_c2c_strided(double2* __restrict__ buf, double2* __restrict__ out2,
+                                                    int64_t inner, int64_t tiles,
+                                                    const double2* __restrict__ tw) {
+    constexpr int T = tile_cols<N>();
+    constexpr int PS = T > 1 ? N + 1 : N;
+    __shared__ double2 lds[T * PS];
+    const int64_t o = blockIdx.x / tiles;
+    const int64_t i0 = (blockIdx.x - o * tiles) * T;
+    double2* base = buf + o * N * inner + i0;
+    for (int e = threadIdx.x; e < N * T; e += NT) {
+        const int t = e % T, p = e / T;
+        lds[t * PS + p] = (i0 + t < inner) ? base[(int64_t)p * inner + t] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    fft_lds<N, T, NT, DIR>(lds, PS, tw);
+    for (int e = threadIdx.x; e < N * T; e += NT) {
+        const int t = e % T, p = e / T;
+        if (i0 + t < inner) base[(int64_t)p * inner + t] = lds[t * PS + p];
+    }
+    if constexpr (MODE == 1) {
+        for (int e = threadIdx.x; e < N * T; e += NT) {
+            const int t = e % T, p = e / T;
+            const double2 v = lds[t * PS + p];
+            lds[t * PS + p] = make_double2(v.x * v.x + v.y * v.y, 0.0);
+        }
+        __syncthreads();
+        fft_lds<N, T, NT, -1>(lds, PS, tw);
+        double2* b2 = out2 + o * N * inner + i0;
+        for (int e = threadIdx.x; e < N * T; e += NT) {
+            const int t = e % T, p = e / T;
+            if (i0 + t < inner) b2[(int64_t)p * inner + t] = lds[t * PS + p];
+        }
+    }
+}
+
+// |C|^2 for d = 1 (no leading axis).
+__global__ void k_abs2(const double2* __restrict__ in, double2* __restrict__ out, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 v = in[i];
+        out[i] = make_double2(v.x * v.x + v.y * v.y, 0.0);
+    }
+}
+
+// ------------------------------------------------------------------ dispatch
+static int ilog2i(int n) { int k = 0; while ((1 << k) < n) ++k; return k; }
+
+template <int N>
+static hipError_t run_r2c_last(const double* in, double2* out, int64_t rows, const double2* tw, hipStream_t s) {
+    constexpr int ROWS = last_rows<N>();
+    const int64_t blocks = (rows + ROWS - 1) / ROWS;
+    hipLaunchKernelGGL((k_r2c_last<N, 256>), dim3((unsigned)blocks), dim3(256), 0, s, in, out, rows, tw);
+    return hipGetLastError();
+}
+template <int N>
+static hipError_t run_c2r_last(const double2* in, double* out, int64_t rows, const double2* tw, hipStream_t s) {
+    constexpr int ROWS = last_rows<N>();
+    const int64_t blocks = (rows + ROWS - 1) / ROWS;
+    hipLaunchKernelGGL((k_c2r_last<N, 256>), dim3((unsigned)blocks), dim3(256), 0, s, in, out, rows, tw);
+    return hipGetLastError();
+}
+template <int N>
+static hipError_t run_c2c(double2* buf, double2* out2, int64_t outer, int64_t inner, int dir, int mode,
+                          const double2* tw, hipStream_t s) {
+    constexpr int T = tile_cols<N>();
+    const int64_t tiles = (inner + T - 1) / T;
+    const dim3 grid((unsigned)(outer * tiles));
+    if (mode == 1)
+        hipLaunchKernelGGL((k_c2c_strided<N, 256, -1, 1>), grid, dim3(256), 0, s, buf, out2, inner, tiles, tw);
+    else if (dir < 0)
+        hipLaunchKernelGGL((k_c2c_strided<N, 256, -1, 0>), grid, dim3(256), 0, s, buf, out2, inner, tiles, tw);
+    else
+        hipLaunchKernelGGL((k_c2c_strided<N, 256, 1, 0>), grid, dim3(256), 0, s, buf, out2, inner, tiles, tw);
+    return hipGetLastError();
+}
+
+#define KDEFFT_SWITCH_N(LOGN, CALL)                           \
+    switch (LOGN) {                                          \
+        case 1: return CALL(2);                              \
+        case 2: return CALL(4);                              \
+        case 3: return CALL(8);                              \
+        case 4: return CALL(16);                             \
+        case 5: return CALL(32);                             \
+        case 6: return CALL(64);                             \
+        case 7: return CALL(128);                            \
+        case 8: return CALL(256);                            \
+        case 9: return CALL(512);                            \
+        case 10: return CALL(1024);                          \
+        case 11: return CALL(2048);                          \
+        case 12: return CALL(4096);                          \
+        default: return hipErrorInvalidValue;                \
+    }
+
+static hipError_t r2c_last(const double* in, double2* out, int64_t rows, int N, const double2* tw, hipStream_t s) {
+#define CALL(NN) run_r2c_last<NN>(in, out, rows, tw, s)
+    if (N < 4) return hipErrorInvalidValue;
+    KDEFFT_SWITCH_N(ilog2i(N), CALL)
+#undef CALL
+}
+static hipError_t c2r_last(const double2* in, double* out, int64_t rows, int N, const double2* tw, hipStream_t s) {
+#define CALL(NN) run_c2r_last<NN>(in, out, rows, tw, s)
+    if (N < 4) return hipErrorInvalidValue;
+    KDEFFT_SWITCH_N(ilog2i(N), CALL)
+#undef CALL
+}
+static hipError_t c2c(double2* buf, double2* out2, int64_t outer, int N, int64_t inner, int dir, int mode,
+                      const double2* tw, hipStream_t s) {
+#define CALL(NN) run_c2c<NN>(buf, out2, outer, inner, dir, mode, tw, s)
+    KDEFFT_SWITCH_N(ilog2i(N), CALL)
+#undef CALL
+}
+
+// Shape helpers: the half-spectrum is [P_0, ..., P_{d-2}, Q].
+static int64_t lead_count(const kdefft_grid& g) {
+    int64_t r = 1;
+    for (int k = 0; k + 1 < g.d; ++k) r *= g.P[k];
+    return r;
+}
+static void axis_shape(const kdefft_grid& g, int axis, int64_t* outer, int64_t* inner) {
+    int64_t o = 1, in = g.P[g.d - 1] / 2 + 1;
+    for (int k = 0; k < axis; ++k) o *= g.P[k];
+    for (int k = axis + 1; k + 1 < g.d; ++k) in *= g.P[k];
+    *outer = o;
+    *inner = in;
+}
+
+hipError_t fft_c2c_axis(double2* buf, const kdefft_grid& g, int axis, int dir, hipStream_t s) {
+    const double2* tw;
+    hipError_t e = twiddles(&tw);
+    if (e != hipSuccess) return e;
+    int64_t outer, inner;
+    axis_shape(g, axis, &outer, &inner);
+    return c2c(buf, nullptr, outer, g.P[axis], inner, dir, 0, tw, s);
+}
+
+hipError_t fft_r2c_nd(const double* in, double2* out, const kdefft_grid& g, hipStream_t s) {
+    const double2* tw;
+    hipError_t e = twiddles(&tw);
+    if (e != hipSuccess) return e;
+    e = r2c_last(in, out, lead_count(g), g.P[g.d - 1], tw, s);
+    for (int ax = g.d - 2; ax >= 0 && e == hipSuccess; --ax) {
+        int64_t outer, inner;
+        axis_shape(g, ax, &outer, &inner);
+        e = c2c(out, nullptr, outer, g.P[ax], inner, -1, 0, tw, s);
+    }
+    return e;
+}
+
+hipError_t fft_c2r_nd(double2* inout, double* out, const kdefft_grid& g, hipStream_t s) {
+    const double2* tw;
+    hipError_t e = twiddles(&tw);
+    if (e != hipSuccess) return e;
+    for (int ax = 0; ax + 1 < g.d && e == hipSuccess; ++ax) {
+        int64_t outer, inner;
+        axis_shape(g, ax, &outer, &inner);
+        e = c2c(inout, nullptr, outer, g.P[ax], inner, 1, 0, tw, s);
+    }
+    if (e != hipSuccess) return e;
+    return c2r_last(inout, out, lead_count(g), g.P[g.d - 1], tw, s);
+}
+
+hipError_t fft_prepare_nd(const double* czp, double2* spec, double2* wmix, const kdefft_grid& g,
+                          hipStream_t s) {
+    const double2* tw;
+    hipError_t e = twiddles(&tw);
+    if (e != hipSuccess) return e;
+    e = r2c_last(czp, spec, lead_count(g), g.P[g.d - 1], tw, s);
+    if (e != hipSuccess) return e;
+    if (g.d == 1) {
+        const int64_t cnt = g.P[0] / 2 + 1;
+        hipLaunchKernelGGL(k_abs2, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, spec, wmix, cnt);
+        return hipGetLastError();
+    }
+    for (int ax = g.d - 2; ax >= 1 && e == hipSuccess; --ax) {
+        int64_t outer, inner;
+        axis_shape(g, ax, &outer, &inner);
+        e = c2c(spec, nullptr, outer, g.P[ax], inner, -1, 0, tw, s);
+    }
+    if (e != hipSuccess) return e;
+    {
+        int64_t outer, inner;
+        axis_shape(g, 0, &outer, &inner);
+        e = c2c(spec, wmix, outer, g.P[0], inner, -1, 1, tw, s);
+    }
+    for (int ax = 1; ax + 1 < g.d && e == hipSuccess; ++ax) {
+        int64_t outer, inner;
+        axis_shape(g, ax, &outer, &inner);
+        e = c2c(wmix, nullptr, outer, g.P[ax], inner, -1, 0, tw, s);
+    }
+    return e;
+}
+
+}  // namespace kdefft

@@ -1,0 +1,126 @@
+// Internal interface between the C-ABI layer (api.cpp) and the HIP kernels.
+// Nothing here is exported.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/kdefft.h"
+
+namespace kdefft {
+
+constexpr int PRM = 64;     // doubles per candidate parameter block
+constexpr int NT_DEF = 256;  // threads per block of the simple kernels
+
+// Parameter block layout (float64 slots) shared by setup, row and finalize kernels.
+// Matrices use row stride 4.
+//   psi:  [0,16) P = G^{-1}   [16] c = (-1)^r (2pi)^{-d/2}|G|^{-1/2}
+//   scv:  [0,16) P1 = (2H+2G)^{-1}  [16,32) P2 = (H+2G)^{-1}  [32] c1  [33] c2
+//   both: [39] wmix pointer bits  [40,44) delta  [44] n  [45] 1/(n^2 prod P)
+//         [46] constant term  [47] singular flag  [48,64) L (scv) / P3 (plain scv)
+enum Slot { S_P1 = 0, S_C = 16, S_P2 = 16, S_C1 = 32, S_C2 = 33, S_WMIX = 39, S_DELTA = 40, S_N = 44,
+            S_SCALE = 45, S_CONST = 46, S_SING = 47, S_L = 48 };
+
+// Per-dataset record kept in the dataset's own device buffer (written by a
+// kernel at prepare time); batched calls pass pointers to these records.
+struct DsDev {
+    const double2* wmix;
+    const double* scal;
+    double n;
+    double delta[4];
+    double G[16];   // pilot, row stride 4
+};
+
+// Kernel-argument views of a batch (no host-to-device copies per call).
+struct ScvBatchArgs {
+    int n_ds;
+    int d;
+    double prodP;
+    const DsDev* rec[KDEFFT_MAX_BATCH_DS];
+    int64_t off[KDEFFT_MAX_BATCH_DS + 1];
+};
+struct PsiBatchArgs {
+    int n_ds;
+    int d;
+    int r;
+    double prodP;
+    const DsDev* rec[KDEFFT_MAX_PSI_DS];
+    double Gv[KDEFFT_MAX_PSI_DS][10];   // vech (columns of the lower triangle)
+};
+// One parameter block passed by value.
+struct ParamBlock {
+    double v[64];
+};
+
+// Geometry of the row decomposition of the lag grid used by the batched kernels.
+struct RowGeom {
+    int d;
+    int M[4];
+    int P[4];
+    int64_t nrows;     // rows of the half lag set with nonzero kernel values
+    int64_t chunk;     // rows per work item
+    int64_t nchunks;   // work items per candidate
+    int Q;             // P[d-1]/2 + 1
+};
+
+// Kinds of kernel families generated on the lag grid.
+enum FunKind { FUN_PSI = 0, FUN_SCV_OBJ = 1, FUN_SCV_OBJGRAD = 2, FUN_SCV_GRAD = 3 };
+
+int ng_of(int kind, int d, int r);   // number of kernel grids of a family
+
+// -------------------------------------------------------------- launchers
+// All return hipSuccess or the first HIP error; they only enqueue work.
+hipError_t twiddles(const double2** out);  // per-device table e^{-2 pi i m/4096}
+
+hipError_t launch_bounds(const double* X, int64_t n, int d, double* partial, int nblk,
+                         double* out, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_linbin(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts,
+                         int32_t* n_out, hipStream_t s);
+hipError_t launch_fill_czp(const int64_t* counts, const kdefft_grid& g, double* czp, hipStream_t s);
+hipError_t launch_write_rec(DsDev* rec, const DsDev& val, hipStream_t s);
+
+// Multi-dimensional transforms over the circular-layout arrays.
+hipError_t fft_r2c_nd(const double* in, double2* out, const kdefft_grid& g, hipStream_t s);
+hipError_t fft_c2r_nd(double2* inout, double* out, const kdefft_grid& g, hipStream_t s);
+// Count spectrum of a prepared dataset: spec = R2C(czp); wmix = |spec|^2
+// transformed forward along the leading axes.
+hipError_t fft_prepare_nd(const double* czp, double2* spec, double2* wmix, const kdefft_grid& g,
+                          hipStream_t s);
+
+// Paper-literal path, one grid per launch.
+hipError_t launch_kgrid_psi(double* out, const kdefft_grid& g, int r, const ParamBlock& prm,
+                            int entry, hipStream_t s);
+hipError_t launch_kgrid_scv(double* out, const kdefft_grid& g, const ParamBlock& prm, int entry,
+                            hipStream_t s);
+hipError_t launch_cmul(double2* K, const double2* C, int64_t count, hipStream_t s);
+hipError_t launch_dot_counts(const int64_t* counts, const double* sreal, const kdefft_grid& g,
+                             double* partial, int nblk, hipStream_t s);
+hipError_t launch_sum_scale(const double* partial, int nblk, double scale, double* out,
+                            hipStream_t s);
+hipError_t launch_scv_plain_final(const double* sums, const ParamBlock& fin, int d, double* out,
+                                  hipStream_t s);
+
+// Batched row kernels.
+struct RowLaunch {
+    int variant;        // compiled launch variant (rows per iteration, radix schedule)
+    int grid_blocks;    // persistent grid size; 0 = occupancy x CUs, -1 = one block per item
+};
+hipError_t launch_rows(int kind, int d, int r, const RowGeom& geo, const double* prm, int64_t ncand,
+                       double* partial, const RowLaunch& rl, hipStream_t s);
+int rows_per_iter(int kind, int d, int r, int N, int variant);
+constexpr int ROW_VARIANTS = 3;
+hipError_t launch_scv_setup(const double* vechL, const ScvBatchArgs& a, int64_t ncand, double* prm,
+                            int32_t* status, hipStream_t s);
+hipError_t launch_psi_setup(const PsiBatchArgs& a, double* prm, hipStream_t s);
+hipError_t launch_scv_final(int kind, const double* partial, const RowGeom& geo,
+                            const double* prm, int64_t ncand, const double* grad_out,
+                            double* obj, double* grad, hipStream_t s);
+hipError_t launch_psi_final(const double* partial, const RowGeom& geo, int ng,
+                            const double* prm, int64_t ncand, double* psi, double* scal_out,
+                            hipStream_t s);
+
+RowGeom make_geom(const kdefft_grid& g, int kind, int r, int64_t ncand, int variant);
+
+}  // namespace kdefft

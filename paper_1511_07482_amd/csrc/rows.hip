@@ -1,0 +1,332 @@
+// Host dispatch of the batched row kernels, and the small per-candidate
+// kernels around them: SCV parameter setup (Cholesky factors of 2H+2G and
+// H+2G) and the final assembly of psi / SCV objective / gradient from the
+// per-item partial sums (fixed summation order).
+#include <hip/hip_runtime.h>
+
+#include "dev_common.h"
+#include "internal.h"
+
+namespace kdefft {
+
+hipError_t launch_rows_d1(int, int, int, int, const double*, RowGeom, int64_t, double*, int, const double2*,
+                          hipStream_t);
+hipError_t launch_rows_d2(int, int, int, int, const double*, RowGeom, int64_t, double*, int, const double2*,
+                          hipStream_t);
+hipError_t launch_rows_d3(int, int, int, int, const double*, RowGeom, int64_t, double*, int, const double2*,
+                          hipStream_t);
+hipError_t launch_rows_d4(int, int, int, int, const double*, RowGeom, int64_t, double*, int, const double2*,
+                          hipStream_t);
+int rows_iter_d1(int, int, int, int);
+int rows_iter_d2(int, int, int, int);
+int rows_iter_d3(int, int, int, int);
+int rows_iter_d4(int, int, int, int);
+
+static int binom_h(int n, int k) {
+    int r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+int ng_of(int kind, int d, int r) {
+    const int q = d * (d + 1) / 2;
+    switch (kind) {
+        case FUN_PSI: return binom_h(d + r - 1, r);
+        case FUN_SCV_OBJ: return 1;
+        case FUN_SCV_OBJGRAD: return 1 + q;
+        case FUN_SCV_GRAD: return q;
+        default: return 0;
+    }
+}
+
+int rows_per_iter(int kind, int d, int r, int N, int variant) {
+    switch (d) {
+        case 1: return rows_iter_d1(kind, r, N, variant);
+        case 2: return rows_iter_d2(kind, r, N, variant);
+        case 3: return rows_iter_d3(kind, r, N, variant);
+        case 4: return rows_iter_d4(kind, r, N, variant);
+        default: return 0;
+    }
+}
+
+RowGeom make_geom(const kdefft_grid& g, int kind, int r, int64_t ncand, int variant) {
+    RowGeom geo{};
+    geo.d = g.d;
+    for (int k = 0; k < 4; ++k) {
+        geo.M[k] = k < g.d ? g.M[k] : 1;
+        geo.P[k] = k < g.d ? g.P[k] : 1;
+    }
+    int64_t nrows = 1;
+    if (g.d >= 2) {
+        nrows = g.M[0];
+        for (int k = 1; k + 1 < g.d; ++k) nrows *= (2 * g.M[k] - 1);
+    }
+    geo.nrows = nrows;
+    geo.Q = g.P[g.d - 1] / 2 + 1;
+    int ri = rows_per_iter(kind, g.d, r, g.P[g.d - 1], variant);
+    if (ri < 1) ri = 1;
+    const int64_t target = 8192;
+    int64_t iters = (nrows * ncand + (int64_t)ri * target - 1) / ((int64_t)ri * target);
+    if (iters < 1) iters = 1;
+    int64_t chunk = iters * ri;
+    if (chunk > nrows) chunk = ((nrows + ri - 1) / ri) * ri;
+    geo.chunk = chunk;
+    geo.nchunks = (nrows + chunk - 1) / chunk;
+    return geo;
+}
+
+hipError_t launch_rows(int kind, int d, int r, const RowGeom& geo, const double* prm, int64_t ncand,
+                       double* partial, const RowLaunch& rl, hipStream_t s) {
+    const double2* tw;
+    hipError_t e = twiddles(&tw);
+    if (e != hipSuccess) return e;
+    const int64_t nitems = ncand * geo.nchunks;
+    const int N = geo.P[d - 1];
+    switch (d) {
+        case 1: return launch_rows_d1(kind, r, N, rl.variant, prm, geo, nitems, partial, rl.grid_blocks, tw, s);
+        case 2: return launch_rows_d2(kind, r, N, rl.variant, prm, geo, nitems, partial, rl.grid_blocks, tw, s);
+        case 3: return launch_rows_d3(kind, r, N, rl.variant, prm, geo, nitems, partial, rl.grid_blocks, tw, s);
+        case 4: return launch_rows_d4(kind, r, N, rl.variant, prm, geo, nitems, partial, rl.grid_blocks, tw, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------------ small dense linear algebra (d <= 4)
+// Cholesky A = L L^T of a symmetric d x d (row stride 4); false if not positive definite.
+__device__ static bool chol4(const double* A, double* L, int d) {
+    for (int i = 0; i < 16; ++i) L[i] = 0.0;
+    for (int j = 0; j < d; ++j) {
+        double s = A[j * 4 + j];
+        for (int k = 0; k < j; ++k) s -= L[j * 4 + k] * L[j * 4 + k];
+        if (!(s > 0.0)) return false;
+        const double ljj = sqrt(s);
+        L[j * 4 + j] = ljj;
+        for (int i = j + 1; i < d; ++i) {
+            double t = A[i * 4 + j];
+            for (int k = 0; k < j; ++k) t -= L[i * 4 + k] * L[j * 4 + k];
+            L[i * 4 + j] = t / ljj;
+        }
+    }
+    return true;
+}
+
+// Inverse of L L^T from the lower factor L (row stride 4).
+__device__ static void chol_inv4(const double* L, double* Ainv, int d) {
+    double Li[16];
+    for (int i = 0; i < 16; ++i) Li[i] = 0.0;
+    for (int j = 0; j < d; ++j) {
+        Li[j * 4 + j] = 1.0 / L[j * 4 + j];
+        for (int i = j + 1; i < d; ++i) {
+            double s = 0.0;
+            for (int k = j; k < i; ++k) s -= L[i * 4 + k] * Li[k * 4 + j];
+            Li[i * 4 + j] = s / L[i * 4 + i];
+        }
+    }
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double s = 0.0;
+            for (int k = (i > j ? i : j); k < d; ++k) s += Li[k * 4 + i] * Li[k * 4 + j];
+            Ainv[i * 4 + j] = s;
+        }
+}
+
+__device__ static double two_pi_pow(int d) {  // (2 pi)^{-d/2}
+    const double c = 0.39894228040143267794;      // (2 pi)^{-1/2}
+    double r = 1.0;
+    for (int k = 0; k < d; ++k) r *= c;
+    return r;
+}
+
+__device__ static void put_ptr(double* slot, const void* p) {
+    *slot = __longlong_as_double(static_cast<long long>(reinterpret_cast<uintptr_t>(p)));
+}
+
+// One thread per candidate: H = L L^T from vechL, S1 = 2H + 2G, S2 = H + 2G,
+// their inverses and normal constants, grid spacing, n and the scale of the
+// Parseval sums, the dataset's constant term.  status 1 = H singular.
+__global__ void k_scv_setup(const double* __restrict__ vechL, ScvBatchArgs a, int64_t ncand,
+                            double* __restrict__ prm, int32_t* __restrict__ status) {
+    const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (h >= ncand) return;
+    const int d = a.d;
+    const int q = d * (d + 1) / 2;
+    int j = 0;
+    while (j + 1 < a.n_ds && h >= a.off[j + 1]) ++j;
+    const DsDev& ds = *a.rec[j];
+    double L[16], H[16], S1[16], S2[16], L1[16], L2[16];
+    for (int i = 0; i < 16; ++i) L[i] = 0.0;
+    int t = 0;
+    bool sing = false;
+    for (int jj = 0; jj < d; ++jj)
+        for (int i = jj; i < d; ++i) {
+            const double v = vechL[h * q + t++];
+            L[i * 4 + jj] = v;
+            if (!isfinite(v) || (i == jj && v == 0.0)) sing = true;
+        }
+    for (int i = 0; i < d; ++i)
+        for (int k2 = 0; k2 < d; ++k2) {
+            double s = 0.0;
+            for (int k = 0; k < d; ++k) s += L[i * 4 + k] * L[k2 * 4 + k];
+            H[i * 4 + k2] = s;
+        }
+    for (int i = 0; i < 16; ++i) { S1[i] = 0.0; S2[i] = 0.0; }
+    for (int i = 0; i < d; ++i)
+        for (int k2 = 0; k2 < d; ++k2) {
+            S1[i * 4 + k2] = 2.0 * H[i * 4 + k2] + 2.0 * ds.G[i * 4 + k2];
+            S2[i * 4 + k2] = H[i * 4 + k2] + 2.0 * ds.G[i * 4 + k2];
+        }
+    double* p = prm + h * PRM;
+    for (int i = 0; i < PRM; ++i) p[i] = 0.0;
+    const bool ok = !sing && chol4(S1, L1, d) && chol4(S2, L2, d);
+    if (!ok) {
+        sing = true;
+        // benign parameters keep the row kernel finite; the result is set to NaN
+        for (int i = 0; i < 16; ++i) { L1[i] = 0.0; L2[i] = 0.0; }
+        for (int k = 0; k < d; ++k) { L1[k * 4 + k] = 1.0; L2[k * 4 + k] = 1.0; }
+    }
+    chol_inv4(L1, p + S_P1, d);
+    chol_inv4(L2, p + S_P2, d);
+    double det1 = 1.0, det2 = 1.0;
+    for (int k = 0; k < d; ++k) { det1 *= L1[k * 4 + k]; det2 *= L2[k * 4 + k]; }
+    p[S_C1] = two_pi_pow(d) / det1;
+    p[S_C2] = two_pi_pow(d) / det2;
+    put_ptr(p + S_WMIX, ds.wmix);
+    for (int k = 0; k < d; ++k) p[S_DELTA + k] = ds.delta[k];
+    p[S_N] = ds.n;
+    p[S_SCALE] = 1.0 / (ds.n * ds.n * a.prodP);
+    p[S_CONST] = ds.scal[0];
+    p[S_SING] = sing ? 1.0 : 0.0;
+    for (int i = 0; i < 16; ++i) p[S_L + i] = L[i];
+    if (status) status[h] = sing ? 1 : 0;
+}
+
+hipError_t launch_scv_setup(const double* vechL, const ScvBatchArgs& a, int64_t ncand, double* prm,
+                            int32_t* status, hipStream_t s) {
+    const int64_t blocks = (ncand + 63) / 64;
+    hipLaunchKernelGGL(k_scv_setup, dim3((unsigned)blocks), dim3(64), 0, s, vechL, a, ncand, prm, status);
+    return hipGetLastError();
+}
+
+// One thread per dataset: P = G^{-1}, c = (-1)^r (2 pi)^{-d/2} |G|^{-1/2}
+// for the psi_r family at the given bandwidth (validated SPD on the host).
+__global__ void k_psi_setup(PsiBatchArgs a, double* __restrict__ prm) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.n_ds) return;
+    const int d = a.d;
+    const DsDev& ds = *a.rec[j];
+    double G[16], L[16];
+    for (int i = 0; i < 16; ++i) G[i] = 0.0;
+    int t = 0;
+    for (int jj = 0; jj < d; ++jj)
+        for (int i = jj; i < d; ++i) {
+            G[i * 4 + jj] = a.Gv[j][t];
+            G[jj * 4 + i] = a.Gv[j][t];
+            ++t;
+        }
+    double* p = prm + (int64_t)j * PRM;
+    for (int i = 0; i < PRM; ++i) p[i] = 0.0;
+    chol4(G, L, d);
+    chol_inv4(L, p + S_P1, d);
+    double det = 1.0;
+    for (int k = 0; k < d; ++k) det *= L[k * 4 + k];
+    p[S_C] = two_pi_pow(d) / det;  // (-1)^r = 1: r is even
+    put_ptr(p + S_WMIX, ds.wmix);
+    for (int k = 0; k < d; ++k) p[S_DELTA + k] = ds.delta[k];
+    p[S_N] = ds.n;
+    p[S_SCALE] = 1.0 / (ds.n * ds.n * a.prodP);
+}
+
+hipError_t launch_psi_setup(const PsiBatchArgs& a, double* prm, hipStream_t s) {
+    hipLaunchKernelGGL(k_psi_setup, dim3(1), dim3(64), 0, s, a, prm);
+    return hipGetLastError();
+}
+
+__global__ void k_write_rec(DsDev* rec, DsDev val) { if (threadIdx.x == 0) *rec = val; }
+
+hipError_t launch_write_rec(DsDev* rec, const DsDev& val, hipStream_t s) {
+    hipLaunchKernelGGL(k_write_rec, dim3(1), dim3(64), 0, s, rec, val);
+    return hipGetLastError();
+}
+
+// SCV assembly.  kind: FUN_SCV_OBJ (obj only), FUN_SCV_OBJGRAD (obj + grad),
+// FUN_SCV_GRAD (adjoint: grad scaled by grad_out).
+__global__ void k_scv_final(int kind, const double* __restrict__ partial, int64_t nchunks, int ng, int d,
+                            const double* __restrict__ prm, int64_t ncand, const double* __restrict__ grad_out,
+                            double* __restrict__ obj, double* __restrict__ grad) {
+    const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (h >= ncand) return;
+    const double* p = prm + h * PRM;
+    const int q = d * (d + 1) / 2;
+    double T[11];
+    for (int g = 0; g < ng; ++g) {
+        double s = 0.0;
+        for (int64_t c = 0; c < nchunks; ++c) s += partial[(h * nchunks + c) * ng + g];
+        T[g] = s * p[S_SCALE];
+    }
+    const bool sing = p[S_SING] != 0.0;
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    const double* L = p + S_L;
+    double ldet = 1.0;
+    for (int k = 0; k < d; ++k) ldet *= fabs(L[k * 4 + k]);
+    // (4 pi)^{-d/2} = 2^{-d/2} (2 pi)^{-d/2}
+    double c4 = 1.0;
+    for (int k = 0; k < d; ++k) c4 *= 0.28209479177387814347;  // (4 pi)^{-1/2}
+    const double first = c4 / (p[S_N] * ldet);
+    if (kind != FUN_SCV_GRAD) obj[h] = sing ? nan : first + T[0] + p[S_CONST];
+    if (kind == FUN_SCV_OBJ || grad == nullptr) return;
+    const int off = kind == FUN_SCV_OBJGRAD ? 1 : 0;
+    double Hinv[16];
+    chol_inv4(L, Hinv, d);
+    double gH[16];
+    int t = off;
+    for (int i = 0; i < d; ++i)
+        for (int j = i; j < d; ++j) {
+            const double v = -0.5 * first * Hinv[i * 4 + j] + T[t++];
+            gH[i * 4 + j] = v;
+            gH[j * 4 + i] = v;
+        }
+    const double sc = kind == FUN_SCV_GRAD ? grad_out[h] : 1.0;
+    int o = 0;
+    for (int j = 0; j < d; ++j)
+        for (int i = j; i < d; ++i) {
+            double s = 0.0;
+            for (int k = 0; k < d; ++k) s += gH[i * 4 + k] * L[k * 4 + j];
+            grad[h * q + o++] = sing ? nan : 2.0 * s * sc;
+        }
+}
+
+hipError_t launch_scv_final(int kind, const double* partial, const RowGeom& geo, const double* prm, int64_t ncand,
+                            const double* grad_out, double* obj, double* grad, hipStream_t s) {
+    const int ng = ng_of(kind, geo.d, 2);
+    const int64_t blocks = (ncand + 63) / 64;
+    hipLaunchKernelGGL(k_scv_final, dim3((unsigned)blocks), dim3(64), 0, s, kind, partial, geo.nchunks, ng, geo.d,
+                       prm, ncand, grad_out, obj, grad);
+    return hipGetLastError();
+}
+
+// psi[h, g] = scale_h * sum over chunks (fixed order); scal_out (if set)
+// receives psi[0, 0] (the constant SCV term of a dataset).
+__global__ void k_psi_final(const double* __restrict__ partial, int64_t nchunks, int ng,
+                            const double* __restrict__ prm, int64_t ncand, double* __restrict__ psi,
+                            double* __restrict__ scal_out) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= ncand * ng) return;
+    const int64_t h = e / ng;
+    const int g = (int)(e - h * ng);
+    double s = 0.0;
+    for (int64_t c = 0; c < nchunks; ++c) s += partial[(h * nchunks + c) * ng + g];
+    const double v = s * prm[h * PRM + S_SCALE];
+    if (psi) psi[h * ng + g] = v;
+    if (scal_out && e == 0) scal_out[0] = v;
+}
+
+hipError_t launch_psi_final(const double* partial, const RowGeom& geo, int ng, const double* prm, int64_t ncand,
+                            double* psi, double* scal_out, hipStream_t s) {
+    const int64_t tot = ncand * ng;
+    const int64_t blocks = (tot + 63) / 64;
+    hipLaunchKernelGGL(k_psi_final, dim3((unsigned)blocks), dim3(64), 0, s, partial, geo.nchunks, ng, prm, ncand,
+                       psi, scal_out);
+    return hipGetLastError();
+}
+
+}  // namespace kdefft

@@ -1,0 +1,71 @@
+"""Shared helpers of the GPU parity tests: seeded inputs, the oracle side of
+each comparison (computed on the CPU from the oracle only), and the
+tolerance rule for floating-point entries."""
+import functools
+import sys
+
+import numpy as np
+
+from oracle import binned, grid, linbin
+
+RTOL_PSI = 1e-11     # FFT route vs direct binned sum, relative
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def mixture_sample(n, d, seed, ncomp=3):
+    rng = np.random.default_rng(seed)
+    means = rng.standard_normal((ncomp, d)) * 1.2
+    X = np.empty((n, d))
+    lab = rng.integers(0, ncomp, size=n)
+    for l in range(ncomp):
+        A = rng.standard_normal((d, d)) * 0.5 + np.eye(d) * 0.6
+        idx = lab == l
+        X[idx] = means[l] + rng.standard_normal((idx.sum(), d)) @ A.T
+    return X
+
+
+def spd(d, seed, scale=0.1):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((d, d))
+    S = A @ A.T / d + 0.5 * np.eye(d)
+    return scale * 0.5 * (S + S.T)
+
+
+@functools.lru_cache(maxsize=32)
+def _oracle_counts_cached(key):
+    X, G, M, pad = _REG[key]
+    g = grid.plan_auto(X, G, list(M), pad)
+    counts, skipped = linbin.linbin(X, g)
+    return g, counts, skipped
+
+
+_REG = {}
+
+
+def oracle_counts(X, G, M, pad=4.0):
+    key = (id(X), X.shape, tuple(M), float(pad), G.tobytes())
+    _REG[key] = (X, G, tuple(M), pad)
+    return _oracle_counts_cached(key)
+
+
+def oracle_autocorr(c, direct_limit=70_000):
+    """Direct shifted-slice autocorrelation when affordable, else numpy.fft
+    (pinned equal to the direct form at small sizes)."""
+    if c.size <= direct_limit:
+        return binned.autocorr_direct(c)
+    return binned.autocorr_fft(c)
+
+
+def assert_psi_close(got, want, scale_abs, rtol=RTOL_PSI, what=""):
+    """Per entry |a-b| <= rtol*|b|; near-zero entries (|b| < 1e-3 S_abs) are
+    compared against S_abs = n^-2 sum |k| A instead."""
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    for k, (a, b, s) in enumerate(zip(got, want, scale_abs)):
+        ref = abs(b) if abs(b) >= 1e-3 * s else s
+        err = abs(a - b) / ref
+        assert err <= rtol, f"{what} entry {k}: got {a!r} want {b!r} rel err {err:.3e}"

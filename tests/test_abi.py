@@ -1,0 +1,157 @@
+"""Host-side checks of the C-ABI library (no GPU needed, nothing launched).
+
+* the library loads and exports every function include/kdefft.h declares;
+* the unique-index order, grid planning and padded sizes agree with the
+  CPU reference bit for bit;
+* invalid arguments return the documented error codes before any launch.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import grid as ogrid
+from oracle import multiindex
+
+
+def _declared(repo_root):
+    txt = open(os.path.join(repo_root, "include", "kdefft.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(kdefft_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(kf, repo_root):
+    lib = kf._lib.load()
+    names = _declared(repo_root)
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(kf._lib.EXPORTS)
+    assert lib.kdefft_version() >= 10000
+
+
+def test_strerror(kf):
+    lib = kf._lib.load()
+    for code in range(0, -9, -1):
+        s = lib.kdefft_strerror(code).decode()
+        assert s and s != "unknown error"
+
+
+@pytest.mark.parametrize("d,r", [(1, 0), (1, 8), (2, 4), (2, 8), (3, 2), (3, 6), (4, 4)])
+def test_unique_order(kf, d, r):
+    got = kf.unique_tuples(d, r)
+    want = multiindex.unique_tuples(d, r) if r else [()]
+    assert got == want
+
+
+def test_grid_plan_matches_oracle(kf):
+    rng = np.random.default_rng(1)
+    for d in (1, 2, 3, 4):
+        for _ in range(20):
+            lo = rng.standard_normal(d) * 10
+            hi = lo + rng.random(d) * 7 + 1e-3
+            M = rng.integers(2, {1: 2000, 2: 300, 3: 100, 4: 30}[d], size=d)
+            g = kf.grid_plan(M, lo, hi).to_dict()
+            o = ogrid.plan(lo, hi, M)
+            assert np.array_equal(g["lo"], o["lo"])
+            assert np.array_equal(g["delta"], o["delta"])     # bitwise
+            assert np.array_equal(g["P"], o["P"])
+
+
+def _grid(kf, d=2, M=16):
+    return kf.grid_plan([M] * d, [0.0] * d, [1.0] * d)
+
+
+def test_ws_bytes(kf):
+    lib = kf._lib.load()
+    g = _grid(kf, 2, 256)
+    n = C.c_size_t()
+    sizes = {}
+    for op in range(1, 9):
+        assert lib.kdefft_ws_bytes(C.byref(g), op, 4, 256, C.byref(n)) == 0
+        sizes[op] = n.value
+        assert n.value > 0
+    assert sizes[kf._lib.OP_PSI_PLAIN] >= 2 * 512 * 512 * 8
+    small, big = C.c_size_t(), C.c_size_t()
+    lib.kdefft_ws_bytes(C.byref(g), kf._lib.OP_SCV_BATCH, 2, 16, C.byref(small))
+    lib.kdefft_ws_bytes(C.byref(g), kf._lib.OP_SCV_BATCH, 2, 4096, C.byref(big))
+    assert big.value > small.value
+    assert lib.kdefft_ws_bytes(C.byref(g), 99, 0, 1, C.byref(n)) == kf._lib.E_ARG
+
+
+def test_dataset_bytes(kf):
+    lib = kf._lib.load()
+    g = _grid(kf, 4, 32)
+    n = C.c_size_t()
+    assert lib.kdefft_dataset_bytes(C.byref(g), C.byref(n)) == 0
+    assert n.value >= 32 ** 4 * 8 + 2 * 64 ** 3 * 33 * 16
+
+
+def test_grid_validation(kf):
+    lib = kf._lib.load()
+    g = kf._lib.Grid()
+    M = np.array([8, 8], dtype=np.int32)
+    lo = np.zeros(2)
+    hi = np.ones(2)
+    assert lib.kdefft_grid_plan(5, M.ctypes.data, None, lo.ctypes.data, hi.ctypes.data, C.byref(g)) == kf._lib.E_ARG
+    M1 = np.array([1, 8], dtype=np.int32)
+    assert lib.kdefft_grid_plan(2, M1.ctypes.data, None, lo.ctypes.data, hi.ctypes.data, C.byref(g)) == kf._lib.E_ARG
+    P = np.array([12, 16], dtype=np.int32)     # not a power of two
+    assert lib.kdefft_grid_plan(2, M.ctypes.data, P.ctypes.data, lo.ctypes.data, hi.ctypes.data, C.byref(g)) == kf._lib.E_ARG
+    P = np.array([8, 16], dtype=np.int32)      # 8 < 2*8-1
+    assert lib.kdefft_grid_plan(2, M.ctypes.data, P.ctypes.data, lo.ctypes.data, hi.ctypes.data, C.byref(g)) == kf._lib.E_ARG
+    bad = np.array([0.0, 2.0])
+    assert lib.kdefft_grid_plan(2, M.ctypes.data, None, lo.ctypes.data, bad.ctypes.data, C.byref(g)) == kf._lib.E_ARG
+
+
+def test_compute_entry_validation(kf):
+    """Errors raised on the host before any launch (pointers are never touched)."""
+    lib = kf._lib.load()
+    L = kf._lib
+    g = _grid(kf, 2, 16)
+    fake = C.c_void_p(0x1000)
+    G = np.array([[0.1, 0.02], [0.02, 0.2]])
+    ws = C.c_void_p(0x100000)
+    psi = lib.kdefft_psi
+    assert psi(fake, 10, C.byref(g), G.ctypes.data, 3, fake, 0, ws, 1 << 30, None) == L.E_ODD_R
+    assert psi(fake, 10, C.byref(g), G.ctypes.data, 10, fake, 0, ws, 1 << 30, None) == L.E_UNSUPPORTED
+    assert psi(fake, 1 << 23, C.byref(g), G.ctypes.data, 2, fake, 0, ws, 1 << 30, None) == L.E_OVERFLOW
+    assert psi(fake, 0, C.byref(g), G.ctypes.data, 2, fake, 0, ws, 1 << 30, None) == L.E_ARG
+    assert psi(None, 10, C.byref(g), G.ctypes.data, 2, fake, 0, ws, 1 << 30, None) == L.E_ARG
+    assert psi(fake, 10, C.byref(g), G.ctypes.data, 2, fake, 7, ws, 1 << 30, None) == L.E_ARG
+    notspd = np.array([[0.1, 0.3], [0.3, 0.2]])
+    assert psi(fake, 10, C.byref(g), notspd.ctypes.data, 2, fake, 0, ws, 1 << 30, None) == L.E_NOT_SPD
+    asym = np.array([[0.1, 0.02], [0.03, 0.2]])
+    assert psi(fake, 10, C.byref(g), asym.ctypes.data, 2, fake, 0, ws, 1 << 30, None) == L.E_NOT_SPD
+    assert psi(fake, 10, C.byref(g), G.ctypes.data, 2, fake, 0, ws, 64, None) == L.E_WORKSPACE
+    assert "workspace" in lib.kdefft_last_error_detail().decode()
+    g3 = _grid(kf, 3, 8)
+    G3 = np.eye(3)
+    assert psi(fake, 10, C.byref(g3), G3.ctypes.data, 8, fake, 0, ws, 1 << 30, None) == L.E_UNSUPPORTED
+    assert lib.kdefft_linbin(fake, 1 << 23, C.byref(g), fake, None, None) == L.E_OVERFLOW
+    assert lib.kdefft_unique_count(5, 2) == L.E_ARG
+
+
+def test_dataset_entry_validation(kf):
+    lib = kf._lib.load()
+    L = kf._lib
+    g = _grid(kf, 2, 16)
+    fake = C.c_void_p(0x1000)
+    G = np.eye(2) * 0.1
+    out = kf._lib.Dataset()
+    # misaligned dataset buffer
+    assert lib.kdefft_dataset_prepare(fake, 10, C.byref(g), G.ctypes.data, C.c_void_p(0x1008), 1 << 30,
+                                      C.byref(out), fake, 1 << 30, None) == L.E_WORKSPACE
+    # too small dataset buffer
+    assert lib.kdefft_dataset_prepare(fake, 10, C.byref(g), G.ctypes.data, C.c_void_p(0x1000), 64,
+                                      C.byref(out), fake, 1 << 30, None) == L.E_WORKSPACE
+    # unprepared dataset in a batch
+    ds = (kf._lib.Dataset * 1)()
+    ds[0].grid = g
+    ds[0].n = 10
+    off = np.array([0, 4], dtype=np.int64)
+    assert lib.kdefft_scv_batch(ds, 1, off.ctypes.data, fake, fake, None, None, fake, 1 << 30, None) == L.E_ARG
+    assert lib.kdefft_set_row_launch(2, 2, 2, 512, 5, 0) == L.E_ARG
+    assert lib.kdefft_set_row_launch(2, 2, 2, 3, 0, 0) == L.E_UNSUPPORTED

@@ -1,0 +1,223 @@
+"""SCV objective, gradient, adjoint and batching on the GPU vs the oracle.
+
+* batched objective and gradient (one persistent launch) vs the oracle's
+  binned SCV evaluated from its own counts (obj <= 1e-11 relative, gradient
+  <= 1e-10 relative to its largest entry);
+* paper-literal plain path vs the same oracle;
+* adjoint = grad_out * gradient; autograd.Function backward;
+* central differences with Richardson extrapolation of the GPU objective
+  (<= 1e-7 relative);
+* uneven multi-dataset batches, every compiled launch variant, a singular
+  candidate (status 1, NaN), bitwise repeatability;
+* the full case-4 workload (d=2, n=1e5, M=256, 256 candidates) on sampled
+  candidates.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import binned, grid, linbin, scv
+
+from _gpu_util import log, mixture_sample, oracle_autocorr, spd
+
+pytestmark = pytest.mark.gpu
+
+_AC = {}
+
+
+def _oracle(name, X, G, M):
+    if name not in _AC:
+        g = grid.plan_auto(X, G, [M] * X.shape[1])
+        co, sk = linbin.linbin(X, g)
+        assert sk == 0
+        _AC[name] = (g, oracle_autocorr(linbin.counts_to_real(co)))
+    return _AC[name]
+
+
+def _vech(H):
+    return synth.vech_chol(H)
+
+
+def _Hs(d, B, seed):
+    if d == 2:
+        return synth.random_H_2d(B, np.random.default_rng(seed))
+    return synth.random_H_haar(B, d, np.random.default_rng(seed))
+
+
+CASES = {
+    "d1": (1, 3000, 64, 6),
+    "d2": (2, 3000, 40, 12),
+    "d2_ragged": (2, 2500, 29, 7),
+    "d3": (3, 3000, 16, 6),
+    "d4": (4, 2000, 8, 5),
+}
+
+
+def _setup(name, gpu):
+    d, n, M, B = CASES[name]
+    X = mixture_sample(n, d, 100 + d)
+    Gp = spd(d, 200 + d, 0.05)
+    H = _Hs(d, B, 300 + d)
+    ds = None
+    return d, X, Gp, M, H, ds
+
+
+def _check_against_oracle(kf, name, d, X, Gp, M, H, obj, gradv, rtol_obj=1e-11, rtol_grad=1e-10):
+    g_o, A = _oracle(name, X, Gp, M)
+    n = X.shape[0]
+    for b in range(H.shape[0]):
+        o, gr = scv.objective_binned(A, n, g_o, H[b], Gp)
+        assert abs(obj[b] - o) <= rtol_obj * abs(o), (name, b, obj[b], o)
+        if gradv is not None:
+            err = np.abs(gradv[b] - gr).max() / np.abs(gr).max()
+            assert err <= rtol_grad, (name, b, gradv[b], gr, err)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_scv_batch_vs_oracle(kf, gpu, name):
+    d, X, Gp, M, H, _ = _setup(name, gpu)
+    log(f"[scv] case={name} B={H.shape[0]}")
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
+    assert ds.out_of_grid() == 0
+    v = torch.from_numpy(_vech(H)).to(gpu)
+    obj, g = kf.scv([ds], v)
+    obj_only = kf.scv([ds], v, grad=False)
+    obj, g, obj_only = obj.cpu().numpy(), g.cpu().numpy(), obj_only.cpu().numpy()
+    _check_against_oracle(kf, name, d, X, Gp, M, H, obj, g)
+    np.testing.assert_allclose(obj_only, obj, rtol=1e-13)
+
+
+@pytest.mark.parametrize("name", ["d1", "d2_ragged", "d3", "d4"])
+def test_scv_plain_vs_oracle(kf, gpu, name):
+    d, X, Gp, M, H, _ = _setup(name, gpu)
+    log(f"[scv-plain] case={name}")
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
+    res = np.stack([kf.scv_plain(ds, H[b]).cpu().numpy() for b in range(min(3, H.shape[0]))])
+    _check_against_oracle(kf, name, d, X, Gp, M, H[:len(res)], res[:, 0], res[:, 1:])
+
+
+def test_adjoint_and_autograd(kf, gpu):
+    d, X, Gp, M, H, _ = _setup("d3", gpu)
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
+    v = torch.from_numpy(_vech(H)).to(gpu)
+    obj, g = kf.scv([ds], v)
+    w = torch.linspace(-1.0, 2.0, H.shape[0], dtype=torch.float64, device=gpu)
+    adj = kf.scv_adjoint([ds], v, w)
+    np.testing.assert_allclose(adj.cpu().numpy(), (w[:, None] * g).cpu().numpy(), rtol=1e-13, atol=1e-300)
+    vv = v.clone().requires_grad_(True)
+    out = kf.SCV.apply(vv, ds)
+    (out * w).sum().backward()
+    np.testing.assert_allclose(vv.grad.cpu().numpy(), adj.cpu().numpy(), rtol=0, atol=0)
+    np.testing.assert_allclose(out.detach().cpu().numpy(), obj.cpu().numpy(), rtol=1e-13)
+
+
+@pytest.mark.parametrize("name", ["d2", "d4"])
+def test_gradient_finite_differences(kf, gpu, name):
+    d, X, Gp, M, H, _ = _setup(name, gpu)
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
+    v0 = _vech(H[:2])
+    q = v0.shape[1]
+    _, g = kf.scv([ds], torch.from_numpy(v0).to(gpu))
+    g = g.cpu().numpy()
+    h = 1e-3
+    pts = []
+    for b in range(2):
+        for k in range(q):
+            for s in (h, -h, h / 2, -h / 2):
+                w = v0[b].copy()
+                w[k] += s
+                pts.append(w)
+    obj = kf.scv([ds], torch.from_numpy(np.array(pts)).to(gpu), grad=False).cpu().numpy().reshape(2, q, 4)
+    d1 = (obj[..., 0] - obj[..., 1]) / (2 * h)
+    d2 = (obj[..., 2] - obj[..., 3]) / h
+    fd = (4 * d2 - d1) / 3
+    err = np.abs(fd - g).max() / np.abs(g).max()
+    assert err <= 1e-7, (fd, g, err)
+
+
+def test_uneven_multi_dataset(kf, gpu):
+    d, M = 2, 32
+    sets = []
+    for j, n in enumerate((800, 5000, 2300)):
+        X = mixture_sample(n, d, 400 + j)
+        Gp = spd(d, 500 + j, 0.04)
+        H = _Hs(d, (5, 3, 7)[j], 600 + j)
+        sets.append((X, Gp, H))
+    dss = [kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M) for X, Gp, _ in sets]
+    v = torch.from_numpy(np.concatenate([_vech(H) for _, _, H in sets])).to(gpu)
+    obj, g = kf.scv(dss, v, per_ds=[5, 3, 7])
+    obj, g = obj.cpu().numpy(), g.cpu().numpy()
+    s = 0
+    for j, (X, Gp, H) in enumerate(sets):
+        _check_against_oracle(kf, f"multi{j}", d, X, Gp, M, H, obj[s:s + len(H)], g[s:s + len(H)])
+        s += len(H)
+
+
+def test_launch_variants_agree(kf, gpu):
+    d, X, Gp, M, H, _ = _setup("d2", gpu)
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
+    v = torch.from_numpy(_vech(H)).to(gpu)
+    N = ds.grid.P[d - 1]
+    ref = None
+    try:
+        for var in range(3):
+            for gb in (0, -1, 7):
+                kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, var, gb)
+                obj, g = kf.scv([ds], v)
+                cur = np.concatenate([obj.cpu().numpy(), g.cpu().numpy().ravel()])
+                if ref is None:
+                    ref = cur
+                np.testing.assert_allclose(cur, ref, rtol=1e-12, atol=1e-15)
+    finally:
+        kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, 0, 0)
+
+
+def test_singular_candidate_and_determinism(kf, gpu):
+    d, X, Gp, M, H, _ = _setup("d2", gpu)
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
+    vn = _vech(H)
+    vn[1, 0] = 0.0                      # zero diagonal of L: H singular
+    v = torch.from_numpy(vn).to(gpu)
+    obj, g, st = kf.scv([ds], v, status=True)
+    st = st.cpu().numpy()
+    assert st[1] == 1 and st[0] == 0 and st[2:].max() == 0
+    assert np.isnan(obj[1].item()) and np.isnan(g[1].cpu().numpy()).all()
+    assert np.isfinite(obj.cpu().numpy()[[0] + list(range(2, len(vn)))]).all()
+    obj2, g2 = kf.scv([ds], v)
+    assert np.array_equal(obj.cpu().numpy(), obj2.cpu().numpy(), equal_nan=True)
+    assert np.array_equal(g.cpu().numpy(), g2.cpu().numpy(), equal_nan=True)
+
+
+def test_case4_full_sampled(kf, gpu):
+    """Case 4 at full size in the benchmark's launch: d=2, n=1e5, M=256, 256 H."""
+    w = synth.case4()
+    X, Gp, H = w.X[0], w.G_pilot[0], w.H[0]
+    log("[scv-full] case4")
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=256)
+    obj, g = kf.scv([ds], torch.from_numpy(_vech(H)).to(gpu))
+    obj, g = obj.cpu().numpy(), g.cpu().numpy()
+    idx = [0, 77, 255]
+    _check_against_oracle(kf, "case4", 2, X, Gp, 256, H[idx], obj[idx], g[idx])
+    pl = kf.scv_plain(ds, H[77]).cpu().numpy()
+    np.testing.assert_allclose(pl[0], obj[77], rtol=1e-11)
+    np.testing.assert_allclose(pl[1:], g[77], rtol=1e-9, atol=1e-10 * np.abs(g[77]).max())
+
+
+def test_psi_batch(kf, gpu):
+    d, M, r = 2, 24, 4
+    dss, Gs, Xs = [], [], []
+    for j, n in enumerate((700, 3000)):
+        X = mixture_sample(n, d, 700 + j)
+        Gp = spd(d, 800 + j, 0.05)
+        Xs.append(X)
+        Gs.append(spd(d, 900 + j, 0.08))
+        dss.append(kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M))
+    out = kf.psi_batch(dss, Gs, r).cpu().numpy()
+    for j in range(2):
+        # the dataset grid is planned from its pilot; the oracle uses the same grid
+        g_o = grid.plan_auto(Xs[j], spd(d, 800 + j, 0.05), [M, M])
+        co, _ = linbin.linbin(Xs[j], g_o)
+        A = binned.autocorr_direct(linbin.counts_to_real(co))
+        want = binned.psi(A, Xs[j].shape[0], g_o, Gs[j], r)
+        np.testing.assert_allclose(out[j], want, rtol=1e-10, atol=1e-12 * np.abs(want).max())
