@@ -1,0 +1,253 @@
+#!/usr/bin/env python3
+"""Throughput of the FFT-based psi_r / SCV hot path on one MI355X.
+
+Workload (synthetic, seeded; see synth.case4): d = 2, n = 100,000 points from
+a four-component normal mixture, grid M = 256 per axis (padded P = 512),
+pilot G = n^{-2/8} S_hat, 256 candidate bandwidths H (random rotations,
+log-eigenvalues U[-3, 0]).
+
+One step = the whole hot path over that batch, inputs already in HBM:
+  grid plan (data bounds) -> linear binning -> count transform (R2C, |C|^2,
+  leading-axis transform, constant SCV term) -> psi_4 at the psi pilot ->
+  SCV objective + gradient w.r.t. vech(chol H) for all 256 candidates in one
+  persistent launch.
+value = 256 / (seconds per step)  [SCV objective+gradient evaluations/s].
+
+Also reported (outside the timed loop): the paper-literal plain path one H at
+a time (with and without per-call binning and count transform), the
+autograd (forward + adjoint) form, psi_4 evals/s, the dominant kernel's
+roofline figures and the CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "psi_r evals/s and SCV objective+grad evals/s, batched+adjoint vs plain, FP64"
+PEAK_FP64_VECTOR = 78.6e12          # MI355X FP64 vector FLOP/s (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
+EXP_FLOPS = 20                      # flops charged per exp in the algorithmic count
+ROW_KERNEL_SOURCES = ["rows_impl.h", "dev_kernels.h", "dev_common.h", "rows_dispatch.h", "rows_d2.hip"]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-h", type=int, default=16, help="candidates timed on the plain path")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-h", type=int, default=48, help="candidates in the CPU oracle sample")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB device copy (counter calibration for rocprofv3 --pmc runs)")
+    ap.add_argument("--tune", action="store_true", help="run the launch autotuner before timing")
+    return ap.parse_args()
+
+
+def row_kernel_hash():
+    h = hashlib.sha256()
+    for f in ROW_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1511_07482_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_flops_per_candidate(M, N, d=2):
+    """FP64 flops of one candidate in the batched objective+gradient kernel.
+
+    Rows of the half lag set: M (l_0 = 0..M-1).  Per row: two complex FFTs of
+    length N (4 real grids, two per transform) at 5 N log2 N flops each; the
+    contraction over the full last axis, 8 flops per complex multiply-add per
+    transform; kernel generation for the 2M-1 nonzero lags of the row: two
+    Gaussians (matrix-vector 2d^2, quadratic form 2d, scale 2, one exp each),
+    the objective combination (2) and 3 Hessian entries (7 each)."""
+    log2n = int(np.log2(N))
+    fft = 2 * 5 * N * log2n
+    contraction = 2 * N * 8
+    gen_point = 2 * (2 * d * d + 2 * d + 2 + EXP_FLOPS) + 2 + 3 * 7
+    gen = (2 * M - 1) * gen_point
+    return M * (fft + contraction + gen)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
+              "(the path shards by candidates/datasets with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1511_07482_amd as kf
+    import synth
+
+    dev = torch.device("cuda:0")
+    w = synth.case4()
+    X_h, Gpsi, Gp, H = w.X[0], w.G_psi[0], w.G_pilot[0], w.H[0]
+    n, d = X_h.shape
+    B = H.shape[0]
+    M = w.M
+    X = torch.from_numpy(X_h).to(dev)
+    vechL = torch.from_numpy(synth.vech_chol(H)).to(dev)
+    tuned = None
+    if a.tune:
+        ds0 = kf.Dataset(X, Gp, M=M)
+        tuned = kf.autotune(ds0)
+
+    def step():
+        g = kf.grid_auto(X, Gp, M)
+        ds = kf.Dataset(X, Gp, grid=g)
+        psi = kf.psi_batch([ds], [Gpsi], 4)
+        obj, grad = kf.scv([ds], vechL)
+        return ds, psi, obj, grad
+
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # ---- timed region: exactly `steps` whole steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        g = kf.grid_auto(X, Gp, M)
+        ds = kf.Dataset(X, Gp, grid=g)
+        psi = kf.psi_batch([ds], [Gpsi], 4)
+        ev[k][0].record(stream)
+        obj, grad = kf.scv([ds], vechL)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec_per_step = (t1 - t0) / a.steps
+    value = B / sec_per_step
+    scv_ms = float(np.mean([s.elapsed_time(e) for s, e in ev]))
+    assert torch.isfinite(obj).all() and torch.isfinite(grad).all()
+
+    # ---- components outside the timed loop
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        s = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - s) / reps, out
+
+    t_prep, ds = timed(lambda: kf.Dataset(X, Gp, grid=g), 5)
+    t_psi_batched, _ = timed(lambda: kf.psi_batch([ds], [Gpsi], 4), 10)
+    t_psi_plain, _ = timed(lambda: kf.psi(X, Gpsi, 4, grid=g, mode="plain"), 5)
+    t_scv_only, _ = timed(lambda: kf.scv([ds], vechL), 10)
+
+    def autograd_step():
+        v = vechL.clone().requires_grad_(True)
+        o = kf.SCV.apply(v, ds)
+        o.sum().backward()
+        return v.grad
+
+    t_autograd, _ = timed(autograd_step, 5)
+    hp = min(a.plain_h, B)
+    kf.scv_plain(ds, H[0])
+    torch.cuda.synchronize()
+    s = time.perf_counter()
+    for b in range(hp):
+        kf.scv_plain(ds, H[b])
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - s) / hp
+    s = time.perf_counter()
+    for b in range(hp):
+        dsb = kf.Dataset(X, Gp, grid=g)
+        kf.scv_plain(dsb, H[b])
+    torch.cuda.synchronize()
+    t_plain_prep = (time.perf_counter() - s) / hp
+
+    if a.calib_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    # ---- roofline of the dominant kernel (batched SCV objective+gradient launch)
+    flops = algorithmic_flops_per_candidate(M, g.P[d - 1]) * B
+    achieved = flops / (scv_ms * 1e-3)
+    traffic = None
+    prof = os.path.join(ROOT, "profiles", "scv_rows_case4_counters.json")
+    if os.path.exists(prof):
+        with open(prof) as fh:
+            rec = json.load(fh)
+        if rec.get("row_kernel_hash") == row_kernel_hash():
+            traffic = rec.get("hbm_bytes_per_launch")
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic,
+                "kernel": "k_rows<2,512,ScvFun<2,1>> (+ setup/final, <1%)", "launch_ms": scv_ms,
+                "flops_per_launch": flops}
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(X_h, Gp, H, M, a.cpu_h)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "SCV objective+gradient evals/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": sec_per_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "case4: d=2 n=1e5 4-comp mixture, M=256 (P=512), psi_4 at pilot + SCV obj+grad "
+                               "for 256 H per step (binning and count transform included)",
+                   "d": d, "n": n, "M": M, "P": int(g.P[d - 1]), "candidates": B, "psi_r": 4},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "components_ms": {"dataset_prepare": t_prep * 1e3, "psi4_batched": t_psi_batched * 1e3,
+                          "scv_objgrad_batched_256": t_scv_only * 1e3, "scv_autograd_fwd_adjoint_256": t_autograd * 1e3,
+                          "psi4_plain_with_binning": t_psi_plain * 1e3, "scv_plain_per_H": t_plain * 1e3,
+                          "scv_plain_per_H_with_binning": t_plain_prep * 1e3},
+        "psi4_evals_per_s": {"batched_on_prepared": 1.0 / t_psi_batched, "plain_with_binning": 1.0 / t_psi_plain},
+        "scv_evals_per_s": {"step": value, "batched_only": B / t_scv_only, "autograd_fwd_adjoint": B / t_autograd,
+                            "plain": 1.0 / t_plain, "plain_with_binning": 1.0 / t_plain_prep},
+        "batched_over_plain": {"step_vs_plain": value * t_plain,
+                               "batched_vs_plain": (B / t_scv_only) * t_plain,
+                               "autograd_vs_plain": (B / t_autograd) * t_plain,
+                               "step_vs_plain_with_binning": value * t_plain_prep},
+        "tuned": tuned,
+        "device": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(out))
+
+
+def cpu_baseline(X, Gp, H, M, nh):
+    """The oracle's binned SCV (objective + gradient) on the host: counts and
+    their direct autocorrelation once, then nh candidates; evals/s over the
+    whole sample (autocorrelation included)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import binned, grid, linbin, scv
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        g = grid.plan_auto(X, Gp, [M, M])
+        counts, _ = linbin.linbin(X, g)
+        A = binned.autocorr_direct(linbin.counts_to_real(counts))
+        t_a = time.perf_counter() - t0
+        nh = min(nh, H.shape[0])
+        t1 = time.perf_counter()
+        for b in range(nh):
+            scv.objective_binned(A, X.shape[0], g, H[b], Gp)
+        t_h = time.perf_counter() - t1
+    return {"value": nh / (t_a + t_h), "unit": "SCV objective+gradient evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"case4 data, binning + direct autocorrelation of the 256^2 counts ({t_a:.1f} s) then "
+                      f"{nh} of the 256 candidates ({t_h:.1f} s), one thread",
+            "per_candidate_s": t_h / nh, "autocorrelation_s": t_a}
+
+
+if __name__ == "__main__":
+    main()
