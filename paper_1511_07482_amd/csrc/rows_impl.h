@@ -11,13 +11,18 @@
 // l_0 >= 0 are formed, the others counted twice, and rows that fall in the
 // zero slots of the layout are skipped.  Two real grids share one complex
 // transform: with Z = DFT(k_a + i k_b), sum_w What Z over the full last axis
-// has real part = grid a's sum and imaginary part = grid b's sum.
+// has real part = grid a's sum and imaginary part = grid b's sum (What is
+// conjugate-symmetric along the last axis).
 //
-// One work item = one candidate bandwidth x one chunk of rows.  A block
-// generates ROWS rows of all NG grids in LDS, transforms them, contracts with
-// the What rows (read once for all grids) and keeps NG running sums in
-// registers.  Blocks loop over items (persistent grid); per-item partial sums
-// are written out and summed later in a fixed order.
+// Work decomposition: one work item = one candidate bandwidth x one chunk of
+// rows; a block of WPB wavefronts takes items in a persistent loop, and each
+// wavefront transforms its own rows (RPW at a time) in a private LDS region,
+// synchronising only at wavefront scope.  The first radix stage is fused with
+// the kernel-grid generation (values go from registers straight into the
+// butterfly) when the registers allow it, and the last stage is fused with
+// the contraction against What (its outputs are never written back).  Each
+// lane keeps NG running sums; a block reduction at the end of an item writes
+// the item's partial sums, which a later kernel adds in a fixed order.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,19 +33,138 @@
 
 namespace kdefft {
 
-template <int D, int N, class Fun, int ROWS, int NT, int SCHED>
-__global__ __launch_bounds__(NT) void k_rows(const double* __restrict__ prm, RowGeom geo, int64_t nitems,
-                                             double* __restrict__ partial, const double2* __restrict__ tw) {
+// LDS written and read by the same wavefront: order the accesses without a
+// block-wide barrier.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int N, int SCHED>
+constexpr int last_L() {
+    int L = 1;
+    while (L * next_radix(N / L, SCHED) < N) L *= next_radix(N / L, SCHED);
+    return L;
+}
+
+// Middle Stockham stages [L, LEND) of NPW pencils, executed by one wavefront.
+template <int N, int L, int LEND, int NPW, int SCHED>
+__device__ __forceinline__ void wave_mid_stages(double2* buf, int lane, const double2* __restrict__ tw) {
+    if constexpr (L < LEND) {
+        constexpr int R = next_radix(N / L, SCHED);
+        constexpr int NB = N / R;
+        constexpr int TOT = NB * NPW;
+        constexpr int PER = (TOT + 63) / 64;
+        constexpr int TWS = TWN / (R * L);
+        double2 v[PER][R];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int b = lane + u * 64;
+            if ((TOT % 64) == 0 || b < TOT) {
+                const int p = b / NB, i = b - p * NB;
+                const int k = i & (L - 1);
+                const double2* src = buf + p * (N + 1) + i;
+#pragma unroll
+                for (int m = 0; m < R; ++m) v[u][m] = src[m * NB];
+#pragma unroll
+                for (int m = 1; m < R; ++m) v[u][m] = c_mul(v[u][m], tw[m * k * TWS]);
+                dft<R, -1>(v[u]);
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int b = lane + u * 64;
+            if ((TOT % 64) == 0 || b < TOT) {
+                const int p = b / NB, i = b - p * NB;
+                const int k = i & (L - 1);
+                double2* dst = buf + p * (N + 1) + (i - k) * R + k;
+#pragma unroll
+                for (int m = 0; m < R; ++m) dst[m * L] = v[u][m];
+            }
+        }
+        wave_sync();
+        wave_mid_stages<N, L * R, LEND, NPW, SCHED>(buf, lane, tw);
+    }
+}
+
+struct RowInfo {
+    double x[4];      // lead lag coordinates
+    const double2* w;  // What row
+    double rw;        // row weight (0 = no row)
+};
+
+template <int D>
+__device__ __forceinline__ RowInfo row_info(int64_t row, int64_t rend, const RowGeom& geo, const double* delta,
+                                            const double2* W) {
+    RowInfo ri;
+    ri.x[0] = ri.x[1] = ri.x[2] = ri.x[3] = 0.0;
+    ri.w = W;
+    ri.rw = 0.0;
+    if (row >= rend) return ri;
+    if constexpr (D == 1) {
+        ri.rw = 1.0;
+    } else {
+        int64_t rem = row;
+        int lag[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = D - 2; k >= 1; --k) {
+            const int64_t E = 2 * geo.M[k] - 1;
+            const int64_t c = rem % E;
+            rem /= E;
+            lag[k] = (int)c - (geo.M[k] - 1);
+        }
+        lag[0] = (int)rem;
+        int64_t wr = 0;
+#pragma unroll
+        for (int k = 0; k < D - 1; ++k) {
+            const int idx = lag[k] >= 0 ? lag[k] : lag[k] + geo.P[k];
+            wr = wr * geo.P[k] + idx;
+            ri.x[k] = delta[k] * (double)lag[k];
+        }
+        ri.w = W + wr * geo.Q;
+        ri.rw = lag[0] == 0 ? 1.0 : 2.0;
+    }
+    return ri;
+}
+
+// Kernel values of all NG grids at last-axis index p of a row.
+template <int D, int N, class Fun>
+__device__ __forceinline__ void gen_point(const Fun& f, const RowInfo& ri, int p, int M_last, const double* delta,
+                                          double* vals) {
+    int lag = 0;
+    if (ri.rw != 0.0 && lag_of(p, M_last, N, &lag)) {
+        double x[D];
+#pragma unroll
+        for (int k = 0; k < D - 1; ++k) x[k] = ri.x[k];
+        x[D - 1] = delta[D - 1] * (double)lag;
+        f.eval(x, vals);
+    } else {
+#pragma unroll
+        for (int g = 0; g < Fun::NG; ++g) vals[g] = 0.0;
+    }
+}
+
+template <int D, int N, class Fun, int RPW, int WPB, int SCHED>
+__global__ __launch_bounds__(WPB * 64, 2) void k_rows(const double* __restrict__ prm, RowGeom geo, int64_t nitems,
+                                                   double* __restrict__ partial, const double2* __restrict__ tw) {
     constexpr int NG = Fun::NG;
     constexpr int NPEN = (NG + 1) / 2;
-    constexpr int NPT = ROWS * NPEN;
+    constexpr int NPW = RPW * NPEN;
     constexpr int PS = N + 1;
-    constexpr int Q = N / 2 + 1;
-    __shared__ double2 pen[NPT * PS];
-    __shared__ double red[(NT / 64) * NG];
-    __shared__ double xlead[ROWS][4];
-    __shared__ int64_t wrow_s[ROWS];
-    __shared__ double rw_s[ROWS];
+    constexpr int R1 = next_radix(N, SCHED);
+    constexpr int NB1 = N / R1;
+    constexpr bool FUSE1 = NPEN * R1 <= 16;
+    constexpr int LL = last_L<N, SCHED>();
+    constexpr int RL = N / LL;
+    constexpr bool ONE_STAGE = (R1 == N);
+    __shared__ double2 pen_all[WPB * NPW * PS];
+    __shared__ double red[WPB * NG];
+    __shared__ RowInfo rtab_all[WPB * RPW];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double2* pen = pen_all + wave * NPW * PS;
+    RowInfo* rtab = rtab_all + wave * RPW;
 
     for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int64_t h = item / geo.nchunks;
@@ -53,90 +177,141 @@ __global__ __launch_bounds__(NT) void k_rows(const double* __restrict__ prm, Row
         for (int k = 0; k < D; ++k) delta[k] = pr[S_DELTA + k];
         const double2* __restrict__ W =
             reinterpret_cast<const double2*>(static_cast<uintptr_t>(__double_as_longlong(pr[S_WMIX])));
+        const int M_last = geo.M[D - 1];
         double acc[NG];
 #pragma unroll
         for (int g = 0; g < NG; ++g) acc[g] = 0.0;
         const int64_t rbeg = ch * geo.chunk;
         const int64_t rend = rbeg + geo.chunk < geo.nrows ? rbeg + geo.chunk : geo.nrows;
 
-        for (int64_t r0 = rbeg; r0 < rend; r0 += ROWS) {
-            // row decode: lead lags, What row index, weight (rows with l_0 > 0 stand
-            // for their mirror images too)
-            if (threadIdx.x < ROWS) {
-                const int rr = threadIdx.x;
-                int64_t rem = r0 + rr;
-                int64_t wr = 0;
-                double w = 0.0;
-                if (r0 + rr < rend) {
-                    if constexpr (D == 1) {
-                        w = 1.0;
-                    } else {
-                        int lag[4] = {0, 0, 0, 0};
+        for (int64_t r0 = rbeg + wave * RPW; r0 < rend; r0 += WPB * RPW) {
+            if (lane < RPW) rtab[lane] = row_info<D>(r0 + lane, rend, geo, delta, W);
+            wave_sync();
+
+            if constexpr (ONE_STAGE) {
+                // whole transform in registers: generate, DFT, contract
+                constexpr int TOT = RPW;
+                for (int b = lane; b < TOT; b += 64) {
+                    const RowInfo rinf = rtab[b];
+                    if (rinf.rw == 0.0) continue;
+                    double2 a[NPEN][N];
 #pragma unroll
-                        for (int k = D - 2; k >= 1; --k) {
-                            const int64_t E = 2 * geo.M[k] - 1;
-                            const int64_t c = rem % E;
-                            rem /= E;
-                            lag[k] = (int)c - (geo.M[k] - 1);
-                        }
-                        lag[0] = (int)rem;
+                    for (int m = 0; m < N; ++m) {
+                        double vals[NG];
+                        gen_point<D, N>(f, rinf, m, M_last, delta, vals);
 #pragma unroll
-                        for (int k = 0; k < D - 1; ++k) {
-                            const int idx = lag[k] >= 0 ? lag[k] : lag[k] + geo.P[k];
-                            wr = wr * geo.P[k] + idx;
-                            xlead[rr][k] = delta[k] * (double)lag[k];
+                        for (int gp = 0; gp < NPEN; ++gp)
+                            a[gp][m] = make_double2(vals[2 * gp], (2 * gp + 1 < NG) ? vals[2 * gp + 1] : 0.0);
+                    }
+#pragma unroll
+                    for (int gp = 0; gp < NPEN; ++gp) dft<N, -1>(a[gp]);
+#pragma unroll
+                    for (int m = 0; m < N; ++m) {
+                        const bool lo = m <= N / 2;
+                        double2 wv = rinf.w[lo ? m : N - m];
+                        if (!lo) wv = c_conj(wv);
+#pragma unroll
+                        for (int gp = 0; gp < NPEN; ++gp) {
+                            const double2 cz = c_mul(wv, a[gp][m]);
+                            acc[2 * gp] += rinf.rw * cz.x;
+                            if (2 * gp + 1 < NG) acc[2 * gp + 1] += rinf.rw * cz.y;
                         }
-                        w = lag[0] == 0 ? 1.0 : 2.0;
                     }
                 }
-                wrow_s[rr] = wr;
-                rw_s[rr] = w;
-            }
-            __syncthreads();
-            // generation of ROWS rows x NG grids, packed two grids per pencil
-            for (int e = threadIdx.x; e < ROWS * N; e += NT) {
-                const int rr = e / N, p = e - rr * N;
-                double vals[NG];
-                int lag = 0;
-                const bool nz = rw_s[rr] != 0.0 && lag_of(p, geo.M[D - 1], N, &lag);
-                if (nz) {
-                    double x[D];
+                wave_sync();
+            } else {
+                // ---- stage 1 (L = 1, no twiddles), generation fused when registers allow
+                if constexpr (FUSE1) {
+                    constexpr int TOT = RPW * NB1;
+                    constexpr int PER = (TOT + 63) / 64;
 #pragma unroll
-                    for (int k = 0; k < D - 1; ++k) x[k] = xlead[rr][k];
-                    x[D - 1] = delta[D - 1] * (double)lag;
-                    f.eval(x, vals);
+                    for (int u = 0; u < PER; ++u) {
+                        const int b = lane + u * 64;
+                        if ((TOT % 64) == 0 || b < TOT) {
+                            const int rr = b / NB1, i = b - rr * NB1;
+                            double2 a[NPEN][R1];
+#pragma unroll
+                            for (int m = 0; m < R1; ++m) {
+                                double vals[NG];
+                                gen_point<D, N>(f, rtab[rr], i + m * NB1, M_last, delta, vals);
+#pragma unroll
+                                for (int gp = 0; gp < NPEN; ++gp)
+                                    a[gp][m] =
+                                        make_double2(vals[2 * gp], (2 * gp + 1 < NG) ? vals[2 * gp + 1] : 0.0);
+                            }
+#pragma unroll
+                            for (int gp = 0; gp < NPEN; ++gp) {
+                                dft<R1, -1>(a[gp]);
+                                double2* dst = pen + (rr * NPEN + gp) * PS + i * R1;
+#pragma unroll
+                                for (int m = 0; m < R1; ++m) dst[m] = a[gp][m];
+                            }
+                        }
+                    }
+                    wave_sync();
+                    wave_mid_stages<N, R1, LL, NPW, SCHED>(pen, lane, tw);
                 } else {
+                    for (int e = lane; e < RPW * N; e += 64) {
+                        const int rr = e / N, p = e - rr * N;
+                        double vals[NG];
+                        gen_point<D, N>(f, rtab[rr], p, M_last, delta, vals);
 #pragma unroll
-                    for (int g = 0; g < NG; ++g) vals[g] = 0.0;
+                        for (int gp = 0; gp < NPEN; ++gp)
+                            pen[(rr * NPEN + gp) * PS + p] =
+                                make_double2(vals[2 * gp], (2 * gp + 1 < NG) ? vals[2 * gp + 1] : 0.0);
+                    }
+                    wave_sync();
+                    wave_mid_stages<N, 1, LL, NPW, SCHED>(pen, lane, tw);
                 }
+                // ---- last stage fused with the contraction against What
+                {
+                    constexpr int NB = N / RL;  // == LL
+                    constexpr int TOT = RPW * NB;
+                    constexpr int PER = (TOT + 63) / 64;
+                    constexpr int TWS = TWN / N;
 #pragma unroll
-                for (int gp = 0; gp < NPEN; ++gp)
-                    pen[(rr * NPEN + gp) * PS + p] =
-                        make_double2(vals[2 * gp], (2 * gp + 1 < NG) ? vals[2 * gp + 1] : 0.0);
-            }
-            __syncthreads();
-            fft_lds<N, NPT, NT, -1, SCHED>(pen, PS, tw);
-            // contraction with the mixed spectrum over the full last axis
-            for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
-                const int rr = e / Q, w = e - rr * Q;
-                const double rw = rw_s[rr];
-                if (rw == 0.0) continue;
-                const double2 Wv = W[wrow_s[rr] * Q + w];
-                const bool two = (w != 0) && (w != N / 2);
-                const double2 Wc = two ? c_conj(Wv) : make_double2(0.0, 0.0);
+                    for (int u = 0; u < PER; ++u) {
+                        const int b = lane + u * 64;
+                        if ((TOT % 64) == 0 || b < TOT) {
+                            const int rr = b / NB, i = b - rr * NB;
+                            const RowInfo rinf = rtab[rr];
+                            if (rinf.rw != 0.0) {
+                                double2 wv[RL];
 #pragma unroll
-                for (int gp = 0; gp < NPEN; ++gp) {
-                    const double2* pp = pen + (rr * NPEN + gp) * PS;
-                    double2 cz = c_mul(Wv, pp[w]);
-                    if (two) cz = c_add(cz, c_mul(Wc, pp[N - w]));
-                    acc[2 * gp] += rw * cz.x;
-                    if (2 * gp + 1 < NG) acc[2 * gp + 1] += rw * cz.y;
+                                for (int m = 0; m < RL; ++m) {
+                                    const int w = i + m * NB;
+                                    const bool lo = w <= N / 2;
+                                    wv[m] = rinf.w[lo ? w : N - w];
+                                    if (!lo) wv[m] = c_conj(wv[m]);
+                                }
+#pragma unroll
+                                for (int gp = 0; gp < NPEN; ++gp) {
+                                    const double2* src = pen + (rr * NPEN + gp) * PS + i;
+                                    double2 a[RL];
+#pragma unroll
+                                    for (int m = 0; m < RL; ++m) a[m] = src[m * NB];
+#pragma unroll
+                                    for (int m = 1; m < RL; ++m) a[m] = c_mul(a[m], tw[m * i * TWS]);
+                                    dft<RL, -1>(a);
+                                    double sre = 0.0, sim = 0.0;
+#pragma unroll
+                                    for (int m = 0; m < RL; ++m) {
+                                        const double2 cz = c_mul(wv[m], a[m]);
+                                        sre += cz.x;
+                                        sim += cz.y;
+                                    }
+                                    acc[2 * gp] += rinf.rw * sre;
+                                    if (2 * gp + 1 < NG) acc[2 * gp + 1] += rinf.rw * sim;
+                                }
+                            }
+                        }
+                    }
                 }
+                wave_sync();
             }
-            __syncthreads();
         }
         double outv[NG];
-        block_sum<NG, NT>(acc, red, outv);
+        block_sum<NG, WPB * 64>(acc, red, outv);
         if (threadIdx.x == 0) {
 #pragma unroll
             for (int g = 0; g < NG; ++g) partial[item * NG + g] = outv[g];
@@ -144,13 +319,22 @@ __global__ __launch_bounds__(NT) void k_rows(const double* __restrict__ prm, Row
     }
 }
 
-// Rows per block iteration: about 32 KiB of pencils (variant 0/2) or 64 KiB (1).
+// Rows per wavefront per pass: enough butterflies for one per lane in a radix-8
+// stage (variant 0, 2) or twice that (variant 1); at most 8.
 template <int N, int NG, int VAR>
 constexpr int rows_for() {
     constexpr int npen = (NG + 1) / 2;
-    constexpr int bytes = (VAR == 1 ? 65536 : 32768) - 2048;
-    constexpr int r = bytes / (npen * (N + 1) * 16);
-    return r >= 16 ? 16 : (r >= 8 ? 8 : (r >= 4 ? 4 : (r >= 2 ? 2 : 1)));
+    constexpr int bfly = npen * (N / 8 > 0 ? N / 8 : 1);
+    constexpr int base = bfly >= 64 ? 1 : (64 / bfly >= 8 ? 8 : (64 / bfly >= 4 ? 4 : (64 / bfly >= 2 ? 2 : 1)));
+    constexpr int r = VAR == 1 ? (base * 2 > 8 ? 8 : base * 2) : base;
+    return r;
+}
+
+// Wavefronts per block: as many (<= 4) as fit 96 KiB of pencils.
+template <int N, int NG, int RPW>
+constexpr int waves_for() {
+    constexpr int per = RPW * ((NG + 1) / 2) * (N + 1) * 16;
+    return per * 4 <= 98304 ? 4 : (per * 2 <= 98304 ? 2 : 1);
 }
 
 // Persistent grid: grid_blocks > 0 as given, 0 = resident blocks per CU x CUs,
@@ -158,9 +342,10 @@ constexpr int rows_for() {
 template <int D, int N, class Fun, int VAR>
 hipError_t run_rows_t(const double* prm, RowGeom geo, int64_t nitems, double* partial, int grid_blocks,
                       const double2* tw, hipStream_t s) {
-    constexpr int ROWS = rows_for<N, Fun::NG, VAR>();
+    constexpr int RPW = rows_for<N, Fun::NG, VAR>();
+    constexpr int WPB = waves_for<N, Fun::NG, RPW>();
     constexpr int SCHED = VAR == 2 ? 1 : 0;
-    auto kern = k_rows<D, N, Fun, ROWS, 256, SCHED>;
+    auto kern = k_rows<D, N, Fun, RPW, WPB, SCHED>;
     int64_t blocks = nitems;
     if (grid_blocks > 0) {
         blocks = grid_blocks;
@@ -168,7 +353,7 @@ hipError_t run_rows_t(const double* prm, RowGeom geo, int64_t nitems, double* pa
         static int resident = -1;  // per instantiation, per process
         if (resident < 0) {
             int per_cu = 0, dev = 0, cus = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess) per_cu = 1;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WPB * 64, 0) != hipSuccess) per_cu = 1;
             if (hipGetDevice(&dev) != hipSuccess ||
                 hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
                 cus = 256;
@@ -178,11 +363,8 @@ hipError_t run_rows_t(const double* prm, RowGeom geo, int64_t nitems, double* pa
     }
     if (blocks > nitems) blocks = nitems;
     if (blocks < 1) return hipSuccess;
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, prm, geo, nitems, partial, tw);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(WPB * 64), 0, s, prm, geo, nitems, partial, tw);
     return hipGetLastError();
 }
-
-template <int N, class Fun, int VAR>
-constexpr int rows_of() { return rows_for<N, Fun::NG, VAR>(); }
 
 }  // namespace kdefft
