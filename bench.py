@@ -48,7 +48,9 @@ def parse():
     ap.add_argument("--cpu-h", type=int, default=48, help="candidates in the CPU oracle sample")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy (counter calibration for rocprofv3 --pmc runs)")
-    ap.add_argument("--tune", action="store_true", help="run the launch autotuner before timing")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner (library defaults)")
+    ap.add_argument("--case5", action="store_true",
+                    help="measure the d=4 uneven multi-dataset workload instead (extra line, not the headline)")
     return ap.parse_args()
 
 
@@ -60,20 +62,29 @@ def row_kernel_hash():
     return h.hexdigest()[:16]
 
 
-def algorithmic_flops_per_candidate(M, N, d=2):
+def gen_flops_per_lag(d=2):
+    """Kernel generation at one lag for the objective+gradient family: two
+    Gaussians (matrix-vector 2d^2, quadratic form 2d, scale 2, one exp each),
+    the objective combination (2) and d(d+1)/2 Hessian entries (7 each)."""
+    return 2 * (2 * d * d + 2 * d + 2 + EXP_FLOPS) + 2 + 7 * d * (d + 1) // 2
+
+
+def algorithmic_flops_per_candidate(M, N, d=2, variant=0):
     """FP64 flops of one candidate in the batched objective+gradient kernel.
 
-    Rows of the half lag set: M (l_0 = 0..M-1).  Per row: two complex FFTs of
-    length N (4 real grids, two per transform) at 5 N log2 N flops each; the
+    Both forms visit the rows of the half lag set, M of them (l_0 = 0..M-1),
+    and generate the kernel at the 2M-1 nonzero lags of each row.
+    Spectral form (variants 0-2), per row: two complex FFTs of length N (the 4
+    real grids packed two per transform) at 5 N log2 N flops each and the
     contraction over the full last axis, 8 flops per complex multiply-add per
-    transform; kernel generation for the 2M-1 nonzero lags of the row: two
-    Gaussians (matrix-vector 2d^2, quadratic form 2d, scale 2, one exp each),
-    the objective combination (2) and 3 Hessian entries (7 each)."""
+    transform.  Lag form (variant 3), per lag: one multiply-add per grid
+    against the autocorrelation (4 grids, 2 flops each)."""
+    gen = (2 * M - 1) * gen_flops_per_lag(d)
+    if variant == 3:
+        return M * (gen + (2 * M - 1) * 2 * 4)
     log2n = int(np.log2(N))
     fft = 2 * 5 * N * log2n
     contraction = 2 * N * 8
-    gen_point = 2 * (2 * d * d + 2 * d + 2 + EXP_FLOPS) + 2 + 3 * 7
-    gen = (2 * M - 1) * gen_point
     return M * (fft + contraction + gen)
 
 
@@ -83,6 +94,8 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
               "(the path shards by candidates/datasets with no exchange; see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if a.case5:
+        return main_case5(a)
     import torch
     import paper_1511_07482_amd as kf
     import synth
@@ -96,9 +109,13 @@ def main():
     X = torch.from_numpy(X_h).to(dev)
     vechL = torch.from_numpy(synth.vech_chol(H)).to(dev)
     tuned = None
-    if a.tune:
+    variant = 3   # library default for untuned shapes
+    if not a.no_tune:
         ds0 = kf.Dataset(X, Gp, M=M)
         tuned = kf.autotune(ds0)
+        for line in tuned.splitlines():
+            if line.startswith("best: variant"):
+                variant = int(line.split()[2])
 
     def step():
         g = kf.grid_auto(X, Gp, M)
@@ -153,6 +170,29 @@ def main():
         return v.grad
 
     t_autograd, _ = timed(autograd_step, 5)
+
+    # the per-candidate FFT route (spectral kernel, best of its variants in the
+    # tuner's list, else variant 1), timed with HIP events like the step's launch
+    N = int(g.P[d - 1])
+    spec_variant = 1
+    if tuned:
+        best_us = None
+        for line in tuned.splitlines():
+            p = line.split()
+            if p and p[0] == "variant" and int(p[1]) < 3:
+                us = float(p[4])
+                if best_us is None or us < best_us:
+                    best_us, spec_variant = us, int(p[1])
+    kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, spec_variant, 0)
+    kf.scv([ds], vechL)
+    es, ee = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    es.record(stream)
+    for _ in range(5):
+        kf.scv([ds], vechL)
+    ee.record(stream)
+    torch.cuda.synchronize()
+    spec_ms = es.elapsed_time(ee) / 5
+    kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, variant if tuned else 3, 0)
     hp = min(a.plain_h, B)
     kf.scv_plain(ds, H[0])
     torch.cuda.synchronize()
@@ -175,8 +215,9 @@ def main():
         torch.cuda.synchronize()
 
     # ---- roofline of the dominant kernel (batched SCV objective+gradient launch)
-    flops = algorithmic_flops_per_candidate(M, g.P[d - 1]) * B
+    flops = algorithmic_flops_per_candidate(M, N, d, variant) * B
     achieved = flops / (scv_ms * 1e-3)
+    spec_flops = algorithmic_flops_per_candidate(M, N, d, spec_variant) * B
     traffic = None
     prof = os.path.join(ROOT, "profiles", "scv_rows_case4_counters.json")
     if os.path.exists(prof):
@@ -184,10 +225,15 @@ def main():
             rec = json.load(fh)
         if rec.get("row_kernel_hash") == row_kernel_hash():
             traffic = rec.get("hbm_bytes_per_launch")
+    kname = ("k_lag<2,512,ScvFun<2,1>,256>" if variant == 3 else f"k_rows<2,512,ScvFun<2,1>> variant {variant}")
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic,
-                "kernel": "k_rows<2,512,ScvFun<2,1>> (+ setup/final, <1%)", "launch_ms": scv_ms,
-                "flops_per_launch": flops}
+                "kernel": kname + " (+ setup/final launches, <3%)", "launch_ms": scv_ms,
+                "flops_per_launch": flops, "variant": variant}
+    fft_route = {"kernel": f"k_rows<2,512,ScvFun<2,1>> variant {spec_variant} (per-candidate last-axis FFTs in LDS)",
+                 "launch_ms": spec_ms, "evals_per_s": B / (spec_ms * 1e-3), "flops_per_launch": spec_flops,
+                 "achieved_tflops": spec_flops / (spec_ms * 1e-3) / 1e12,
+                 "frac": spec_flops / (spec_ms * 1e-3) / PEAK_FP64_VECTOR}
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -210,6 +256,7 @@ def main():
                                "for 256 H per step (binning and count transform included)",
                    "d": d, "n": n, "M": M, "P": int(g.P[d - 1]), "candidates": B, "psi_r": 4},
         "roofline": roofline,
+        "fft_route_batched": fft_route,
         "cpu_baseline": cpu,
         "components_ms": {"dataset_prepare": t_prep * 1e3, "psi4_batched": t_psi_batched * 1e3,
                           "scv_objgrad_batched_256": t_scv_only * 1e3, "scv_autograd_fwd_adjoint_256": t_autograd * 1e3,
@@ -225,6 +272,71 @@ def main():
         "tuned": tuned,
         "device": torch.cuda.get_device_name(0),
     }
+    print(json.dumps(out))
+
+
+def fft_stage_bytes(P, d):
+    """HBM bytes of the count transform of one dataset: the last-axis R2C pass
+    reads the real grid and writes the half spectrum; each of the d-1 leading
+    passes reads and writes the half spectrum, the fused axis-0 pass writes it
+    twice (C and the mixed spectrum); the autocorrelation adds |C|^2 (read C,
+    write), d-1 inverse leading passes and the last-axis C2R (read half
+    spectrum, write real grid)."""
+    real = 8 * P ** d
+    half = 16 * P ** (d - 1) * (P // 2 + 1)
+    fwd = (real + half) + (d - 1) * 2 * half + half + (d - 2) * 2 * half
+    auto = 2 * half + (d - 1) * 2 * half + (half + real)
+    return fwd + auto
+
+
+def main_case5(a):
+    import torch
+    import paper_1511_07482_amd as kf
+    import synth
+    dev = torch.device("cuda:0")
+    w = synth.case5()
+    d, M = w.d, w.M
+    Xs = [torch.from_numpy(X).to(dev) for X in w.X]
+    ns = [X.shape[0] for X in w.X]
+    per = [H.shape[0] for H in w.H]
+    B = sum(per)
+    vech = torch.from_numpy(np.concatenate([synth.vech_chol(H) for H in w.H])).to(dev)
+    torch.cuda.synchronize()
+
+    def prepare():
+        return [kf.Dataset(X, Gp, M=M) for X, Gp in zip(Xs, w.G_pilot)]
+
+    dss = prepare()
+    tuned = None if a.no_tune else kf.autotune(dss[0])
+    stream = torch.cuda.current_stream(dev)
+
+    def ev_time(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            out = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, out
+
+    t_prep, dss = ev_time(prepare, 2)
+    t_psi, _ = ev_time(lambda: kf.psi_batch(dss, w.G_psi, 4), 3)
+    t_scv, (obj, grad) = ev_time(lambda: kf.scv(dss, vech, per_ds=per), 3)
+    assert torch.isfinite(obj).all() and torch.isfinite(grad).all()
+    # one large dataset: binning alone vs full preparation -> count-transform time
+    big = int(np.argmax(ns))
+    gbig = dss[big].grid
+    t_bin, _ = ev_time(lambda: kf.linbin(Xs[big], gbig), 3)
+    t_prep1, _ = ev_time(lambda: kf.Dataset(Xs[big], w.G_pilot[big], grid=gbig), 3)
+    P = int(gbig.P[0])
+    out = {"metric": "case5 (extra line): d=4, 32 datasets n~U[1e4,1e6], M=32 (P=64), 64 H each",
+           "n_total": int(sum(ns)), "candidates": B,
+           "prepare_all_ms": t_prep, "psi4_batch_ms": t_psi, "scv_objgrad_batch_ms": t_scv,
+           "scv_evals_per_s": B / (t_scv * 1e-3), "psi4_evals_per_s": len(dss) / (t_psi * 1e-3),
+           "largest_n": ns[big], "linbin_largest_ms": t_bin, "prepare_largest_ms": t_prep1,
+           "fft_stage_bytes_per_dataset": fft_stage_bytes(P, d), "tuned": tuned}
     print(json.dumps(out))
 
 

@@ -88,6 +88,9 @@ typedef struct kdefft_grid {
  *                                           interleaved (re, im) float64
  *   wmix    complex [prod_{k<d-1} P_k][Q]   |C|^2 transformed forward along
  *                                           axes 0..d-2 (mixed-domain spectrum)
+ *   alag    float64 [P_0, ..., P_{d-1}]     prod P times the autocorrelation of the
+ *                                           counts, A_l = sum_i c_i c_{i+l}, lag l at
+ *                                           index l mod P (inverse transform of |C|^2)
  *   scal    float64 [4]                     scal[0] = n^-2 sum sum phi_{2G} (binned)
  *   n_out   int32 [1]                       number of points outside the grid
  *   rec     opaque device record (pointers, n, spacing, pilot) read by the
@@ -99,6 +102,7 @@ typedef struct kdefft_dataset {
     int64_t* counts;
     double* spec;
     double* wmix;
+    double* alag;
     double* scal;
     int32_t* n_out;
     void* rec;
@@ -235,10 +239,13 @@ int kdefft_scv_plain(const kdefft_dataset* ds_host, const double* H_host, double
 /* Pin the launch of the batched row kernels for one kernel family (kind: 0 psi,
  * 1 SCV objective, 2 SCV objective+gradient, 3 SCV gradient), dimension d,
  * order r (2 for the SCV families) and last-axis length N for the rest of the
- * process: variant = compiled variant in [0, 3) (0: ~32 KiB of LDS pencils per
- * block, radix-8 first; 1: ~64 KiB; 2: ~32 KiB, radix-4 first); grid_blocks =
+ * process: variant in [0, 4): 0, 1, 2 run the per-candidate last-axis FFTs in
+ * LDS (0: one radix-8 butterfly per lane per stage, radix-8 first; 1: twice the
+ * rows per wavefront; 2: radix-4 first); grid_blocks =
  * persistent grid size, 0 = resident blocks per CU x CUs, -1 = one block per
- * work item.  Used by kdefft_autotune and by tests that cover every variant.
+ * work item.  Variant 3 evaluates each candidate in the lag domain instead:
+ * sum_l k(l) A(l) against the prepared count autocorrelation (identical sums,
+ * no per-candidate transform).  Used by kdefft_autotune and by tests that cover every variant.
  * Host only. */
 int kdefft_set_row_launch(int kind, int d, int r, int N, int variant, int grid_blocks);
 

@@ -31,7 +31,7 @@ class Grid(C.Structure):
 
 class Dataset(C.Structure):
     _fields_ = [("grid", Grid), ("n", C.c_int64), ("G", C.c_double * 16),
-                ("counts", C.c_void_p), ("spec", C.c_void_p), ("wmix", C.c_void_p),
+                ("counts", C.c_void_p), ("spec", C.c_void_p), ("wmix", C.c_void_p), ("alag", C.c_void_p),
                 ("scal", C.c_void_p), ("n_out", C.c_void_p), ("rec", C.c_void_p)]
 
 

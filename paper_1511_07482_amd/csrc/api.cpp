@@ -238,7 +238,8 @@ RowLaunch launch_for(int kind, int d, int r, int N) {
     load_cache_locked(dev);
     auto it = g_launch.find(LaunchKey{dev, kind, d, r, N});
     if (it != g_launch.end()) return it->second;
-    return RowLaunch{0, 0};
+    // untuned default: the lag-domain evaluation (fewest operations, no LDS)
+    return RowLaunch{3, 0};
 }
 
 void set_launch(int kind, int d, int r, int N, RowLaunch rl) {
@@ -253,6 +254,7 @@ struct DsLayout {
     int64_t* counts;
     double2* spec;
     double2* wmix;
+    double* alag;
     double* scal;
     int32_t* n_out;
     DsDev* rec;
@@ -263,6 +265,7 @@ DsLayout carve_dataset(Arena& a, const kdefft_grid& g) {
     L.counts = a.take<int64_t>(s.prodM);
     L.spec = a.take<double2>(s.spec);
     L.wmix = a.take<double2>(s.spec);
+    L.alag = a.take<double>(s.prodP);
     L.scal = a.take<double>(4);
     L.n_out = a.take<int32_t>(1);
     L.rec = a.take<DsDev>(1);
@@ -271,12 +274,14 @@ DsLayout carve_dataset(Arena& a, const kdefft_grid& g) {
 
 struct PrepScratch {
     double* czp;
+    double2* tmp;
     double* prm;
     double* partial;
 };
 PrepScratch carve_prepare(Arena& a, const kdefft_grid& g) {
     PrepScratch p;
     p.czp = a.take<double>(sizes_of(g).prodP);
+    p.tmp = a.take<double2>(sizes_of(g).spec);
     p.prm = a.take<double>(PRM);
     p.partial = a.take<double>(max_nchunks(g, FUN_PSI, 0, 1));
     return p;
@@ -394,8 +399,10 @@ int prepare_into(const double* X, int64_t n, const kdefft_grid& g, const double*
     int rc = bin_and_fill(X, n, g, L.counts, L.n_out, p.czp, s);
     if (rc) return rc;
     HIPCHK(fft_prepare_nd(p.czp, L.spec, L.wmix, g, s), "count transform");
+    HIPCHK(fft_autocorr_nd(L.spec, p.tmp, L.alag, g, s), "count autocorrelation");
     DsDev rec{};
     rec.wmix = L.wmix;
+    rec.alag = L.alag;
     rec.scal = L.scal;
     rec.n = (double)n;
     for (int k = 0; k < g.d; ++k) rec.delta[k] = g.delta[k];
@@ -446,7 +453,7 @@ int check_batch_ds(const kdefft_dataset* ds, int n_ds, int max_ds) {
     int rc = check_grid(&ds[0].grid);
     if (rc) return rc;
     for (int j = 0; j < n_ds; ++j) {
-        if (!ds[j].rec || !ds[j].wmix || !ds[j].scal)
+        if (!ds[j].rec || !ds[j].wmix || !ds[j].alag || !ds[j].scal)
             return fail(KDEFFT_E_ARG, "dataset %d is not prepared", j);
         rc = check_grid(&ds[j].grid);
         if (rc) return rc;
@@ -713,6 +720,7 @@ int kdefft_dataset_prepare(const double* X, int64_t n, const kdefft_grid* g, con
     o.counts = dl.counts;
     o.spec = reinterpret_cast<double*>(dl.spec);
     o.wmix = reinterpret_cast<double*>(dl.wmix);
+    o.alag = dl.alag;
     o.scal = dl.scal;
     o.n_out = dl.n_out;
     o.rec = dl.rec;
@@ -940,6 +948,11 @@ int kdefft_autotune(const kdefft_dataset* ds, void* ws, size_t ws_bytes, const c
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
+    {
+        char buf[96];
+        snprintf(buf, sizeof(buf), "best: variant %d grid %d\n", best.variant, best.grid_blocks);
+        lines += buf;
+    }
     for (int kind = FUN_SCV_OBJ; kind <= FUN_SCV_GRAD; ++kind)
         if (rows_per_iter(kind, d, 2, N, best.variant) >= 1) set_launch(kind, d, 2, N, best);
     if (cache_path && *cache_path) {

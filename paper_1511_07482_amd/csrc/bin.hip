@@ -41,22 +41,38 @@ __global__ __launch_bounds__(256) void k_bounds(const double* __restrict__ X, in
     }
 }
 
-__global__ void k_bounds_final(const double* __restrict__ partial, int nblk, int d, double* __restrict__ out) {
-    const int k = threadIdx.x;
-    if (k >= d) return;
-    double mn = INFINITY, mx = -INFINITY;
-    for (int b = 0; b < nblk; ++b) {
-        mn = fmin(mn, partial[b * 8 + k]);
-        mx = fmax(mx, partial[b * 8 + 4 + k]);
+__global__ __launch_bounds__(256) void k_bounds_final(const double* __restrict__ partial, int nblk, int d,
+                                                      double* __restrict__ out) {
+    __shared__ double smin[4][256], smax[4][256];
+    for (int k = 0; k < 4; ++k) {
+        double mn = INFINITY, mx = -INFINITY;
+        if (k < d)
+            for (int b = threadIdx.x; b < nblk; b += 256) {
+                mn = fmin(mn, partial[b * 8 + k]);
+                mx = fmax(mx, partial[b * 8 + 4 + k]);
+            }
+        smin[k][threadIdx.x] = mn;
+        smax[k][threadIdx.x] = mx;
     }
-    out[k] = mn;
-    out[4 + k] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int k = 0; k < 4; ++k) {
+                smin[k][threadIdx.x] = fmin(smin[k][threadIdx.x], smin[k][threadIdx.x + s]);
+                smax[k][threadIdx.x] = fmax(smax[k][threadIdx.x], smax[k][threadIdx.x + s]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < (unsigned)d) {
+        out[threadIdx.x] = smin[threadIdx.x][0];
+        out[4 + threadIdx.x] = smax[threadIdx.x][0];
+    }
 }
 
 hipError_t launch_bounds(const double* X, int64_t n, int d, double* partial, int nblk, double* out,
                          hipStream_t s) {
     hipLaunchKernelGGL(k_bounds, dim3(nblk), dim3(256), 0, s, X, n, d, partial);
-    hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(64), 0, s, partial, nblk, d, out);
+    hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(256), 0, s, partial, nblk, d, out);
     return hipGetLastError();
 }
 

@@ -353,4 +353,14 @@ hipError_t fft_prepare_nd(const double* czp, double2* spec, double2* wmix, const
     return e;
 }
 
+hipError_t fft_autocorr_nd(const double2* spec, double2* tmp, double* alag, const kdefft_grid& g, hipStream_t s) {
+    const int64_t cnt = lead_count(g) * (g.P[g.d - 1] / 2 + 1);
+    int64_t blocks = (cnt + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_abs2, dim3((unsigned)blocks), dim3(256), 0, s, spec, tmp, cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return fft_c2r_nd(tmp, alag, g, s);
+}
+
 }  // namespace kdefft

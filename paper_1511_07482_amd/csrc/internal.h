@@ -17,15 +17,16 @@ constexpr int NT_DEF = 256;  // threads per block of the simple kernels
 // Matrices use row stride 4.
 //   psi:  [0,16) P = G^{-1}   [16] c = (-1)^r (2pi)^{-d/2}|G|^{-1/2}
 //   scv:  [0,16) P1 = (2H+2G)^{-1}  [16,32) P2 = (H+2G)^{-1}  [32] c1  [33] c2
-//   both: [39] wmix pointer bits  [40,44) delta  [44] n  [45] 1/(n^2 prod P)
+//   both: [38] alag pointer bits  [39] wmix pointer bits  [40,44) delta  [44] n  [45] 1/(n^2 prod P)
 //         [46] constant term  [47] singular flag  [48,64) L (scv) / P3 (plain scv)
-enum Slot { S_P1 = 0, S_C = 16, S_P2 = 16, S_C1 = 32, S_C2 = 33, S_WMIX = 39, S_DELTA = 40, S_N = 44,
+enum Slot { S_P1 = 0, S_C = 16, S_P2 = 16, S_C1 = 32, S_C2 = 33, S_ALAG = 38, S_WMIX = 39, S_DELTA = 40, S_N = 44,
             S_SCALE = 45, S_CONST = 46, S_SING = 47, S_L = 48 };
 
 // Per-dataset record kept in the dataset's own device buffer (written by a
 // kernel at prepare time); batched calls pass pointers to these records.
 struct DsDev {
     const double2* wmix;
+    const double* alag;
     const double* scal;
     double n;
     double delta[4];
@@ -88,6 +89,8 @@ hipError_t fft_c2r_nd(double2* inout, double* out, const kdefft_grid& g, hipStre
 // transformed forward along the leading axes.
 hipError_t fft_prepare_nd(const double* czp, double2* spec, double2* wmix, const kdefft_grid& g,
                           hipStream_t s);
+// alag = C2R(|spec|^2) (prod P times the count autocorrelation); tmp: spectrum-sized scratch.
+hipError_t fft_autocorr_nd(const double2* spec, double2* tmp, double* alag, const kdefft_grid& g, hipStream_t s);
 
 // Paper-literal path, one grid per launch.
 hipError_t launch_kgrid_psi(double* out, const kdefft_grid& g, int r, const ParamBlock& prm,
@@ -110,7 +113,7 @@ struct RowLaunch {
 hipError_t launch_rows(int kind, int d, int r, const RowGeom& geo, const double* prm, int64_t ncand,
                        double* partial, const RowLaunch& rl, hipStream_t s);
 int rows_per_iter(int kind, int d, int r, int N, int variant);
-constexpr int ROW_VARIANTS = 3;
+constexpr int ROW_VARIANTS = 4;   // 0-2: spectral (per-candidate FFT), 3: lag domain
 hipError_t launch_scv_setup(const double* vechL, const ScvBatchArgs& a, int64_t ncand, double* prm,
                             int32_t* status, hipStream_t s);
 hipError_t launch_psi_setup(const PsiBatchArgs& a, double* prm, hipStream_t s);

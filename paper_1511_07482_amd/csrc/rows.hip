@@ -93,39 +93,54 @@ hipError_t launch_rows(int kind, int d, int r, const RowGeom& geo, const double*
 
 // ------------------------------------------------------------------ small dense linear algebra (d <= 4)
 // Cholesky A = L L^T of a symmetric d x d (row stride 4); false if not positive definite.
-__device__ static bool chol4(const double* A, double* L, int d) {
+template <int D>
+__device__ __forceinline__ static bool chol4(const double* A, double* L) {
+#pragma unroll
     for (int i = 0; i < 16; ++i) L[i] = 0.0;
-    for (int j = 0; j < d; ++j) {
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
         double s = A[j * 4 + j];
+#pragma unroll
         for (int k = 0; k < j; ++k) s -= L[j * 4 + k] * L[j * 4 + k];
-        if (!(s > 0.0)) return false;
-        const double ljj = sqrt(s);
+        ok = ok && (s > 0.0);
+        const double ljj = sqrt(s > 0.0 ? s : 1.0);
         L[j * 4 + j] = ljj;
-        for (int i = j + 1; i < d; ++i) {
+#pragma unroll
+        for (int i = j + 1; i < D; ++i) {
             double t = A[i * 4 + j];
+#pragma unroll
             for (int k = 0; k < j; ++k) t -= L[i * 4 + k] * L[j * 4 + k];
             L[i * 4 + j] = t / ljj;
         }
     }
-    return true;
+    return ok;
 }
 
 // Inverse of L L^T from the lower factor L (row stride 4).
-__device__ static void chol_inv4(const double* L, double* Ainv, int d) {
+template <int D>
+__device__ __forceinline__ static void chol_inv4(const double* L, double* Ainv) {
     double Li[16];
+#pragma unroll
     for (int i = 0; i < 16; ++i) Li[i] = 0.0;
-    for (int j = 0; j < d; ++j) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
         Li[j * 4 + j] = 1.0 / L[j * 4 + j];
-        for (int i = j + 1; i < d; ++i) {
+#pragma unroll
+        for (int i = j + 1; i < D; ++i) {
             double s = 0.0;
+#pragma unroll
             for (int k = j; k < i; ++k) s -= L[i * 4 + k] * Li[k * 4 + j];
             Li[i * 4 + j] = s / L[i * 4 + i];
         }
     }
-    for (int i = 0; i < d; ++i)
-        for (int j = 0; j < d; ++j) {
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
             double s = 0.0;
-            for (int k = (i > j ? i : j); k < d; ++k) s += Li[k * 4 + i] * Li[k * 4 + j];
+#pragma unroll
+            for (int k = (i > j ? i : j); k < D; ++k) s += Li[k * 4 + i] * Li[k * 4 + j];
             Ainv[i * 4 + j] = s;
         }
 }
@@ -144,15 +159,20 @@ __device__ static void put_ptr(double* slot, const void* p) {
 // One thread per candidate: H = L L^T from vechL, S1 = 2H + 2G, S2 = H + 2G,
 // their inverses and normal constants, grid spacing, n and the scale of the
 // Parseval sums, the dataset's constant term.  status 1 = H singular.
+template <int D>
 __global__ void k_scv_setup(const double* __restrict__ vechL, ScvBatchArgs a, int64_t ncand,
                             double* __restrict__ prm, int32_t* __restrict__ status) {
     const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (h >= ncand) return;
-    const int d = a.d;
+    constexpr int d = D;
     const int q = d * (d + 1) / 2;
-    int j = 0;
-    while (j + 1 < a.n_ds && h >= a.off[j + 1]) ++j;
-    const DsDev& ds = *a.rec[j];
+    // dataset of candidate h; unrolled with constant indices so the by-value
+    // argument arrays stay in scalar registers
+    const DsDev* dsp = a.rec[0];
+#pragma unroll
+    for (int jj = 1; jj < KDEFFT_MAX_BATCH_DS; ++jj)
+        if (jj < a.n_ds && h >= a.off[jj]) dsp = a.rec[jj];
+    const DsDev& ds = *dsp;
     double L[16], H[16], S1[16], S2[16], L1[16], L2[16];
     for (int i = 0; i < 16; ++i) L[i] = 0.0;
     int t = 0;
@@ -177,20 +197,23 @@ __global__ void k_scv_setup(const double* __restrict__ vechL, ScvBatchArgs a, in
         }
     double* p = prm + h * PRM;
     for (int i = 0; i < PRM; ++i) p[i] = 0.0;
-    const bool ok = !sing && chol4(S1, L1, d) && chol4(S2, L2, d);
+    const bool ok1 = chol4<D>(S1, L1);
+    const bool ok2 = chol4<D>(S2, L2);
+    const bool ok = !sing && ok1 && ok2;
     if (!ok) {
         sing = true;
         // benign parameters keep the row kernel finite; the result is set to NaN
         for (int i = 0; i < 16; ++i) { L1[i] = 0.0; L2[i] = 0.0; }
         for (int k = 0; k < d; ++k) { L1[k * 4 + k] = 1.0; L2[k * 4 + k] = 1.0; }
     }
-    chol_inv4(L1, p + S_P1, d);
-    chol_inv4(L2, p + S_P2, d);
+    chol_inv4<D>(L1, p + S_P1);
+    chol_inv4<D>(L2, p + S_P2);
     double det1 = 1.0, det2 = 1.0;
     for (int k = 0; k < d; ++k) { det1 *= L1[k * 4 + k]; det2 *= L2[k * 4 + k]; }
     p[S_C1] = two_pi_pow(d) / det1;
     p[S_C2] = two_pi_pow(d) / det2;
     put_ptr(p + S_WMIX, ds.wmix);
+    put_ptr(p + S_ALAG, ds.alag);
     for (int k = 0; k < d; ++k) p[S_DELTA + k] = ds.delta[k];
     p[S_N] = ds.n;
     p[S_SCALE] = 1.0 / (ds.n * ds.n * a.prodP);
@@ -203,41 +226,65 @@ __global__ void k_scv_setup(const double* __restrict__ vechL, ScvBatchArgs a, in
 hipError_t launch_scv_setup(const double* vechL, const ScvBatchArgs& a, int64_t ncand, double* prm,
                             int32_t* status, hipStream_t s) {
     const int64_t blocks = (ncand + 63) / 64;
-    hipLaunchKernelGGL(k_scv_setup, dim3((unsigned)blocks), dim3(64), 0, s, vechL, a, ncand, prm, status);
+    switch (a.d) {
+        case 1: hipLaunchKernelGGL(k_scv_setup<1>, dim3((unsigned)blocks), dim3(64), 0, s, vechL, a, ncand, prm, status); break;
+        case 2: hipLaunchKernelGGL(k_scv_setup<2>, dim3((unsigned)blocks), dim3(64), 0, s, vechL, a, ncand, prm, status); break;
+        case 3: hipLaunchKernelGGL(k_scv_setup<3>, dim3((unsigned)blocks), dim3(64), 0, s, vechL, a, ncand, prm, status); break;
+        case 4: hipLaunchKernelGGL(k_scv_setup<4>, dim3((unsigned)blocks), dim3(64), 0, s, vechL, a, ncand, prm, status); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 // One thread per dataset: P = G^{-1}, c = (-1)^r (2 pi)^{-d/2} |G|^{-1/2}
 // for the psi_r family at the given bandwidth (validated SPD on the host).
+template <int D>
 __global__ void k_psi_setup(PsiBatchArgs a, double* __restrict__ prm) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= a.n_ds) return;
-    const int d = a.d;
-    const DsDev& ds = *a.rec[j];
+    constexpr int d = D;
+    const DsDev* dsp = a.rec[0];
+    double gv[10];
+    for (int t = 0; t < 10; ++t) gv[t] = a.Gv[0][t];
+#pragma unroll
+    for (int jj = 1; jj < KDEFFT_MAX_PSI_DS; ++jj)
+        if (jj == j) {
+            dsp = a.rec[jj];
+#pragma unroll
+            for (int t = 0; t < 10; ++t) gv[t] = a.Gv[jj][t];
+        }
+    const DsDev& ds = *dsp;
     double G[16], L[16];
     for (int i = 0; i < 16; ++i) G[i] = 0.0;
     int t = 0;
     for (int jj = 0; jj < d; ++jj)
         for (int i = jj; i < d; ++i) {
-            G[i * 4 + jj] = a.Gv[j][t];
-            G[jj * 4 + i] = a.Gv[j][t];
+            G[i * 4 + jj] = gv[t];
+            G[jj * 4 + i] = gv[t];
             ++t;
         }
     double* p = prm + (int64_t)j * PRM;
     for (int i = 0; i < PRM; ++i) p[i] = 0.0;
-    chol4(G, L, d);
-    chol_inv4(L, p + S_P1, d);
+    chol4<D>(G, L);
+    chol_inv4<D>(L, p + S_P1);
     double det = 1.0;
     for (int k = 0; k < d; ++k) det *= L[k * 4 + k];
     p[S_C] = two_pi_pow(d) / det;  // (-1)^r = 1: r is even
     put_ptr(p + S_WMIX, ds.wmix);
+    put_ptr(p + S_ALAG, ds.alag);
     for (int k = 0; k < d; ++k) p[S_DELTA + k] = ds.delta[k];
     p[S_N] = ds.n;
     p[S_SCALE] = 1.0 / (ds.n * ds.n * a.prodP);
 }
 
 hipError_t launch_psi_setup(const PsiBatchArgs& a, double* prm, hipStream_t s) {
-    hipLaunchKernelGGL(k_psi_setup, dim3(1), dim3(64), 0, s, a, prm);
+    switch (a.d) {
+        case 1: hipLaunchKernelGGL(k_psi_setup<1>, dim3(1), dim3(64), 0, s, a, prm); break;
+        case 2: hipLaunchKernelGGL(k_psi_setup<2>, dim3(1), dim3(64), 0, s, a, prm); break;
+        case 3: hipLaunchKernelGGL(k_psi_setup<3>, dim3(1), dim3(64), 0, s, a, prm); break;
+        case 4: hipLaunchKernelGGL(k_psi_setup<4>, dim3(1), dim3(64), 0, s, a, prm); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -248,35 +295,44 @@ hipError_t launch_write_rec(DsDev* rec, const DsDev& val, hipStream_t s) {
     return hipGetLastError();
 }
 
-// SCV assembly.  kind: FUN_SCV_OBJ (obj only), FUN_SCV_OBJGRAD (obj + grad),
-// FUN_SCV_GRAD (adjoint: grad scaled by grad_out).
-__global__ void k_scv_final(int kind, const double* __restrict__ partial, int64_t nchunks, int ng, int d,
-                            const double* __restrict__ prm, int64_t ncand, const double* __restrict__ grad_out,
-                            double* __restrict__ obj, double* __restrict__ grad) {
-    const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// Sum of the partial sums of candidate h, grid g over its chunks, by one
+// wavefront: lane t takes chunks t, t+64, ... in order, then a fixed xor tree.
+__device__ static double chunk_sum(const double* __restrict__ partial, int64_t h, int64_t nchunks, int ng, int g) {
+    const int lane = threadIdx.x & 63;
+    double s = 0.0;
+    for (int64_t c = lane; c < nchunks; c += 64) s += partial[(h * nchunks + c) * ng + g];
+    return wave_sum(s);
+}
+
+// SCV assembly, one wavefront per candidate.  kind: FUN_SCV_OBJ (obj only),
+// FUN_SCV_OBJGRAD (obj + grad), FUN_SCV_GRAD (adjoint: grad scaled by grad_out).
+template <int D>
+__global__ __launch_bounds__(64) void k_scv_final(int kind, const double* __restrict__ partial, int64_t nchunks,
+                                                  int ng, const double* __restrict__ prm, int64_t ncand,
+                                                  const double* __restrict__ grad_out, double* __restrict__ obj,
+                                                  double* __restrict__ grad) {
+    const int64_t h = blockIdx.x;
     if (h >= ncand) return;
+    constexpr int d = D;
     const double* p = prm + h * PRM;
-    const int q = d * (d + 1) / 2;
-    double T[11];
-    for (int g = 0; g < ng; ++g) {
-        double s = 0.0;
-        for (int64_t c = 0; c < nchunks; ++c) s += partial[(h * nchunks + c) * ng + g];
-        T[g] = s * p[S_SCALE];
-    }
+    constexpr int q = d * (d + 1) / 2;
+    double T[1 + q];
+#pragma unroll
+    for (int g = 0; g < 1 + q; ++g) T[g] = g < ng ? chunk_sum(partial, h, nchunks, ng, g) * p[S_SCALE] : 0.0;
+    if (threadIdx.x != 0) return;
     const bool sing = p[S_SING] != 0.0;
     const double nan = __longlong_as_double(0x7ff8000000000000LL);
     const double* L = p + S_L;
     double ldet = 1.0;
     for (int k = 0; k < d; ++k) ldet *= fabs(L[k * 4 + k]);
-    // (4 pi)^{-d/2} = 2^{-d/2} (2 pi)^{-d/2}
-    double c4 = 1.0;
-    for (int k = 0; k < d; ++k) c4 *= 0.28209479177387814347;  // (4 pi)^{-1/2}
+    double c4 = 1.0;  // (4 pi)^{-d/2}
+    for (int k = 0; k < d; ++k) c4 *= 0.28209479177387814347;
     const double first = c4 / (p[S_N] * ldet);
     if (kind != FUN_SCV_GRAD) obj[h] = sing ? nan : first + T[0] + p[S_CONST];
     if (kind == FUN_SCV_OBJ || grad == nullptr) return;
     const int off = kind == FUN_SCV_OBJGRAD ? 1 : 0;
     double Hinv[16];
-    chol_inv4(L, Hinv, d);
+    chol_inv4<D>(L, Hinv);
     double gH[16];
     int t = off;
     for (int i = 0; i < d; ++i)
@@ -298,34 +354,37 @@ __global__ void k_scv_final(int kind, const double* __restrict__ partial, int64_
 hipError_t launch_scv_final(int kind, const double* partial, const RowGeom& geo, const double* prm, int64_t ncand,
                             const double* grad_out, double* obj, double* grad, hipStream_t s) {
     const int ng = ng_of(kind, geo.d, 2);
-    const int64_t blocks = (ncand + 63) / 64;
-    hipLaunchKernelGGL(k_scv_final, dim3((unsigned)blocks), dim3(64), 0, s, kind, partial, geo.nchunks, ng, geo.d,
-                       prm, ncand, grad_out, obj, grad);
+    const dim3 grid((unsigned)ncand);
+    switch (geo.d) {
+        case 1: hipLaunchKernelGGL(k_scv_final<1>, grid, dim3(64), 0, s, kind, partial, geo.nchunks, ng, prm, ncand, grad_out, obj, grad); break;
+        case 2: hipLaunchKernelGGL(k_scv_final<2>, grid, dim3(64), 0, s, kind, partial, geo.nchunks, ng, prm, ncand, grad_out, obj, grad); break;
+        case 3: hipLaunchKernelGGL(k_scv_final<3>, grid, dim3(64), 0, s, kind, partial, geo.nchunks, ng, prm, ncand, grad_out, obj, grad); break;
+        case 4: hipLaunchKernelGGL(k_scv_final<4>, grid, dim3(64), 0, s, kind, partial, geo.nchunks, ng, prm, ncand, grad_out, obj, grad); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-// psi[h, g] = scale_h * sum over chunks (fixed order); scal_out (if set)
-// receives psi[0, 0] (the constant SCV term of a dataset).
-__global__ void k_psi_final(const double* __restrict__ partial, int64_t nchunks, int ng,
-                            const double* __restrict__ prm, int64_t ncand, double* __restrict__ psi,
-                            double* __restrict__ scal_out) {
-    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// psi[h, g] = scale_h * sum over chunks (fixed order), one wavefront per
+// (candidate, grid); scal_out (if set) receives psi[0, 0] (the constant SCV
+// term of a dataset).
+__global__ __launch_bounds__(64) void k_psi_final(const double* __restrict__ partial, int64_t nchunks, int ng,
+                                                  const double* __restrict__ prm, int64_t ncand,
+                                                  double* __restrict__ psi, double* __restrict__ scal_out) {
+    const int64_t e = blockIdx.x;
     if (e >= ncand * ng) return;
     const int64_t h = e / ng;
     const int g = (int)(e - h * ng);
-    double s = 0.0;
-    for (int64_t c = 0; c < nchunks; ++c) s += partial[(h * nchunks + c) * ng + g];
-    const double v = s * prm[h * PRM + S_SCALE];
+    const double v = chunk_sum(partial, h, nchunks, ng, g) * prm[h * PRM + S_SCALE];
+    if (threadIdx.x != 0) return;
     if (psi) psi[h * ng + g] = v;
     if (scal_out && e == 0) scal_out[0] = v;
 }
 
 hipError_t launch_psi_final(const double* partial, const RowGeom& geo, int ng, const double* prm, int64_t ncand,
                             double* psi, double* scal_out, hipStream_t s) {
-    const int64_t tot = ncand * ng;
-    const int64_t blocks = (tot + 63) / 64;
-    hipLaunchKernelGGL(k_psi_final, dim3((unsigned)blocks), dim3(64), 0, s, partial, geo.nchunks, ng, prm, ncand,
-                       psi, scal_out);
+    hipLaunchKernelGGL(k_psi_final, dim3((unsigned)(ncand * ng)), dim3(64), 0, s, partial, geo.nchunks, ng, prm,
+                       ncand, psi, scal_out);
     return hipGetLastError();
 }
 

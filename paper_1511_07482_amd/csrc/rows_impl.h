@@ -41,6 +41,14 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Position of element e of a pencil in LDS: the low four index bits are XORed
+// with a function of the next bits, so that 16 consecutive lanes hit 16
+// different 16-byte bank groups for contiguous reads, stride-8 writes (first
+// radix-8 stage) and the grouped writes of later stages alike.
+__device__ __forceinline__ constexpr int swz(int e) {
+    return e ^ (((e >> 4) & 7) | (((e >> 4) & 4) << 1));
+}
+
 template <int N, int SCHED>
 constexpr int last_L() {
     int L = 1;
@@ -49,6 +57,9 @@ constexpr int last_L() {
 }
 
 // Middle Stockham stages [L, LEND) of NPW pencils, executed by one wavefront.
+// Butterflies are taken in groups that cover whole pencils (one pencil, or
+// several short ones, per group), each group read, transformed and written
+// back before the next, so only one group's values are live in registers.
 template <int N, int L, int LEND, int NPW, int SCHED>
 __device__ __forceinline__ void wave_mid_stages(double2* buf, int lane, const double2* __restrict__ tw) {
     if constexpr (L < LEND) {
@@ -56,35 +67,41 @@ __device__ __forceinline__ void wave_mid_stages(double2* buf, int lane, const do
         constexpr int NB = N / R;
         constexpr int TOT = NB * NPW;
         constexpr int PER = (TOT + 63) / 64;
+        constexpr int G = NB >= 64 ? NB / 64 : 1;     // butterfly sets per group
+        constexpr int NGRP = (PER + G - 1) / G;
         constexpr int TWS = TWN / (R * L);
-        double2 v[PER][R];
+#pragma unroll 1
+        for (int grp = 0; grp < NGRP; ++grp) {
+            double2 v[G][R];
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int b = lane + u * 64;
-            if ((TOT % 64) == 0 || b < TOT) {
-                const int p = b / NB, i = b - p * NB;
-                const int k = i & (L - 1);
-                const double2* src = buf + p * (N + 1) + i;
+            for (int g = 0; g < G; ++g) {
+                const int b = lane + (grp * G + g) * 64;
+                if ((TOT % 64) == 0 || b < TOT) {
+                    const int p = b / NB, i = b - p * NB;
+                    const int k = i & (L - 1);
+                    const double2* src = buf + p * N;
 #pragma unroll
-                for (int m = 0; m < R; ++m) v[u][m] = src[m * NB];
+                    for (int m = 0; m < R; ++m) v[g][m] = src[swz(i + m * NB)];
 #pragma unroll
-                for (int m = 1; m < R; ++m) v[u][m] = c_mul(v[u][m], tw[m * k * TWS]);
-                dft<R, -1>(v[u]);
+                    for (int m = 1; m < R; ++m) v[g][m] = c_mul(v[g][m], tw[m * k * TWS]);
+                    dft<R, -1>(v[g]);
+                }
             }
-        }
-        wave_sync();
+            wave_sync();
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int b = lane + u * 64;
-            if ((TOT % 64) == 0 || b < TOT) {
-                const int p = b / NB, i = b - p * NB;
-                const int k = i & (L - 1);
-                double2* dst = buf + p * (N + 1) + (i - k) * R + k;
+            for (int g = 0; g < G; ++g) {
+                const int b = lane + (grp * G + g) * 64;
+                if ((TOT % 64) == 0 || b < TOT) {
+                    const int p = b / NB, i = b - p * NB;
+                    const int k = i & (L - 1);
+                    double2* dst = buf + p * N;
+                    const int base = (i - k) * R + k;
 #pragma unroll
-                for (int m = 0; m < R; ++m) dst[m * L] = v[u][m];
+                    for (int m = 0; m < R; ++m) dst[swz(base + m * L)] = v[g][m];
+                }
             }
+            wave_sync();
         }
-        wave_sync();
         wave_mid_stages<N, L * R, LEND, NPW, SCHED>(buf, lane, tw);
     }
 }
@@ -92,6 +109,7 @@ __device__ __forceinline__ void wave_mid_stages(double2* buf, int lane, const do
 struct RowInfo {
     double x[4];      // lead lag coordinates
     const double2* w;  // What row
+    int64_t wr;       // flat index of the row over the leading axes
     double rw;        // row weight (0 = no row)
 };
 
@@ -101,21 +119,22 @@ __device__ __forceinline__ RowInfo row_info(int64_t row, int64_t rend, const Row
     RowInfo ri;
     ri.x[0] = ri.x[1] = ri.x[2] = ri.x[3] = 0.0;
     ri.w = W;
+    ri.wr = 0;
     ri.rw = 0.0;
     if (row >= rend) return ri;
     if constexpr (D == 1) {
         ri.rw = 1.0;
     } else {
-        int64_t rem = row;
+        int rem = (int)row;  // rows < 2^31 for every supported grid
         int lag[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int k = D - 2; k >= 1; --k) {
-            const int64_t E = 2 * geo.M[k] - 1;
-            const int64_t c = rem % E;
+            const int E = 2 * geo.M[k] - 1;
+            const int c = rem % E;
             rem /= E;
-            lag[k] = (int)c - (geo.M[k] - 1);
+            lag[k] = c - (geo.M[k] - 1);
         }
-        lag[0] = (int)rem;
+        lag[0] = rem;
         int64_t wr = 0;
 #pragma unroll
         for (int k = 0; k < D - 1; ++k) {
@@ -124,6 +143,7 @@ __device__ __forceinline__ RowInfo row_info(int64_t row, int64_t rend, const Row
             ri.x[k] = delta[k] * (double)lag[k];
         }
         ri.w = W + wr * geo.Q;
+        ri.wr = wr;
         ri.rw = lag[0] == 0 ? 1.0 : 2.0;
     }
     return ri;
@@ -147,12 +167,12 @@ __device__ __forceinline__ void gen_point(const Fun& f, const RowInfo& ri, int p
 }
 
 template <int D, int N, class Fun, int RPW, int WPB, int SCHED>
-__global__ __launch_bounds__(WPB * 64, 2) void k_rows(const double* __restrict__ prm, RowGeom geo, int64_t nitems,
+__global__ __launch_bounds__(WPB * 64) void k_rows(const double* __restrict__ prm, RowGeom geo, int64_t nitems,
                                                    double* __restrict__ partial, const double2* __restrict__ tw) {
     constexpr int NG = Fun::NG;
     constexpr int NPEN = (NG + 1) / 2;
     constexpr int NPW = RPW * NPEN;
-    constexpr int PS = N + 1;
+    constexpr int PS = N;
     constexpr int R1 = next_radix(N, SCHED);
     constexpr int NB1 = N / R1;
     constexpr bool FUSE1 = NPEN * R1 <= 16;
@@ -242,9 +262,9 @@ __global__ __launch_bounds__(WPB * 64, 2) void k_rows(const double* __restrict__
 #pragma unroll
                             for (int gp = 0; gp < NPEN; ++gp) {
                                 dft<R1, -1>(a[gp]);
-                                double2* dst = pen + (rr * NPEN + gp) * PS + i * R1;
+                                double2* dst = pen + (rr * NPEN + gp) * PS;
 #pragma unroll
-                                for (int m = 0; m < R1; ++m) dst[m] = a[gp][m];
+                                for (int m = 0; m < R1; ++m) dst[swz(i * R1 + m)] = a[gp][m];
                             }
                         }
                     }
@@ -257,7 +277,7 @@ __global__ __launch_bounds__(WPB * 64, 2) void k_rows(const double* __restrict__
                         gen_point<D, N>(f, rtab[rr], p, M_last, delta, vals);
 #pragma unroll
                         for (int gp = 0; gp < NPEN; ++gp)
-                            pen[(rr * NPEN + gp) * PS + p] =
+                            pen[(rr * NPEN + gp) * PS + swz(p)] =
                                 make_double2(vals[2 * gp], (2 * gp + 1 < NG) ? vals[2 * gp + 1] : 0.0);
                     }
                     wave_sync();
@@ -286,10 +306,10 @@ __global__ __launch_bounds__(WPB * 64, 2) void k_rows(const double* __restrict__
                                 }
 #pragma unroll
                                 for (int gp = 0; gp < NPEN; ++gp) {
-                                    const double2* src = pen + (rr * NPEN + gp) * PS + i;
+                                    const double2* src = pen + (rr * NPEN + gp) * PS;
                                     double2 a[RL];
 #pragma unroll
-                                    for (int m = 0; m < RL; ++m) a[m] = src[m * NB];
+                                    for (int m = 0; m < RL; ++m) a[m] = src[swz(i + m * NB)];
 #pragma unroll
                                     for (int m = 1; m < RL; ++m) a[m] = c_mul(a[m], tw[m * i * TWS]);
                                     dft<RL, -1>(a);
@@ -319,6 +339,95 @@ __global__ __launch_bounds__(WPB * 64, 2) void k_rows(const double* __restrict__
     }
 }
 
+// Lag-domain evaluation of the same sums (variant 3): with the prepared
+// count autocorrelation A (times prod P, circular layout),
+//     sum_w |C|^2 K = prod P * sum_l k(l) A(l),
+// so each candidate needs no transform at all: every thread generates kernel
+// values at its lags and accumulates k_g(l) A(l).  The same half set of rows
+// (l_0 >= 0, mirror rows counted twice) is used.
+template <int D, int N, class Fun, int NT>
+__global__ __launch_bounds__(NT) void k_lag(const double* __restrict__ prm, RowGeom geo, int64_t nitems,
+                                            double* __restrict__ partial) {
+    constexpr int NG = Fun::NG;
+    constexpr int RPP = N >= NT ? 1 : NT / N;  // rows per pass
+    constexpr int PPT = N >= NT ? N / NT : 1;  // points per thread per row
+    __shared__ double red[(NT / 64) * NG];
+    for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int64_t h = item / geo.nchunks;
+        const int64_t ch = item - h * geo.nchunks;
+        const double* pr = prm + h * PRM;
+        Fun f;
+        f.load(pr);
+        double delta[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) delta[k] = pr[S_DELTA + k];
+        const double* __restrict__ A =
+            reinterpret_cast<const double*>(static_cast<uintptr_t>(__double_as_longlong(pr[S_ALAG])));
+        const int M_last = geo.M[D - 1];
+        double acc[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) acc[g] = 0.0;
+        const int64_t rbeg = ch * geo.chunk;
+        const int64_t rend = rbeg + geo.chunk < geo.nrows ? rbeg + geo.chunk : geo.nrows;
+        const int rr = N >= NT ? 0 : (int)threadIdx.x / N;
+        for (int64_t r0 = rbeg; r0 < rend; r0 += RPP) {
+            const RowInfo ri = row_info<D>(r0 + rr, rend, geo, delta, nullptr);
+            if (ri.rw == 0.0) continue;
+            const double* __restrict__ Arow = A + ri.wr * N;
+#pragma unroll
+            for (int t = 0; t < PPT; ++t) {
+                const int p = N >= NT ? (int)threadIdx.x + t * NT : (int)threadIdx.x - rr * N;
+                int lag = 0;
+                if (!lag_of(p, M_last, N, &lag)) continue;
+                double x[D];
+#pragma unroll
+                for (int k = 0; k < D - 1; ++k) x[k] = ri.x[k];
+                x[D - 1] = delta[D - 1] * (double)lag;
+                double vals[NG];
+                f.eval(x, vals);
+                const double a = ri.rw * Arow[p];
+#pragma unroll
+                for (int g = 0; g < NG; ++g) acc[g] += vals[g] * a;
+            }
+        }
+        double outv[NG];
+        block_sum<NG, NT>(acc, red, outv);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int g = 0; g < NG; ++g) partial[item * NG + g] = outv[g];
+        }
+    }
+}
+
+template <int D, int N, class Fun>
+hipError_t run_lag_t(const double* prm, RowGeom geo, int64_t nitems, double* partial, int grid_blocks,
+                     hipStream_t s) {
+    constexpr int NT = 256;
+    auto kern = k_lag<D, N, Fun, NT>;
+    int64_t blocks = nitems;
+    if (grid_blocks > 0) {
+        blocks = grid_blocks;
+    } else if (grid_blocks == 0) {
+        static int resident = -1;
+        if (resident < 0) {
+            int per_cu = 0, dev = 0, cus = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0) != hipSuccess) per_cu = 1;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+                cus = 256;
+            resident = (per_cu < 1 ? 1 : per_cu) * cus;
+        }
+        blocks = resident;
+    }
+    if (blocks > nitems) blocks = nitems;
+    if (blocks < 1) return hipSuccess;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(NT), 0, s, prm, geo, nitems, partial);
+    return hipGetLastError();
+}
+
+template <int N>
+constexpr int lag_rows_per_pass() { return N >= 256 ? 1 : 256 / N; }
+
 // Rows per wavefront per pass: enough butterflies for one per lane in a radix-8
 // stage (variant 0, 2) or twice that (variant 1); at most 8.
 template <int N, int NG, int VAR>
@@ -333,7 +442,7 @@ constexpr int rows_for() {
 // Wavefronts per block: as many (<= 4) as fit 96 KiB of pencils.
 template <int N, int NG, int RPW>
 constexpr int waves_for() {
-    constexpr int per = RPW * ((NG + 1) / 2) * (N + 1) * 16;
+    constexpr int per = RPW * ((NG + 1) / 2) * N * 16;
     return per * 4 <= 98304 ? 4 : (per * 2 <= 98304 ? 2 : 1);
 }
 

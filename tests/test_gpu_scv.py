@@ -161,7 +161,7 @@ def test_launch_variants_agree(kf, gpu):
     N = ds.grid.P[d - 1]
     ref = None
     try:
-        for var in range(3):
+        for var in range(4):
             for gb in (0, -1, 7):
                 kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, var, gb)
                 obj, g = kf.scv([ds], v)
@@ -221,3 +221,49 @@ def test_psi_batch(kf, gpu):
         A = binned.autocorr_direct(linbin.counts_to_real(co))
         want = binned.psi(A, Xs[j].shape[0], g_o, Gs[j], r)
         np.testing.assert_allclose(out[j], want, rtol=1e-10, atol=1e-12 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("name", ["d1", "d2_ragged", "d3", "d4"])
+def test_every_variant_vs_oracle(kf, gpu, name, variant):
+    """Each compiled launch variant (three spectral, one lag-domain) against the
+    oracle, for the objective+gradient, objective-only and adjoint families."""
+    d, X, Gp, M, H, _ = _setup(name, gpu)
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
+    N = ds.grid.P[d - 1]
+    v = torch.from_numpy(_vech(H)).to(gpu)
+    kinds = (kf.FUN_SCV_OBJ, kf.FUN_SCV_OBJGRAD, kf.FUN_SCV_GRAD)
+    try:
+        for k in kinds:
+            kf.set_row_launch(k, d, 2, N, variant, 0)
+        obj, g = kf.scv([ds], v)
+        obj_only = kf.scv([ds], v, grad=False)
+        w = torch.ones(H.shape[0], dtype=torch.float64, device=gpu)
+        adj = kf.scv_adjoint([ds], v, w)
+    finally:
+        for k in kinds:
+            kf.set_row_launch(k, d, 2, N, 0, 0)
+    obj, g = obj.cpu().numpy(), g.cpu().numpy()
+    _check_against_oracle(kf, name, d, X, Gp, M, H, obj, g)
+    np.testing.assert_allclose(obj_only.cpu().numpy(), obj, rtol=1e-13)
+    np.testing.assert_allclose(adj.cpu().numpy(), g, rtol=1e-11, atol=1e-12 * np.abs(g).max())
+
+
+@pytest.mark.parametrize("variant", [0, 3])
+def test_psi_batch_variants(kf, gpu, variant):
+    d, M, r = 3, 14, 4
+    X = mixture_sample(2500, d, 950)
+    Gp = spd(d, 951, 0.05)
+    Gpsi = spd(d, 952, 0.08)
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
+    N = ds.grid.P[d - 1]
+    try:
+        kf.set_row_launch(kf.FUN_PSI, d, r, N, variant, 0)
+        out = kf.psi_batch([ds], [Gpsi], r).cpu().numpy()[0]
+    finally:
+        kf.set_row_launch(kf.FUN_PSI, d, r, N, 0, 0)
+    g_o = grid.plan_auto(X, Gp, [M] * d)
+    co, _ = linbin.linbin(X, g_o)
+    A = binned.autocorr_direct(linbin.counts_to_real(co))
+    want = binned.psi(A, X.shape[0], g_o, Gpsi, r)
+    np.testing.assert_allclose(out, want, rtol=1e-10, atol=1e-11 * np.abs(want).max())
