@@ -78,7 +78,9 @@ def algorithmic_flops_per_candidate(M, N, d=2, variant=0):
     real grids packed two per transform) at 5 N log2 N flops each and the
     contraction over the full last axis, 8 flops per complex multiply-add per
     transform.  Lag form (variant 3), per lag: one multiply-add per grid
-    against the autocorrelation (4 grids, 2 flops each)."""
+    against the autocorrelation (4 grids, 2 flops each).  Generation is
+    charged at its direct-evaluation cost in both forms (the lag kernel's
+    exponential recurrence does fewer operations for the same work)."""
     gen = (2 * M - 1) * gen_flops_per_lag(d)
     if variant == 3:
         return M * (gen + (2 * M - 1) * 2 * 4)

@@ -273,15 +273,11 @@ DsLayout carve_dataset(Arena& a, const kdefft_grid& g) {
 }
 
 struct PrepScratch {
-    double* czp;
-    double2* tmp;
     double* prm;
     double* partial;
 };
 PrepScratch carve_prepare(Arena& a, const kdefft_grid& g) {
     PrepScratch p;
-    p.czp = a.take<double>(sizes_of(g).prodP);
-    p.tmp = a.take<double2>(sizes_of(g).spec);
     p.prm = a.take<double>(PRM);
     p.partial = a.take<double>(max_nchunks(g, FUN_PSI, 0, 1));
     return p;
@@ -396,10 +392,10 @@ PsiBatchArgs psi_args(const kdefft_grid& g, int r, int n_ds, const DsDev* const*
 // Prepare a dataset whose buffers are described by L (in a caller buffer or workspace).
 int prepare_into(const double* X, int64_t n, const kdefft_grid& g, const double* Gpilot, const DsLayout& L,
                  const PrepScratch& p, bool with_const, hipStream_t s) {
-    int rc = bin_and_fill(X, n, g, L.counts, L.n_out, p.czp, s);
+    int rc = bin_and_fill(X, n, g, L.counts, L.n_out, nullptr, s);
     if (rc) return rc;
-    HIPCHK(fft_prepare_nd(p.czp, L.spec, L.wmix, g, s), "count transform");
-    HIPCHK(fft_autocorr_nd(L.spec, p.tmp, L.alag, g, s), "count autocorrelation");
+    HIPCHK(fft_prepare_nd(L.counts, L.spec, L.wmix, g, s), "count transform");
+    HIPCHK(fft_autocorr_nd(L.wmix, L.alag, g, s), "count autocorrelation");
     DsDev rec{};
     rec.wmix = L.wmix;
     rec.alag = L.alag;
@@ -581,9 +577,15 @@ int kdefft_grid_auto(const double* X, int64_t n, int d, const double* G_host, co
     if (rc) return rc;
     hipStream_t s = S(stream);
     HIPCHK(launch_bounds(X, n, d, partial, (int)nb, dout, s), "bounds");
-    double host[8];
-    HIPCHK(hipMemcpyAsync(host, dout, sizeof(host), hipMemcpyDeviceToHost, s), "bounds readback");
+    // 8 doubles of pinned host memory per thread, allocated once, so the
+    // readback is a direct DMA rather than a staged pageable copy
+    static thread_local double* pinned = nullptr;
+    if (!pinned) HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&pinned), 8 * sizeof(double), hipHostMallocDefault),
+                        "pinned readback buffer");
+    HIPCHK(hipMemcpyAsync(pinned, dout, 8 * sizeof(double), hipMemcpyDeviceToHost, s), "bounds readback");
     HIPCHK(hipStreamSynchronize(s), "bounds sync");
+    double host[8];
+    for (int k = 0; k < 8; ++k) host[k] = pinned[k];
     double lo[4], hi[4];
     for (int k = 0; k < d; ++k) {
         const double sd = std::sqrt(G_host[k * d + k]);

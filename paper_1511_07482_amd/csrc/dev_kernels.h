@@ -96,11 +96,18 @@ __device__ __forceinline__ void herm_all(const double* z, const double* P, doubl
     ((he[B + 1] = herm_one<D, R, B + 1>(z, P, he, std::make_integer_sequence<int, D>{})), ...);
 }
 
+// Every family below is a combination of NGAUSS Gaussians phi_{S_k}: at a lag
+// x it needs z_k = S_k^{-1} x and e_k = c_k exp(-x.z_k / 2), then combines
+// them (combine()).  eval() does it directly; the lag-domain kernel instead
+// walks z_k and e_k along the last axis by exact recurrences.
+
 // psi_r family: the NU unique D^alpha phi_G, |alpha| = R, canonical order.
-// Parameters: P = G^{-1} at prm[0..D*D), c = (-1)^R (2 pi)^{-D/2} |G|^{-1/2} at prm[16].
+// Parameters: P = G^{-1} at prm[0..) (row stride 4), c = (2 pi)^{-D/2} |G|^{-1/2}
+// at prm[16] (the sign (-1)^R is +1 for even R).
 template <int D, int R>
 struct PsiFun {
     static constexpr int NG = HermTab<D, R>::NU;
+    static constexpr int NGAUSS = 1;
     double P[D * D];
     double c;
     __device__ __forceinline__ void load(const double* prm) {
@@ -108,29 +115,21 @@ struct PsiFun {
         for (int i = 0; i < D * D; ++i) P[i] = prm[S_P1 + (i / D) * 4 + (i % D)];
         c = prm[S_C];
     }
-    __device__ __forceinline__ void eval(const double* x, double* out) const {
-        double z[D];
-        double q = 0.0;
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            double s = 0.0;
-#pragma unroll
-            for (int j = 0; j < D; ++j) s += P[i * D + j] * x[j];
-            z[i] = s;
-            q += x[i] * s;
-        }
-        const double e = c * exp(-0.5 * q);
+    __device__ __forceinline__ const double* Pm(int) const { return P; }
+    __device__ __forceinline__ double cn(int) const { return c; }
+    __device__ __forceinline__ void combine(const double (*z)[D], const double* e, double* out) const {
         if constexpr (R == 0) {
-            out[0] = e;
+            out[0] = e[0];
         } else {
             using T = HermTab<D, R>;
             double he[T::NB];
             he[0] = 1.0;
-            herm_all<D, R>(z, P, he, std::make_integer_sequence<int, T::NB - 1>{});
+            herm_all<D, R>(z[0], P, he, std::make_integer_sequence<int, T::NB - 1>{});
 #pragma unroll
-            for (int u = 0; u < T::NU; ++u) out[u] = he[T::NB - T::NU + u] * e;
+            for (int u = 0; u < T::NU; ++u) out[u] = he[T::NB - T::NU + u] * e[0];
         }
     }
+    __device__ __forceinline__ void eval(const double* x, double* out) const;
 };
 
 // SCV families with S1 = 2H + 2G, S2 = H + 2G (P1, P2 their inverses, c1, c2
@@ -143,6 +142,7 @@ template <int D, int MODE>
 struct ScvFun {
     static constexpr int NQ = D * (D + 1) / 2;
     static constexpr int NG = MODE == 0 ? 1 : (MODE == 1 ? 1 + NQ : NQ);
+    static constexpr int NGAUSS = 2;
     double P1[D * D], P2[D * D];
     double c1, c2;
     __device__ __forceinline__ void load(const double* prm) {
@@ -154,35 +154,52 @@ struct ScvFun {
         c1 = prm[S_C1];
         c2 = prm[S_C2];
     }
-    __device__ __forceinline__ void eval(const double* x, double* out) const {
-        double z1[D], z2[D];
-        double q1 = 0.0, q2 = 0.0;
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                s1 += P1[i * D + j] * x[j];
-                s2 += P2[i * D + j] * x[j];
-            }
-            z1[i] = s1;
-            z2[i] = s2;
-            q1 += x[i] * s1;
-            q2 += x[i] * s2;
-        }
-        const double e1 = c1 * exp(-0.5 * q1);
-        const double e2 = c2 * exp(-0.5 * q2);
+    __device__ __forceinline__ const double* Pm(int k) const { return k == 0 ? P1 : P2; }
+    __device__ __forceinline__ double cn(int k) const { return k == 0 ? c1 : c2; }
+    __device__ __forceinline__ void combine(const double (*z)[D], const double* e, double* out) const {
         int o = 0;
-        if constexpr (MODE != 2) out[o++] = e1 - 2.0 * e2;
+        if constexpr (MODE != 2) out[o++] = e[0] - 2.0 * e[1];
         if constexpr (MODE != 0) {
 #pragma unroll
             for (int i = 0; i < D; ++i)
 #pragma unroll
                 for (int j = i; j < D; ++j)
-                    out[o++] = e1 * (z1[i] * z1[j] - P1[i * D + j]) - e2 * (z2[i] * z2[j] - P2[i * D + j]);
+                    out[o++] = e[0] * (z[0][i] * z[0][j] - P1[i * D + j]) - e[1] * (z[1][i] * z[1][j] - P2[i * D + j]);
         }
     }
+    __device__ __forceinline__ void eval(const double* x, double* out) const;
 };
+
+// Direct evaluation at one lag x.
+template <class Fun, int D>
+__device__ __forceinline__ void eval_direct(const Fun& f, const double* x, double* out) {
+    double z[Fun::NGAUSS][D];
+    double e[Fun::NGAUSS];
+#pragma unroll
+    for (int k = 0; k < Fun::NGAUSS; ++k) {
+        const double* P = f.Pm(k);
+        double q = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) s += P[i * D + j] * x[j];
+            z[k][i] = s;
+            q += x[i] * s;
+        }
+        e[k] = f.cn(k) * exp(-0.5 * q);
+    }
+    f.combine(z, e, out);
+}
+
+template <int D, int R>
+__device__ __forceinline__ void PsiFun<D, R>::eval(const double* x, double* out) const {
+    eval_direct<PsiFun<D, R>, D>(*this, x, out);
+}
+template <int D, int MODE>
+__device__ __forceinline__ void ScvFun<D, MODE>::eval(const double* x, double* out) const {
+    eval_direct<ScvFun<D, MODE>, D>(*this, x, out);
+}
 
 // Plain-path SCV grids: entry 0 is the whole objective kernel
 // phi_{S1} - 2 phi_{S2} + phi_{S3} (S3 = 2G), entries 1..q the Hessian grids.

@@ -71,22 +71,79 @@ hipError_t twiddles(const double2** out) {
 }
 
 // ------------------------------------------------------------------ last axis
+// Optional input maps of the last-axis passes.
+//  * CountSrc: the R2C input row is read straight from the int64 grid counts
+//    (c = count 2^-40 at [0, M)^d of the circular layout, zero elsewhere), so
+//    the zero-padded real array is never materialised.
+//  * RowFlip: the C2R pass reads input row -l' (each leading index negated
+//    modulo P) for output row l'.
+struct CountSrc {
+    const int64_t* counts;  // nullptr: read the real input array
+    int d;
+    int M[4];
+    int P[4];
+};
+struct RowFlip {
+    int on;
+    int nlead;
+    int P[3];
+};
+
+__device__ __forceinline__ int64_t flip_row(int64_t r, const RowFlip& f) {
+    int64_t out = 0, mul = 1;
+    for (int k = f.nlead - 1; k >= 0; --k) {
+        const int64_t i = r % f.P[k];
+        r /= f.P[k];
+        out += ((f.P[k] - i) % f.P[k]) * mul;
+        mul *= f.P[k];
+    }
+    return out;
+}
+
 // Rows per block for a last-axis pass of real length N.
 template <int N>
 constexpr int last_rows() { return (N / 2) >= 2048 ? 1 : 2048 / (N / 2); }
 
-template <int N, int NT>
+template <int N, int NT, int ROWS>
 __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, double2* __restrict__ out,
-                                                 int64_t rows, const double2* __restrict__ tw) {
-    constexpr int H = N / 2, Q = H + 1, ROWS = last_rows<N>();
+                                                 int64_t rows, const double2* __restrict__ tw, CountSrc cs) {
+    constexpr int H = N / 2, Q = H + 1;
     constexpr int PS = H + 1;
     __shared__ double2 buf[ROWS * PS];
     const int64_t r0 = (int64_t)blockIdx.x * ROWS;
     const double2* src = reinterpret_cast<const double2*>(in);
-    for (int e = threadIdx.x; e < ROWS * H; e += NT) {
-        const int rr = e / H, m = e - rr * H;
-        const int64_t row = r0 + rr;
-        buf[rr * PS + m] = row < rows ? src[row * H + m] : make_double2(0.0, 0.0);
+    if (cs.counts) {
+        const double quantum = 9.094947017729282379150390625e-13;  // 2^-40
+        const int Ml = cs.M[cs.d - 1];
+        for (int e = threadIdx.x; e < ROWS * H; e += NT) {
+            const int rr = e / H, m = e - rr * H;
+            const int64_t row = r0 + rr;
+            double2 v = make_double2(0.0, 0.0);
+            if (row < rows) {
+                int64_t rem = row, cf = 0, mul = 1;
+                bool ok = true;
+                for (int k = cs.d - 2; k >= 0; --k) {
+                    const int i = (int)(rem % cs.P[k]);
+                    rem /= cs.P[k];
+                    ok = ok && i < cs.M[k];
+                    cf += i * mul;
+                    mul *= cs.M[k];
+                }
+                if (ok) {
+                    const int64_t base = cf * Ml;
+                    const int p0 = 2 * m, p1 = 2 * m + 1;
+                    if (p0 < Ml) v.x = (double)cs.counts[base + p0] * quantum;
+                    if (p1 < Ml) v.y = (double)cs.counts[base + p1] * quantum;
+                }
+            }
+            buf[rr * PS + m] = v;
+        }
+    } else {
+        for (int e = threadIdx.x; e < ROWS * H; e += NT) {
+            const int rr = e / H, m = e - rr * H;
+            const int64_t row = r0 + rr;
+            buf[rr * PS + m] = row < rows ? src[row * H + m] : make_double2(0.0, 0.0);
+        }
     }
     __syncthreads();
     fft_lds<H, ROWS, NT, -1>(buf, PS, tw);
@@ -103,17 +160,18 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
     }
 }
 
-template <int N, int NT>
+template <int N, int NT, int ROWS>
 __global__ __launch_bounds__(NT) void k_c2r_last(const double2* __restrict__ in, double* __restrict__ out,
-                                                 int64_t rows, const double2* __restrict__ tw) {
-    constexpr int H = N / 2, Q = H + 1, ROWS = last_rows<N>();
+                                                 int64_t rows, const double2* __restrict__ tw, RowFlip fl) {
+    constexpr int H = N / 2, Q = H + 1;
     constexpr int PS = H + 1;
     __shared__ double2 buf[ROWS * PS];
     const int64_t r0 = (int64_t)blockIdx.x * ROWS;
     for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
         const int rr = e / Q, k = e - rr * Q;
         const int64_t row = r0 + rr;
-        buf[rr * PS + k] = row < rows ? in[row * Q + k] : make_double2(0.0, 0.0);
+        const int64_t src_row = fl.on ? flip_row(row, fl) : row;
+        buf[rr * PS + k] = row < rows ? in[src_row * Q + k] : make_double2(0.0, 0.0);
     }
     __syncthreads();
     constexpr int PER = (ROWS * H + NT - 1) / NT;
@@ -160,11 +218,10 @@ constexpr int tile_cols() {
 // MODE 0: in-place transform.  MODE 1: forward transform stored in place
 // (the finished count spectrum C), then |C|^2 transformed forward again and
 // stored to out2.
-template <int N, int NT, int DIR, int MODE>
+template <int N, int NT, int DIR, int MODE, int T>
 __global__ __launch_bounds__(NT) void k_c2c_strided(double2* __restrict__ buf, double2* __restrict__ out2,
                                                     int64_t inner, int64_t tiles,
                                                     const double2* __restrict__ tw) {
-    constexpr int T = tile_cols<N>();
     constexpr int PS = T > 1 ? N + 1 : N;
     __shared__ double2 lds[T * PS];
     const int64_t o = blockIdx.x / tiles;
@@ -208,32 +265,67 @@ __global__ void k_abs2(const double2* __restrict__ in, double2* __restrict__ out
 // ------------------------------------------------------------------ dispatch
 static int ilog2i(int n) { int k = 0; while ((1 << k) < n) ++k; return k; }
 
+// Launch shapes.  Default: ~2048 complex values per block (256 threads).
+// Small problems (fewer than ~512 blocks at the default shape) use one
+// wavefront per block with one or two pencils, so more CUs take part.
+constexpr int64_t kMinBlocks = 512;
+
 template <int N>
-static hipError_t run_r2c_last(const double* in, double2* out, int64_t rows, const double2* tw, hipStream_t s) {
+constexpr int small_rows() { return (N / 2) >= 512 ? 1 : ((512 / (N / 2)) > 16 ? 16 : 512 / (N / 2)); }
+
+template <int N>
+static hipError_t run_r2c_last(const double* in, double2* out, int64_t rows, const double2* tw, hipStream_t s,
+                               CountSrc cs) {
     constexpr int ROWS = last_rows<N>();
-    const int64_t blocks = (rows + ROWS - 1) / ROWS;
-    hipLaunchKernelGGL((k_r2c_last<N, 256>), dim3((unsigned)blocks), dim3(256), 0, s, in, out, rows, tw);
+    constexpr int RS = small_rows<N>();
+    if ((rows + ROWS - 1) / ROWS < kMinBlocks && RS < ROWS) {
+        const int64_t blocks = (rows + RS - 1) / RS;
+        hipLaunchKernelGGL((k_r2c_last<N, 64, RS>), dim3((unsigned)blocks), dim3(64), 0, s, in, out, rows, tw, cs);
+    } else {
+        const int64_t blocks = (rows + ROWS - 1) / ROWS;
+        hipLaunchKernelGGL((k_r2c_last<N, 256, ROWS>), dim3((unsigned)blocks), dim3(256), 0, s, in, out, rows, tw,
+                           cs);
+    }
     return hipGetLastError();
 }
 template <int N>
-static hipError_t run_c2r_last(const double2* in, double* out, int64_t rows, const double2* tw, hipStream_t s) {
+static hipError_t run_c2r_last(const double2* in, double* out, int64_t rows, const double2* tw, hipStream_t s,
+                               RowFlip fl) {
     constexpr int ROWS = last_rows<N>();
-    const int64_t blocks = (rows + ROWS - 1) / ROWS;
-    hipLaunchKernelGGL((k_c2r_last<N, 256>), dim3((unsigned)blocks), dim3(256), 0, s, in, out, rows, tw);
+    constexpr int RS = small_rows<N>();
+    if ((rows + ROWS - 1) / ROWS < kMinBlocks && RS < ROWS) {
+        const int64_t blocks = (rows + RS - 1) / RS;
+        hipLaunchKernelGGL((k_c2r_last<N, 64, RS>), dim3((unsigned)blocks), dim3(64), 0, s, in, out, rows, tw, fl);
+    } else {
+        const int64_t blocks = (rows + ROWS - 1) / ROWS;
+        hipLaunchKernelGGL((k_c2r_last<N, 256, ROWS>), dim3((unsigned)blocks), dim3(256), 0, s, in, out, rows, tw,
+                           fl);
+    }
     return hipGetLastError();
 }
+
+template <int N, int NT, int T>
+static void launch_c2c_t(double2* buf, double2* out2, int64_t outer, int64_t inner, int dir, int mode,
+                         const double2* tw, hipStream_t s) {
+    const int64_t tiles = (inner + T - 1) / T;
+    const dim3 grid((unsigned)(outer * tiles));
+    if (mode == 1)
+        hipLaunchKernelGGL((k_c2c_strided<N, NT, -1, 1, T>), grid, dim3(NT), 0, s, buf, out2, inner, tiles, tw);
+    else if (dir < 0)
+        hipLaunchKernelGGL((k_c2c_strided<N, NT, -1, 0, T>), grid, dim3(NT), 0, s, buf, out2, inner, tiles, tw);
+    else
+        hipLaunchKernelGGL((k_c2c_strided<N, NT, 1, 0, T>), grid, dim3(NT), 0, s, buf, out2, inner, tiles, tw);
+}
+
 template <int N>
 static hipError_t run_c2c(double2* buf, double2* out2, int64_t outer, int64_t inner, int dir, int mode,
                           const double2* tw, hipStream_t s) {
     constexpr int T = tile_cols<N>();
-    const int64_t tiles = (inner + T - 1) / T;
-    const dim3 grid((unsigned)(outer * tiles));
-    if (mode == 1)
-        hipLaunchKernelGGL((k_c2c_strided<N, 256, -1, 1>), grid, dim3(256), 0, s, buf, out2, inner, tiles, tw);
-    else if (dir < 0)
-        hipLaunchKernelGGL((k_c2c_strided<N, 256, -1, 0>), grid, dim3(256), 0, s, buf, out2, inner, tiles, tw);
+    constexpr int TS = N >= 64 ? 1 : (64 / N > 16 ? 16 : 64 / N);  // one radix pass per lane
+    if (outer * ((inner + T - 1) / T) < kMinBlocks && TS < T)
+        launch_c2c_t<N, 64, TS>(buf, out2, outer, inner, dir, mode, tw, s);
     else
-        hipLaunchKernelGGL((k_c2c_strided<N, 256, 1, 0>), grid, dim3(256), 0, s, buf, out2, inner, tiles, tw);
+        launch_c2c_t<N, 256, T>(buf, out2, outer, inner, dir, mode, tw, s);
     return hipGetLastError();
 }
 
@@ -254,14 +346,16 @@ static hipError_t run_c2c(double2* buf, double2* out2, int64_t outer, int64_t in
         default: return hipErrorInvalidValue;                \
     }
 
-static hipError_t r2c_last(const double* in, double2* out, int64_t rows, int N, const double2* tw, hipStream_t s) {
-#define CALL(NN) run_r2c_last<NN>(in, out, rows, tw, s)
+static hipError_t r2c_last(const double* in, double2* out, int64_t rows, int N, const double2* tw, hipStream_t s,
+                           CountSrc cs = CountSrc{nullptr, 0, {0, 0, 0, 0}, {0, 0, 0, 0}}) {
+#define CALL(NN) run_r2c_last<NN>(in, out, rows, tw, s, cs)
     if (N < 4) return hipErrorInvalidValue;
     KDEFFT_SWITCH_N(ilog2i(N), CALL)
 #undef CALL
 }
-static hipError_t c2r_last(const double2* in, double* out, int64_t rows, int N, const double2* tw, hipStream_t s) {
-#define CALL(NN) run_c2r_last<NN>(in, out, rows, tw, s)
+static hipError_t c2r_last(const double2* in, double* out, int64_t rows, int N, const double2* tw, hipStream_t s,
+                           RowFlip fl = RowFlip{0, 0, {1, 1, 1}}) {
+#define CALL(NN) run_c2r_last<NN>(in, out, rows, tw, s, fl)
     if (N < 4) return hipErrorInvalidValue;
     KDEFFT_SWITCH_N(ilog2i(N), CALL)
 #undef CALL
@@ -322,12 +416,17 @@ hipError_t fft_c2r_nd(double2* inout, double* out, const kdefft_grid& g, hipStre
     return c2r_last(inout, out, lead_count(g), g.P[g.d - 1], tw, s);
 }
 
-hipError_t fft_prepare_nd(const double* czp, double2* spec, double2* wmix, const kdefft_grid& g,
+hipError_t fft_prepare_nd(const int64_t* counts, double2* spec, double2* wmix, const kdefft_grid& g,
                           hipStream_t s) {
     const double2* tw;
     hipError_t e = twiddles(&tw);
     if (e != hipSuccess) return e;
-    e = r2c_last(czp, spec, lead_count(g), g.P[g.d - 1], tw, s);
+    CountSrc cs{counts, g.d, {1, 1, 1, 1}, {1, 1, 1, 1}};
+    for (int k = 0; k < g.d; ++k) {
+        cs.M[k] = g.M[k];
+        cs.P[k] = g.P[k];
+    }
+    e = r2c_last(nullptr, spec, lead_count(g), g.P[g.d - 1], tw, s, cs);
     if (e != hipSuccess) return e;
     if (g.d == 1) {
         const int64_t cnt = g.P[0] / 2 + 1;
@@ -353,14 +452,15 @@ hipError_t fft_prepare_nd(const double* czp, double2* spec, double2* wmix, const
     return e;
 }
 
-hipError_t fft_autocorr_nd(const double2* spec, double2* tmp, double* alag, const kdefft_grid& g, hipStream_t s) {
-    const int64_t cnt = lead_count(g) * (g.P[g.d - 1] / 2 + 1);
-    int64_t blocks = (cnt + 255) / 256;
-    if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_abs2, dim3((unsigned)blocks), dim3(256), 0, s, spec, tmp, cnt);
-    hipError_t e = hipGetLastError();
+hipError_t fft_autocorr_nd(const double2* wmix, double* alag, const kdefft_grid& g, hipStream_t s) {
+    const double2* tw;
+    hipError_t e = twiddles(&tw);
     if (e != hipSuccess) return e;
-    return fft_c2r_nd(tmp, alag, g, s);
+    // inverting |C|^2 along the leading axes = the forward transform (wmix)
+    // read at negated leading indices; then the last-axis inverse
+    RowFlip fl{g.d > 1 ? 1 : 0, g.d - 1, {1, 1, 1}};
+    for (int k = 0; k + 1 < g.d; ++k) fl.P[k] = g.P[k];
+    return c2r_last(wmix, alag, lead_count(g), g.P[g.d - 1], tw, s, fl);
 }
 
 }  // namespace kdefft

@@ -87,10 +87,12 @@ hipError_t fft_r2c_nd(const double* in, double2* out, const kdefft_grid& g, hipS
 hipError_t fft_c2r_nd(double2* inout, double* out, const kdefft_grid& g, hipStream_t s);
 // Count spectrum of a prepared dataset: spec = R2C(czp); wmix = |spec|^2
 // transformed forward along the leading axes.
-hipError_t fft_prepare_nd(const double* czp, double2* spec, double2* wmix, const kdefft_grid& g,
+// (the first pass reads the int64 counts directly)
+hipError_t fft_prepare_nd(const int64_t* counts, double2* spec, double2* wmix, const kdefft_grid& g,
                           hipStream_t s);
-// alag = C2R(|spec|^2) (prod P times the count autocorrelation); tmp: spectrum-sized scratch.
-hipError_t fft_autocorr_nd(const double2* spec, double2* tmp, double* alag, const kdefft_grid& g, hipStream_t s);
+// alag = inverse transform of |C|^2 = prod P times the count autocorrelation,
+// computed from the mixed spectrum (rows at negated leading indices).
+hipError_t fft_autocorr_nd(const double2* wmix, double* alag, const kdefft_grid& g, hipStream_t s);
 
 // Paper-literal path, one grid per launch.
 hipError_t launch_kgrid_psi(double* out, const kdefft_grid& g, int r, const ParamBlock& prm,

@@ -342,16 +342,24 @@ __global__ __launch_bounds__(WPB * 64) void k_rows(const double* __restrict__ pr
 // Lag-domain evaluation of the same sums (variant 3): with the prepared
 // count autocorrelation A (times prod P, circular layout),
 //     sum_w |C|^2 K = prod P * sum_l k(l) A(l),
-// so each candidate needs no transform at all: every thread generates kernel
-// values at its lags and accumulates k_g(l) A(l).  The same half set of rows
-// (l_0 >= 0, mirror rows counted twice) is used.
-template <int D, int N, class Fun, int NT>
+// so each candidate needs no transform at all.  The same half set of rows
+// (l_0 >= 0, mirror rows counted twice) is used.  Each thread walks a run of
+// RUN consecutive lags of one row.  Along the last axis every Gaussian's
+// exponent is quadratic in the lag, so with x advancing by dl = delta_last:
+//     z(l+1) = z(l) + dl S^{-1} e_last,
+//     e(l+1) = e(l) rho(l),  rho(l) = exp(-(dl z_last(l) + dl^2 P_ll / 2)),
+//     rho(l+1) = rho(l) sigma,  sigma = exp(-dl^2 P_ll),
+// which replaces RUN exponentials per Gaussian by two (each step adds a few
+// ulps of rounding).  A run whose start underflows or whose ratio is huge is
+// evaluated directly instead.
+template <int D, int N, class Fun, int NT, int RUN>
 __global__ __launch_bounds__(NT) void k_lag(const double* __restrict__ prm, RowGeom geo, int64_t nitems,
                                             double* __restrict__ partial) {
     constexpr int NG = Fun::NG;
-    constexpr int RPP = N >= NT ? 1 : NT / N;  // rows per pass
-    constexpr int PPT = N >= NT ? N / NT : 1;  // points per thread per row
+    constexpr int NGS = Fun::NGAUSS;
     __shared__ double red[(NT / 64) * NG];
+    const int M_last = geo.M[D - 1];
+    const int nrun = (2 * M_last - 1 + RUN - 1) / RUN;
     for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int64_t h = item / geo.nchunks;
         const int64_t ch = item - h * geo.nchunks;
@@ -363,31 +371,72 @@ __global__ __launch_bounds__(NT) void k_lag(const double* __restrict__ prm, RowG
         for (int k = 0; k < D; ++k) delta[k] = pr[S_DELTA + k];
         const double* __restrict__ A =
             reinterpret_cast<const double*>(static_cast<uintptr_t>(__double_as_longlong(pr[S_ALAG])));
-        const int M_last = geo.M[D - 1];
+        const double dl = delta[D - 1];
+        double dz[NGS][D], sig[NGS], hpl[NGS];
+#pragma unroll
+        for (int k = 0; k < NGS; ++k) {
+            const double* P = f.Pm(k);
+#pragma unroll
+            for (int i = 0; i < D; ++i) dz[k][i] = dl * P[i * D + D - 1];
+            hpl[k] = 0.5 * dl * dl * P[(D - 1) * D + D - 1];
+            sig[k] = exp(-2.0 * hpl[k]);
+        }
         double acc[NG];
 #pragma unroll
         for (int g = 0; g < NG; ++g) acc[g] = 0.0;
         const int64_t rbeg = ch * geo.chunk;
         const int64_t rend = rbeg + geo.chunk < geo.nrows ? rbeg + geo.chunk : geo.nrows;
-        const int rr = N >= NT ? 0 : (int)threadIdx.x / N;
-        for (int64_t r0 = rbeg; r0 < rend; r0 += RPP) {
-            const RowInfo ri = row_info<D>(r0 + rr, rend, geo, delta, nullptr);
-            if (ri.rw == 0.0) continue;
+        const int64_t total = (rend - rbeg) * nrun;
+        for (int64_t e = threadIdx.x; e < total; e += NT) {
+            const int64_t ro = e / nrun;
+            const int j = (int)(e - ro * nrun);
+            const RowInfo ri = row_info<D>(rbeg + ro, rend, geo, delta, nullptr);
             const double* __restrict__ Arow = A + ri.wr * N;
+            const int lag0 = -(M_last - 1) + j * RUN;
+            double x[D];
 #pragma unroll
-            for (int t = 0; t < PPT; ++t) {
-                const int p = N >= NT ? (int)threadIdx.x + t * NT : (int)threadIdx.x - rr * N;
-                int lag = 0;
-                if (!lag_of(p, M_last, N, &lag)) continue;
-                double x[D];
+            for (int k = 0; k < D - 1; ++k) x[k] = ri.x[k];
+            x[D - 1] = dl * (double)lag0;
+            double z[NGS][D], ev[NGS], rho[NGS];
+            bool direct = false;
 #pragma unroll
-                for (int k = 0; k < D - 1; ++k) x[k] = ri.x[k];
-                x[D - 1] = delta[D - 1] * (double)lag;
-                double vals[NG];
-                f.eval(x, vals);
-                const double a = ri.rw * Arow[p];
+            for (int k = 0; k < NGS; ++k) {
+                const double* P = f.Pm(k);
+                double q = 0.0;
 #pragma unroll
-                for (int g = 0; g < NG; ++g) acc[g] += vals[g] * a;
+                for (int i = 0; i < D; ++i) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int jj = 0; jj < D; ++jj) s += P[i * D + jj] * x[jj];
+                    z[k][i] = s;
+                    q += x[i] * s;
+                }
+                ev[k] = f.cn(k) * exp(-0.5 * q);
+                rho[k] = exp(-(dl * z[k][D - 1] + hpl[k]));
+                direct = direct || !(ev[k] >= 1e-290) || !(rho[k] <= 1e200);
+            }
+#pragma unroll
+            for (int t = 0; t < RUN; ++t) {
+                const int lag = lag0 + t;
+                if (lag <= M_last - 1) {
+                    double vals[NG];
+                    if (direct) {
+                        x[D - 1] = dl * (double)lag;
+                        eval_direct<Fun, D>(f, x, vals);
+                    } else {
+                        f.combine(z, ev, vals);
+                    }
+                    const double a = ri.rw * Arow[lag >= 0 ? lag : lag + N];
+#pragma unroll
+                    for (int g = 0; g < NG; ++g) acc[g] += vals[g] * a;
+                }
+#pragma unroll
+                for (int k = 0; k < NGS; ++k) {
+                    ev[k] *= rho[k];
+                    rho[k] *= sig[k];
+#pragma unroll
+                    for (int i = 0; i < D; ++i) z[k][i] += dz[k][i];
+                }
             }
         }
         double outv[NG];
@@ -399,11 +448,18 @@ __global__ __launch_bounds__(NT) void k_lag(const double* __restrict__ prm, RowG
     }
 }
 
+constexpr int LAG_RUN = 8;
+
+// Families whose combine step dominates (many Hermite outputs) gain nothing
+// from the exponential recurrence and lose registers to it: runs of one lag.
+template <class Fun>
+constexpr int lag_run_of() { return Fun::NG > 12 ? 1 : LAG_RUN; }
+
 template <int D, int N, class Fun>
 hipError_t run_lag_t(const double* prm, RowGeom geo, int64_t nitems, double* partial, int grid_blocks,
                      hipStream_t s) {
     constexpr int NT = 256;
-    auto kern = k_lag<D, N, Fun, NT>;
+    auto kern = k_lag<D, N, Fun, NT, lag_run_of<Fun>()>;
     int64_t blocks = nitems;
     if (grid_blocks > 0) {
         blocks = grid_blocks;
@@ -425,8 +481,9 @@ hipError_t run_lag_t(const double* prm, RowGeom geo, int64_t nitems, double* par
     return hipGetLastError();
 }
 
+// rows covered by one pass of a 256-thread block (runs of LAG_RUN lags)
 template <int N>
-constexpr int lag_rows_per_pass() { return N >= 256 ? 1 : 256 / N; }
+constexpr int lag_rows_per_pass() { return (256 * LAG_RUN) / N >= 1 ? (256 * LAG_RUN) / N : 1; }
 
 // Rows per wavefront per pass: enough butterflies for one per lane in a radix-8
 // stage (variant 0, 2) or twice that (variant 1); at most 8.

@@ -267,3 +267,21 @@ def test_psi_batch_variants(kf, gpu, variant):
     A = binned.autocorr_direct(linbin.counts_to_real(co))
     want = binned.psi(A, X.shape[0], g_o, Gpsi, r)
     np.testing.assert_allclose(out, want, rtol=1e-10, atol=1e-11 * np.abs(want).max())
+
+
+def test_narrow_kernels_recurrence_fallback(kf, gpu):
+    """Kernels much narrower than the bins: the far lags underflow, so the
+    lag-domain kernel's recurrence falls back to direct evaluation there."""
+    d, M = 2, 48
+    X = mixture_sample(1500, d, 990)
+    Gp = np.diag([2e-4, 3e-4])
+    H = np.stack([np.diag([1e-4, 2e-4]), np.array([[3e-4, 1e-4], [1e-4, 2e-4]]), np.eye(2) * 0.3])
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
+    v = torch.from_numpy(_vech(H)).to(gpu)
+    N = ds.grid.P[d - 1]
+    try:
+        kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, 3, 0)
+        obj, g = kf.scv([ds], v)
+    finally:
+        kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, 3, 0)
+    _check_against_oracle(kf, "narrow", d, X, Gp, M, H, obj.cpu().numpy(), g.cpu().numpy())
