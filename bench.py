@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--plain-h", type=int, default=16, help="candidates timed on the plain path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--launch", default=None, metavar="VARIANT,GRID",
+                    help="pin the SCV row launch (e.g. 3,-1) instead of tuning; used for counter runs")
     ap.add_argument("--cpu-h", type=int, default=48, help="candidates in the CPU oracle sample")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy (counter calibration for rocprofv3 --pmc runs)")
@@ -111,13 +113,16 @@ def main():
     X = torch.from_numpy(X_h).to(dev)
     vechL = torch.from_numpy(synth.vech_chol(H)).to(dev)
     tuned = None
-    variant = 3   # library default for untuned shapes
-    if not a.no_tune:
+    variant, grid_blocks = 3, 0   # library default for untuned shapes
+    if a.launch:
+        variant, grid_blocks = (int(x) for x in a.launch.split(","))
+        kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, max(4, 1 << (2 * M - 2).bit_length()), variant, grid_blocks)
+    elif not a.no_tune:
         ds0 = kf.Dataset(X, Gp, M=M)
         tuned = kf.autotune(ds0)
         for line in tuned.splitlines():
             if line.startswith("best: variant"):
-                variant = int(line.split()[2])
+                variant, grid_blocks = int(line.split()[2]), int(line.split()[4])
 
     def step():
         g = kf.grid_auto(X, Gp, M)
@@ -133,6 +138,8 @@ def main():
 
     # ---- timed region: exactly `steps` whole steps
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
+    # the library brackets each row-kernel launch with HIP events on its stream
+    kf.timing_start(4 * a.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(a.steps):
@@ -144,9 +151,14 @@ def main():
         ev[k][1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    recs = kf.timing_stop()
     sec_per_step = (t1 - t0) / a.steps
     value = B / sec_per_step
-    scv_ms = float(np.mean([s.elapsed_time(e) for s, e in ev]))
+    scv_call_ms = float(np.mean([s.elapsed_time(e) for s, e in ev]))
+    scv_k = [ms for ms, fam, r in recs if fam == kf.FUN_SCV_OBJGRAD]
+    psi_k = [ms for ms, fam, r in recs if fam == kf.FUN_PSI]
+    assert len(scv_k) == a.steps and len(psi_k) == a.steps, recs
+    scv_ms = float(np.mean(scv_k))
     assert torch.isfinite(obj).all() and torch.isfinite(grad).all()
 
     # ---- components outside the timed loop
@@ -187,14 +199,12 @@ def main():
                     best_us, spec_variant = us, int(p[1])
     kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, spec_variant, 0)
     kf.scv([ds], vechL)
-    es, ee = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    es.record(stream)
+    kf.timing_start(5)
     for _ in range(5):
         kf.scv([ds], vechL)
-    ee.record(stream)
     torch.cuda.synchronize()
-    spec_ms = es.elapsed_time(ee) / 5
-    kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, variant if tuned else 3, 0)
+    spec_ms = float(np.mean([ms for ms, fam, r in kf.timing_stop()]))
+    kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, variant, grid_blocks)
     hp = min(a.plain_h, B)
     kf.scv_plain(ds, H[0])
     torch.cuda.synchronize()
@@ -225,12 +235,17 @@ def main():
     if os.path.exists(prof):
         with open(prof) as fh:
             rec = json.load(fh)
+        # counters are kept per launch configuration (variant, grid) and only
+        # for the row-kernel sources they were taken on
         if rec.get("row_kernel_hash") == row_kernel_hash():
-            traffic = rec.get("hbm_bytes_per_launch")
-    kname = ("k_lag<2,512,ScvFun<2,1>,256>" if variant == 3 else f"k_rows<2,512,ScvFun<2,1>> variant {variant}")
+            ent = rec.get("launches", {}).get(f"{variant},{grid_blocks}")
+            if ent:
+                traffic = ent["hbm_bytes_per_launch"]
+    kname = ("k_lag<2,512,ScvFun<2,1>,256,8>" if variant == 3 else f"k_rows<2,512,ScvFun<2,1>> variant {variant}")
+    kname += " (grid: one block per work item)" if grid_blocks < 0 else " (grid: resident blocks)"
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic,
-                "kernel": kname + " (+ setup/final launches, <3%)", "launch_ms": scv_ms,
+                "kernel": kname, "launch_ms": scv_ms, "call_ms": scv_call_ms,
                 "flops_per_launch": flops, "variant": variant}
     fft_route = {"kernel": f"k_rows<2,512,ScvFun<2,1>> variant {spec_variant} (per-candidate last-axis FFTs in LDS)",
                  "launch_ms": spec_ms, "evals_per_s": B / (spec_ms * 1e-3), "flops_per_launch": spec_flops,
@@ -260,6 +275,8 @@ def main():
         "roofline": roofline,
         "fft_route_batched": fft_route,
         "cpu_baseline": cpu,
+        "row_kernels_in_timed_steps_ms": {"scv_objgrad_256": scv_ms, "psi4": float(np.mean(psi_k)),
+                                          "scv_call_with_setup_final": scv_call_ms},
         "components_ms": {"dataset_prepare": t_prep * 1e3, "psi4_batched": t_psi_batched * 1e3,
                           "scv_objgrad_batched_256": t_scv_only * 1e3, "scv_autograd_fwd_adjoint_256": t_autograd * 1e3,
                           "psi4_plain_with_binning": t_psi_plain * 1e3, "scv_plain_per_H": t_plain * 1e3,

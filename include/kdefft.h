@@ -249,12 +249,31 @@ int kdefft_scv_plain(const kdefft_dataset* ds_host, const double* H_host, double
  * Host only. */
 int kdefft_set_row_launch(int kind, int d, int r, int N, int variant, int grid_blocks);
 
+/* Measurement hook for the batched row kernels (the dominant launches of
+ * kdefft_psi, kdefft_psi_batch, kdefft_scv_batch, kdefft_scv_adjoint and
+ * kdefft_autotune).  kdefft_timing_start arms it for up to max_launches
+ * launches, max_launches in [1, KDEFFT_MAX_TIMED]: each of the next row-kernel
+ * launches, on any stream, is bracketed by a pair of HIP events recorded on
+ * that launch's stream (events are created once and reused; no device memory
+ * is allocated).  kdefft_timing_stop disarms, waits for the recorded events
+ * and writes, for the first min(recorded, cap) launches in launch order, the
+ * kernel's duration in milliseconds to ms_out[k] and a tag 16 * family + r to
+ * tag_out[k] (family: 0 psi_r, 1 SCV objective, 2 objective + gradient,
+ * 3 adjoint gradient); *count_out receives that number.  Stopping when not
+ * armed reports 0 launches.  One timer per process; calls from several threads
+ * are serialized. */
+#define KDEFFT_MAX_TIMED 4096
+int kdefft_timing_start(int max_launches);
+int kdefft_timing_stop(float* ms_out, int32_t* tag_out, int cap, int* count_out);
+
 /* Time the compiled launch variants of the batched kernels (rows per block
  * iteration / LDS footprint, radix schedule of the row transforms, persistent
  * grid size) for this dataset's grid shape on the current device, keep the
  * fastest for the rest of the process, and append the choice to cache_path
- * (one JSON object per line; NULL = no file).  Workspace: KDEFFT_OP_AUTOTUNE.
- * Synchronizes `stream`. */
+ * (one JSON object per line; NULL = no file).  Each launch is timed on 256
+ * candidates H = s G (s spread over [0.5, 8], G the dataset's matrix); the
+ * default (variant 3, grid 0) is kept unless another launch is more than 3%
+ * faster.  Workspace: KDEFFT_OP_AUTOTUNE.  Synchronizes `stream`. */
 int kdefft_autotune(const kdefft_dataset* ds_host, void* ws, size_t ws_bytes,
                     const char* cache_path, void* stream);
 

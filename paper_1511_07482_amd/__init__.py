@@ -24,7 +24,8 @@ from . import _lib
 from ._lib import FUN_PSI, FUN_SCV_GRAD, FUN_SCV_OBJ, FUN_SCV_OBJGRAD, Grid, KdefftError  # noqa: F401
 
 __all__ = ["Grid", "Dataset", "KdefftError", "grid_plan", "grid_auto", "linbin", "psi", "psi_batch", "scv",
-           "scv_adjoint", "scv_plain", "SCV", "unique_tuples", "autotune", "set_row_launch", "library_path"]
+           "scv_adjoint", "scv_plain", "SCV", "unique_tuples", "autotune", "set_row_launch", "library_path",
+           "timing_start", "timing_stop"]
 
 
 def library_path():
@@ -312,8 +313,23 @@ def set_row_launch(kind: int, d: int, r: int, N: int, variant: int, grid_blocks:
 
 
 def autotune(dataset: Dataset, cache_path: Optional[str] = None) -> str:
-    ws = _ws(dataset.grid, _lib.OP_AUTOTUNE, 2, 64, dataset.device)
+    ws = _ws(dataset.grid, _lib.OP_AUTOTUNE, 2, 256, dataset.device)
     arr = _ds_array([dataset])
     _lib.check(_L().kdefft_autotune(arr, _ptr(ws), ws.numel(), cache_path.encode() if cache_path else None,
                                     _stream(dataset.device)), "kdefft_autotune")
     return _L().kdefft_last_error_detail().decode()
+
+
+def timing_start(max_launches: int = 1024):
+    """Arm the row-kernel timer for the next `max_launches` batched row launches."""
+    _lib.check(_L().kdefft_timing_start(int(max_launches)), "kdefft_timing_start")
+
+
+def timing_stop(cap: int = _lib.MAX_TIMED):
+    """Disarm the timer; returns [(ms, family, r), ...] in launch order."""
+    import ctypes as C
+    ms = (C.c_float * cap)()
+    tag = (C.c_int32 * cap)()
+    cnt = C.c_int(0)
+    _lib.check(_L().kdefft_timing_stop(ms, tag, cap, C.byref(cnt)), "kdefft_timing_stop")
+    return [(float(ms[k]), int(tag[k]) // 16, int(tag[k]) % 16) for k in range(cnt.value)]

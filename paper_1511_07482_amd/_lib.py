@@ -16,6 +16,7 @@ PSI_PLAIN, PSI_FUSED = 0, 1
 FUN_PSI, FUN_SCV_OBJ, FUN_SCV_OBJGRAD, FUN_SCV_GRAD = range(4)
 MAX_BATCH_DS = 64
 MAX_PSI_DS = 32
+MAX_TIMED = 4096
 
 
 class Grid(C.Structure):
@@ -62,6 +63,8 @@ EXPORTS = {
                                    C.c_void_p]),
     "kdefft_set_row_launch": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "kdefft_autotune": (C.c_int, [C.POINTER(Dataset), C.c_void_p, C.c_size_t, C.c_char_p, C.c_void_p]),
+    "kdefft_timing_start": (C.c_int, [C.c_int]),
+    "kdefft_timing_stop": (C.c_int, [C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int)]),
 }
 
 _lib = None

@@ -19,6 +19,9 @@ using namespace kdefft;
 
 namespace {
 
+// Candidates per timed launch in kdefft_autotune.
+constexpr int TUNE_B = 256;
+
 thread_local std::string g_err;
 
 int fail(int code, const char* fmt, ...) {
@@ -350,11 +353,11 @@ int plan_bytes(const kdefft_grid& g, int op, int r, int64_t batch, Arena& a) {
             return KDEFFT_OK;
         case KDEFFT_OP_SCV_PLAIN: carve_plain(a, g, false); return KDEFFT_OK;
         case KDEFFT_OP_AUTOTUNE: {
-            carve_batch(a, g, FUN_SCV_OBJGRAD, 2, 64);
+            carve_batch(a, g, FUN_SCV_OBJGRAD, 2, TUNE_B);
             const int q = g.d * (g.d + 1) / 2;
-            a.take<double>(64 * q);
-            a.take<double>(64);
-            a.take<double>(64 * q);
+            a.take<double>(TUNE_B * q);
+            a.take<double>(TUNE_B);
+            a.take<double>(TUNE_B * q);
             return KDEFFT_OK;
         }
         default: return fail(KDEFFT_E_ARG, "unknown op %d", op);
@@ -461,6 +464,35 @@ int check_batch_ds(const kdefft_dataset* ds, int n_ds, int max_ds) {
         if (rc) return rc;
     }
     return KDEFFT_OK;
+}
+
+
+// Row-kernel timing: while armed, every row-kernel launch is bracketed by a
+// pair of HIP events on its own stream, so the kernel's duration can be read
+// afterwards without synchronizing in between.
+struct RowTimer {
+    std::mutex mu;
+    bool armed = false;
+    int cap = 0;
+    int used = 0;
+    std::vector<hipEvent_t> ev;  // 2 per record, created once and reused
+    std::vector<int32_t> tag;
+};
+RowTimer g_timer;
+
+hipError_t timed_rows(int kind, int d, int r, const RowGeom& geo, const double* prm, int64_t ncand,
+                      double* partial, const RowLaunch& rl, hipStream_t s) {
+    std::unique_lock<std::mutex> lk(g_timer.mu);
+    if (!g_timer.armed || g_timer.used >= g_timer.cap) {
+        lk.unlock();
+        return launch_rows(kind, d, r, geo, prm, ncand, partial, rl, s);
+    }
+    const int k = g_timer.used++;
+    g_timer.tag[k] = 16 * kind + r;
+    hipError_t e = hipEventRecord(g_timer.ev[2 * k], s);
+    if (e == hipSuccess) e = launch_rows(kind, d, r, geo, prm, ncand, partial, rl, s);
+    if (e == hipSuccess) e = hipEventRecord(g_timer.ev[2 * k + 1], s);
+    return e;
 }
 
 }  // namespace
@@ -674,7 +706,7 @@ int kdefft_psi(const double* X, int64_t n, const kdefft_grid* g, const double* G
     HIPCHK(launch_psi_setup(args, b.prm, s), "psi setup");
     const RowLaunch rl = launch_for(FUN_PSI, d, r, g->P[d - 1]);
     const RowGeom geo = make_geom(*g, FUN_PSI, r, 1, rl.variant);
-    HIPCHK(launch_rows(FUN_PSI, d, r, geo, b.prm, 1, b.partial, rl, s), "psi rows");
+    HIPCHK(timed_rows(FUN_PSI, d, r, geo, b.prm, 1, b.partial, rl, s), "psi rows");
     HIPCHK(launch_psi_final(b.partial, geo, nu, b.prm, 1, psi, nullptr, s), "psi final");
     return KDEFFT_OK;
 }
@@ -760,7 +792,7 @@ int kdefft_psi_batch(const kdefft_dataset* ds, int n_ds, const double* G_host, i
     HIPCHK(launch_psi_setup(args, b.prm, s), "psi setup");
     const RowLaunch rl = launch_for(FUN_PSI, d, r, g.P[d - 1]);
     const RowGeom geo = make_geom(g, FUN_PSI, r, n_ds, rl.variant);
-    HIPCHK(launch_rows(FUN_PSI, d, r, geo, b.prm, n_ds, b.partial, rl, s), "psi rows");
+    HIPCHK(timed_rows(FUN_PSI, d, r, geo, b.prm, n_ds, b.partial, rl, s), "psi rows");
     HIPCHK(launch_psi_final(b.partial, geo, (int)binom(d + r - 1, r), b.prm, n_ds, psi, nullptr, s), "psi final");
     return KDEFFT_OK;
 }
@@ -795,7 +827,7 @@ static int scv_common(const kdefft_dataset* ds, int n_ds, const int64_t* off, co
     const RowLaunch rl = force ? *force : launch_for(kind, g.d, 2, g.P[g.d - 1]);
     const RowGeom geo = make_geom(g, kind, 2, B, rl.variant);
     HIPCHK(launch_scv_setup(vechL, a, B, b.prm, status, s), "scv setup");
-    HIPCHK(launch_rows(kind, g.d, 2, geo, b.prm, B, b.partial, rl, s), "scv rows");
+    HIPCHK(timed_rows(kind, g.d, 2, geo, b.prm, B, b.partial, rl, s), "scv rows");
     HIPCHK(launch_scv_final(kind, b.partial, geo, b.prm, B, grad_out, obj, grad, s), "scv final");
     return KDEFFT_OK;
 }
@@ -888,32 +920,36 @@ int kdefft_autotune(const kdefft_dataset* ds, void* ws, size_t ws_bytes, const c
     const int d = g.d, q = d * (d + 1) / 2, N = g.P[d - 1];
     if (!ws) return fail(KDEFFT_E_ARG, "workspace is NULL");
     Arena a(ws, ws_bytes, false);
-    carve_batch(a, g, FUN_SCV_OBJGRAD, 2, 64);
-    double* vech = a.take<double>(64 * q);
-    double* obj = a.take<double>(64);
-    double* grad = a.take<double>(64 * q);
+    carve_batch(a, g, FUN_SCV_OBJGRAD, 2, TUNE_B);
+    double* vech = a.take<double>(TUNE_B * q);
+    double* obj = a.take<double>(TUNE_B);
+    double* grad = a.take<double>(TUNE_B * q);
     rc = check_ws(a, ws_bytes);
     if (rc) return rc;
-    // 64 candidates H_b = s_b * Gpilot with s_b spread over [0.5, 8]
+    // TUNE_B candidates H_b = s_b * Gpilot with s_b spread over [0.5, 8]
     double LG[16];
     rc = check_spd(ds->G, d, "Gpilot", LG);
     if (rc) return rc;
-    std::vector<double> hv(64 * q);
-    for (int b = 0; b < 64; ++b) {
-        const double sc = std::sqrt(0.5 * std::pow(16.0, b / 63.0));
+    std::vector<double> hv(TUNE_B * q);
+    for (int b = 0; b < TUNE_B; ++b) {
+        const double sc = std::sqrt(0.5 * std::pow(16.0, b / double(TUNE_B - 1)));
         int t = 0;
         for (int j = 0; j < d; ++j)
             for (int i = j; i < d; ++i) hv[b * q + t++] = sc * LG[i * 4 + j];
     }
     hipStream_t s = S(stream);
     HIPCHK(hipMemcpyAsync(vech, hv.data(), hv.size() * sizeof(double), hipMemcpyHostToDevice, s), "tuner upload");
-    int64_t off[2] = {0, 64};
+    int64_t off[2] = {0, TUNE_B};
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0), "event");
     HIPCHK(hipEventCreate(&e1), "event");
     const int grids[2] = {0, -1};
     RowLaunch best{0, 0};
     float best_ms = 1e30f;
+    // The untuned default keeps its place unless another launch beats it by
+    // more than 3%, so that timing noise does not flip the choice run to run.
+    const RowLaunch dflt{3, 0};
+    float dflt_ms = -1.f;
     std::string lines;
     const std::string arch = [] {
         int dev = 0;
@@ -927,7 +963,7 @@ int kdefft_autotune(const kdefft_dataset* ds, void* ws, size_t ws_bytes, const c
             rc = scv_common(ds, 1, off, vech, FUN_SCV_OBJGRAD, nullptr, obj, grad, nullptr, ws, ws_bytes, stream, &rl);
             if (rc) break;
             HIPCHK(hipEventRecord(e0, s), "event");
-            for (int rep = 0; rep < 3; ++rep) {
+            for (int rep = 0; rep < 5; ++rep) {
                 rc = scv_common(ds, 1, off, vech, FUN_SCV_OBJGRAD, nullptr, obj, grad, nullptr, ws, ws_bytes, stream,
                                 &rl);
                 if (rc) break;
@@ -936,7 +972,7 @@ int kdefft_autotune(const kdefft_dataset* ds, void* ws, size_t ws_bytes, const c
             HIPCHK(hipEventSynchronize(e1), "event sync");
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, e0, e1), "elapsed");
-            ms /= 3.f;
+            ms /= 5.f;
             char buf[256];
             snprintf(buf, sizeof(buf), "variant %d grid %d: %.1f us\n", v, rl.grid_blocks, ms * 1000.0);
             lines += buf;
@@ -944,12 +980,14 @@ int kdefft_autotune(const kdefft_dataset* ds, void* ws, size_t ws_bytes, const c
                 best_ms = ms;
                 best = rl;
             }
+            if (rl.variant == dflt.variant && rl.grid_blocks == dflt.grid_blocks) dflt_ms = ms;
         }
         if (rc) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
+    if (dflt_ms > 0.f && best_ms > 0.97f * dflt_ms) best = dflt;
     {
         char buf[96];
         snprintf(buf, sizeof(buf), "best: variant %d grid %d\n", best.variant, best.grid_blocks);
@@ -973,3 +1011,37 @@ int kdefft_autotune(const kdefft_dataset* ds, void* ws, size_t ws_bytes, const c
 }
 
 }  // extern "C"
+
+int kdefft_timing_start(int max_launches) {
+    if (max_launches < 1 || max_launches > KDEFFT_MAX_TIMED)
+        return fail(KDEFFT_E_ARG, "max_launches %d outside [1, %d]", max_launches, KDEFFT_MAX_TIMED);
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    while ((int)g_timer.ev.size() < 2 * max_launches) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e), "timing event");
+        g_timer.ev.push_back(e);
+    }
+    g_timer.tag.assign(max_launches, 0);
+    g_timer.cap = max_launches;
+    g_timer.used = 0;
+    g_timer.armed = true;
+    return KDEFFT_OK;
+}
+
+int kdefft_timing_stop(float* ms_out, int32_t* tag_out, int cap, int* count_out) {
+    if (!count_out || cap < 0 || (cap > 0 && (!ms_out || !tag_out)))
+        return fail(KDEFFT_E_ARG, "bad output arrays");
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    const int used = g_timer.armed ? g_timer.used : 0;
+    g_timer.armed = false;
+    const int cnt = std::min(used, cap);
+    for (int k = 0; k < cnt; ++k) {
+        HIPCHK(hipEventSynchronize(g_timer.ev[2 * k + 1]), "timing sync");
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, g_timer.ev[2 * k], g_timer.ev[2 * k + 1]), "timing elapsed");
+        ms_out[k] = ms;
+        tag_out[k] = g_timer.tag[k];
+    }
+    *count_out = cnt;
+    return KDEFFT_OK;
+}

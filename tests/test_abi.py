@@ -155,3 +155,17 @@ def test_dataset_entry_validation(kf):
     assert lib.kdefft_scv_batch(ds, 1, off.ctypes.data, fake, fake, None, None, fake, 1 << 30, None) == L.E_ARG
     assert lib.kdefft_set_row_launch(2, 2, 2, 512, 5, 0) == L.E_ARG
     assert lib.kdefft_set_row_launch(2, 2, 2, 3, 0, 0) == L.E_UNSUPPORTED
+
+
+def test_timing_hook_validation(kf):
+    """Out-of-range arming and bad output arrays fail before any HIP call;
+    stopping an unarmed timer reports no launches."""
+    lib = kf._lib.load()
+    L = kf._lib
+    assert lib.kdefft_timing_start(0) == L.E_ARG
+    assert lib.kdefft_timing_start(L.MAX_TIMED + 1) == L.E_ARG
+    cnt = C.c_int(-1)
+    assert lib.kdefft_timing_stop(None, None, 4, C.byref(cnt)) == L.E_ARG
+    assert lib.kdefft_timing_stop(None, None, 0, None) == L.E_ARG
+    assert lib.kdefft_timing_stop(None, None, 0, C.byref(cnt)) == L.OK and cnt.value == 0
+    assert kf.timing_stop() == []

@@ -285,3 +285,31 @@ def test_narrow_kernels_recurrence_fallback(kf, gpu):
     finally:
         kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, 3, 0)
     _check_against_oracle(kf, "narrow", d, X, Gp, M, H, obj.cpu().numpy(), g.cpu().numpy())
+
+
+def test_timing_hook_records_row_launches(kf, gpu):
+    """The row-kernel timer brackets exactly the batched row launches, tags
+    them by family and r, and leaves the results unchanged."""
+    name = "d2"
+    d, n, M, B = CASES[name]
+    X = mixture_sample(n, d, 100 + d)
+    Gp = spd(d, 200 + d, 0.05)
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
+    v = torch.from_numpy(_vech(_Hs(d, B, 5))).to(gpu)
+    o0, g0 = kf.scv([ds], v)
+    kf.timing_start(8)
+    o1, g1 = kf.scv([ds], v)
+    kf.psi_batch([ds], [spd(d, 300, 0.08)], 4)
+    kf.scv([ds], v, grad=False)
+    torch.cuda.synchronize()
+    recs = kf.timing_stop()
+    log(f"timing records {recs}")
+    assert [(f, r) for _, f, r in recs] == [(kf.FUN_SCV_OBJGRAD, 2), (kf.FUN_PSI, 4), (kf.FUN_SCV_OBJ, 2)]
+    assert all(0.0 < ms < 1000.0 for ms, _, _ in recs)
+    assert torch.equal(o0, o1) and torch.equal(g0, g1)
+    assert kf.timing_stop() == []
+    # a full timer records no more than it was armed for
+    kf.timing_start(1)
+    kf.scv([ds], v)
+    kf.scv([ds], v)
+    assert len(kf.timing_stop()) == 1
