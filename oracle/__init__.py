@@ -24,8 +24,12 @@ multivariate kernel density estimation"):
 * ``scv``       the smoothed cross-validation objective and its gradient
                 (the SCV selector is named in Sec. 3 and Sec. 5; its formula
                 is the standard Gaussian-kernel SCV, read as a V-statistic)
+* ``plugin``    the plug-in (AMISE) objective built on psi_4 and its gradient
+                (Sec. 5 names the PI selector; standard normal-kernel AMISE)
+* ``eta``       the scalar functions eta_r of Eq. (30)-(31), the V-statistic
+                Q_r of Eq. (32), LSCV_r of Eq. (35)-(36) and the LSCV gradient
 
 Pins (what ties this code to the paper and to mathematics rather than to
 itself) live in ``tests/test_oracle_*.py``.
 """
-from . import multiindex, grid, linbin, gauss, direct, binned, layout, scv  # noqa: F401
+from . import multiindex, grid, linbin, gauss, direct, binned, layout, scv, plugin, eta  # noqa: F401
