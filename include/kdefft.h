@@ -228,6 +228,57 @@ int kdefft_scv_adjoint(const kdefft_dataset* ds_host, int n_ds, const int64_t* h
                        const double* vechL, const double* grad_out, double* grad_vechL,
                        void* ws, size_t ws_bytes, void* stream);
 
+/* Criteria built on the same batched lag-domain evaluation (crit):
+ *   KDEFFT_CRIT_SCV         the SCV objective above (r must be 0);
+ *   KDEFFT_CRIT_LSCV        LSCV_r of Eq. (36) (n - 1 replaced by n):
+ *       (-1)^r { n^-2 sum sum [eta_r(.; 2H) - 2 eta_r(.; H)] + 2 n^-1 eta_r(0; H) },
+ *       for r = 0 the paper's LSCV of Eq. (11);
+ *   KDEFFT_CRIT_LSCV_EXACT  LSCV_r of Eq. (35), the leave-one-out weights:
+ *       (-1)^r { n^-2 sum sum [eta_r(.; 2H) - 2n/(n-1) eta_r(.; H)] + 2 (n-1)^-1 eta_r(0; H) };
+ *   KDEFFT_CRIT_QR          the V-statistic Q_r(S) of Eq. (32) with S = L L^T
+ *       the candidate matrix itself: n^-2 sum sum eta_r(X_i - X_j; S).
+ * eta_r(x; S) = (vec^T I)^{(x)r} D^{(x)2r} phi_S(x) (Eq. (31)); the paper prints
+ * K_H(0) for the diagonal correction at every r, read here as eta_r(0; H), its
+ * r = 0 value.  Binned sums as in the SCV path (the binned self-pairs make the
+ * diagonal correction approximate, as in the paper). */
+#define KDEFFT_CRIT_SCV 0
+#define KDEFFT_CRIT_LSCV 1
+#define KDEFFT_CRIT_LSCV_EXACT 2
+#define KDEFFT_CRIT_QR 3
+
+/* Batched criterion for B = h_offsets_host[n_ds] candidates (dataset grouping
+ * and vechL as in kdefft_scv_batch), r in [0, 8] (0 for SCV).  obj: device
+ * [B].  grad: device [B, q] = d crit / d vechL, or NULL; a gradient exists for
+ * r = 0 and the SCV / LSCV criteria only (else KDEFFT_E_UNSUPPORTED).  status
+ * as in kdefft_scv_batch.  Workspace: KDEFFT_OP_SCV_BATCH with batch = B. */
+int kdefft_crit_batch(const kdefft_dataset* ds_host, int n_ds, const int64_t* h_offsets_host,
+                      const double* vechL, int crit, int r, double* obj, double* grad,
+                      int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of kdefft_crit_batch for r = 0 and crit SCV / LSCV / LSCV_EXACT:
+ * grad_vechL[b, :] = grad_out[b] * d crit(H_b) / d vechL_b.  Same workspace. */
+int kdefft_crit_adjoint(const kdefft_dataset* ds_host, int n_ds, const int64_t* h_offsets_host,
+                        const double* vechL, int crit, const double* grad_out, double* grad_vechL,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* Plug-in criterion (Sec. 5 names the PI selector; normal-kernel AMISE with
+ * the estimated fourth-derivative functional):
+ *   PI(H) = n^-1 (4 pi)^{-d/2} |H|^{-1/2} + 1/4 (vec H (x) vec H)^T psi_4,
+ * psi_4 the d^4 Kronecker-ordered vector filled from the unique entries.
+ * psi4: device [n_ds, kdefft_unique_count(d, 4)] (e.g. from kdefft_psi_batch at
+ * the pilot bandwidths); n_host[j] the sample size of dataset j; candidates
+ * grouped by h_offsets_host as in kdefft_scv_batch.  obj: device [B]; grad:
+ * device [B, q] = d PI / d vechL or NULL; status: device int32 [B] or NULL
+ * (1 = singular H, NaN results).  No workspace; one launch. */
+int kdefft_pi_batch(int d, int n_ds, const int64_t* n_host, const double* psi4,
+                    const int64_t* h_offsets_host, const double* vechL, double* obj, double* grad,
+                    int32_t* status, void* stream);
+
+/* Fill the d^r Kronecker-ordered vector (first index slowest) from the unique
+ * entries (sorted index tuples in lexicographic order; Sec. 5): full_host
+ * [d^r] from unique_host [kdefft_unique_count(d, r)].  Host only. */
+int kdefft_expand_full(int d, int r, const double* unique_host, double* full_host);
+
 /* One candidate H at a time by the paper's literal steps: for the objective
  * grid and each of the q Hessian grids, kernel grid -> R2C -> multiply by the
  * prepared count spectrum -> C2R -> scale -> contract with the counts, each a

@@ -25,7 +25,8 @@ from ._lib import FUN_PSI, FUN_SCV_GRAD, FUN_SCV_OBJ, FUN_SCV_OBJGRAD, Grid, Kde
 
 __all__ = ["Grid", "Dataset", "KdefftError", "grid_plan", "grid_auto", "linbin", "psi", "psi_batch", "scv",
            "scv_adjoint", "scv_plain", "SCV", "unique_tuples", "autotune", "set_row_launch", "library_path",
-           "timing_start", "timing_stop"]
+           "timing_start", "timing_stop", "crit", "crit_adjoint", "pi", "expand_full", "Criterion", "PI",
+           "CRIT_SCV", "CRIT_LSCV", "CRIT_LSCV_EXACT", "CRIT_QR"]
 
 
 def library_path():
@@ -221,6 +222,85 @@ def _split_counts(datasets, vechL, per_ds):
     return per_ds
 
 
+CRIT_SCV, CRIT_LSCV, CRIT_LSCV_EXACT, CRIT_QR = 0, 1, 2, 3
+_CRIT_NAMES = {"scv": CRIT_SCV, "lscv": CRIT_LSCV, "lscv_exact": CRIT_LSCV_EXACT, "qr": CRIT_QR}
+
+
+def _crit_code(crit):
+    if isinstance(crit, str):
+        return _CRIT_NAMES[crit]
+    return int(crit)
+
+
+def crit(datasets: Sequence[Dataset], vechL: torch.Tensor, crit="scv", r: int = 0, per_ds=None,
+         grad: bool = True, status: bool = False):
+    """Batched criterion ("scv", "lscv", "lscv_exact" or "qr", include/kdefft.h)
+    for candidates vechL [B, q] (H = L L^T; for "qr" the matrix S itself);
+    candidates are grouped by dataset in order, per_ds[j] of them for dataset j.
+    Gradients (d/d vechL) exist for r = 0 and the SCV / LSCV criteria."""
+    code = _crit_code(crit)
+    datasets = list(datasets)
+    dev = datasets[0].device
+    vechL = vechL.to(device=dev, dtype=torch.float64).contiguous()
+    B, q = vechL.shape
+    per_ds = _split_counts(datasets, vechL, per_ds)
+    obj = torch.empty(B, dtype=torch.float64, device=dev)
+    g = torch.empty((B, q), dtype=torch.float64, device=dev) if grad else None
+    st = torch.empty(B, dtype=torch.int32, device=dev)
+    start = 0
+    for s in range(0, len(datasets), _lib.MAX_BATCH_DS):
+        part = datasets[s:s + _lib.MAX_BATCH_DS]
+        cnts = per_ds[s:s + _lib.MAX_BATCH_DS]
+        nb = sum(cnts)
+        if nb == 0:
+            continue
+        off = _offsets(part, cnts)
+        ws = _ws(part[0].grid, _lib.OP_SCV_BATCH, 2, nb, dev)
+        arr = _ds_array(part)
+        sl = slice(start, start + nb)
+        _lib.check(_L().kdefft_crit_batch(arr, len(part), off.ctypes.data, _ptr(vechL[sl]), code, int(r),
+                                          _ptr(obj[sl]), _ptr(g[sl]) if grad else None, _ptr(st[sl]), _ptr(ws),
+                                          ws.numel(), _stream(dev)), "kdefft_crit_batch")
+        start += nb
+    if status:
+        return obj, g, st
+    return (obj, g) if grad else obj
+
+
+def crit_adjoint(datasets: Sequence[Dataset], vechL: torch.Tensor, grad_out: torch.Tensor, crit="scv",
+                 per_ds=None):
+    """grad_out[b] * d crit(H_b) / d vechL_b (r = 0, SCV / LSCV criteria)."""
+    code = _crit_code(crit)
+    datasets = list(datasets)
+    dev = datasets[0].device
+    vechL = vechL.to(device=dev, dtype=torch.float64).contiguous()
+    grad_out = grad_out.to(device=dev, dtype=torch.float64).contiguous()
+    B, q = vechL.shape
+    per_ds = _split_counts(datasets, vechL, per_ds)
+    out = torch.empty((B, q), dtype=torch.float64, device=dev)
+    start = 0
+    for s in range(0, len(datasets), _lib.MAX_BATCH_DS):
+        part = datasets[s:s + _lib.MAX_BATCH_DS]
+        cnts = per_ds[s:s + _lib.MAX_BATCH_DS]
+        nb = sum(cnts)
+        if nb == 0:
+            continue
+        off = _offsets(part, cnts)
+        ws = _ws(part[0].grid, _lib.OP_SCV_BATCH, 2, nb, dev)
+        arr = _ds_array(part)
+        sl = slice(start, start + nb)
+        if code == CRIT_SCV:
+            rc = _L().kdefft_scv_adjoint(arr, len(part), off.ctypes.data, _ptr(vechL[sl]), _ptr(grad_out[sl]),
+                                         _ptr(out[sl]), _ptr(ws), ws.numel(), _stream(dev))
+            _lib.check(rc, "kdefft_scv_adjoint")
+        else:
+            rc = _L().kdefft_crit_adjoint(arr, len(part), off.ctypes.data, _ptr(vechL[sl]), code,
+                                          _ptr(grad_out[sl]), _ptr(out[sl]), _ptr(ws), ws.numel(), _stream(dev))
+            _lib.check(rc, "kdefft_crit_adjoint")
+        start += nb
+    return out
+
+
 def scv(datasets: Sequence[Dataset], vechL: torch.Tensor, per_ds=None, grad: bool = True, status: bool = False):
     """SCV objective (and d/d vechL) for candidates vechL [B, q]; candidates are
     grouped by dataset in order, per_ds[j] of them for dataset j."""
@@ -253,27 +333,54 @@ def scv(datasets: Sequence[Dataset], vechL: torch.Tensor, per_ds=None, grad: boo
 
 
 def scv_adjoint(datasets: Sequence[Dataset], vechL: torch.Tensor, grad_out: torch.Tensor, per_ds=None):
-    datasets = list(datasets)
-    dev = datasets[0].device
+    return crit_adjoint(datasets, vechL, grad_out, "scv", per_ds)
+
+
+def pi(psi4: torch.Tensor, ns: Sequence[int], vechL: torch.Tensor, per_ds=None, grad: bool = True,
+       status: bool = False):
+    """Plug-in criterion for candidates vechL [B, q] from psi_4 [n_ds, C(d+3,4)]
+    of each dataset (sample sizes ns), candidates grouped by dataset in order."""
+    dev = psi4.device
+    psi4 = psi4.to(dtype=torch.float64).contiguous()
     vechL = vechL.to(device=dev, dtype=torch.float64).contiguous()
-    grad_out = grad_out.to(device=dev, dtype=torch.float64).contiguous()
     B, q = vechL.shape
-    per_ds = _split_counts(datasets, vechL, per_ds)
-    out = torch.empty((B, q), dtype=torch.float64, device=dev)
+    d = int(round((np.sqrt(8 * q + 1) - 1) / 2))
+    ns = [int(v) for v in ns]
+    if per_ds is None:
+        if len(ns) != 1:
+            raise ValueError("give per_ds (candidates per dataset) for several datasets")
+        per_ds = [B]
+    per_ds = [int(c) for c in per_ds]
+    if sum(per_ds) != B or len(per_ds) != len(ns) or psi4.shape[0] != len(ns):
+        raise ValueError("per_ds, ns and psi4 must describe the same datasets and add up to B")
+    obj = torch.empty(B, dtype=torch.float64, device=dev)
+    g = torch.empty((B, q), dtype=torch.float64, device=dev) if grad else None
+    st = torch.empty(B, dtype=torch.int32, device=dev)
     start = 0
-    for s in range(0, len(datasets), _lib.MAX_BATCH_DS):
-        part = datasets[s:s + _lib.MAX_BATCH_DS]
+    for s in range(0, len(ns), _lib.MAX_BATCH_DS):
         cnts = per_ds[s:s + _lib.MAX_BATCH_DS]
         nb = sum(cnts)
         if nb == 0:
             continue
-        off = _offsets(part, cnts)
-        ws = _ws(part[0].grid, _lib.OP_SCV_BATCH, 2, nb, dev)
-        arr = _ds_array(part)
+        nn = np.array(ns[s:s + _lib.MAX_BATCH_DS], dtype=np.int64)
+        off = np.zeros(len(cnts) + 1, dtype=np.int64)
+        off[1:] = np.cumsum(cnts)
         sl = slice(start, start + nb)
-        _lib.check(_L().kdefft_scv_adjoint(arr, len(part), off.ctypes.data, _ptr(vechL[sl]), _ptr(grad_out[sl]),
-                                           _ptr(out[sl]), _ptr(ws), ws.numel(), _stream(dev)), "kdefft_scv_adjoint")
+        _lib.check(_L().kdefft_pi_batch(d, len(cnts), nn.ctypes.data, _ptr(psi4[s:s + len(cnts)]),
+                                        off.ctypes.data, _ptr(vechL[sl]), _ptr(obj[sl]),
+                                        _ptr(g[sl]) if grad else None, _ptr(st[sl]), _stream(dev)),
+                   "kdefft_pi_batch")
         start += nb
+    if status:
+        return obj, g, st
+    return (obj, g) if grad else obj
+
+
+def expand_full(vals, d: int, r: int) -> np.ndarray:
+    """Unique entries -> the d^r Kronecker-ordered vector (host)."""
+    u = np.ascontiguousarray(np.asarray(vals, dtype=np.float64))
+    out = np.empty(d ** r, dtype=np.float64)
+    _lib.check(_L().kdefft_expand_full(d, r, u.ctypes.data, out.ctypes.data), "kdefft_expand_full")
     return out
 
 
@@ -286,6 +393,43 @@ def scv_plain(dataset: Dataset, H) -> torch.Tensor:
     _lib.check(_L().kdefft_scv_plain(arr, Hm.ctypes.data, _ptr(out), _ptr(ws), ws.numel(), _stream(dataset.device)),
                "kdefft_scv_plain")
     return out
+
+
+class Criterion(torch.autograd.Function):
+    """obj[b] = crit(H_b) (SCV or LSCV at r = 0); backward runs the adjoint
+    kernel (Hessian grids recomputed, never stored)."""
+
+    @staticmethod
+    def forward(ctx, vechL, dataset, crit_name="lscv", per_ds=None):
+        datasets = dataset if isinstance(dataset, (list, tuple)) else [dataset]
+        obj = crit(datasets, vechL.detach(), crit_name, 0, per_ds=per_ds, grad=False)
+        ctx.datasets = datasets
+        ctx.per_ds = per_ds
+        ctx.crit = crit_name
+        ctx.save_for_backward(vechL.detach())
+        return obj
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (vechL,) = ctx.saved_tensors
+        g = crit_adjoint(ctx.datasets, vechL, grad_out.detach(), ctx.crit, per_ds=ctx.per_ds)
+        return g, None, None, None
+
+
+class PI(torch.autograd.Function):
+    """obj[b] = PI(H_b) from psi_4; the exact gradient comes from the same
+    launch and is kept for backward."""
+
+    @staticmethod
+    def forward(ctx, vechL, psi4, ns, per_ds=None):
+        obj, g = pi(psi4, ns, vechL.detach(), per_ds=per_ds, grad=True)
+        ctx.save_for_backward(g)
+        return obj
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return grad_out[:, None] * g, None, None, None
 
 
 class SCV(torch.autograd.Function):

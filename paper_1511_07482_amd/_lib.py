@@ -63,6 +63,13 @@ EXPORTS = {
                                    C.c_void_p]),
     "kdefft_set_row_launch": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "kdefft_autotune": (C.c_int, [C.POINTER(Dataset), C.c_void_p, C.c_size_t, C.c_char_p, C.c_void_p]),
+    "kdefft_crit_batch": (C.c_int, [C.POINTER(Dataset), C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "kdefft_crit_adjoint": (C.c_int, [C.POINTER(Dataset), C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "kdefft_pi_batch": (C.c_int, [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p]),
+    "kdefft_expand_full": (C.c_int, [C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
     "kdefft_timing_start": (C.c_int, [C.c_int]),
     "kdefft_timing_stop": (C.c_int, [C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int)]),
 }

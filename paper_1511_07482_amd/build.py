@@ -32,7 +32,8 @@ COMMON = [
 HOST_EXTRA = ["-ffp-contract=off"]
 
 UNITS = ["api.cpp", "fft.hip", "bin.hip", "plain.hip", "rows.hip",
-         "rows_d1.hip", "rows_d2.hip", "rows_d3.hip", "rows_d4.hip"]
+         "rows_d1.hip", "rows_d2.hip", "rows_d3.hip", "rows_d4.hip",
+         "rows_eta_d1.hip", "rows_eta_d2.hip", "rows_eta_d3.hip", "rows_eta_d4.hip"]
 HEADERS = ["dev_common.h", "dev_kernels.h", "internal.h", "rows_impl.h", "rows_dispatch.h"]
 
 

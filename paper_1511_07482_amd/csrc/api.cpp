@@ -325,7 +325,7 @@ BatchScratch carve_batch(Arena& a, const kdefft_grid& g, int kind, int r, int64_
     if (kind == FUN_PSI) {
         need = max_nchunks(g, kind, r, ncand) * ng_of(kind, g.d, r);
     } else {
-        for (int k = FUN_SCV_OBJ; k <= FUN_SCV_GRAD; ++k)
+        for (int k = FUN_SCV_OBJ; k <= FUN_ETA2; ++k)
             need = std::max<int64_t>(need, max_nchunks(g, k, 2, ncand) * ng_of(k, g.d, 2));
     }
     b.partial = a.take<double>(ncand * need);
@@ -428,7 +428,9 @@ int prepare_into(const double* X, int64_t n, const kdefft_grid& g, const double*
 // The batched row kernels are compiled for last-axis lengths up to 2048, 1024,
 // 256, 128 (d = 1..4) and enough LDS for the family's grids.
 int check_rows(int kind, int d, int r, int N) {
-    if (rows_per_iter(kind, d, r, N, 0) < 1)
+    // the scalar eta families exist in the lag-domain form only
+    const int v = (kind == FUN_ETA1 || kind == FUN_ETA2) ? 3 : 0;
+    if (rows_per_iter(kind, d, r, N, v) < 1)
         return fail(KDEFFT_E_UNSUPPORTED,
                     "no batched row kernel for d=%d, r=%d, last-axis P=%d (family %d); use the plain path", d, r, N,
                     kind);
@@ -797,11 +799,24 @@ int kdefft_psi_batch(const kdefft_dataset* ds, int n_ds, const double* G_host, i
     return KDEFFT_OK;
 }
 
-static int scv_common(const kdefft_dataset* ds, int n_ds, const int64_t* off, const double* vechL, int kind,
-                      const double* grad_out, double* obj, double* grad, int32_t* status, void* ws,
-                      size_t ws_bytes, void* stream, const RowLaunch* force) {
+// Row-kernel family of a criterion: the two-Gaussian SCV families (with the
+// Hessian grids for gradients) serve SCV and LSCV at r = 0; LSCV_r for r > 0 and
+// Q_r use the scalar eta_r families.  The dispatch order passed to the row
+// kernels is 2 for the SCV families and 0 (unused) for the eta families.
+static int crit_kind(int crit, int r, bool want_grad, bool adjoint) {
+    if (crit == KDEFFT_CRIT_QR) return FUN_ETA1;
+    if (r > 0) return FUN_ETA2;
+    return adjoint ? FUN_SCV_GRAD : (want_grad ? FUN_SCV_OBJGRAD : FUN_SCV_OBJ);
+}
+
+static int crit_common(const kdefft_dataset* ds, int n_ds, const int64_t* off, const double* vechL, int crit,
+                       int r, int kind, const double* grad_out, double* obj, double* grad, int32_t* status,
+                       void* ws, size_t ws_bytes, void* stream, const RowLaunch* force) {
     int rc = check_batch_ds(ds, n_ds, KDEFFT_MAX_BATCH_DS);
     if (rc) return rc;
+    if (crit < KDEFFT_CRIT_SCV || crit > KDEFFT_CRIT_QR) return fail(KDEFFT_E_ARG, "crit=%d", crit);
+    if (r < 0 || r > 8) return fail(KDEFFT_E_ARG, "r=%d outside [0, 8]", r);
+    if (crit == KDEFFT_CRIT_SCV && r != 0) return fail(KDEFFT_E_UNSUPPORTED, "SCV is defined for r = 0 only");
     if (!off || !vechL) return fail(KDEFFT_E_ARG, "NULL h_offsets or vechL");
     if (off[0] != 0) return fail(KDEFFT_E_ARG, "h_offsets[0] must be 0");
     for (int j = 0; j < n_ds; ++j)
@@ -810,11 +825,17 @@ static int scv_common(const kdefft_dataset* ds, int n_ds, const int64_t* off, co
     if (B < 1) return fail(KDEFFT_E_ARG, "no candidate bandwidths");
     if (B > (1LL << 24)) return fail(KDEFFT_E_ARG, "too many candidates in one call");
     const kdefft_grid& g = ds[0].grid;
-    rc = check_rows(kind, g.d, 2, g.P[g.d - 1]);
+    if (crit == KDEFFT_CRIT_LSCV_EXACT)
+        for (int j = 0; j < n_ds; ++j)
+            if (ds[j].n < 2) return fail(KDEFFT_E_ARG, "the leave-one-out form needs n >= 2 (dataset %d)", j);
+    const int kr = (kind == FUN_ETA1 || kind == FUN_ETA2) ? 0 : 2;
+    rc = check_rows(kind, g.d, kr, g.P[g.d - 1]);
     if (rc) return rc;
     ScvBatchArgs a{};
     a.n_ds = n_ds;
     a.d = g.d;
+    a.crit = crit;
+    a.r = r;
     a.prodP = (double)sizes_of(g).prodP;
     for (int j = 0; j < n_ds; ++j) a.rec[j] = static_cast<const DsDev*>(ds[j].rec);
     for (int j = 0; j <= n_ds; ++j) a.off[j] = off[j];
@@ -824,12 +845,19 @@ static int scv_common(const kdefft_dataset* ds, int n_ds, const int64_t* off, co
     rc = check_ws(ar, ws_bytes);
     if (rc) return rc;
     hipStream_t s = S(stream);
-    const RowLaunch rl = force ? *force : launch_for(kind, g.d, 2, g.P[g.d - 1]);
-    const RowGeom geo = make_geom(g, kind, 2, B, rl.variant);
-    HIPCHK(launch_scv_setup(vechL, a, B, b.prm, status, s), "scv setup");
-    HIPCHK(timed_rows(kind, g.d, 2, geo, b.prm, B, b.partial, rl, s), "scv rows");
-    HIPCHK(launch_scv_final(kind, b.partial, geo, b.prm, B, grad_out, obj, grad, s), "scv final");
+    const RowLaunch rl = force ? *force : launch_for(kind, g.d, kr, g.P[g.d - 1]);
+    const RowGeom geo = make_geom(g, kind, kr, B, rl.variant);
+    HIPCHK(launch_scv_setup(vechL, a, B, b.prm, status, s), "criterion setup");
+    HIPCHK(timed_rows(kind, g.d, kr, geo, b.prm, B, b.partial, rl, s), "criterion rows");
+    HIPCHK(launch_scv_final(kind, b.partial, geo, b.prm, B, grad_out, obj, grad, s), "criterion final");
     return KDEFFT_OK;
+}
+
+static int scv_common(const kdefft_dataset* ds, int n_ds, const int64_t* off, const double* vechL, int kind,
+                      const double* grad_out, double* obj, double* grad, int32_t* status, void* ws,
+                      size_t ws_bytes, void* stream, const RowLaunch* force) {
+    return crit_common(ds, n_ds, off, vechL, KDEFFT_CRIT_SCV, 0, kind, grad_out, obj, grad, status, ws, ws_bytes,
+                       stream, force);
 }
 
 int kdefft_scv_batch(const kdefft_dataset* ds, int n_ds, const int64_t* h_offsets_host, const double* vechL,
@@ -844,6 +872,80 @@ int kdefft_scv_adjoint(const kdefft_dataset* ds, int n_ds, const int64_t* h_offs
     if (!grad_out || !grad_vechL) return fail(KDEFFT_E_ARG, "NULL grad_out or grad_vechL");
     return scv_common(ds, n_ds, h_offsets_host, vechL, FUN_SCV_GRAD, grad_out, nullptr, grad_vechL, nullptr, ws,
                       ws_bytes, stream, nullptr);
+}
+
+int kdefft_crit_batch(const kdefft_dataset* ds, int n_ds, const int64_t* h_offsets_host, const double* vechL,
+                      int crit, int r, double* obj, double* grad, int32_t* status, void* ws, size_t ws_bytes,
+                      void* stream) {
+    if (!obj) return fail(KDEFFT_E_ARG, "obj is NULL");
+    if (grad && (r != 0 || crit == KDEFFT_CRIT_QR))
+        return fail(KDEFFT_E_UNSUPPORTED, "gradients exist for r = 0 SCV / LSCV criteria only");
+    return crit_common(ds, n_ds, h_offsets_host, vechL, crit, r, crit_kind(crit, r, grad != nullptr, false),
+                       nullptr, obj, grad, status, ws, ws_bytes, stream, nullptr);
+}
+
+int kdefft_crit_adjoint(const kdefft_dataset* ds, int n_ds, const int64_t* h_offsets_host, const double* vechL,
+                        int crit, const double* grad_out, double* grad_vechL, void* ws, size_t ws_bytes,
+                        void* stream) {
+    if (!grad_out || !grad_vechL) return fail(KDEFFT_E_ARG, "NULL grad_out or grad_vechL");
+    if (crit == KDEFFT_CRIT_QR) return fail(KDEFFT_E_UNSUPPORTED, "no adjoint for Q_r");
+    return crit_common(ds, n_ds, h_offsets_host, vechL, crit, 0, FUN_SCV_GRAD, grad_out, nullptr, grad_vechL,
+                       nullptr, ws, ws_bytes, stream, nullptr);
+}
+
+int kdefft_pi_batch(int d, int n_ds, const int64_t* n_host, const double* psi4, const int64_t* h_offsets_host,
+                    const double* vechL, double* obj, double* grad, int32_t* status, void* stream) {
+    if (d < 1 || d > 4) return fail(KDEFFT_E_ARG, "d=%d outside [1, 4]", d);
+    if (n_ds < 1 || n_ds > KDEFFT_MAX_BATCH_DS) return fail(KDEFFT_E_ARG, "n_ds=%d", n_ds);
+    if (!n_host || !psi4 || !h_offsets_host || !vechL) return fail(KDEFFT_E_ARG, "NULL argument");
+    if (!obj && !grad) return fail(KDEFFT_E_ARG, "neither obj nor grad requested");
+    if (h_offsets_host[0] != 0) return fail(KDEFFT_E_ARG, "h_offsets[0] must be 0");
+    PiArgs a{};
+    a.n_ds = n_ds;
+    a.d = d;
+    for (int j = 0; j < n_ds; ++j) {
+        if (h_offsets_host[j + 1] < h_offsets_host[j]) return fail(KDEFFT_E_ARG, "h_offsets must be non-decreasing");
+        if (n_host[j] < 1) return fail(KDEFFT_E_ARG, "n of dataset %d is %lld", j, (long long)n_host[j]);
+        a.n[j] = (double)n_host[j];
+        a.off[j] = h_offsets_host[j];
+    }
+    a.off[n_ds] = h_offsets_host[n_ds];
+    const int64_t B = h_offsets_host[n_ds];
+    if (B < 1) return fail(KDEFFT_E_ARG, "no candidate bandwidths");
+    if (B > (1LL << 24)) return fail(KDEFFT_E_ARG, "too many candidates in one call");
+    HIPCHK(launch_pi(a, psi4, vechL, B, obj, grad, status, S(stream)), "pi");
+    return KDEFFT_OK;
+}
+
+int kdefft_expand_full(int d, int r, const double* unique_host, double* full_host) {
+    if (d < 1 || d > 4 || r < 0 || r > 8) return fail(KDEFFT_E_ARG, "d=%d r=%d", d, r);
+    if (!unique_host || !full_host) return fail(KDEFFT_E_ARG, "NULL argument");
+    // rank of every sorted tuple, in lexicographic order
+    std::map<std::vector<int>, int> pos;
+    std::vector<int> t(r, 0);
+    int cnt = 0;
+    while (true) {
+        pos[t] = cnt++;
+        int m = r - 1;
+        while (m >= 0 && t[m] == d - 1) --m;
+        if (m < 0) break;
+        t[m] += 1;
+        for (int k = m + 1; k < r; ++k) t[k] = t[m];
+    }
+    int64_t total = 1;
+    for (int k = 0; k < r; ++k) total *= d;
+    std::vector<int> idx(r);
+    for (int64_t f = 0; f < total; ++f) {
+        int64_t x = f;
+        for (int k = r - 1; k >= 0; --k) {  // first index slowest
+            idx[k] = (int)(x % d);
+            x /= d;
+        }
+        std::vector<int> srt(idx);
+        std::sort(srt.begin(), srt.end());
+        full_host[f] = unique_host[pos[srt]];
+    }
+    return KDEFFT_OK;
 }
 
 int kdefft_scv_plain(const kdefft_dataset* ds, const double* H_host, double* out, void* ws, size_t ws_bytes,
@@ -904,7 +1006,7 @@ int kdefft_scv_plain(const kdefft_dataset* ds, const double* H_host, double* out
 }
 
 int kdefft_set_row_launch(int kind, int d, int r, int N, int variant, int grid_blocks) {
-    if (kind < 0 || kind > 3) return fail(KDEFFT_E_ARG, "kind=%d", kind);
+    if (kind < 0 || kind > FUN_ETA2) return fail(KDEFFT_E_ARG, "kind=%d", kind);
     if (variant < 0 || variant >= ROW_VARIANTS) return fail(KDEFFT_E_ARG, "variant=%d", variant);
     if (grid_blocks < -1) return fail(KDEFFT_E_ARG, "grid_blocks=%d", grid_blocks);
     if (rows_per_iter(kind, d, r, N, variant) < 1)

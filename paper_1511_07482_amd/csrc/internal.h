@@ -19,8 +19,9 @@ constexpr int NT_DEF = 256;  // threads per block of the simple kernels
 //   scv:  [0,16) P1 = (2H+2G)^{-1}  [16,32) P2 = (H+2G)^{-1}  [32] c1  [33] c2
 //   both: [38] alag pointer bits  [39] wmix pointer bits  [40,44) delta  [44] n  [45] 1/(n^2 prod P)
 //         [46] constant term  [47] singular flag  [48,64) L (scv) / P3 (plain scv)
-enum Slot { S_P1 = 0, S_C = 16, S_P2 = 16, S_C1 = 32, S_C2 = 33, S_ALAG = 38, S_WMIX = 39, S_DELTA = 40, S_N = 44,
-            S_SCALE = 45, S_CONST = 46, S_SING = 47, S_L = 48 };
+//   criteria: [34] first (closed-form) term  [35] r of eta_r  [36] sign (-1)^r
+enum Slot { S_P1 = 0, S_C = 16, S_P2 = 16, S_C1 = 32, S_C2 = 33, S_FIRST = 34, S_R = 35, S_SIGN = 36, S_ALAG = 38,
+            S_WMIX = 39, S_DELTA = 40, S_N = 44, S_SCALE = 45, S_CONST = 46, S_SING = 47, S_L = 48 };
 
 // Per-dataset record kept in the dataset's own device buffer (written by a
 // kernel at prepare time); batched calls pass pointers to these records.
@@ -37,6 +38,8 @@ struct DsDev {
 struct ScvBatchArgs {
     int n_ds;
     int d;
+    int crit;   // KDEFFT_CRIT_*
+    int r;      // order of eta_r (0 for SCV)
     double prodP;
     const DsDev* rec[KDEFFT_MAX_BATCH_DS];
     int64_t off[KDEFFT_MAX_BATCH_DS + 1];
@@ -48,6 +51,12 @@ struct PsiBatchArgs {
     double prodP;
     const DsDev* rec[KDEFFT_MAX_PSI_DS];
     double Gv[KDEFFT_MAX_PSI_DS][10];   // vech (columns of the lower triangle)
+};
+struct PiArgs {
+    int n_ds;
+    int d;
+    double n[KDEFFT_MAX_BATCH_DS];
+    int64_t off[KDEFFT_MAX_BATCH_DS + 1];
 };
 // One parameter block passed by value.
 struct ParamBlock {
@@ -66,7 +75,9 @@ struct RowGeom {
 };
 
 // Kinds of kernel families generated on the lag grid.
-enum FunKind { FUN_PSI = 0, FUN_SCV_OBJ = 1, FUN_SCV_OBJGRAD = 2, FUN_SCV_GRAD = 3 };
+// FUN_SCV_* serve every criterion with two Gaussians and a Hessian gradient
+// (SCV, LSCV); FUN_ETA1 / FUN_ETA2 are the scalar eta_r families (Q_r, LSCV_r).
+enum FunKind { FUN_PSI = 0, FUN_SCV_OBJ = 1, FUN_SCV_OBJGRAD = 2, FUN_SCV_GRAD = 3, FUN_ETA1 = 4, FUN_ETA2 = 5 };
 
 int ng_of(int kind, int d, int r);   // number of kernel grids of a family
 
@@ -125,6 +136,9 @@ hipError_t launch_scv_final(int kind, const double* partial, const RowGeom& geo,
 hipError_t launch_psi_final(const double* partial, const RowGeom& geo, int ng,
                             const double* prm, int64_t ncand, double* psi, double* scal_out,
                             hipStream_t s);
+
+hipError_t launch_pi(const PiArgs& a, const double* psi4, const double* vechL, int64_t ncand, double* obj,
+                     double* grad, int32_t* status, hipStream_t s);
 
 RowGeom make_geom(const kdefft_grid& g, int kind, int r, int64_t ncand, int variant);
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dev_common.h"
+#include "dev_kernels.h"
 #include "internal.h"
 
 namespace kdefft {
@@ -17,6 +18,14 @@ hipError_t launch_rows_d3(int, int, int, int, const double*, RowGeom, int64_t, d
                           hipStream_t);
 hipError_t launch_rows_d4(int, int, int, int, const double*, RowGeom, int64_t, double*, int, const double2*,
                           hipStream_t);
+hipError_t launch_rows_eta_d1(int, int, int, const double*, RowGeom, int64_t, double*, int, hipStream_t);
+hipError_t launch_rows_eta_d2(int, int, int, const double*, RowGeom, int64_t, double*, int, hipStream_t);
+hipError_t launch_rows_eta_d3(int, int, int, const double*, RowGeom, int64_t, double*, int, hipStream_t);
+hipError_t launch_rows_eta_d4(int, int, int, const double*, RowGeom, int64_t, double*, int, hipStream_t);
+int rows_iter_eta_d1(int, int, int);
+int rows_iter_eta_d2(int, int, int);
+int rows_iter_eta_d3(int, int, int);
+int rows_iter_eta_d4(int, int, int);
 int rows_iter_d1(int, int, int, int);
 int rows_iter_d2(int, int, int, int);
 int rows_iter_d3(int, int, int, int);
@@ -35,11 +44,22 @@ int ng_of(int kind, int d, int r) {
         case FUN_SCV_OBJ: return 1;
         case FUN_SCV_OBJGRAD: return 1 + q;
         case FUN_SCV_GRAD: return q;
+        case FUN_ETA1:
+        case FUN_ETA2: return 1;
         default: return 0;
     }
 }
 
 int rows_per_iter(int kind, int d, int r, int N, int variant) {
+    if (kind == FUN_ETA1 || kind == FUN_ETA2) {
+        switch (d) {
+            case 1: return rows_iter_eta_d1(kind, N, variant);
+            case 2: return rows_iter_eta_d2(kind, N, variant);
+            case 3: return rows_iter_eta_d3(kind, N, variant);
+            case 4: return rows_iter_eta_d4(kind, N, variant);
+            default: return 0;
+        }
+    }
     switch (d) {
         case 1: return rows_iter_d1(kind, r, N, variant);
         case 2: return rows_iter_d2(kind, r, N, variant);
@@ -82,6 +102,15 @@ hipError_t launch_rows(int kind, int d, int r, const RowGeom& geo, const double*
     if (e != hipSuccess) return e;
     const int64_t nitems = ncand * geo.nchunks;
     const int N = geo.P[d - 1];
+    if (kind == FUN_ETA1 || kind == FUN_ETA2) {
+        switch (d) {
+            case 1: return launch_rows_eta_d1(kind, N, rl.variant, prm, geo, nitems, partial, rl.grid_blocks, s);
+            case 2: return launch_rows_eta_d2(kind, N, rl.variant, prm, geo, nitems, partial, rl.grid_blocks, s);
+            case 3: return launch_rows_eta_d3(kind, N, rl.variant, prm, geo, nitems, partial, rl.grid_blocks, s);
+            case 4: return launch_rows_eta_d4(kind, N, rl.variant, prm, geo, nitems, partial, rl.grid_blocks, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (d) {
         case 1: return launch_rows_d1(kind, r, N, rl.variant, prm, geo, nitems, partial, rl.grid_blocks, tw, s);
         case 2: return launch_rows_d2(kind, r, N, rl.variant, prm, geo, nitems, partial, rl.grid_blocks, tw, s);
@@ -156,9 +185,15 @@ __device__ static void put_ptr(double* slot, const void* p) {
     *slot = __longlong_as_double(static_cast<long long>(reinterpret_cast<uintptr_t>(p)));
 }
 
-// One thread per candidate: H = L L^T from vechL, S1 = 2H + 2G, S2 = H + 2G,
+// One thread per candidate: H = L L^T from vechL, then per criterion
+//   SCV:          S1 = 2H + 2G, S2 = H + 2G, first = n^-1 (4 pi)^{-d/2} |H|^{-1/2},
+//                 constant = the dataset's phi_{2G} sum;
+//   LSCV (r):     S1 = 2H, S2 = H with the S2 weight a/2 folded into c2
+//                 (a = 2, or 2n/(n-1) for the leave-one-out form), sign (-1)^r,
+//                 first = (-1)^r b eta_r(0; H) (b = 2/n, or 2/(n-1));
+//   Q_r:          S1 = H (the candidate matrix itself), no first or constant term;
 // their inverses and normal constants, grid spacing, n and the scale of the
-// Parseval sums, the dataset's constant term.  status 1 = H singular.
+// lag sums.  status 1 = singular candidate.
 template <int D>
 __global__ void k_scv_setup(const double* __restrict__ vechL, ScvBatchArgs a, int64_t ncand,
                             double* __restrict__ prm, int32_t* __restrict__ status) {
@@ -189,11 +224,16 @@ __global__ void k_scv_setup(const double* __restrict__ vechL, ScvBatchArgs a, in
             for (int k = 0; k < d; ++k) s += L[i * 4 + k] * L[k2 * 4 + k];
             H[i * 4 + k2] = s;
         }
+    const int crit = a.crit;
+    const bool scv = crit == KDEFFT_CRIT_SCV;
+    const bool qr = crit == KDEFFT_CRIT_QR;
+    const double gw = scv ? 2.0 : 0.0;      // weight of the pilot in S1, S2
+    const double hw = qr ? 1.0 : 2.0;       // weight of H in S1
     for (int i = 0; i < 16; ++i) { S1[i] = 0.0; S2[i] = 0.0; }
     for (int i = 0; i < d; ++i)
         for (int k2 = 0; k2 < d; ++k2) {
-            S1[i * 4 + k2] = 2.0 * H[i * 4 + k2] + 2.0 * ds.G[i * 4 + k2];
-            S2[i * 4 + k2] = H[i * 4 + k2] + 2.0 * ds.G[i * 4 + k2];
+            S1[i * 4 + k2] = hw * H[i * 4 + k2] + gw * ds.G[i * 4 + k2];
+            S2[i * 4 + k2] = H[i * 4 + k2] + gw * ds.G[i * 4 + k2];
         }
     double* p = prm + h * PRM;
     for (int i = 0; i < PRM; ++i) p[i] = 0.0;
@@ -208,16 +248,41 @@ __global__ void k_scv_setup(const double* __restrict__ vechL, ScvBatchArgs a, in
     }
     chol_inv4<D>(L1, p + S_P1);
     chol_inv4<D>(L2, p + S_P2);
-    double det1 = 1.0, det2 = 1.0;
-    for (int k = 0; k < d; ++k) { det1 *= L1[k * 4 + k]; det2 *= L2[k * 4 + k]; }
+    double det1 = 1.0, det2 = 1.0, ldet = 1.0;
+    for (int k = 0; k < d; ++k) {
+        det1 *= L1[k * 4 + k];
+        det2 *= L2[k * 4 + k];
+        ldet *= fabs(L[k * 4 + k]);
+    }
+    const double n = ds.n;
+    const int r = a.r;
+    const double sgn = (r & 1) ? -1.0 : 1.0;
     p[S_C1] = two_pi_pow(d) / det1;
     p[S_C2] = two_pi_pow(d) / det2;
+    p[S_R] = (double)r;
+    p[S_SIGN] = 1.0;
+    if (scv) {
+        double c4 = 1.0;  // (4 pi)^{-d/2}
+        for (int k = 0; k < d; ++k) c4 *= 0.28209479177387814347;
+        p[S_FIRST] = c4 / (n * ldet);
+        p[S_CONST] = ds.scal[0];
+    } else if (!qr) {
+        const bool exact = crit == KDEFFT_CRIT_LSCV_EXACT;
+        const double b = exact ? 2.0 / (n - 1.0) : 2.0 / n;
+        // eta_r(0; H) = phi_H(0) Y_r(kappa at x = 0); phi_H(0) = c2 before weighting
+        double P2[D * D], T2[ETA_RMAX + 1], z0[D];
+        for (int i = 0; i < D * D; ++i) P2[i] = p[S_P2 + (i / D) * 4 + (i % D)];
+        for (int i = 0; i < D; ++i) z0[i] = 0.0;
+        eta_traces<D>(P2, T2);
+        p[S_FIRST] = sgn * b * p[S_C2] * eta_ratio<D>(z0, P2, T2, r);
+        if (exact) p[S_C2] *= n / (n - 1.0);
+        p[S_SIGN] = sgn;
+    }
     put_ptr(p + S_WMIX, ds.wmix);
     put_ptr(p + S_ALAG, ds.alag);
     for (int k = 0; k < d; ++k) p[S_DELTA + k] = ds.delta[k];
-    p[S_N] = ds.n;
-    p[S_SCALE] = 1.0 / (ds.n * ds.n * a.prodP);
-    p[S_CONST] = ds.scal[0];
+    p[S_N] = n;
+    p[S_SCALE] = 1.0 / (n * n * a.prodP);
     p[S_SING] = sing ? 1.0 : 0.0;
     for (int i = 0; i < 16; ++i) p[S_L + i] = L[i];
     if (status) status[h] = sing ? 1 : 0;
@@ -304,7 +369,7 @@ __device__ static double chunk_sum(const double* __restrict__ partial, int64_t h
     return wave_sum(s);
 }
 
-// SCV assembly, one wavefront per candidate.  kind: FUN_SCV_OBJ (obj only),
+// Criterion assembly, one wavefront per candidate.  kind: FUN_SCV_OBJ or FUN_ETA* (obj only),
 // FUN_SCV_OBJGRAD (obj + grad), FUN_SCV_GRAD (adjoint: grad scaled by grad_out).
 template <int D>
 __global__ __launch_bounds__(64) void k_scv_final(int kind, const double* __restrict__ partial, int64_t nchunks,
@@ -323,13 +388,11 @@ __global__ __launch_bounds__(64) void k_scv_final(int kind, const double* __rest
     const bool sing = p[S_SING] != 0.0;
     const double nan = __longlong_as_double(0x7ff8000000000000LL);
     const double* L = p + S_L;
-    double ldet = 1.0;
-    for (int k = 0; k < d; ++k) ldet *= fabs(L[k * 4 + k]);
-    double c4 = 1.0;  // (4 pi)^{-d/2}
-    for (int k = 0; k < d; ++k) c4 *= 0.28209479177387814347;
-    const double first = c4 / (p[S_N] * ldet);
+    // closed-form term: proportional to |H|^{-1/2} for every criterion with a
+    // gradient, so its matrix gradient is -1/2 first H^{-1}
+    const double first = p[S_FIRST];
     if (kind != FUN_SCV_GRAD) obj[h] = sing ? nan : first + T[0] + p[S_CONST];
-    if (kind == FUN_SCV_OBJ || grad == nullptr) return;
+    if (kind == FUN_SCV_OBJ || kind == FUN_ETA1 || kind == FUN_ETA2 || grad == nullptr) return;
     const int off = kind == FUN_SCV_OBJGRAD ? 1 : 0;
     double Hinv[16];
     chol_inv4<D>(L, Hinv);
@@ -360,6 +423,118 @@ hipError_t launch_scv_final(int kind, const double* partial, const RowGeom& geo,
         case 2: hipLaunchKernelGGL(k_scv_final<2>, grid, dim3(64), 0, s, kind, partial, geo.nchunks, ng, prm, ncand, grad_out, obj, grad); break;
         case 3: hipLaunchKernelGGL(k_scv_final<3>, grid, dim3(64), 0, s, kind, partial, geo.nchunks, ng, prm, ncand, grad_out, obj, grad); break;
         case 4: hipLaunchKernelGGL(k_scv_final<4>, grid, dim3(64), 0, s, kind, partial, geo.nchunks, ng, prm, ncand, grad_out, obj, grad); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Position of each Kronecker-ordered 4-index (i, j, k, l) (first slowest)
+// among the unique entries: sorted tuples in lexicographic order (Sec. 5).
+template <int D>
+struct Kron4 {
+    int u[D * D * D * D];
+    static constexpr Kron4 make() {
+        Kron4 t{};
+        int code[256] = {};
+        int cnt = 0;
+        for (int a = 0; a < D; ++a)
+            for (int b = a; b < D; ++b)
+                for (int c = b; c < D; ++c)
+                    for (int e = c; e < D; ++e) code[((a * D + b) * D + c) * D + e] = cnt++;
+        for (int f = 0; f < D * D * D * D; ++f) {
+            int v[4] = {f / (D * D * D), (f / (D * D)) % D, (f / D) % D, f % D};
+            for (int x = 0; x < 4; ++x)
+                for (int y = 0; y + 1 < 4 - x; ++y)
+                    if (v[y] > v[y + 1]) { const int tmp = v[y]; v[y] = v[y + 1]; v[y + 1] = tmp; }
+            t.u[f] = code[((v[0] * D + v[1]) * D + v[2]) * D + v[3]];
+        }
+        return t;
+    }
+};
+
+// Plug-in criterion, one thread per candidate:
+//   PI(H) = n^-1 (4 pi)^{-d/2} |H|^{-1/2} + 1/4 sum_{ijkl} H_ij H_kl psi_ijkl,
+//   grad_H = -1/2 (first term) H^{-1} + 1/2 sum_kl psi_ijkl H_kl,
+// chained to vech(L) by dPI/dL = lower(2 grad_H L).
+template <int D>
+__global__ void k_pi(PiArgs a, const double* __restrict__ psi4, const double* __restrict__ vechL, int64_t ncand,
+                     double* __restrict__ obj, double* __restrict__ grad, int32_t* __restrict__ status) {
+    const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (h >= ncand) return;
+    constexpr int d = D, q = D * (D + 1) / 2, NU = (D + 3) * (D + 2) * (D + 1) * D / 24;
+    constexpr Kron4<D> K = Kron4<D>::make();
+    int ds = 0;
+    double n = a.n[0];
+#pragma unroll
+    for (int jj = 1; jj < KDEFFT_MAX_BATCH_DS; ++jj)
+        if (jj < a.n_ds && h >= a.off[jj]) { ds = jj; n = a.n[jj]; }
+    const double* ps = psi4 + (int64_t)ds * NU;
+    double L[16], H[16];
+    for (int i = 0; i < 16; ++i) L[i] = 0.0;
+    int t = 0;
+    bool sing = false;
+    for (int jj = 0; jj < d; ++jj)
+        for (int i = jj; i < d; ++i) {
+            const double v = vechL[h * q + t++];
+            L[i * 4 + jj] = v;
+            if (!isfinite(v) || (i == jj && v == 0.0)) sing = true;
+        }
+    for (int i = 0; i < d; ++i)
+        for (int k2 = 0; k2 < d; ++k2) {
+            double s = 0.0;
+            for (int k = 0; k < d; ++k) s += L[i * 4 + k] * L[k2 * 4 + k];
+            H[i * 4 + k2] = s;
+        }
+    double ldet = 1.0;
+    for (int k = 0; k < d; ++k) ldet *= fabs(L[k * 4 + k]);
+    double c4 = 1.0;  // (4 pi)^{-d/2}
+    for (int k = 0; k < d; ++k) c4 *= 0.28209479177387814347;
+    const double first = sing ? 0.0 : c4 / (n * ldet);
+    // M_ij = sum_kl psi_ijkl H_kl
+    double Mq[16];
+    double quad = 0.0;
+#pragma unroll
+    for (int i = 0; i < d; ++i)
+#pragma unroll
+        for (int j = 0; j < d; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < d; ++k)
+#pragma unroll
+                for (int l = 0; l < d; ++l) s += ps[K.u[((i * D + j) * D + k) * D + l]] * H[k * 4 + l];
+            Mq[i * 4 + j] = s;
+            quad += H[i * 4 + j] * s;
+        }
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    if (status) status[h] = sing ? 1 : 0;
+    if (obj) obj[h] = sing ? nan : first + 0.25 * quad;
+    if (!grad) return;
+    double Hinv[16];
+    if (!sing) {
+        chol_inv4<D>(L, Hinv);
+    } else {
+        for (int i = 0; i < 16; ++i) Hinv[i] = 0.0;
+    }
+    double gH[16];
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) gH[i * 4 + j] = -0.5 * first * Hinv[i * 4 + j] + 0.5 * Mq[i * 4 + j];
+    int o = 0;
+    for (int j = 0; j < d; ++j)
+        for (int i = j; i < d; ++i) {
+            double s = 0.0;
+            for (int k = 0; k < d; ++k) s += gH[i * 4 + k] * L[k * 4 + j];
+            grad[h * q + o++] = sing ? nan : 2.0 * s;
+        }
+}
+
+hipError_t launch_pi(const PiArgs& a, const double* psi4, const double* vechL, int64_t ncand, double* obj,
+                     double* grad, int32_t* status, hipStream_t s) {
+    const int64_t blocks = (ncand + 63) / 64;
+    switch (a.d) {
+        case 1: hipLaunchKernelGGL(k_pi<1>, dim3((unsigned)blocks), dim3(64), 0, s, a, psi4, vechL, ncand, obj, grad, status); break;
+        case 2: hipLaunchKernelGGL(k_pi<2>, dim3((unsigned)blocks), dim3(64), 0, s, a, psi4, vechL, ncand, obj, grad, status); break;
+        case 3: hipLaunchKernelGGL(k_pi<3>, dim3((unsigned)blocks), dim3(64), 0, s, a, psi4, vechL, ncand, obj, grad, status); break;
+        case 4: hipLaunchKernelGGL(k_pi<4>, dim3((unsigned)blocks), dim3(64), 0, s, a, psi4, vechL, ncand, obj, grad, status); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

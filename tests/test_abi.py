@@ -169,3 +169,51 @@ def test_timing_hook_validation(kf):
     assert lib.kdefft_timing_stop(None, None, 0, None) == L.E_ARG
     assert lib.kdefft_timing_stop(None, None, 0, C.byref(cnt)) == L.OK and cnt.value == 0
     assert kf.timing_stop() == []
+
+
+def _fake_prepared(kf, d=2, M=16, n=100):
+    """A dataset descriptor that passes the host checks (pointers never touched)."""
+    ds = (kf._lib.Dataset * 1)()
+    ds[0].grid = _grid(kf, d, M)
+    ds[0].n = n
+    for f in ("counts", "spec", "wmix", "alag", "scal", "n_out", "rec"):
+        setattr(ds[0], f, 0x100000)
+    return ds
+
+
+def test_criterion_entry_validation(kf):
+    lib = kf._lib.load()
+    L = kf._lib
+    ds = _fake_prepared(kf)
+    fake = C.c_void_p(0x1000)
+    off = np.array([0, 4], dtype=np.int64)
+    cb = lib.kdefft_crit_batch
+    # gradient only for r = 0 and the SCV / LSCV criteria
+    assert cb(ds, 1, off.ctypes.data, fake, kf.CRIT_LSCV, 2, fake, fake, None, fake, 1 << 30, None) == L.E_UNSUPPORTED
+    assert cb(ds, 1, off.ctypes.data, fake, kf.CRIT_QR, 0, fake, fake, None, fake, 1 << 30, None) == L.E_UNSUPPORTED
+    assert cb(ds, 1, off.ctypes.data, fake, 7, 0, fake, None, None, fake, 1 << 30, None) == L.E_ARG
+    assert cb(ds, 1, off.ctypes.data, fake, kf.CRIT_QR, 9, fake, None, None, fake, 1 << 30, None) == L.E_ARG
+    assert cb(ds, 1, off.ctypes.data, fake, kf.CRIT_SCV, 2, fake, None, None, fake, 1 << 30, None) == L.E_UNSUPPORTED
+    assert cb(ds, 1, off.ctypes.data, fake, kf.CRIT_LSCV, 0, None, None, None, fake, 1 << 30, None) == L.E_ARG
+    assert cb(ds, 1, off.ctypes.data, fake, kf.CRIT_LSCV, 0, fake, None, None, fake, 64, None) == L.E_WORKSPACE
+    ds1 = _fake_prepared(kf, n=1)
+    assert cb(ds1, 1, off.ctypes.data, fake, kf.CRIT_LSCV_EXACT, 0, fake, None, None, fake, 1 << 30,
+              None) == L.E_ARG
+    ca = lib.kdefft_crit_adjoint
+    assert ca(ds, 1, off.ctypes.data, fake, kf.CRIT_QR, fake, fake, fake, 1 << 30, None) == L.E_UNSUPPORTED
+    assert ca(ds, 1, off.ctypes.data, fake, kf.CRIT_LSCV, None, fake, fake, 1 << 30, None) == L.E_ARG
+    pb = lib.kdefft_pi_batch
+    nn = np.array([100], dtype=np.int64)
+    assert pb(5, 1, nn.ctypes.data, fake, off.ctypes.data, fake, fake, None, None, None) == L.E_ARG
+    assert pb(2, 0, nn.ctypes.data, fake, off.ctypes.data, fake, fake, None, None, None) == L.E_ARG
+    assert pb(2, 1, nn.ctypes.data, fake, off.ctypes.data, fake, None, None, None, None) == L.E_ARG
+    bad = np.array([1, 4], dtype=np.int64)
+    assert pb(2, 1, nn.ctypes.data, fake, bad.ctypes.data, fake, fake, None, None, None) == L.E_ARG
+    n0 = np.array([0], dtype=np.int64)
+    assert pb(2, 1, n0.ctypes.data, fake, off.ctypes.data, fake, fake, None, None, None) == L.E_ARG
+
+
+@pytest.mark.parametrize("d,r", [(1, 0), (1, 4), (2, 0), (2, 4), (3, 2), (3, 4), (4, 4), (2, 8), (4, 3)])
+def test_expand_full_matches_oracle(kf, d, r):
+    u = np.arange(1, multiindex.n_unique(d, r) + 1, dtype=np.float64) * 1.5
+    np.testing.assert_array_equal(kf.expand_full(u, d, r), multiindex.expand_full(u, d, r))
