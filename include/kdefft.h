@@ -123,6 +123,7 @@ typedef struct kdefft_dataset {
 #define KDEFFT_OP_SCV_BATCH 6   /* kdefft_scv_batch / kdefft_scv_adjoint: batch = total H */
 #define KDEFFT_OP_SCV_PLAIN 7   /* kdefft_scv_plain */
 #define KDEFFT_OP_AUTOTUNE 8    /* kdefft_autotune */
+#define KDEFFT_OP_PSI_FFTL 9    /* kdefft_psi_fftl (sized for the largest Eq. (27) padding) */
 
 /* psi modes */
 #define KDEFFT_PSI_PLAIN 0  /* the paper's steps literally: per entry, kernel grid ->
@@ -181,6 +182,25 @@ int kdefft_linbin(const double* X, int64_t n, const kdefft_grid* g,
  * Out-of-grid points are dropped (see kdefft_check_binning on the workspace). */
 int kdefft_psi(const double* X, int64_t n, const kdefft_grid* g, const double* G_host,
                int r, double* psi, int mode, void* ws, size_t ws_bytes, void* stream);
+
+/* fft-L sizes (Sec. 4, Eq. (26)-(27)) for bandwidth matrix S_host (d x d
+ * row-major, SPD) on grid g: L_k = min(M_k - 1, ceil(tau sqrt(lambda)/delta_k))
+ * with lambda the largest eigenvalue of S (Jacobi rotations on the host), and
+ * P_k the smallest power of two >= M_k + 2 L_k - 1.  The paper suggests
+ * tau = 3.7 for the two-dimensional normal kernel.  L_host, P_host: int32 [d].
+ * Host only. */
+int kdefft_fftl_plan(const kdefft_grid* g, const double* S_host, double tau, int32_t* L_host,
+                     int32_t* P_host);
+
+/* psi_r(G) by the paper's fft-L variant (Eq. (25)-(27)): the kernel support is
+ * cut to |l_k| <= L_k (L from G by kdefft_fftl_plan) and the transforms use the
+ * Eq. (27) lengths P_k instead of g's; otherwise the literal four steps of
+ * kdefft_psi(PLAIN).  An approximation of Eq. (17): lags beyond L_k are
+ * dropped.  L_host, P_host (int32 [d], may be NULL) receive the sizes used.
+ * Workspace: KDEFFT_OP_PSI_FFTL.  KDEFFT_E_UNSUPPORTED if some P_k > 4096. */
+int kdefft_psi_fftl(const double* X, int64_t n, const kdefft_grid* g, const double* G_host, int r,
+                    double tau, double* psi, int32_t* L_host, int32_t* P_host, void* ws,
+                    size_t ws_bytes, void* stream);
 
 /* Synchronize `stream` and return KDEFFT_E_OUT_OF_GRID if the int32 counter
  * n_out_dev is non-zero (its value is stored in *n_out_host if not NULL). */

@@ -40,8 +40,9 @@ def plan_P(M, L):
     return out
 
 
-def psi_truncated(A, n, g, G, r, L):
-    """Binned psi_r(G) over the lags |l_k| <= L_k only (Eq. (25))."""
+def psi_truncated(A, n, g, G, r, L, absval=False):
+    """Binned psi_r(G) over the lags |l_k| <= L_k only (Eq. (25)); absval: the
+    same sum of |kernel| (scale for near-zero entries)."""
     d = g["d"]
     M = [int(m) for m in g["M"]]
     alphas = multiindex.unique_alphas(d, r)
@@ -51,4 +52,6 @@ def psi_truncated(A, n, g, G, r, L):
     axes = [np.arange(-l, l + 1) * g["delta"][k] for k, l in enumerate(L)]
     mesh = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1)
     vals = gauss.dphi_many(mesh, G, alphas)
+    if absval:
+        vals = np.abs(vals)
     return np.array([math.fsum((vals[t] * Ab).ravel()) for t in range(len(alphas))]) / float(n) ** 2

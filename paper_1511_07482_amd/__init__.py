@@ -26,7 +26,7 @@ from ._lib import FUN_PSI, FUN_SCV_GRAD, FUN_SCV_OBJ, FUN_SCV_OBJGRAD, Grid, Kde
 __all__ = ["Grid", "Dataset", "KdefftError", "grid_plan", "grid_auto", "linbin", "psi", "psi_batch", "scv",
            "scv_adjoint", "scv_plain", "SCV", "unique_tuples", "autotune", "set_row_launch", "library_path",
            "timing_start", "timing_stop", "crit", "crit_adjoint", "pi", "expand_full", "Criterion", "PI",
-           "CRIT_SCV", "CRIT_LSCV", "CRIT_LSCV_EXACT", "CRIT_QR"]
+           "CRIT_SCV", "CRIT_LSCV", "CRIT_LSCV_EXACT", "CRIT_QR", "fftl_plan", "psi_fftl"]
 
 
 def library_path():
@@ -135,6 +135,39 @@ def psi(X: torch.Tensor, G, r: int, M=None, grid: Optional[Grid] = None, mode: s
     _lib.check(_L().kdefft_psi(_ptr(X), n, C.byref(grid), Gm.ctypes.data, r, _ptr(out), m, _ptr(ws), ws.numel(),
                                _stream(X.device)), "kdefft_psi")
     return out
+
+
+def fftl_plan(grid: Grid, S, tau: float = 3.7):
+    """(L, P) of the fft-L variant (Eq. (26)-(27)) for bandwidth S on grid."""
+    d = grid.d
+    Sm = _mat(S, d, "S")
+    L = np.zeros(d, dtype=np.int32)
+    P = np.zeros(d, dtype=np.int32)
+    _lib.check(_L().kdefft_fftl_plan(C.byref(grid), Sm.ctypes.data, float(tau), L.ctypes.data, P.ctypes.data),
+               "kdefft_fftl_plan")
+    return L.tolist(), P.tolist()
+
+
+def psi_fftl(X: torch.Tensor, G, r: int, M=None, grid: Optional[Grid] = None, tau: float = 3.7,
+             pad_sd: float = 4.0):
+    """psi_r(G) by the fft-L variant (kernel support cut to |l_k| <= L_k,
+    transforms of the Eq. (27) lengths); returns (psi, L, P)."""
+    X = _as_X(X)
+    n, d = X.shape
+    Gm = _mat(G, d, "G")
+    if grid is None:
+        if M is None:
+            raise ValueError("give M or grid")
+        grid = grid_auto(X, Gm, M, pad_sd)
+    ws = _ws(grid, _lib.OP_PSI_FFTL, r, 1, X.device)
+    cnt = _L().kdefft_unique_count(d, r)
+    out = torch.empty(max(cnt, 1), dtype=torch.float64, device=X.device)
+    L = np.zeros(d, dtype=np.int32)
+    P = np.zeros(d, dtype=np.int32)
+    _lib.check(_L().kdefft_psi_fftl(_ptr(X), n, C.byref(grid), Gm.ctypes.data, r, float(tau), _ptr(out),
+                                    L.ctypes.data, P.ctypes.data, _ptr(ws), ws.numel(), _stream(X.device)),
+               "kdefft_psi_fftl")
+    return out, L.tolist(), P.tolist()
 
 
 class Dataset:

@@ -144,6 +144,54 @@ double normal_const(const double* L, int d) {  // (2 pi)^{-d/2} / prod L_kk
     return c;
 }
 
+// Largest eigenvalue of a symmetric d x d (row-major) matrix by cyclic Jacobi
+// rotations (d <= 4; converges to rounding level in a few sweeps).
+double max_eig_sym(const double* A_host, int d) {
+    double a[4][4];
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) a[i][j] = 0.5 * (A_host[i * d + j] + A_host[j * d + i]);
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0;
+        for (int i = 0; i < d; ++i)
+            for (int j = i + 1; j < d; ++j) off += a[i][j] * a[i][j];
+        if (off == 0.0) break;
+        for (int p = 0; p < d; ++p)
+            for (int q = p + 1; q < d; ++q) {
+                if (a[p][q] == 0.0) continue;
+                const double th = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < d; ++k) {  // columns p, q
+                    const double akp = a[k][p], akq = a[k][q];
+                    a[k][p] = c * akp - sn * akq;
+                    a[k][q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < d; ++k) {  // rows p, q
+                    const double apk = a[p][k], aqk = a[q][k];
+                    a[p][k] = c * apk - sn * aqk;
+                    a[q][k] = sn * apk + c * aqk;
+                }
+            }
+    }
+    double m = a[0][0];
+    for (int i = 1; i < d; ++i) m = std::max(m, a[i][i]);
+    return m;
+}
+
+// fft-L sizes (Eq. (26)-(27)) for bandwidth S on grid g.
+void fftl_sizes(const kdefft_grid& g, const double* S_host, double tau, int32_t* L, int32_t* P) {
+    const double lam = max_eig_sym(S_host, g.d);
+    for (int k = 0; k < g.d; ++k) {
+        const double v = std::ceil(tau * std::sqrt(std::fabs(lam)) / g.delta[k]);
+        const int lk = v < (double)(g.M[k] - 1) ? (int)v : g.M[k] - 1;
+        L[k] = lk;
+        const int64_t x = (int64_t)g.M[k] + 2 * (int64_t)lk - 1;
+        int64_t p = 1;
+        while (p < x) p *= 2;
+        P[k] = (int32_t)p;
+    }
+}
+
 struct Arena {
     char* base;
     size_t cap;
@@ -352,6 +400,17 @@ int plan_bytes(const kdefft_grid& g, int op, int r, int64_t batch, Arena& a) {
             carve_batch(a, g, FUN_SCV_OBJGRAD, 2, std::max<int64_t>(batch, 1));
             return KDEFFT_OK;
         case KDEFFT_OP_SCV_PLAIN: carve_plain(a, g, false); return KDEFFT_OK;
+        case KDEFFT_OP_PSI_FFTL: {
+            // the largest padded grid Eq. (27) can ask for (L_k = M_k - 1)
+            kdefft_grid gm = g;
+            for (int k = 0; k < g.d; ++k) {
+                int p = 4;
+                while (p < 3 * g.M[k] - 3) p *= 2;
+                gm.P[k] = p;
+            }
+            carve_plain(a, gm, true);
+            return KDEFFT_OK;
+        }
         case KDEFFT_OP_AUTOTUNE: {
             carve_batch(a, g, FUN_SCV_OBJGRAD, 2, TUNE_B);
             const int q = g.d * (g.d + 1) / 2;
@@ -577,7 +636,7 @@ int kdefft_ws_bytes(const kdefft_grid* g, int op, int r, int64_t batch, size_t* 
     if (!out) return fail(KDEFFT_E_ARG, "out is NULL");
     int rc = check_grid(g);
     if (rc) return rc;
-    if (op == KDEFFT_OP_PSI_PLAIN || op == KDEFFT_OP_PSI_FUSED || op == KDEFFT_OP_PSI_BATCH) {
+    if (op == KDEFFT_OP_PSI_PLAIN || op == KDEFFT_OP_PSI_FUSED || op == KDEFFT_OP_PSI_BATCH || op == KDEFFT_OP_PSI_FFTL) {
         rc = check_d_r(g->d, r);
         if (rc) return rc;
     }
@@ -710,6 +769,76 @@ int kdefft_psi(const double* X, int64_t n, const kdefft_grid* g, const double* G
     const RowGeom geo = make_geom(*g, FUN_PSI, r, 1, rl.variant);
     HIPCHK(timed_rows(FUN_PSI, d, r, geo, b.prm, 1, b.partial, rl, s), "psi rows");
     HIPCHK(launch_psi_final(b.partial, geo, nu, b.prm, 1, psi, nullptr, s), "psi final");
+    return KDEFFT_OK;
+}
+
+int kdefft_fftl_plan(const kdefft_grid* g, const double* S_host, double tau, int32_t* L_host, int32_t* P_host) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!L_host || !P_host) return fail(KDEFFT_E_ARG, "NULL output");
+    if (!(tau > 0.0) || !std::isfinite(tau)) return fail(KDEFFT_E_ARG, "tau must be positive and finite");
+    double Ls[16];
+    rc = check_spd(S_host, g->d, "S", Ls);
+    if (rc) return rc;
+    fftl_sizes(*g, S_host, tau, L_host, P_host);
+    return KDEFFT_OK;
+}
+
+int kdefft_psi_fftl(const double* X, int64_t n, const kdefft_grid* g, const double* G_host, int r, double tau,
+                    double* psi, int32_t* L_host, int32_t* P_host, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    rc = check_d_r(g->d, r);
+    if (rc) return rc;
+    rc = check_n(n);
+    if (rc) return rc;
+    if (!X || !psi) return fail(KDEFFT_E_ARG, "NULL X or psi");
+    if (!(tau > 0.0) || !std::isfinite(tau)) return fail(KDEFFT_E_ARG, "tau must be positive and finite");
+    double L[16];
+    rc = check_spd(G_host, g->d, "G", L);
+    if (rc) return rc;
+    if (!ws) return fail(KDEFFT_E_ARG, "workspace is NULL");
+    const int d = g->d;
+    int32_t Lk[4] = {0, 0, 0, 0}, Pk[4] = {0, 0, 0, 0};
+    fftl_sizes(*g, G_host, tau, Lk, Pk);
+    if (L_host)
+        for (int k = 0; k < d; ++k) L_host[k] = Lk[k];
+    if (P_host)
+        for (int k = 0; k < d; ++k) P_host[k] = Pk[k];
+    // g2: the data grid padded per Eq. (27); gk: the same lengths with the
+    // kernel support cut to |l_k| <= L_k (lags beyond are zero-filled)
+    kdefft_grid g2 = *g, gk = *g;
+    double total = 1.0;
+    for (int k = 0; k < d; ++k) {
+        if (Pk[k] > KDEFFT_MAX_P) return fail(KDEFFT_E_UNSUPPORTED, "Eq. (27) gives P[%d]=%d > %d", k, Pk[k], KDEFFT_MAX_P);
+        g2.P[k] = gk.P[k] = Pk[k];
+        gk.M[k] = Lk[k] + 1;
+        total *= Pk[k];
+    }
+    if (total > (double)(1LL << 30)) return fail(KDEFFT_E_UNSUPPORTED, "prod P = %.0f exceeds 2^30", total);
+    const Sizes sz = sizes_of(g2);
+    const double scale = 1.0 / ((double)n * (double)n * (double)sz.prodP);
+    const int nu = (int)binom(d + r - 1, r);
+    hipStream_t s = S(stream);
+    Arena a(ws, ws_bytes, false);
+    const PlainScratch p = carve_plain(a, g2, true);
+    rc = check_ws(a, ws_bytes);
+    if (rc) return rc;
+    ParamBlock prm{};
+    chol_inv_host(L, d, prm.v + S_P1);
+    prm.v[S_C] = normal_const(L, d);
+    rc = bin_and_fill(X, n, g2, p.counts, p.n_out, p.czp, s);
+    if (rc) return rc;
+    HIPCHK(fft_r2c_nd(p.czp, p.C, g2, s), "R2C counts");
+    const int nb = nblk_dot(g2);
+    for (int u = 0; u < nu; ++u) {
+        HIPCHK(launch_kgrid_psi(p.kreal, gk, r, prm, u, s), "truncated kernel grid");
+        HIPCHK(fft_r2c_nd(p.kreal, p.K, g2, s), "R2C kernel");
+        HIPCHK(launch_cmul(p.K, p.C, sz.spec, s), "spectrum product");
+        HIPCHK(fft_c2r_nd(p.K, p.kreal, g2, s), "C2R");
+        HIPCHK(launch_dot_counts(p.counts, p.kreal, g2, p.partial, nb, s), "count contraction");
+        HIPCHK(launch_sum_scale(p.partial, nb, scale, psi + u, s), "final sum");
+    }
     return KDEFFT_OK;
 }
 

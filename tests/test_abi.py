@@ -217,3 +217,43 @@ def test_criterion_entry_validation(kf):
 def test_expand_full_matches_oracle(kf, d, r):
     u = np.arange(1, multiindex.n_unique(d, r) + 1, dtype=np.float64) * 1.5
     np.testing.assert_array_equal(kf.expand_full(u, d, r), multiindex.expand_full(u, d, r))
+
+
+def test_fftl_plan_table2_from_table3(kf, repo_root):
+    """The library's Eq. (27) turns Table 3's L values into Table 2's P values:
+    pick S and delta so that Eq. (26) returns exactly the printed L."""
+    from test_oracle_fftl import _tables
+    L, P = _tables(repo_root)
+    for (n, M) in sorted(set(L) & set(P)):
+        # axis spacings chosen so that 3.7 * sqrt(1) / delta_k is just below L_k
+        lo = np.zeros(2)
+        hi = np.array([3.7 / (L[(n, M)][0] - 0.5) * (M - 1), 3.7 / (L[(n, M)][1] - 0.5) * (M - 1)])
+        g = kf.grid_plan([M, M], lo, hi)
+        Lg, Pg = kf.fftl_plan(g, np.eye(2))
+        assert tuple(Lg) == L[(n, M)] and tuple(Pg) == P[(n, M)], (n, M, Lg, Pg)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_fftl_plan_matches_oracle(kf, d):
+    from oracle import fftl
+    rng = np.random.default_rng(60 + d)
+    checked = 0
+    for t in range(40):
+        M = [int(m) for m in rng.integers(8, 200 if d <= 2 else 40, size=d)]
+        lo = rng.normal(size=d)
+        hi = lo + rng.uniform(1.0, 6.0, size=d)
+        g = kf.grid_plan(M, lo, hi)
+        Q, _ = np.linalg.qr(rng.normal(size=(d, d)))
+        S = Q @ np.diag(10 ** rng.uniform(-3, 0, d)) @ Q.T
+        S = 0.5 * (S + S.T)
+        tau = float(rng.uniform(2.0, 5.0))
+        gd = g.to_dict()
+        lam = float(np.max(np.linalg.eigvalsh(S)))
+        ratios = tau * np.sqrt(lam) / gd["delta"]
+        if np.any(np.abs(ratios - np.round(ratios)) < 1e-9):
+            continue   # a ceiling at an exact integer could round either way
+        Lg, Pg = kf.fftl_plan(g, S, tau)
+        Lo = fftl.plan_L(gd, S, tau)
+        assert Lg == Lo and Pg == fftl.plan_P(M, Lo), (M, Lg, Lo)
+        checked += 1
+    assert checked >= 30
