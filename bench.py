@@ -252,6 +252,9 @@ def main():
                  "achieved_tflops": spec_flops / (spec_ms * 1e-3) / 1e12,
                  "frac": spec_flops / (spec_ms * 1e-3) / PEAK_FP64_VECTOR}
 
+    crit_out = criteria_section(kf, torch, ds, vechL, Gpsi, n, B)
+    fftl_out = fftl_section(kf, torch, dev, X, Gpsi, g)
+
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(X_h, Gp, H, M, a.cpu_h)
@@ -288,10 +291,85 @@ def main():
                                "batched_vs_plain": (B / t_scv_only) * t_plain,
                                "autograd_vs_plain": (B / t_autograd) * t_plain,
                                "step_vs_plain_with_binning": value * t_plain_prep},
+        "criteria_256": crit_out,
+        "fftl": fftl_out,
         "tuned": tuned,
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(out))
+
+
+def _kernel_and_call(kf, torch, fn, reps=10):
+    """(mean row-kernel ms from the library's HIP events, mean wall ms per call)."""
+    for _ in range(2):
+        fn()
+    torch.cuda.synchronize()
+    kf.timing_start(4 * reps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps * 1e3
+    recs = kf.timing_stop()
+    kern = float(np.mean([ms for ms, _, _ in recs])) if recs else None
+    return kern, wall
+
+
+def criteria_section(kf, torch, ds, vechL, Gpsi, n, B):
+    """The other criteria on the same prepared case-4 dataset and candidates:
+    LSCV (paper's objective) with gradient, LSCV_4 and Q_4 (scalar eta_r
+    kernels), and PI (psi_4 at the psi pilot + closed-form contraction)."""
+    out = {}
+    for name, fn in (
+        ("lscv_objgrad", lambda: kf.crit([ds], vechL, "lscv", 0)),
+        ("lscv_exact_objgrad", lambda: kf.crit([ds], vechL, "lscv_exact", 0)),
+        ("lscv4_obj", lambda: kf.crit([ds], vechL, "lscv", 4, grad=False)),
+        ("qr4", lambda: kf.crit([ds], vechL, "qr", 4, grad=False)),
+        ("qr8", lambda: kf.crit([ds], vechL, "qr", 8, grad=False)),
+    ):
+        kern, wall = _kernel_and_call(kf, torch, fn)
+        out[name] = {"row_kernel_ms": kern, "call_ms": wall, "evals_per_s": B / (wall * 1e-3)}
+
+    def pi_step():
+        p4 = kf.psi_batch([ds], [Gpsi], 4)
+        return kf.pi(p4, [n], vechL)
+    kern, wall = _kernel_and_call(kf, torch, pi_step)
+    out["pi_objgrad_with_psi4"] = {"psi4_row_kernel_ms": kern, "call_ms": wall, "evals_per_s": B / (wall * 1e-3)}
+    return out
+
+
+def fftl_section(kf, torch, dev, X, Gpsi, g):
+    """The paper's fft-L variant against the full-support plain route (fft-M),
+    binning included as in the paper's timing: its speed-experiment shape
+    (d = 2, N(0, I), n = 4000, M = 160, psi_0) and the case-2 shape (psi_4)."""
+    rng = np.random.default_rng(151107482 + 60)
+    Xs = rng.standard_normal((4000, 2))
+    Gs = 4000 ** (-2.0 / 6.0) * np.cov(Xs.T)
+    Xt = torch.from_numpy(Xs).to(dev)
+    gs = kf.grid_auto(Xt, Gs, 160)
+    res = {}
+    for label, XX, G, gg, r in (("paper_shape_n4000_M160_psi0", Xt, Gs, gs, 0), ("case2_shape_psi4", X, Gpsi, g, 4)):
+        def full():
+            return kf.psi(XX, G, r, grid=gg, mode="plain")
+
+        def trunc():
+            return kf.psi_fftl(XX, G, r, grid=gg)
+        t = {}
+        for nm, fn in (("fft_M_ms", full), ("fft_L_ms", trunc)):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                fn()
+            torch.cuda.synchronize()
+            t[nm] = (time.perf_counter() - t0) / 5 * 1e3
+        vf = full().cpu().numpy()
+        vt, L, P = trunc()
+        vt = vt.cpu().numpy()
+        t.update({"L": L, "P_fft_L": P, "P_fft_M": [int(p) for p in gg.P[:gg.d]],
+                  "max_rel_diff": float(np.max(np.abs(vt - vf) / np.abs(vf)))})
+        res[label] = t
+    return res
 
 
 def fft_stage_bytes(P, d):

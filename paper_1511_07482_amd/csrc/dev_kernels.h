@@ -156,6 +156,34 @@ struct ScvFun {
     }
     __device__ __forceinline__ const double* Pm(int k) const { return k == 0 ? P1 : P2; }
     __device__ __forceinline__ double cn(int k) const { return k == 0 ? c1 : c2; }
+    // Moment form along a run of lags t = 0, 1, ...: z_k(t) = z_k + t dz_k is
+    // linear in t, so with w_k(t) = e_k(t) A(t) every output is a polynomial of
+    // degree <= 2 in t weighted by w_k, and the run needs only the moments
+    // m_k[p] = sum_t t^p w_k(t), p < NMOM, folded in once per run:
+    //   sum_t w (z_i z_j - P_ij)(t) = z_i z_j m0 + (z_i dz_j + dz_i z_j) m1 + dz_i dz_j m2 - P_ij m0.
+    static constexpr int NMOM = MODE == 0 ? 1 : 3;
+    __device__ __forceinline__ void fold(const double (*z)[D], const double (*dz)[D], const double (*m)[3],
+                                         double* acc) const {
+        int o = 0;
+        if constexpr (MODE != 2) acc[o++] += m[0][0] - 2.0 * m[1][0];
+        if constexpr (MODE != 0) {
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = i; j < D; ++j) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) {
+                        const double* P = k == 0 ? P1 : P2;
+                        const double t = (z[k][i] * z[k][j] - P[i * D + j]) * m[k][0] +
+                                         (z[k][i] * dz[k][j] + dz[k][i] * z[k][j]) * m[k][1] +
+                                         dz[k][i] * dz[k][j] * m[k][2];
+                        v += k == 0 ? t : -t;
+                    }
+                    acc[o++] += v;
+                }
+        }
+    }
     __device__ __forceinline__ void combine(const double (*z)[D], const double* e, double* out) const {
         int o = 0;
         if constexpr (MODE != 2) out[o++] = e[0] - 2.0 * e[1];
@@ -302,6 +330,12 @@ struct EtaFun {
     }
     __device__ __forceinline__ void eval(const double* x, double* out) const;
 };
+
+// Families that provide the moment form (fold) along a run of lags.
+template <class Fun, class = void>
+struct HasMoments { static constexpr bool value = false; };
+template <class Fun>
+struct HasMoments<Fun, decltype((void)Fun::NMOM)> { static constexpr bool value = true; };
 
 // Direct evaluation at one lag x.
 template <class Fun, int D>

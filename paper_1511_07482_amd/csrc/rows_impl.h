@@ -360,6 +360,10 @@ __global__ __launch_bounds__(NT) void k_lag(const double* __restrict__ prm, RowG
     __shared__ double red[(NT / 64) * NG];
     const int M_last = geo.M[D - 1];
     const int nrun = (2 * M_last - 1 + RUN - 1) / RUN;
+    // thread t takes the (row, run) pairs t, t + NT, ... of its item in row-major
+    // order; the pair is advanced incrementally (no division in the loop)
+    const int step_ro = NT / nrun, step_j = NT % nrun;
+    const int ro0 = (int)threadIdx.x / nrun, j0 = (int)threadIdx.x % nrun;
     for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int64_t h = item / geo.nchunks;
         const int64_t ch = item - h * geo.nchunks;
@@ -386,10 +390,9 @@ __global__ __launch_bounds__(NT) void k_lag(const double* __restrict__ prm, RowG
         for (int g = 0; g < NG; ++g) acc[g] = 0.0;
         const int64_t rbeg = ch * geo.chunk;
         const int64_t rend = rbeg + geo.chunk < geo.nrows ? rbeg + geo.chunk : geo.nrows;
-        const int64_t total = (rend - rbeg) * nrun;
-        for (int64_t e = threadIdx.x; e < total; e += NT) {
-            const int64_t ro = e / nrun;
-            const int j = (int)(e - ro * nrun);
+        const int nro = (int)(rend - rbeg);   // rows of one item < 2^31
+        for (int ro = ro0, j = j0; ro < nro; ro += step_ro + (j + step_j >= nrun ? 1 : 0),
+                 j = j + step_j >= nrun ? j + step_j - nrun : j + step_j) {
             const RowInfo ri = row_info<D>(rbeg + ro, rend, geo, delta, nullptr);
             const double* __restrict__ Arow = A + ri.wr * N;
             const int lag0 = -(M_last - 1) + j * RUN;
@@ -398,7 +401,7 @@ __global__ __launch_bounds__(NT) void k_lag(const double* __restrict__ prm, RowG
             for (int k = 0; k < D - 1; ++k) x[k] = ri.x[k];
             x[D - 1] = dl * (double)lag0;
             double z[NGS][D], ev[NGS], rho[NGS];
-            bool direct = false;
+            bool direct = false, alive = false;
 #pragma unroll
             for (int k = 0; k < NGS; ++k) {
                 const double* P = f.Pm(k);
@@ -413,8 +416,17 @@ __global__ __launch_bounds__(NT) void k_lag(const double* __restrict__ prm, RowG
                 }
                 ev[k] = f.cn(k) * exp(-0.5 * q);
                 rho[k] = exp(-(dl * z[k][D - 1] + hpl[k]));
-                direct = direct || !(ev[k] >= 1e-290) || !(rho[k] <= 1e200);
+                // ratios along the run are rho, rho sig, ... with sig < 1: if the
+                // first value is below 1e-290 and rho <= 1 the whole run is, and
+                // it adds nothing a float64 sum can hold next to the lag-0 term
+                if (!(ev[k] >= 1e-290) && rho[k] <= 1.0) {
+                    ev[k] = 0.0;
+                } else {
+                    direct = direct || !(ev[k] >= 1e-290) || !(rho[k] <= 1e200);
+                    alive = true;
+                }
             }
+            if (!alive) continue;
 #pragma unroll
             for (int t = 0; t < RUN; ++t) {
                 const int lag = lag0 + t;
@@ -448,6 +460,163 @@ __global__ __launch_bounds__(NT) void k_lag(const double* __restrict__ prm, RowG
     }
 }
 
+// Lag-domain evaluation for the families with a moment form (SCV / LSCV):
+// runs of RL consecutive array positions of the circular row (see below),
+// their RL autocorrelation values loaded as one aligned block, and per run
+// only the moments sum_t t^p e(t) A(t) of each Gaussian (Fun::fold).
+template <int D, int N, class Fun, int NT, int RUN>
+__global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, RowGeom geo, int64_t nitems,
+                                            double* __restrict__ partial) {
+    constexpr int NG = Fun::NG;
+    constexpr int NGS = Fun::NGAUSS;
+    // Runs of RL consecutive array positions of the circular row: p in [0, N/2)
+    // holds lags p, p in [N/2, N) lags p - N; N/2 is a multiple of RL, so a run
+    // never mixes the two sides, its lags are consecutive, and its RL values of
+    // the autocorrelation form one aligned block that is loaded at once.
+    // Positions outside |lag| <= M-1 (the zero slots) get weight 0.
+    constexpr int RL = RUN < N / 2 ? RUN : N / 2;
+    constexpr int nrun = N / RL;
+    __shared__ double red[(NT / 64) * NG];
+    const int M_last = geo.M[D - 1];
+    // thread t takes the (row, run) pairs t, t + NT, ... of its item in row-major
+    // order; the pair is advanced incrementally (no division in the loop)
+    constexpr int step_ro = NT / nrun, step_j = NT % nrun;
+    const int ro0 = (int)threadIdx.x / nrun, j0 = (int)threadIdx.x % nrun;
+    for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int64_t h = item / geo.nchunks;
+        const int64_t ch = item - h * geo.nchunks;
+        const double* pr = prm + h * PRM;
+        Fun f;
+        f.load(pr);
+        double delta[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) delta[k] = pr[S_DELTA + k];
+        const double* __restrict__ A =
+            reinterpret_cast<const double*>(static_cast<uintptr_t>(__double_as_longlong(pr[S_ALAG])));
+        const double dl = delta[D - 1];
+        double dz[NGS][D], sig[NGS], hpl[NGS];
+#pragma unroll
+        for (int k = 0; k < NGS; ++k) {
+            const double* P = f.Pm(k);
+#pragma unroll
+            for (int i = 0; i < D; ++i) dz[k][i] = dl * P[i * D + D - 1];
+            hpl[k] = 0.5 * dl * dl * P[(D - 1) * D + D - 1];
+            sig[k] = exp(-2.0 * hpl[k]);
+        }
+        double acc[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) acc[g] = 0.0;
+        const int64_t rbeg = ch * geo.chunk;
+        const int64_t rend = rbeg + geo.chunk < geo.nrows ? rbeg + geo.chunk : geo.nrows;
+        const int nro = (int)(rend - rbeg);   // rows of one item < 2^31
+        for (int ro = ro0, j = j0; ro < nro; ro += step_ro + (j + step_j >= nrun ? 1 : 0),
+                 j = j + step_j >= nrun ? j + step_j - nrun : j + step_j) {
+            const int p0 = j * RL;
+            const bool pos = p0 < N / 2;
+            const int lag0 = pos ? p0 : p0 - N;
+            // runs that lie wholly in the zero slots
+            if (pos ? lag0 > M_last - 1 : lag0 + RL - 1 < -(M_last - 1)) continue;
+            const RowInfo ri = row_info<D>(rbeg + ro, rend, geo, delta, nullptr);
+            const double* __restrict__ Arow = A + ri.wr * N + p0;
+            double av[RL];
+            if constexpr (RL % 2 == 0) {
+                const double2* a2 = reinterpret_cast<const double2*>(Arow);
+#pragma unroll
+                for (int t = 0; t < RL / 2; ++t) {
+                    const double2 v = a2[t];
+                    av[2 * t] = v.x;
+                    av[2 * t + 1] = v.y;
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < RL; ++t) av[t] = Arow[t];
+            }
+#pragma unroll
+            for (int t = 0; t < RL; ++t) {
+                const int lag = lag0 + t;
+                const bool ok = pos ? lag <= M_last - 1 : lag >= -(M_last - 1);
+                av[t] = ok ? ri.rw * av[t] : 0.0;
+            }
+            double x[D];
+#pragma unroll
+            for (int k = 0; k < D - 1; ++k) x[k] = ri.x[k];
+            x[D - 1] = dl * (double)lag0;
+            double z[NGS][D], ev[NGS], rho[NGS];
+            bool direct = false, alive = false;
+#pragma unroll
+            for (int k = 0; k < NGS; ++k) {
+                const double* P = f.Pm(k);
+                double q = 0.0;
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int jj = 0; jj < D; ++jj) s += P[i * D + jj] * x[jj];
+                    z[k][i] = s;
+                    q += x[i] * s;
+                }
+                ev[k] = f.cn(k) * exp(-0.5 * q);
+                rho[k] = exp(-(dl * z[k][D - 1] + hpl[k]));
+                // ratios along the run are rho, rho sig, ... with sig < 1: if the
+                // first value is below 1e-290 and rho <= 1 the whole run is, and
+                // it adds nothing a float64 sum can hold next to the lag-0 term
+                if (!(ev[k] >= 1e-290) && rho[k] <= 1.0) {
+                    ev[k] = 0.0;
+                } else {
+                    direct = direct || !(ev[k] >= 1e-290) || !(rho[k] <= 1e200);
+                    alive = true;
+                }
+            }
+            if (!alive) continue;
+            if (direct) {
+                // exact evaluation lag by lag (values near the float64 range
+                // limits; rare): a rolled loop keeps one copy of the evaluation
+#pragma unroll 1
+                for (int t = 0; t < RL; ++t) {
+                    const int lag = lag0 + t;
+                    const bool ok = pos ? lag <= M_last - 1 : lag >= -(M_last - 1);
+                    if (ok) {
+                        double vals[NG];
+                        x[D - 1] = dl * (double)lag;
+                        eval_direct<Fun, D>(f, x, vals);
+                        const double a = ri.rw * Arow[t];
+#pragma unroll
+                        for (int g = 0; g < NG; ++g) acc[g] += vals[g] * a;
+                    }
+                }
+                continue;
+            }
+            {
+                constexpr int NM = Fun::NMOM;
+                double m[NGS][3];
+#pragma unroll
+                for (int k = 0; k < NGS; ++k) m[k][0] = m[k][1] = m[k][2] = 0.0;
+#pragma unroll
+                for (int t = 0; t < RL; ++t) {
+#pragma unroll
+                    for (int k = 0; k < NGS; ++k) {
+                        const double w = ev[k] * av[t];
+                        m[k][0] += w;
+                        if constexpr (NM > 1) {
+                            m[k][1] += (double)t * w;
+                            m[k][2] += (double)(t * t) * w;
+                        }
+                        ev[k] *= rho[k];
+                        rho[k] *= sig[k];
+                    }
+                }
+                f.fold(z, dz, m, acc);
+            }
+        }
+        double outv[NG];
+        block_sum<NG, NT>(acc, red, outv);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int g = 0; g < NG; ++g) partial[item * NG + g] = outv[g];
+        }
+    }
+}
+
 constexpr int LAG_RUN = 8;
 
 // Families whose combine step dominates (many Hermite outputs) gain nothing
@@ -455,11 +624,19 @@ constexpr int LAG_RUN = 8;
 template <class Fun>
 constexpr int lag_run_of() { return Fun::NG > 12 ? 1 : LAG_RUN; }
 
+template <int D, int N, class Fun, int NT>
+constexpr auto select_lag() {
+    if constexpr (HasMoments<Fun>::value)
+        return k_lag_mom<D, N, Fun, NT, lag_run_of<Fun>()>;
+    else
+        return k_lag<D, N, Fun, NT, lag_run_of<Fun>()>;
+}
+
 template <int D, int N, class Fun>
 hipError_t run_lag_t(const double* prm, RowGeom geo, int64_t nitems, double* partial, int grid_blocks,
                      hipStream_t s) {
     constexpr int NT = 256;
-    auto kern = k_lag<D, N, Fun, NT, lag_run_of<Fun>()>;
+    auto kern = select_lag<D, N, Fun, NT>();
     int64_t blocks = nitems;
     if (grid_blocks > 0) {
         blocks = grid_blocks;
