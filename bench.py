@@ -79,12 +79,12 @@ def algorithmic_flops_per_candidate(M, N, d=2, variant=0):
     Spectral form (variants 0-2), per row: two complex FFTs of length N (the 4
     real grids packed two per transform) at 5 N log2 N flops each and the
     contraction over the full last axis, 8 flops per complex multiply-add per
-    transform.  Lag form (variant 3), per lag: one multiply-add per grid
+    transform.  Lag form (variants 3, 4), per lag: one multiply-add per grid
     against the autocorrelation (4 grids, 2 flops each).  Generation is
     charged at its direct-evaluation cost in both forms (the lag kernel's
     exponential recurrence does fewer operations for the same work)."""
     gen = (2 * M - 1) * gen_flops_per_lag(d)
-    if variant == 3:
+    if variant >= 3:
         return M * (gen + (2 * M - 1) * 2 * 4)
     log2n = int(np.log2(N))
     fft = 2 * 5 * N * log2n
@@ -113,7 +113,7 @@ def main():
     X = torch.from_numpy(X_h).to(dev)
     vechL = torch.from_numpy(synth.vech_chol(H)).to(dev)
     tuned = None
-    variant, grid_blocks = 3, 0   # library default for untuned shapes
+    variant, grid_blocks = 4, 0   # library default for untuned shapes
     if a.launch:
         variant, grid_blocks = (int(x) for x in a.launch.split(","))
         kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, max(4, 1 << (2 * M - 2).bit_length()), variant, grid_blocks)
@@ -241,7 +241,8 @@ def main():
             ent = rec.get("launches", {}).get(f"{variant},{grid_blocks}")
             if ent:
                 traffic = ent["hbm_bytes_per_launch"]
-    kname = ("k_lag<2,512,ScvFun<2,1>,256,8>" if variant == 3 else f"k_rows<2,512,ScvFun<2,1>> variant {variant}")
+    kname = (f"k_lag_mom<2,512,ScvFun<2,1>,256,8,{'true' if variant == 4 else 'false'}>" if variant >= 3
+             else f"k_rows<2,512,ScvFun<2,1>> variant {variant}")
     kname += " (grid: one block per work item)" if grid_blocks < 0 else " (grid: resident blocks)"
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic,

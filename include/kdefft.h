@@ -308,16 +308,20 @@ int kdefft_scv_plain(const kdefft_dataset* ds_host, const double* H_host, double
                      void* ws, size_t ws_bytes, void* stream);
 
 /* Pin the launch of the batched row kernels for one kernel family (kind: 0 psi,
- * 1 SCV objective, 2 SCV objective+gradient, 3 SCV gradient), dimension d,
- * order r (2 for the SCV families) and last-axis length N for the rest of the
- * process: variant in [0, 4): 0, 1, 2 run the per-candidate last-axis FFTs in
- * LDS (0: one radix-8 butterfly per lane per stage, radix-8 first; 1: twice the
- * rows per wavefront; 2: radix-4 first); grid_blocks =
+ * 1 SCV objective, 2 SCV objective+gradient, 3 SCV gradient, 4 Q_r, 5 LSCV_r
+ * for r > 0), dimension d, order r (2 for the SCV families) and last-axis
+ * length N for the rest of the process, for the psi / SCV / Q_r calls (LSCV
+ * keeps its own choice): variant in [0, 5): 0, 1, 2 run the per-candidate
+ * last-axis FFTs in LDS (0: one radix-8 butterfly per lane per stage, radix-8
+ * first; 1: twice the rows per wavefront; 2: radix-4 first); grid_blocks =
  * persistent grid size, 0 = resident blocks per CU x CUs, -1 = one block per
- * work item.  Variant 3 evaluates each candidate in the lag domain instead:
- * sum_l k(l) A(l) against the prepared count autocorrelation (identical sums,
- * no per-candidate transform).  Used by kdefft_autotune and by tests that cover every variant.
- * Host only. */
+ * work item.  Variants 3 and 4 evaluate each candidate in the lag domain
+ * instead: sum_l k(l) A(l) against the prepared count autocorrelation
+ * (identical sums, no per-candidate transform); for the SCV families, runs of
+ * lags that start below 1e-290 and rise are evaluated lag by lag (3) or
+ * walked with values scaled by e^600 (4, the untuned default); the psi and eta
+ * families treat 3 and 4 alike and have no spectral variants for eta.  Used by
+ * kdefft_autotune and by tests that cover every variant.  Host only. */
 int kdefft_set_row_launch(int kind, int d, int r, int N, int variant, int grid_blocks);
 
 /* Measurement hook for the batched row kernels (the dominant launches of
@@ -343,7 +347,7 @@ int kdefft_timing_stop(float* ms_out, int32_t* tag_out, int cap, int* count_out)
  * fastest for the rest of the process, and append the choice to cache_path
  * (one JSON object per line; NULL = no file).  Each launch is timed on 256
  * candidates H = s G (s spread over [0.5, 8], G the dataset's matrix); the
- * default (variant 3, grid 0) is kept unless another launch is more than 3%
+ * default (variant 4, grid 0) is kept unless another launch is more than 3%
  * faster.  Workspace: KDEFFT_OP_AUTOTUNE.  Synchronizes `stream`. */
 int kdefft_autotune(const kdefft_dataset* ds_host, void* ws, size_t ws_bytes,
                     const char* cache_path, void* stream);

@@ -235,10 +235,12 @@ int64_t max_nchunks(const kdefft_grid& g, int kind, int r, int64_t ncand) {
 }
 
 // ---------------------------------------------------------------- launch choices
+// crit: the criterion the family serves (the SCV families also run LSCV,
+// whose kernels are narrower, so each keeps its own choice); 0 for psi / SCV.
 struct LaunchKey {
-    int dev, kind, d, r, N;
+    int dev, kind, d, r, N, crit;
     bool operator<(const LaunchKey& o) const {
-        return std::tie(dev, kind, d, r, N) < std::tie(o.dev, o.kind, o.d, o.r, o.N);
+        return std::tie(dev, kind, d, r, N, crit) < std::tie(o.dev, o.kind, o.d, o.r, o.N, o.crit);
     }
 };
 std::mutex g_launch_mu;
@@ -275,29 +277,31 @@ void load_cache_locked(int dev) {
         std::string line(buf);
         if (line.find("\"arch\": \"" + arch + "\"") == std::string::npos) continue;
         LaunchKey k{dev, json_int(line, "kind", -1), json_int(line, "d", 0), json_int(line, "r", 0),
-                    json_int(line, "N", 0)};
+                    json_int(line, "N", 0), 0};
         RowLaunch rl{json_int(line, "variant", 0), json_int(line, "grid", 0)};
         if (k.kind >= 0 && rl.variant >= 0 && rl.variant < ROW_VARIANTS) g_launch[k] = rl;
     }
     std::fclose(f);
 }
 
-RowLaunch launch_for(int kind, int d, int r, int N) {
+RowLaunch launch_for(int kind, int d, int r, int N, int crit = 0) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     std::lock_guard<std::mutex> lk(g_launch_mu);
     load_cache_locked(dev);
-    auto it = g_launch.find(LaunchKey{dev, kind, d, r, N});
+    auto it = g_launch.find(LaunchKey{dev, kind, d, r, N, crit});
     if (it != g_launch.end()) return it->second;
-    // untuned default: the lag-domain evaluation (fewest operations, no LDS)
-    return RowLaunch{3, 0};
+    // untuned default: the lag-domain evaluation (fewest operations, no LDS),
+    // with the scaled walk for the SCV families (robust to narrow kernels)
+    const bool mom = kind == FUN_SCV_OBJ || kind == FUN_SCV_OBJGRAD || kind == FUN_SCV_GRAD;
+    return RowLaunch{mom ? 4 : 3, 0};
 }
 
 void set_launch(int kind, int d, int r, int N, RowLaunch rl) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     std::lock_guard<std::mutex> lk(g_launch_mu);
-    g_launch[LaunchKey{dev, kind, d, r, N}] = rl;
+    g_launch[LaunchKey{dev, kind, d, r, N, 0}] = rl;
 }
 
 // ---------------------------------------------------------------- workspace plans
@@ -974,7 +978,8 @@ static int crit_common(const kdefft_dataset* ds, int n_ds, const int64_t* off, c
     rc = check_ws(ar, ws_bytes);
     if (rc) return rc;
     hipStream_t s = S(stream);
-    const RowLaunch rl = force ? *force : launch_for(kind, g.d, kr, g.P[g.d - 1]);
+    const int ckey = crit == KDEFFT_CRIT_LSCV_EXACT ? KDEFFT_CRIT_LSCV : crit;
+    const RowLaunch rl = force ? *force : launch_for(kind, g.d, kr, g.P[g.d - 1], ckey);
     const RowGeom geo = make_geom(g, kind, kr, B, rl.variant);
     HIPCHK(launch_scv_setup(vechL, a, B, b.prm, status, s), "criterion setup");
     HIPCHK(timed_rows(kind, g.d, kr, geo, b.prm, B, b.partial, rl, s), "criterion rows");
@@ -1179,7 +1184,7 @@ int kdefft_autotune(const kdefft_dataset* ds, void* ws, size_t ws_bytes, const c
     float best_ms = 1e30f;
     // The untuned default keeps its place unless another launch beats it by
     // more than 3%, so that timing noise does not flip the choice run to run.
-    const RowLaunch dflt{3, 0};
+    const RowLaunch dflt{4, 0};
     float dflt_ms = -1.f;
     std::string lines;
     const std::string arch = [] {

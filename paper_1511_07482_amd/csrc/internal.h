@@ -10,7 +10,7 @@
 
 namespace kdefft {
 
-constexpr int PRM = 64;     // doubles per candidate parameter block
+constexpr int PRM = 80;     // doubles per candidate parameter block
 constexpr int NT_DEF = 256;  // threads per block of the simple kernels
 
 // Parameter block layout (float64 slots) shared by setup, row and finalize kernels.
@@ -20,8 +20,10 @@ constexpr int NT_DEF = 256;  // threads per block of the simple kernels
 //   both: [38] alag pointer bits  [39] wmix pointer bits  [40,44) delta  [44] n  [45] 1/(n^2 prod P)
 //         [46] constant term  [47] singular flag  [48,64) L (scv) / P3 (plain scv)
 //   criteria: [34] first (closed-form) term  [35] r of eta_r  [36] sign (-1)^r
+//   lag walk of Gaussian k (k = 0, 1) at [64 + 8k, 72 + 8k): dz[0..3] = delta_last P_k[i][last],
+//         [4] hpl = delta_last^2 P_k[last][last] / 2, [5] sig = exp(-2 hpl), [6] log(1e-290 / c_k)
 enum Slot { S_P1 = 0, S_C = 16, S_P2 = 16, S_C1 = 32, S_C2 = 33, S_FIRST = 34, S_R = 35, S_SIGN = 36, S_ALAG = 38,
-            S_WMIX = 39, S_DELTA = 40, S_N = 44, S_SCALE = 45, S_CONST = 46, S_SING = 47, S_L = 48 };
+            S_WMIX = 39, S_DELTA = 40, S_N = 44, S_SCALE = 45, S_CONST = 46, S_SING = 47, S_L = 48, S_WALK = 64 };
 
 // Per-dataset record kept in the dataset's own device buffer (written by a
 // kernel at prepare time); batched calls pass pointers to these records.
@@ -126,7 +128,7 @@ struct RowLaunch {
 hipError_t launch_rows(int kind, int d, int r, const RowGeom& geo, const double* prm, int64_t ncand,
                        double* partial, const RowLaunch& rl, hipStream_t s);
 int rows_per_iter(int kind, int d, int r, int N, int variant);
-constexpr int ROW_VARIANTS = 4;   // 0-2: spectral (per-candidate FFT), 3: lag domain
+constexpr int ROW_VARIANTS = 5;   // 0-2: spectral (per-candidate FFT), 3, 4: lag domain (4: scaled walk)
 hipError_t launch_scv_setup(const double* vechL, const ScvBatchArgs& a, int64_t ncand, double* prm,
                             int32_t* status, hipStream_t s);
 hipError_t launch_psi_setup(const PsiBatchArgs& a, double* prm, hipStream_t s);

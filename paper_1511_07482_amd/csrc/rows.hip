@@ -85,7 +85,8 @@ RowGeom make_geom(const kdefft_grid& g, int kind, int r, int64_t ncand, int vari
     geo.Q = g.P[g.d - 1] / 2 + 1;
     int ri = rows_per_iter(kind, g.d, r, g.P[g.d - 1], variant);
     if (ri < 1) ri = 1;
-    const int64_t target = 8192;
+    // lag kernel: larger items amortise the per-item set-up and block reduction
+    const int64_t target = variant >= 3 ? 2048 : 8192;
     int64_t iters = (nrows * ncand + (int64_t)ri * target - 1) / ((int64_t)ri * target);
     if (iters < 1) iters = 1;
     int64_t chunk = iters * ri;
@@ -179,6 +180,18 @@ __device__ static double two_pi_pow(int d) {  // (2 pi)^{-d/2}
     double r = 1.0;
     for (int k = 0; k < d; ++k) r *= c;
     return r;
+}
+
+// Constants of the lag-domain walk along the last axis for inverse covariance
+// P (row stride 4) and spacing dl; read by the lag kernels as uniform values.
+template <int D>
+__device__ static void put_walk(double* p, int k, const double* P, double dl, double c) {
+    double* w = p + S_WALK + 8 * k;
+    for (int i = 0; i < D; ++i) w[i] = dl * P[i * 4 + D - 1];
+    const double hpl = 0.5 * dl * dl * P[(D - 1) * 4 + D - 1];
+    w[4] = hpl;
+    w[5] = exp(-2.0 * hpl);
+    w[6] = -667.74967696827317 - log(c);   // exponents below this give c e^x < 1e-290
 }
 
 __device__ static void put_ptr(double* slot, const void* p) {
@@ -281,6 +294,8 @@ __global__ void k_scv_setup(const double* __restrict__ vechL, ScvBatchArgs a, in
     put_ptr(p + S_WMIX, ds.wmix);
     put_ptr(p + S_ALAG, ds.alag);
     for (int k = 0; k < d; ++k) p[S_DELTA + k] = ds.delta[k];
+    put_walk<D>(p, 0, p + S_P1, ds.delta[d - 1], p[S_C1]);
+    put_walk<D>(p, 1, p + S_P2, ds.delta[d - 1], p[S_C2]);
     p[S_N] = n;
     p[S_SCALE] = 1.0 / (n * n * a.prodP);
     p[S_SING] = sing ? 1.0 : 0.0;
@@ -338,6 +353,7 @@ __global__ void k_psi_setup(PsiBatchArgs a, double* __restrict__ prm) {
     put_ptr(p + S_WMIX, ds.wmix);
     put_ptr(p + S_ALAG, ds.alag);
     for (int k = 0; k < d; ++k) p[S_DELTA + k] = ds.delta[k];
+    put_walk<D>(p, 0, p + S_P1, ds.delta[d - 1], p[S_C]);
     p[S_N] = ds.n;
     p[S_SCALE] = 1.0 / (ds.n * ds.n * a.prodP);
 }

@@ -22,7 +22,8 @@ hipError_t rows_var(int var, const double* prm, RowGeom geo, int64_t nitems, dou
             case 0: return run_rows_t<D, N, Fun, 0>(prm, geo, nitems, partial, grid_blocks, tw, s);
             case 1: return run_rows_t<D, N, Fun, 1>(prm, geo, nitems, partial, grid_blocks, tw, s);
             case 2: return run_rows_t<D, N, Fun, 2>(prm, geo, nitems, partial, grid_blocks, tw, s);
-            case 3: return run_lag_t<D, N, Fun>(prm, geo, nitems, partial, grid_blocks, s);
+            case 3: return run_lag_t<D, N, Fun>(prm, geo, nitems, partial, grid_blocks, s, false);
+            case 4: return run_lag_t<D, N, Fun>(prm, geo, nitems, partial, grid_blocks, s, true);
             default: return hipErrorInvalidValue;
         }
     }
@@ -31,7 +32,7 @@ hipError_t rows_var(int var, const double* prm, RowGeom geo, int64_t nitems, dou
 // Rows one block transforms per pass (rows per wavefront x wavefronts).
 template <int D, int N, class Fun>
 constexpr int rows_per_iter_t(int var) {
-    return var == 3 ? lag_rows_per_pass<N>() : var == 1 ? rows_for<N, Fun::NG, 1>() * waves_for<N, Fun::NG, rows_for<N, Fun::NG, 1>()>()
+    return var >= 3 ? lag_rows_per_pass<N>() : var == 1 ? rows_for<N, Fun::NG, 1>() * waves_for<N, Fun::NG, rows_for<N, Fun::NG, 1>()>()
                     : rows_for<N, Fun::NG, 0>() * waves_for<N, Fun::NG, rows_for<N, Fun::NG, 0>()>();
 }
 

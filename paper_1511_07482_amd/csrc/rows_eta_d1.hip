@@ -1,4 +1,5 @@
-// Scalar eta_r families (Q_r, LSCV_r) for d = 1: lag-domain kernel only (see rows_impl.h).
+// Scalar eta_r families (Q_r, LSCV_r) for d = 1: lag-domain kernel only (variants 3 and 4
+// coincide for them; see rows_impl.h).
 #include "rows_dispatch.h"
 
 namespace kdefft {
@@ -6,23 +7,23 @@ namespace kdefft {
 template <class Fun>
 static hipError_t lag_1(int N, const double* prm, RowGeom geo, int64_t nitems, double* partial, int gb, hipStream_t s) {
     switch (N) {
-        case 4: return run_lag_t<1, 4, Fun>(prm, geo, nitems, partial, gb, s);
-        case 8: return run_lag_t<1, 8, Fun>(prm, geo, nitems, partial, gb, s);
-        case 16: return run_lag_t<1, 16, Fun>(prm, geo, nitems, partial, gb, s);
-        case 32: return run_lag_t<1, 32, Fun>(prm, geo, nitems, partial, gb, s);
-        case 64: return run_lag_t<1, 64, Fun>(prm, geo, nitems, partial, gb, s);
-        case 128: return run_lag_t<1, 128, Fun>(prm, geo, nitems, partial, gb, s);
-        case 256: return run_lag_t<1, 256, Fun>(prm, geo, nitems, partial, gb, s);
-        case 512: return run_lag_t<1, 512, Fun>(prm, geo, nitems, partial, gb, s);
-        case 1024: return run_lag_t<1, 1024, Fun>(prm, geo, nitems, partial, gb, s);
-        case 2048: return run_lag_t<1, 2048, Fun>(prm, geo, nitems, partial, gb, s);
+        case 4: return run_lag_t<1, 4, Fun>(prm, geo, nitems, partial, gb, s, false);
+        case 8: return run_lag_t<1, 8, Fun>(prm, geo, nitems, partial, gb, s, false);
+        case 16: return run_lag_t<1, 16, Fun>(prm, geo, nitems, partial, gb, s, false);
+        case 32: return run_lag_t<1, 32, Fun>(prm, geo, nitems, partial, gb, s, false);
+        case 64: return run_lag_t<1, 64, Fun>(prm, geo, nitems, partial, gb, s, false);
+        case 128: return run_lag_t<1, 128, Fun>(prm, geo, nitems, partial, gb, s, false);
+        case 256: return run_lag_t<1, 256, Fun>(prm, geo, nitems, partial, gb, s, false);
+        case 512: return run_lag_t<1, 512, Fun>(prm, geo, nitems, partial, gb, s, false);
+        case 1024: return run_lag_t<1, 1024, Fun>(prm, geo, nitems, partial, gb, s, false);
+        case 2048: return run_lag_t<1, 2048, Fun>(prm, geo, nitems, partial, gb, s, false);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_rows_eta_d1(int kind, int N, int var, const double* prm, RowGeom geo, int64_t nitems,
                                double* partial, int gb, hipStream_t s) {
-    if (var != 3) return hipErrorInvalidValue;
+    if (var != 3 && var != 4) return hipErrorInvalidValue;
     switch (kind) {
         case FUN_ETA1: return lag_1<EtaFun<1, 1>>(N, prm, geo, nitems, partial, gb, s);
         case FUN_ETA2: return lag_1<EtaFun<1, 2>>(N, prm, geo, nitems, partial, gb, s);
@@ -31,7 +32,7 @@ hipError_t launch_rows_eta_d1(int kind, int N, int var, const double* prm, RowGe
 }
 
 int rows_iter_eta_d1(int kind, int N, int var) {
-    if (var != 3 || (kind != FUN_ETA1 && kind != FUN_ETA2)) return 0;
+    if ((var != 3 && var != 4) || (kind != FUN_ETA1 && kind != FUN_ETA2)) return 0;
     switch (N) {
         case 4: return lag_rows_per_pass<4>();
         case 8: return lag_rows_per_pass<8>();

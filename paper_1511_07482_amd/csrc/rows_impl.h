@@ -464,7 +464,7 @@ __global__ __launch_bounds__(NT) void k_lag(const double* __restrict__ prm, RowG
 // runs of RL consecutive array positions of the circular row (see below),
 // their RL autocorrelation values loaded as one aligned block, and per run
 // only the moments sum_t t^p e(t) A(t) of each Gaussian (Fun::fold).
-template <int D, int N, class Fun, int NT, int RUN>
+template <int D, int N, class Fun, int NT, int RUN, bool SCALED>
 __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, RowGeom geo, int64_t nitems,
                                             double* __restrict__ partial) {
     constexpr int NG = Fun::NG;
@@ -494,7 +494,8 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
         const double* __restrict__ A =
             reinterpret_cast<const double*>(static_cast<uintptr_t>(__double_as_longlong(pr[S_ALAG])));
         const double dl = delta[D - 1];
-        double dz[NGS][D], sig[NGS], hpl[NGS];
+        // walk constants written by the setup kernel (uniform: scalar loads)
+        double dz[NGS][D], sig[NGS], hpl[NGS], lcut[NGS];
 #pragma unroll
         for (int k = 0; k < NGS; ++k) {
             const double* P = f.Pm(k);
@@ -502,6 +503,7 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
             for (int i = 0; i < D; ++i) dz[k][i] = dl * P[i * D + D - 1];
             hpl[k] = 0.5 * dl * dl * P[(D - 1) * D + D - 1];
             sig[k] = exp(-2.0 * hpl[k]);
+            if constexpr (SCALED) lcut[k] = -667.74967696827317 - log(f.cn(k));   // c e^x < 1e-290 below
         }
         double acc[NG];
 #pragma unroll
@@ -542,6 +544,7 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
             for (int k = 0; k < D - 1; ++k) x[k] = ri.x[k];
             x[D - 1] = dl * (double)lag0;
             double z[NGS][D], ev[NGS], rho[NGS];
+            bool scl[NGS];
             bool direct = false, alive = false;
 #pragma unroll
             for (int k = 0; k < NGS; ++k) {
@@ -555,16 +558,32 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
                     z[k][i] = s;
                     q += x[i] * s;
                 }
-                ev[k] = f.cn(k) * exp(-0.5 * q);
+                // A run starting below 1e-290 with ratios rho, rho sig, ... <= 1
+                // (sig < 1) stays there and adds nothing a float64 sum can hold
+                // next to the lag-0 term.  A run that rises from there is walked
+                // with values scaled by e^600 (kept in the normal range) and its
+                // moments scaled back at the end (SCALED), or evaluated lag by lag.
+                const double ea = -0.5 * q;
                 rho[k] = exp(-(dl * z[k][D - 1] + hpl[k]));
-                // ratios along the run are rho, rho sig, ... with sig < 1: if the
-                // first value is below 1e-290 and rho <= 1 the whole run is, and
-                // it adds nothing a float64 sum can hold next to the lag-0 term
-                if (!(ev[k] >= 1e-290) && rho[k] <= 1.0) {
-                    ev[k] = 0.0;
+                if constexpr (SCALED) {
+                    const bool low = ea < lcut[k];
+                    scl[k] = low;
+                    if (low && rho[k] <= 1.0) {
+                        ev[k] = 0.0;
+                    } else {
+                        ev[k] = f.cn(k) * exp(low ? ea + 600.0 : ea);
+                        direct = direct || !(rho[k] <= 1e200);
+                        alive = true;
+                    }
                 } else {
-                    direct = direct || !(ev[k] >= 1e-290) || !(rho[k] <= 1e200);
-                    alive = true;
+                    scl[k] = false;
+                    ev[k] = f.cn(k) * exp(ea);
+                    if (!(ev[k] >= 1e-290) && rho[k] <= 1.0) {
+                        ev[k] = 0.0;
+                    } else {
+                        direct = direct || !(ev[k] >= 1e-290) || !(rho[k] <= 1e200);
+                        alive = true;
+                    }
                 }
             }
             if (!alive) continue;
@@ -605,6 +624,14 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
                         rho[k] *= sig[k];
                     }
                 }
+#pragma unroll
+                for (int k = 0; k < NGS; ++k)
+                    if (SCALED && scl[k]) {
+                        constexpr double E_M600 = 2.6503965530043108e-261;   // e^-600
+                        m[k][0] *= E_M600;
+                        m[k][1] *= E_M600;
+                        m[k][2] *= E_M600;
+                    }
                 f.fold(z, dz, m, acc);
             }
         }
@@ -624,19 +651,20 @@ constexpr int LAG_RUN = 8;
 template <class Fun>
 constexpr int lag_run_of() { return Fun::NG > 12 ? 1 : LAG_RUN; }
 
-template <int D, int N, class Fun, int NT>
+template <int D, int N, class Fun, int NT, bool SCALED>
 constexpr auto select_lag() {
     if constexpr (HasMoments<Fun>::value)
-        return k_lag_mom<D, N, Fun, NT, lag_run_of<Fun>()>;
+        return k_lag_mom<D, N, Fun, NT, lag_run_of<Fun>(), SCALED>;
     else
         return k_lag<D, N, Fun, NT, lag_run_of<Fun>()>;
 }
 
 template <int D, int N, class Fun>
 hipError_t run_lag_t(const double* prm, RowGeom geo, int64_t nitems, double* partial, int grid_blocks,
-                     hipStream_t s) {
+                     hipStream_t s, bool scaled) {
     constexpr int NT = 256;
-    auto kern = select_lag<D, N, Fun, NT>();
+    // variant 4 (scaled walk) differs from variant 3 only for the moment families
+    auto kern = scaled ? select_lag<D, N, Fun, NT, true>() : select_lag<D, N, Fun, NT, false>();
     int64_t blocks = nitems;
     if (grid_blocks > 0) {
         blocks = grid_blocks;

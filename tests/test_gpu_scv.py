@@ -223,10 +223,10 @@ def test_psi_batch(kf, gpu):
         np.testing.assert_allclose(out[j], want, rtol=1e-10, atol=1e-12 * np.abs(want).max())
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("name", ["d1", "d2_ragged", "d3", "d4"])
 def test_every_variant_vs_oracle(kf, gpu, name, variant):
-    """Each compiled launch variant (three spectral, one lag-domain) against the
+    """Each compiled launch variant (three spectral, two lag-domain) against the
     oracle, for the objective+gradient, objective-only and adjoint families."""
     d, X, Gp, M, H, _ = _setup(name, gpu)
     ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
@@ -242,7 +242,7 @@ def test_every_variant_vs_oracle(kf, gpu, name, variant):
         adj = kf.scv_adjoint([ds], v, w)
     finally:
         for k in kinds:
-            kf.set_row_launch(k, d, 2, N, 0, 0)
+            kf.set_row_launch(k, d, 2, N, 4, 0)
     obj, g = obj.cpu().numpy(), g.cpu().numpy()
     _check_against_oracle(kf, name, d, X, Gp, M, H, obj, g)
     np.testing.assert_allclose(obj_only.cpu().numpy(), obj, rtol=1e-13)
@@ -261,7 +261,7 @@ def test_psi_batch_variants(kf, gpu, variant):
         kf.set_row_launch(kf.FUN_PSI, d, r, N, variant, 0)
         out = kf.psi_batch([ds], [Gpsi], r).cpu().numpy()[0]
     finally:
-        kf.set_row_launch(kf.FUN_PSI, d, r, N, 0, 0)
+        kf.set_row_launch(kf.FUN_PSI, d, r, N, 3, 0)
     g_o = grid.plan_auto(X, Gp, [M] * d)
     co, _ = linbin.linbin(X, g_o)
     A = binned.autocorr_direct(linbin.counts_to_real(co))
@@ -269,9 +269,11 @@ def test_psi_batch_variants(kf, gpu, variant):
     np.testing.assert_allclose(out, want, rtol=1e-10, atol=1e-11 * np.abs(want).max())
 
 
-def test_narrow_kernels_recurrence_fallback(kf, gpu):
+@pytest.mark.parametrize("variant", [3, 4])
+def test_narrow_kernels_recurrence_fallback(kf, gpu, variant):
     """Kernels much narrower than the bins: the far lags underflow, so the
-    lag-domain kernel's recurrence falls back to direct evaluation there."""
+    lag-domain kernel's recurrence falls back to direct evaluation (variant 3)
+    or walks scaled values (variant 4) there."""
     d, M = 2, 48
     X = mixture_sample(1500, d, 990)
     Gp = np.diag([2e-4, 3e-4])
@@ -280,10 +282,10 @@ def test_narrow_kernels_recurrence_fallback(kf, gpu):
     v = torch.from_numpy(_vech(H)).to(gpu)
     N = ds.grid.P[d - 1]
     try:
-        kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, 3, 0)
+        kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, variant, 0)
         obj, g = kf.scv([ds], v)
     finally:
-        kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, 3, 0)
+        kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, 4, 0)
     _check_against_oracle(kf, "narrow", d, X, Gp, M, H, obj.cpu().numpy(), g.cpu().numpy())
 
 
