@@ -252,7 +252,7 @@ int kdefft_scv_adjoint(const kdefft_dataset* ds_host, int n_ds, const int64_t* h
  *   KDEFFT_CRIT_SCV         the SCV objective above (r must be 0);
  *   KDEFFT_CRIT_LSCV        LSCV_r of Eq. (36) (n - 1 replaced by n):
  *       (-1)^r { n^-2 sum sum [eta_r(.; 2H) - 2 eta_r(.; H)] + 2 n^-1 eta_r(0; H) },
- *       for r = 0 the paper's LSCV of Eq. (11);
+ *       for r = 0 the paper's LSCV of Eq. (10)-(11);
  *   KDEFFT_CRIT_LSCV_EXACT  LSCV_r of Eq. (35), the leave-one-out weights:
  *       (-1)^r { n^-2 sum sum [eta_r(.; 2H) - 2n/(n-1) eta_r(.; H)] + 2 (n-1)^-1 eta_r(0; H) };
  *   KDEFFT_CRIT_QR          the V-statistic Q_r(S) of Eq. (32) with S = L L^T

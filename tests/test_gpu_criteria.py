@@ -1,6 +1,6 @@
 """LSCV, LSCV_r, Q_r and the plug-in criterion on the GPU vs the oracle.
 
-* LSCV (r = 0, Eq. (11) / Eq. (35) weights) objective and gradient from the
+* LSCV (r = 0, Eq. (10) / Eq. (35) weights) objective and gradient from the
   batched launch vs the oracle's binned LSCV from its own counts (obj <= 1e-11
   relative, gradient <= 1e-10 of its largest entry), d = 1..4;
 * the LSCV adjoint and its autograd.Function;
