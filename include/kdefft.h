@@ -124,6 +124,7 @@ typedef struct kdefft_dataset {
 #define KDEFFT_OP_SCV_PLAIN 7   /* kdefft_scv_plain */
 #define KDEFFT_OP_AUTOTUNE 8    /* kdefft_autotune */
 #define KDEFFT_OP_PSI_FFTL 9    /* kdefft_psi_fftl (sized for the largest Eq. (27) padding) */
+#define KDEFFT_OP_PREPARE_AUTO 10 /* kdefft_dataset_prepare_auto: batch = n (points) */
 
 /* psi modes */
 #define KDEFFT_PSI_PLAIN 0  /* the paper's steps literally: per entry, kernel grid ->
@@ -217,6 +218,24 @@ int kdefft_dataset_bytes(const kdefft_grid* g, size_t* out);
 int kdefft_dataset_prepare(const double* X, int64_t n, const kdefft_grid* g,
                            const double* Gpilot_host, void* ds_mem, size_t ds_bytes,
                            kdefft_dataset* out, void* ws, size_t ws_bytes, void* stream);
+
+/* kdefft_grid_auto and kdefft_dataset_prepare in one call, with no host
+ * round trip: the data bounds, the grid origin and spacing (the same IEEE
+ * steps as kdefft_grid_auto / kdefft_grid_plan, bit for bit) and the binning
+ * all stay on the device.  The grid in *out carries d, M and P; its lo and
+ * delta are NaN on the host until kdefft_dataset_grid reads them back (every
+ * batched call works without them; kdefft_scv_plain reads them back itself).
+ * Non-finite data leave non-finite spacing: every point is then counted as out
+ * of the grid (kdefft_check_binning) and kdefft_dataset_grid reports
+ * KDEFFT_E_ARG.  ds_mem: kdefft_dataset_bytes of the grid's shape (any lo,
+ * delta).  Workspace: KDEFFT_OP_PREPARE_AUTO with batch = n. */
+int kdefft_dataset_prepare_auto(const double* X, int64_t n, int d, const int32_t* M_host, double pad_sd,
+                                const double* Gpilot_host, void* ds_mem, size_t ds_bytes,
+                                kdefft_dataset* out, void* ws, size_t ws_bytes, void* stream);
+
+/* The grid of a prepared dataset with its device-side origin and spacing
+ * read back into *out (synchronizes `stream`). */
+int kdefft_dataset_grid(const kdefft_dataset* ds_host, kdefft_grid* out, void* stream);
 
 /* psi_r at bandwidth G_host + 16*j (row-major d x d) for each of n_ds prepared
  * datasets, one launch (Parseval form against the prepared spectra; Sec. 5).

@@ -171,26 +171,57 @@ def psi_fftl(X: torch.Tensor, G, r: int, M=None, grid: Optional[Grid] = None, ta
 
 
 class Dataset:
-    """A sample binned on a grid and transformed once (counts, spectra, constant SCV term)."""
+    """A sample binned on a grid and transformed once (counts, spectra,
+    autocorrelation, constant SCV term).  Without an explicit grid the grid is
+    planned on the device (no host round trip); ``grid`` reads it back on first
+    use."""
 
     def __init__(self, X: torch.Tensor, G_pilot, M=None, grid: Optional[Grid] = None, pad_sd: float = 4.0):
         X = _as_X(X)
         n, d = X.shape
         self.G_pilot = _mat(G_pilot, d, "G_pilot")
-        self.grid = grid if grid is not None else grid_auto(X, self.G_pilot, M, pad_sd)
         self.device = X.device
-        nb = C.c_size_t()
-        _lib.check(_L().kdefft_dataset_bytes(C.byref(self.grid), C.byref(nb)), "kdefft_dataset_bytes")
-        self.mem = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=X.device)
-        base = self.mem.data_ptr()
-        off = (-base) % 256
-        ws = _ws(self.grid, _lib.OP_PREPARE, 0, 1, X.device)
-        self.desc = _lib.Dataset()
-        _lib.check(_L().kdefft_dataset_prepare(_ptr(X), n, C.byref(self.grid), self.G_pilot.ctypes.data,
-                                               C.c_void_p(base + off), int(nb.value), C.byref(self.desc),
-                                               _ptr(ws), ws.numel(), _stream(X.device)), "kdefft_dataset_prepare")
         self.n = n
         self.d = d
+        self.desc = _lib.Dataset()
+        if grid is None:
+            if M is None:
+                raise ValueError("give M or grid")
+            Ms = np.broadcast_to(np.asarray(M, dtype=np.int32), (d,)).copy()
+            shape = grid_plan(Ms, [0.0] * d, [1.0] * d)
+            nb = C.c_size_t()
+            _lib.check(_L().kdefft_dataset_bytes(C.byref(shape), C.byref(nb)), "kdefft_dataset_bytes")
+            self.mem = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=X.device)
+            base = self.mem.data_ptr()
+            off = (-base) % 256
+            ws = _ws(shape, _lib.OP_PREPARE_AUTO, 0, n, X.device)
+            _lib.check(_L().kdefft_dataset_prepare_auto(_ptr(X), n, d, Ms.ctypes.data, float(pad_sd),
+                                                        self.G_pilot.ctypes.data, C.c_void_p(base + off),
+                                                        int(nb.value), C.byref(self.desc), _ptr(ws), ws.numel(),
+                                                        _stream(X.device)), "kdefft_dataset_prepare_auto")
+            self.shape_grid = shape
+            self._grid = None
+        else:
+            nb = C.c_size_t()
+            _lib.check(_L().kdefft_dataset_bytes(C.byref(grid), C.byref(nb)), "kdefft_dataset_bytes")
+            self.mem = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=X.device)
+            base = self.mem.data_ptr()
+            off = (-base) % 256
+            ws = _ws(grid, _lib.OP_PREPARE, 0, 1, X.device)
+            _lib.check(_L().kdefft_dataset_prepare(_ptr(X), n, C.byref(grid), self.G_pilot.ctypes.data,
+                                                   C.c_void_p(base + off), int(nb.value), C.byref(self.desc),
+                                                   _ptr(ws), ws.numel(), _stream(X.device)), "kdefft_dataset_prepare")
+            self.shape_grid = grid
+            self._grid = grid
+
+    @property
+    def grid(self) -> Grid:
+        if self._grid is None:
+            g = Grid()
+            _lib.check(_L().kdefft_dataset_grid(C.byref(self.desc), C.byref(g), _stream(self.device)),
+                       "kdefft_dataset_grid")
+            self._grid = g
+        return self._grid
 
     @property
     def q(self):
@@ -205,7 +236,7 @@ class Dataset:
 
     def counts(self) -> torch.Tensor:
         """Copy of the int64 grid counts."""
-        shape = tuple(self.grid.M[:self.d])
+        shape = tuple(self.shape_grid.M[:self.d])
         numel = int(np.prod(shape))
         base = self.mem.data_ptr()
         start = self.desc.counts - base
@@ -231,7 +262,7 @@ def psi_batch(datasets: Sequence[Dataset], Gs, r: int) -> torch.Tensor:
         Gh = np.zeros((len(part), 16))
         for j in range(len(part)):
             Gh[j, :d * d] = _mat(Gs[s + j], d, "G").ravel()
-        ws = _ws(part[0].grid, _lib.OP_PSI_BATCH, r, len(part), dev)
+        ws = _ws(part[0].shape_grid, _lib.OP_PSI_BATCH, r, len(part), dev)
         arr = _ds_array(part)
         _lib.check(_L().kdefft_psi_batch(arr, len(part), Gh.ctypes.data, r, _ptr(out[s:s + len(part)]), _ptr(ws),
                                          ws.numel(), _stream(dev)), "kdefft_psi_batch")
@@ -288,7 +319,7 @@ def crit(datasets: Sequence[Dataset], vechL: torch.Tensor, crit="scv", r: int = 
         if nb == 0:
             continue
         off = _offsets(part, cnts)
-        ws = _ws(part[0].grid, _lib.OP_SCV_BATCH, 2, nb, dev)
+        ws = _ws(part[0].shape_grid, _lib.OP_SCV_BATCH, 2, nb, dev)
         arr = _ds_array(part)
         sl = slice(start, start + nb)
         _lib.check(_L().kdefft_crit_batch(arr, len(part), off.ctypes.data, _ptr(vechL[sl]), code, int(r),
@@ -319,7 +350,7 @@ def crit_adjoint(datasets: Sequence[Dataset], vechL: torch.Tensor, grad_out: tor
         if nb == 0:
             continue
         off = _offsets(part, cnts)
-        ws = _ws(part[0].grid, _lib.OP_SCV_BATCH, 2, nb, dev)
+        ws = _ws(part[0].shape_grid, _lib.OP_SCV_BATCH, 2, nb, dev)
         arr = _ds_array(part)
         sl = slice(start, start + nb)
         if code == CRIT_SCV:
@@ -353,7 +384,7 @@ def scv(datasets: Sequence[Dataset], vechL: torch.Tensor, per_ds=None, grad: boo
         if nb == 0:
             continue
         off = _offsets(part, cnts)
-        ws = _ws(part[0].grid, _lib.OP_SCV_BATCH, 2, nb, dev)
+        ws = _ws(part[0].shape_grid, _lib.OP_SCV_BATCH, 2, nb, dev)
         arr = _ds_array(part)
         sl = slice(start, start + nb)
         _lib.check(_L().kdefft_scv_batch(arr, len(part), off.ctypes.data, _ptr(vechL[sl]), _ptr(obj[sl]),
@@ -420,7 +451,7 @@ def expand_full(vals, d: int, r: int) -> np.ndarray:
 def scv_plain(dataset: Dataset, H) -> torch.Tensor:
     """[SCV(H), d SCV / d vechL] for one H by the paper's literal steps."""
     Hm = _mat(H, dataset.d, "H")
-    ws = _ws(dataset.grid, _lib.OP_SCV_PLAIN, 2, 1, dataset.device)
+    ws = _ws(dataset.shape_grid, _lib.OP_SCV_PLAIN, 2, 1, dataset.device)
     out = torch.empty(1 + dataset.q, dtype=torch.float64, device=dataset.device)
     arr = _ds_array([dataset])
     _lib.check(_L().kdefft_scv_plain(arr, Hm.ctypes.data, _ptr(out), _ptr(ws), ws.numel(), _stream(dataset.device)),
@@ -490,7 +521,7 @@ def set_row_launch(kind: int, d: int, r: int, N: int, variant: int, grid_blocks:
 
 
 def autotune(dataset: Dataset, cache_path: Optional[str] = None) -> str:
-    ws = _ws(dataset.grid, _lib.OP_AUTOTUNE, 2, 256, dataset.device)
+    ws = _ws(dataset.shape_grid, _lib.OP_AUTOTUNE, 2, 256, dataset.device)
     arr = _ds_array([dataset])
     _lib.check(_L().kdefft_autotune(arr, _ptr(ws), ws.numel(), cache_path.encode() if cache_path else None,
                                     _stream(dataset.device)), "kdefft_autotune")

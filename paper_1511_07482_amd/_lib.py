@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(HERE, "libkdefft.so")
 OK = 0
 E_ARG, E_NOT_SPD, E_ODD_R, E_OUT_OF_GRID, E_OVERFLOW, E_WORKSPACE, E_HIP, E_UNSUPPORTED = range(-1, -9, -1)
 OP_GRID_AUTO, OP_PSI_PLAIN, OP_PSI_FUSED, OP_PREPARE, OP_PSI_BATCH, OP_SCV_BATCH, OP_SCV_PLAIN, OP_AUTOTUNE, \
-    OP_PSI_FFTL = range(1, 10)
+    OP_PSI_FFTL, OP_PREPARE_AUTO = range(1, 11)
 PSI_PLAIN, PSI_FUSED = 0, 1
 FUN_PSI, FUN_SCV_OBJ, FUN_SCV_OBJGRAD, FUN_SCV_GRAD = range(4)
 MAX_BATCH_DS = 64
@@ -54,6 +54,10 @@ EXPORTS = {
     "kdefft_dataset_bytes": (C.c_int, [C.POINTER(Grid), C.POINTER(C.c_size_t)]),
     "kdefft_dataset_prepare": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(Grid), C.c_void_p, C.c_void_p,
                                          C.c_size_t, C.POINTER(Dataset), C.c_void_p, C.c_size_t, C.c_void_p]),
+    "kdefft_dataset_prepare_auto": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, C.c_void_p, C.c_double, C.c_void_p,
+                                              C.c_void_p, C.c_size_t, C.POINTER(Dataset), C.c_void_p, C.c_size_t,
+                                              C.c_void_p]),
+    "kdefft_dataset_grid": (C.c_int, [C.POINTER(Dataset), C.POINTER(Grid), C.c_void_p]),
     "kdefft_psi_batch": (C.c_int, [C.POINTER(Dataset), C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
                                    C.c_size_t, C.c_void_p]),
     "kdefft_scv_batch": (C.c_int, [C.POINTER(Dataset), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,

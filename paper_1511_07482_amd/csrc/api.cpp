@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <mutex>
 #include <string>
@@ -399,6 +400,13 @@ int plan_bytes(const kdefft_grid& g, int op, int r, int64_t batch, Arena& a) {
             carve_batch(a, g, FUN_PSI, r, 1);
             return KDEFFT_OK;
         case KDEFFT_OP_PREPARE: carve_prepare(a, g); return KDEFFT_OK;
+        case KDEFFT_OP_PREPARE_AUTO: {
+            carve_prepare(a, g);
+            const int64_t nb = std::min<int64_t>(std::max<int64_t>((batch + 255) / 256, 1), 1024);
+            a.take<double>(nb * 8);
+            a.take<double>(8);
+            return KDEFFT_OK;
+        }
         case KDEFFT_OP_PSI_BATCH: carve_batch(a, g, FUN_PSI, r, std::max<int64_t>(batch, 1)); return KDEFFT_OK;
         case KDEFFT_OP_SCV_BATCH:
             carve_batch(a, g, FUN_SCV_OBJGRAD, 2, std::max<int64_t>(batch, 1));
@@ -431,11 +439,11 @@ hipStream_t S(void* stream) { return static_cast<hipStream_t>(stream); }
 
 // Bin X into counts (zeroed first) and build the circular real count array.
 int bin_and_fill(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts, int32_t* n_out, double* czp,
-                 hipStream_t s) {
+                 hipStream_t s, const double* gdev = nullptr) {
     const Sizes sz = sizes_of(g);
     HIPCHK(launch_zero(counts, sz.prodM * sizeof(int64_t), s), "zero counts");
     if (n_out) HIPCHK(launch_zero(n_out, sizeof(int32_t), s), "zero n_out");
-    HIPCHK(launch_linbin(X, n, g, counts, n_out, s), "linbin");
+    HIPCHK(launch_linbin(X, n, g, counts, n_out, s, gdev), "linbin");
     if (czp) HIPCHK(launch_fill_czp(counts, g, czp, s), "fill czp");
     return KDEFFT_OK;
 }
@@ -456,9 +464,12 @@ PsiBatchArgs psi_args(const kdefft_grid& g, int r, int n_ds, const DsDev* const*
 }
 
 // Prepare a dataset whose buffers are described by L (in a caller buffer or workspace).
+// dev_grid: the grid's origin and spacing were computed on the device into the
+// dataset record (L.rec->lo, ->delta); g then carries the shape only.
 int prepare_into(const double* X, int64_t n, const kdefft_grid& g, const double* Gpilot, const DsLayout& L,
-                 const PrepScratch& p, bool with_const, hipStream_t s) {
-    int rc = bin_and_fill(X, n, g, L.counts, L.n_out, nullptr, s);
+                 const PrepScratch& p, bool with_const, hipStream_t s, bool dev_grid = false) {
+    const double* gdev = dev_grid ? &L.rec->lo[0] : nullptr;
+    int rc = bin_and_fill(X, n, g, L.counts, L.n_out, nullptr, s, gdev);
     if (rc) return rc;
     HIPCHK(fft_prepare_nd(L.counts, L.spec, L.wmix, g, s), "count transform");
     HIPCHK(fft_autocorr_nd(L.wmix, L.alag, g, s), "count autocorrelation");
@@ -467,11 +478,14 @@ int prepare_into(const double* X, int64_t n, const kdefft_grid& g, const double*
     rec.alag = L.alag;
     rec.scal = L.scal;
     rec.n = (double)n;
-    for (int k = 0; k < g.d; ++k) rec.delta[k] = g.delta[k];
+    for (int k = 0; k < g.d; ++k) {
+        rec.lo[k] = g.lo[k];
+        rec.delta[k] = g.delta[k];
+    }
     if (Gpilot)
         for (int i = 0; i < g.d; ++i)
             for (int j = 0; j < g.d; ++j) rec.G[i * 4 + j] = Gpilot[i * g.d + j];
-    HIPCHK(launch_write_rec(L.rec, rec, s), "dataset record");
+    HIPCHK(launch_write_rec(L.rec, rec, dev_grid, s), "dataset record");
     HIPCHK(launch_zero(L.scal, 4 * sizeof(double), s), "zero scal");
     if (with_const) {
         // constant SCV term: n^-2 sum sum phi_{2G}, the psi_0 functional at 2G
@@ -511,15 +525,28 @@ int check_ptr_align(const void* p, const char* name) {
     return KDEFFT_OK;
 }
 
+// A prepared dataset's grid may carry its shape only (origin and spacing
+// computed on the device, NaN on the host): batch calls check the shape.
+int check_grid_shape(const kdefft_grid* g) {
+    if (!g) return fail(KDEFFT_E_ARG, "grid is NULL");
+    kdefft_grid t = *g;
+    for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(t.delta[k]) || !std::isfinite(t.lo[k])) {
+            t.lo[k] = 0.0;
+            t.delta[k] = 1.0;
+        }
+    return check_grid(&t);
+}
+
 int check_batch_ds(const kdefft_dataset* ds, int n_ds, int max_ds) {
     if (!ds) return fail(KDEFFT_E_ARG, "dataset array is NULL");
     if (n_ds < 1 || n_ds > max_ds) return fail(KDEFFT_E_ARG, "n_ds=%d outside [1,%d]", n_ds, max_ds);
-    int rc = check_grid(&ds[0].grid);
+    int rc = check_grid_shape(&ds[0].grid);
     if (rc) return rc;
     for (int j = 0; j < n_ds; ++j) {
         if (!ds[j].rec || !ds[j].wmix || !ds[j].alag || !ds[j].scal)
             return fail(KDEFFT_E_ARG, "dataset %d is not prepared", j);
-        rc = check_grid(&ds[j].grid);
+        rc = check_grid_shape(&ds[j].grid);
         if (rc) return rc;
         if (ds[j].grid.d != ds[0].grid.d) return fail(KDEFFT_E_ARG, "datasets differ in d");
         for (int k = 0; k < ds[0].grid.d; ++k)
@@ -897,6 +924,88 @@ int kdefft_dataset_prepare(const double* X, int64_t n, const kdefft_grid* g, con
     return KDEFFT_OK;
 }
 
+int kdefft_dataset_prepare_auto(const double* X, int64_t n, int d, const int32_t* M_host, double pad_sd,
+                                const double* Gpilot_host, void* ds_mem, size_t ds_bytes, kdefft_dataset* out,
+                                void* ws, size_t ws_bytes, void* stream) {
+    if (!X || !M_host || !Gpilot_host || !out) return fail(KDEFFT_E_ARG, "NULL argument");
+    int rc = check_n(n);
+    if (rc) return rc;
+    if (d < 1 || d > KDEFFT_MAX_D) return fail(KDEFFT_E_ARG, "d=%d outside [1,4]", d);
+    if (!(pad_sd >= 0.0) || !std::isfinite(pad_sd)) return fail(KDEFFT_E_ARG, "pad_sd must be finite and >= 0");
+    double L[16];
+    rc = check_spd(Gpilot_host, d, "Gpilot", L);
+    if (rc) return rc;
+    // the grid's shape (M, P) from the planner; origin and spacing follow on the device
+    double lo0[4] = {0, 0, 0, 0}, hi0[4] = {1, 1, 1, 1};
+    kdefft_grid g;
+    rc = kdefft_grid_plan(d, M_host, nullptr, lo0, hi0, &g);
+    if (rc) return rc;
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    for (int k = 0; k < 4; ++k) g.lo[k] = g.delta[k] = nan;
+    rc = check_rows(FUN_PSI, d, 0, g.P[d - 1]);
+    if (rc) return rc;
+    rc = check_ptr_align(ds_mem, "ds_mem");
+    if (rc) return rc;
+    if (!ws) return fail(KDEFFT_E_ARG, "workspace is NULL");
+    Arena da(ds_mem, ds_bytes, false);
+    const DsLayout dl = carve_dataset(da, g);
+    if (!da.fits()) return fail(KDEFFT_E_WORKSPACE, "dataset buffer of %zu bytes, need %zu", ds_bytes, da.off);
+    Arena a(ws, ws_bytes, false);
+    const PrepScratch p = carve_prepare(a, g);
+    const int64_t nb = std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 1024);
+    double* partial = a.take<double>(nb * 8);
+    double* bounds = a.take<double>(8);
+    rc = check_ws(a, ws_bytes);
+    if (rc) return rc;
+    hipStream_t s = S(stream);
+    double pad[4] = {0, 0, 0, 0};
+    for (int k = 0; k < d; ++k) {
+        const double sd = std::sqrt(Gpilot_host[k * d + k]);
+        volatile double pk = pad_sd * sd;   // the same product as kdefft_grid_auto
+        pad[k] = pk;
+    }
+    HIPCHK(launch_bounds(X, n, d, partial, (int)nb, bounds, s), "bounds");
+    HIPCHK(launch_grid_from_bounds(bounds, g, pad, &dl.rec->lo[0], s), "grid on the device");
+    rc = prepare_into(X, n, g, Gpilot_host, dl, p, true, s, true);
+    if (rc) return rc;
+    kdefft_dataset o;
+    std::memset(&o, 0, sizeof(o));
+    o.grid = g;
+    o.n = n;
+    for (int i = 0; i < d * d; ++i) o.G[i] = Gpilot_host[i];
+    o.counts = dl.counts;
+    o.spec = reinterpret_cast<double*>(dl.spec);
+    o.wmix = reinterpret_cast<double*>(dl.wmix);
+    o.alag = dl.alag;
+    o.scal = dl.scal;
+    o.n_out = dl.n_out;
+    o.rec = dl.rec;
+    *out = o;
+    return KDEFFT_OK;
+}
+
+int kdefft_dataset_grid(const kdefft_dataset* ds, kdefft_grid* out, void* stream) {
+    if (!ds || !out || !ds->rec) return fail(KDEFFT_E_ARG, "NULL or unprepared dataset");
+    int rc = check_grid_shape(&ds->grid);
+    if (rc) return rc;
+    static thread_local double* pinned = nullptr;
+    if (!pinned) HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&pinned), 8 * sizeof(double), hipHostMallocDefault),
+                        "pinned readback buffer");
+    hipStream_t s = S(stream);
+    const DsDev* rec = static_cast<const DsDev*>(ds->rec);
+    HIPCHK(hipMemcpyAsync(pinned, &rec->lo[0], 8 * sizeof(double), hipMemcpyDeviceToHost, s), "grid readback");
+    HIPCHK(hipStreamSynchronize(s), "grid sync");
+    kdefft_grid g = ds->grid;
+    for (int k = 0; k < g.d; ++k) {
+        g.lo[k] = pinned[k];
+        g.delta[k] = pinned[4 + k];
+    }
+    rc = check_grid(&g);
+    if (rc) return fail(KDEFFT_E_ARG, "the data of this dataset are not finite (grid origin or spacing invalid)");
+    *out = g;
+    return KDEFFT_OK;
+}
+
 int kdefft_psi_batch(const kdefft_dataset* ds, int n_ds, const double* G_host, int r, double* psi, void* ws,
                      size_t ws_bytes, void* stream) {
     int rc = check_batch_ds(ds, n_ds, KDEFFT_MAX_PSI_DS);
@@ -1088,7 +1197,12 @@ int kdefft_scv_plain(const kdefft_dataset* ds, const double* H_host, double* out
     int rc = check_batch_ds(ds, 1, 1);
     if (rc) return rc;
     if (!ds->counts || !ds->spec) return fail(KDEFFT_E_ARG, "dataset is not prepared");
-    const kdefft_grid& g = ds->grid;
+    // the literal steps need the grid spacing on the host
+    kdefft_grid g = ds->grid;
+    if (!std::isfinite(g.delta[0])) {
+        rc = kdefft_dataset_grid(ds, &g, stream);
+        if (rc) return rc;
+    }
     const int d = g.d, q = d * (d + 1) / 2;
     double LH[16];
     rc = check_spd(H_host, d, "H", LH);

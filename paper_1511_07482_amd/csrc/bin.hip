@@ -69,6 +69,33 @@ __global__ __launch_bounds__(256) void k_bounds_final(const double* __restrict__
     }
 }
 
+// Grid from data bounds on the device (one thread).  Same IEEE steps, in the
+// same order, as the host planner: lo = min - pad, hi = max + pad, a
+// degenerate axis gets a unit span, delta = (hi - lo) / (M - 1).
+struct PadArg {
+    double v[4];
+};
+__global__ void k_grid_from_bounds(const double* __restrict__ bounds, kdefft_grid g, PadArg pad,
+                                   double* __restrict__ gdev) {
+#pragma clang fp contract(off)
+    if (threadIdx.x != 0) return;
+    for (int k = 0; k < g.d; ++k) {
+        const double lo = bounds[k] - pad.v[k];
+        double hi = bounds[4 + k] + pad.v[k];
+        if (!(hi > lo)) hi = lo + 1.0;
+        gdev[k] = lo;
+        gdev[4 + k] = (hi - lo) / (double)(g.M[k] - 1);
+    }
+}
+
+hipError_t launch_grid_from_bounds(const double* bounds, const kdefft_grid& g, const double* pad, double* gdev,
+                                   hipStream_t s) {
+    PadArg p{};
+    for (int k = 0; k < g.d; ++k) p.v[k] = pad[k];
+    hipLaunchKernelGGL(k_grid_from_bounds, dim3(1), dim3(64), 0, s, bounds, g, p, gdev);
+    return hipGetLastError();
+}
+
 hipError_t launch_bounds(const double* X, int64_t n, int d, double* partial, int nblk, double* out,
                          hipStream_t s) {
     hipLaunchKernelGGL(k_bounds, dim3(nblk), dim3(256), 0, s, X, n, d, partial);
@@ -104,10 +131,18 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
 // operation, as on the host.
 template <int D>
 __global__ __launch_bounds__(256) void k_linbin(const double* __restrict__ X, int64_t n, kdefft_grid g,
+                                                const double* __restrict__ gdev,
                                                 unsigned long long* __restrict__ counts,
                                                 int32_t* __restrict__ n_out) {
 #pragma clang fp contract(off)
     constexpr int NC = 1 << D;
+    if (gdev) {   // origin and spacing computed on the device
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            g.lo[k] = gdev[k];
+            g.delta[k] = gdev[4 + k];
+        }
+    }
     const double one_q = 1099511627776.0;  // 2^40
     for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         double w0[D], w1[D];
@@ -155,16 +190,16 @@ __global__ __launch_bounds__(256) void k_linbin(const double* __restrict__ X, in
 }
 
 hipError_t launch_linbin(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts, int32_t* n_out,
-                         hipStream_t s) {
+                         hipStream_t s, const double* gdev) {
     int64_t blocks = (n + 255) / 256;
     if (blocks > 16384) blocks = 16384;
     if (blocks < 1) blocks = 1;
     auto* c = reinterpret_cast<unsigned long long*>(counts);
     switch (g.d) {
-        case 1: hipLaunchKernelGGL(k_linbin<1>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, c, n_out); break;
-        case 2: hipLaunchKernelGGL(k_linbin<2>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, c, n_out); break;
-        case 3: hipLaunchKernelGGL(k_linbin<3>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, c, n_out); break;
-        case 4: hipLaunchKernelGGL(k_linbin<4>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, c, n_out); break;
+        case 1: hipLaunchKernelGGL(k_linbin<1>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out); break;
+        case 2: hipLaunchKernelGGL(k_linbin<2>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out); break;
+        case 3: hipLaunchKernelGGL(k_linbin<3>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out); break;
+        case 4: hipLaunchKernelGGL(k_linbin<4>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

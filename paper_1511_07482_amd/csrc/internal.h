@@ -32,7 +32,8 @@ struct DsDev {
     const double* alag;
     const double* scal;
     double n;
-    double delta[4];
+    double lo[4];      // grid origin and spacing (lo, delta contiguous: the
+    double delta[4];   // binning kernel reads them from here on the device path)
     double G[16];   // pilot, row stride 4
 };
 
@@ -90,10 +91,17 @@ hipError_t twiddles(const double2** out);  // per-device table e^{-2 pi i m/4096
 hipError_t launch_bounds(const double* X, int64_t n, int d, double* partial, int nblk,
                          double* out, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// gdev: if not NULL, 8 device doubles (lo[4], delta[4]) that replace g's
 hipError_t launch_linbin(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts,
-                         int32_t* n_out, hipStream_t s);
+                         int32_t* n_out, hipStream_t s, const double* gdev = nullptr);
+// lo = min - pad, hi = max + pad (hi = lo + 1 for a degenerate axis),
+// delta = (hi - lo) / (M - 1) from the bounds written by launch_bounds, on the
+// device, into gdev (lo[4], delta[4]) -- the same IEEE steps as the host planner
+hipError_t launch_grid_from_bounds(const double* bounds, const kdefft_grid& g, const double* pad, double* gdev,
+                                   hipStream_t s);
 hipError_t launch_fill_czp(const int64_t* counts, const kdefft_grid& g, double* czp, hipStream_t s);
-hipError_t launch_write_rec(DsDev* rec, const DsDev& val, hipStream_t s);
+// keep_grid: leave the record's lo / delta (written on the device) as they are
+hipError_t launch_write_rec(DsDev* rec, const DsDev& val, bool keep_grid, hipStream_t s);
 
 // Multi-dimensional transforms over the circular-layout arrays.
 hipError_t fft_r2c_nd(const double* in, double2* out, const kdefft_grid& g, hipStream_t s);

@@ -369,10 +369,19 @@ hipError_t launch_psi_setup(const PsiBatchArgs& a, double* prm, hipStream_t s) {
     return hipGetLastError();
 }
 
-__global__ void k_write_rec(DsDev* rec, DsDev val) { if (threadIdx.x == 0) *rec = val; }
+__global__ void k_write_rec(DsDev* rec, DsDev val, int keep_grid) {
+    if (threadIdx.x != 0) return;
+    if (keep_grid) {
+        for (int k = 0; k < 4; ++k) {
+            val.lo[k] = rec->lo[k];
+            val.delta[k] = rec->delta[k];
+        }
+    }
+    *rec = val;
+}
 
-hipError_t launch_write_rec(DsDev* rec, const DsDev& val, hipStream_t s) {
-    hipLaunchKernelGGL(k_write_rec, dim3(1), dim3(64), 0, s, rec, val);
+hipError_t launch_write_rec(DsDev* rec, const DsDev& val, bool keep_grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_write_rec, dim3(1), dim3(64), 0, s, rec, val, keep_grid ? 1 : 0);
     return hipGetLastError();
 }
 

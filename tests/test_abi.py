@@ -257,3 +257,29 @@ def test_fftl_plan_matches_oracle(kf, d):
         assert Lg == Lo and Pg == fftl.plan_P(M, Lo), (M, Lg, Lo)
         checked += 1
     assert checked >= 30
+
+
+def test_prepare_auto_validation(kf):
+    lib = kf._lib.load()
+    L = kf._lib
+    fake = C.c_void_p(0x1000)
+    M = np.array([16, 16], dtype=np.int32)
+    G = np.eye(2) * 0.1
+    out = kf._lib.Dataset()
+    pa = lib.kdefft_dataset_prepare_auto
+    assert pa(None, 10, 2, M.ctypes.data, 4.0, G.ctypes.data, fake, 1 << 30, C.byref(out), fake, 1 << 30,
+              None) == L.E_ARG
+    assert pa(fake, 10, 5, M.ctypes.data, 4.0, G.ctypes.data, fake, 1 << 30, C.byref(out), fake, 1 << 30,
+              None) == L.E_ARG
+    assert pa(fake, 10, 2, M.ctypes.data, -1.0, G.ctypes.data, fake, 1 << 30, C.byref(out), fake, 1 << 30,
+              None) == L.E_ARG
+    bad = np.array([[0.1, 0.3], [0.3, 0.1]])
+    assert pa(fake, 10, 2, M.ctypes.data, 4.0, bad.ctypes.data, fake, 1 << 30, C.byref(out), fake, 1 << 30,
+              None) == L.E_NOT_SPD
+    assert pa(fake, 10, 2, M.ctypes.data, 4.0, G.ctypes.data, C.c_void_p(0x1008), 1 << 30, C.byref(out), fake,
+              1 << 30, None) == L.E_WORKSPACE
+    assert pa(fake, 10, 2, M.ctypes.data, 4.0, G.ctypes.data, fake, 64, C.byref(out), fake, 1 << 30,
+              None) == L.E_WORKSPACE
+    assert pa(fake, 10, 2, M.ctypes.data, 4.0, G.ctypes.data, fake, 1 << 30, C.byref(out), fake, 64,
+              None) == L.E_WORKSPACE
+    assert lib.kdefft_dataset_grid(None, C.byref(kf._lib.Grid()), None) == L.E_ARG

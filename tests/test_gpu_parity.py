@@ -63,6 +63,28 @@ def test_grid_and_linbin_bitexact(kf, gpu, name):
     np.testing.assert_array_equal(counts.cpu().numpy(), counts_o)
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_prepare_auto_bitexact(kf, gpu, name):
+    """A dataset planned on the device (no host round trip) has the host
+    planner's grid bit for bit and the oracle's counts."""
+    X, G, M = CASES[name]()
+    g_o, counts_o, skipped, _, _ = _case(name, X, G, M)
+    ds = kf.Dataset(_to_dev(X, gpu), G, M=M)
+    gd = ds.grid.to_dict()
+    assert np.array_equal(gd["lo"], g_o["lo"]) and np.array_equal(gd["delta"], g_o["delta"])
+    np.testing.assert_array_equal(ds.counts().cpu().numpy(), counts_o)
+    assert ds.out_of_grid() == 0
+
+
+def test_prepare_auto_nonfinite_data(kf, gpu):
+    X = np.random.default_rng(3).normal(size=(500, 2))
+    X[7, 1] = np.nan
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), np.eye(2) * 0.1, M=16)
+    assert ds.out_of_grid() == 500
+    with pytest.raises(kf.KdefftError):
+        ds.grid
+
+
 def test_linbin_fixture(kf, gpu, repo_root):
     from test_oracle_linbin import _read_fixture
     cases = _read_fixture(os.path.join(repo_root, "tests", "golden", "linbin_tiny.txt"))
