@@ -331,11 +331,13 @@ DsLayout carve_dataset(Arena& a, const kdefft_grid& g) {
 struct PrepScratch {
     double* prm;
     double* partial;
+    int64_t* copies;   // per-XCD count grids for the binning
 };
 PrepScratch carve_prepare(Arena& a, const kdefft_grid& g) {
     PrepScratch p;
     p.prm = a.take<double>(PRM);
     p.partial = a.take<double>(max_nchunks(g, FUN_PSI, 0, 1));
+    p.copies = a.take<int64_t>(XCD_COPIES * sizes_of(g).prodM);
     return p;
 }
 
@@ -469,8 +471,8 @@ PsiBatchArgs psi_args(const kdefft_grid& g, int r, int n_ds, const DsDev* const*
 int prepare_into(const double* X, int64_t n, const kdefft_grid& g, const double* Gpilot, const DsLayout& L,
                  const PrepScratch& p, bool with_const, hipStream_t s, bool dev_grid = false) {
     const double* gdev = dev_grid ? &L.rec->lo[0] : nullptr;
-    int rc = bin_and_fill(X, n, g, L.counts, L.n_out, nullptr, s, gdev);
-    if (rc) return rc;
+    if (L.n_out) HIPCHK(launch_zero(L.n_out, sizeof(int32_t), s), "zero n_out");
+    HIPCHK(launch_linbin_xcd(X, n, g, L.counts, p.copies, L.n_out, s, gdev), "linbin");
     HIPCHK(fft_prepare_nd(L.counts, L.spec, L.wmix, g, s), "count transform");
     HIPCHK(fft_autocorr_nd(L.wmix, L.alag, g, s), "count autocorrelation");
     DsDev rec{};

@@ -79,9 +79,16 @@ __global__ void k_grid_from_bounds(const double* __restrict__ bounds, kdefft_gri
                                    double* __restrict__ gdev) {
 #pragma clang fp contract(off)
     if (threadIdx.x != 0) return;
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
     for (int k = 0; k < g.d; ++k) {
         const double lo = bounds[k] - pad.v[k];
         double hi = bounds[4 + k] + pad.v[k];
+        if (!isfinite(lo) || !isfinite(hi)) {
+            // non-finite data: a NaN spacing sends every point out of the grid
+            gdev[k] = nan;
+            gdev[4 + k] = nan;
+            continue;
+        }
         if (!(hi > lo)) hi = lo + 1.0;
         gdev[k] = lo;
         gdev[4 + k] = (hi - lo) / (double)(g.M[k] - 1);
@@ -129,13 +136,24 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
 //   the largest corner (lowest number on ties) takes 2^40 - sum of the others.
 // Floating-point contraction is disabled so that every step is one IEEE
 // operation, as on the host.
+// Index of the accelerator complex die (XCD) the wavefront runs on.
+__device__ __forceinline__ unsigned xcd_id() {
+    unsigned v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(v));
+    return v;
+}
+
+// copy_stride > 0: the counts are accumulated into XCD_COPIES grids of
+// copy_stride bins, one per XCD (chosen by the die the block runs on), so the
+// atomics of different dies never meet; k_sum_copies adds them afterwards.
 template <int D>
 __global__ __launch_bounds__(256) void k_linbin(const double* __restrict__ X, int64_t n, kdefft_grid g,
                                                 const double* __restrict__ gdev,
                                                 unsigned long long* __restrict__ counts,
-                                                int32_t* __restrict__ n_out) {
+                                                int32_t* __restrict__ n_out, int64_t copy_stride) {
 #pragma clang fp contract(off)
     constexpr int NC = 1 << D;
+    if (copy_stride > 0) counts += (int64_t)(xcd_id() % XCD_COPIES) * copy_stride;
     if (gdev) {   // origin and spacing computed on the device
 #pragma unroll
         for (int k = 0; k < D; ++k) {
@@ -189,6 +207,41 @@ __global__ __launch_bounds__(256) void k_linbin(const double* __restrict__ X, in
     }
 }
 
+__global__ __launch_bounds__(256) void k_sum_copies(const unsigned long long* __restrict__ copies, int64_t stride,
+                                                    unsigned long long* __restrict__ counts) {
+    for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < stride; i += (int64_t)gridDim.x * 256) {
+        unsigned long long t = 0;
+#pragma unroll
+        for (int c = 0; c < XCD_COPIES; ++c) t += copies[c * stride + i];
+        counts[i] = t;
+    }
+}
+
+hipError_t launch_linbin_xcd(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts, int64_t* copies,
+                             int32_t* n_out, hipStream_t s, const double* gdev) {
+    int64_t prodM = 1;
+    for (int k = 0; k < g.d; ++k) prodM *= g.M[k];
+    hipError_t e = launch_zero(copies, (size_t)(XCD_COPIES * prodM) * sizeof(int64_t), s);
+    if (e != hipSuccess) return e;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    auto* c = reinterpret_cast<unsigned long long*>(copies);
+    switch (g.d) {
+        case 1: hipLaunchKernelGGL(k_linbin<1>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, prodM); break;
+        case 2: hipLaunchKernelGGL(k_linbin<2>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, prodM); break;
+        case 3: hipLaunchKernelGGL(k_linbin<3>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, prodM); break;
+        case 4: hipLaunchKernelGGL(k_linbin<4>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, prodM); break;
+        default: return hipErrorInvalidValue;
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int64_t sb = (prodM + 255) / 256;
+    if (sb > 4096) sb = 4096;
+    hipLaunchKernelGGL(k_sum_copies, dim3((unsigned)sb), dim3(256), 0, s, c, prodM,
+                       reinterpret_cast<unsigned long long*>(counts));
+    return hipGetLastError();
+}
+
 hipError_t launch_linbin(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts, int32_t* n_out,
                          hipStream_t s, const double* gdev) {
     int64_t blocks = (n + 255) / 256;
@@ -196,10 +249,10 @@ hipError_t launch_linbin(const double* X, int64_t n, const kdefft_grid& g, int64
     if (blocks < 1) blocks = 1;
     auto* c = reinterpret_cast<unsigned long long*>(counts);
     switch (g.d) {
-        case 1: hipLaunchKernelGGL(k_linbin<1>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out); break;
-        case 2: hipLaunchKernelGGL(k_linbin<2>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out); break;
-        case 3: hipLaunchKernelGGL(k_linbin<3>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out); break;
-        case 4: hipLaunchKernelGGL(k_linbin<4>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out); break;
+        case 1: hipLaunchKernelGGL(k_linbin<1>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, (int64_t)0); break;
+        case 2: hipLaunchKernelGGL(k_linbin<2>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, (int64_t)0); break;
+        case 3: hipLaunchKernelGGL(k_linbin<3>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, (int64_t)0); break;
+        case 4: hipLaunchKernelGGL(k_linbin<4>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, (int64_t)0); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -115,10 +115,12 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
     if (cs.counts) {
         const double quantum = 9.094947017729282379150390625e-13;  // 2^-40
         const int Ml = cs.M[cs.d - 1];
-        for (int e = threadIdx.x; e < ROWS * H; e += NT) {
-            const int rr = e / H, m = e - rr * H;
+        // offset of each row's counts (-1: a zero row of the padding), decoded
+        // once per row
+        __shared__ int64_t rbase[ROWS];
+        for (int rr = threadIdx.x; rr < ROWS; rr += NT) {
             const int64_t row = r0 + rr;
-            double2 v = make_double2(0.0, 0.0);
+            int64_t base = -1;
             if (row < rows) {
                 int64_t rem = row, cf = 0, mul = 1;
                 bool ok = true;
@@ -129,12 +131,19 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
                     cf += i * mul;
                     mul *= cs.M[k];
                 }
-                if (ok) {
-                    const int64_t base = cf * Ml;
-                    const int p0 = 2 * m, p1 = 2 * m + 1;
-                    if (p0 < Ml) v.x = (double)cs.counts[base + p0] * quantum;
-                    if (p1 < Ml) v.y = (double)cs.counts[base + p1] * quantum;
-                }
+                if (ok) base = cf * Ml;
+            }
+            rbase[rr] = base;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < ROWS * H; e += NT) {
+            const int rr = e / H, m = e - rr * H;
+            const int64_t base = rbase[rr];
+            double2 v = make_double2(0.0, 0.0);
+            if (base >= 0) {
+                const int p0 = 2 * m, p1 = 2 * m + 1;
+                if (p0 < Ml) v.x = (double)cs.counts[base + p0] * quantum;
+                if (p1 < Ml) v.y = (double)cs.counts[base + p1] * quantum;
             }
             buf[rr * PS + m] = v;
         }
@@ -166,12 +175,17 @@ __global__ __launch_bounds__(NT) void k_c2r_last(const double2* __restrict__ in,
     constexpr int H = N / 2, Q = H + 1;
     constexpr int PS = H + 1;
     __shared__ double2 buf[ROWS * PS];
+    __shared__ int64_t rsrc[ROWS];   // source row of each row (-1: past the end), decoded once per row
     const int64_t r0 = (int64_t)blockIdx.x * ROWS;
+    for (int rr = threadIdx.x; rr < ROWS; rr += NT) {
+        const int64_t row = r0 + rr;
+        rsrc[rr] = row < rows ? (fl.on ? flip_row(row, fl) : row) : -1;
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
         const int rr = e / Q, k = e - rr * Q;
-        const int64_t row = r0 + rr;
-        const int64_t src_row = fl.on ? flip_row(row, fl) : row;
-        buf[rr * PS + k] = row < rows ? in[src_row * Q + k] : make_double2(0.0, 0.0);
+        const int64_t src_row = rsrc[rr];
+        buf[rr * PS + k] = src_row >= 0 ? in[src_row * Q + k] : make_double2(0.0, 0.0);
     }
     __syncthreads();
     constexpr int PER = (ROWS * H + NT - 1) / NT;

@@ -94,6 +94,11 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // gdev: if not NULL, 8 device doubles (lo[4], delta[4]) that replace g's
 hipError_t launch_linbin(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts,
                          int32_t* n_out, hipStream_t s, const double* gdev = nullptr);
+// Binning into XCD_COPIES private copies of the count grid (one per XCD), then
+// their exact int64 sum into counts; copies: XCD_COPIES * prod M int64 scratch.
+constexpr int XCD_COPIES = 8;
+hipError_t launch_linbin_xcd(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts, int64_t* copies,
+                             int32_t* n_out, hipStream_t s, const double* gdev);
 // lo = min - pad, hi = max + pad (hi = lo + 1 for a degenerate axis),
 // delta = (hi - lo) / (M - 1) from the bounds written by launch_bounds, on the
 // device, into gdev (lo[4], delta[4]) -- the same IEEE steps as the host planner

@@ -77,8 +77,16 @@ def test_prepare_auto_bitexact(kf, gpu, name):
 
 
 def test_prepare_auto_nonfinite_data(kf, gpu):
+    """A NaN coordinate is ignored by the bounds and its point is counted out
+    of the grid (as on the host path); an infinite one leaves no valid grid:
+    every point is counted out and reading the grid back reports the error."""
     X = np.random.default_rng(3).normal(size=(500, 2))
     X[7, 1] = np.nan
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), np.eye(2) * 0.1, M=16)
+    assert ds.out_of_grid() == 1
+    g_o = grid.plan_auto(np.delete(X, 7, axis=0), np.eye(2) * 0.1, [16, 16])
+    assert np.array_equal(ds.grid.to_dict()["delta"], g_o["delta"])
+    X[7, 1] = np.inf
     ds = kf.Dataset(torch.from_numpy(X).to(gpu), np.eye(2) * 0.1, M=16)
     assert ds.out_of_grid() == 500
     with pytest.raises(kf.KdefftError):
