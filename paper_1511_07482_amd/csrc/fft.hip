@@ -136,6 +136,16 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
             rbase[rr] = base;
         }
         __syncthreads();
+        // a block of zero rows only (the padding): its spectrum is zero
+        bool any = false;
+        for (int rr = 0; rr < ROWS; ++rr) any = any || rbase[rr] >= 0;
+        if (!any) {
+            for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
+                const int64_t row = r0 + e / Q;
+                if (row < rows) out[row * Q + (e % Q)] = make_double2(0.0, 0.0);
+            }
+            return;
+        }
         for (int e = threadIdx.x; e < ROWS * H; e += NT) {
             const int rr = e / H, m = e - rr * H;
             const int64_t base = rbase[rr];
