@@ -465,37 +465,47 @@ PsiBatchArgs psi_args(const kdefft_grid& g, int r, int n_ds, const DsDev* const*
     return a;
 }
 
-// Prepare a dataset whose buffers are described by L (in a caller buffer or workspace).
-// dev_grid: the grid's origin and spacing were computed on the device into the
-// dataset record (L.rec->lo, ->delta); g then carries the shape only.
+// Prepare a dataset whose buffers are described by L (in a caller buffer or
+// workspace).  bounds (device, 8 doubles: min[4], max[4]) and
+// pad: the grid's origin and spacing are computed on the device from the data
+// bounds (g then carries the shape only) and the binning scratch was already
+// cleared by the bounds kernel; otherwise g's origin and spacing are used.
 int prepare_into(const double* X, int64_t n, const kdefft_grid& g, const double* Gpilot, const DsLayout& L,
-                 const PrepScratch& p, bool with_const, hipStream_t s, bool dev_grid = false) {
-    const double* gdev = dev_grid ? &L.rec->lo[0] : nullptr;
-    if (L.n_out) HIPCHK(launch_zero(L.n_out, sizeof(int32_t), s), "zero n_out");
-    HIPCHK(launch_linbin_xcd(X, n, g, L.counts, p.copies, L.n_out, s, gdev), "linbin");
-    HIPCHK(fft_prepare_nd(L.counts, L.spec, L.wmix, g, s), "count transform");
-    HIPCHK(fft_autocorr_nd(L.wmix, L.alag, g, s), "count autocorrelation");
-    DsDev rec{};
-    rec.wmix = L.wmix;
-    rec.alag = L.alag;
-    rec.scal = L.scal;
-    rec.n = (double)n;
+                 const PrepScratch& p, bool with_const, hipStream_t s, const double* bounds = nullptr,
+                 const double* pad = nullptr) {
+    HeaderArgs h{};
+    h.rec = L.rec;
+    h.val.wmix = L.wmix;
+    h.val.alag = L.alag;
+    h.val.scal = L.scal;
+    h.val.n = (double)n;
     for (int k = 0; k < g.d; ++k) {
-        rec.lo[k] = g.lo[k];
-        rec.delta[k] = g.delta[k];
+        h.val.lo[k] = g.lo[k];
+        h.val.delta[k] = g.delta[k];
     }
     if (Gpilot)
         for (int i = 0; i < g.d; ++i)
-            for (int j = 0; j < g.d; ++j) rec.G[i * 4 + j] = Gpilot[i * g.d + j];
-    HIPCHK(launch_write_rec(L.rec, rec, dev_grid, s), "dataset record");
-    HIPCHK(launch_zero(L.scal, 4 * sizeof(double), s), "zero scal");
+            for (int j = 0; j < g.d; ++j) h.val.G[i * 4 + j] = Gpilot[i * g.d + j];
+    h.bounds = bounds;
+    h.g = g;
+    for (int k = 0; k < g.d; ++k) h.pad[k] = pad ? pad[k] : 0.0;
+    h.n_out = L.n_out;
+    h.scal = L.scal;
+    h.prodP = (double)sizes_of(g).prodP;
     if (with_const) {
         // constant SCV term: n^-2 sum sum phi_{2G}, the psi_0 functional at 2G
-        std::vector<double> G2(g.d * g.d);
-        for (int i = 0; i < g.d * g.d; ++i) G2[i] = 2.0 * Gpilot[i];
-        const DsDev* recs[1] = {L.rec};
-        const PsiBatchArgs a = psi_args(g, 0, 1, recs, G2.data());
-        HIPCHK(launch_psi_setup(a, p.prm, s), "const-term setup");
+        h.prm = p.prm;
+        int t = 0;
+        for (int c = 0; c < g.d; ++c)
+            for (int i = c; i < g.d; ++i) h.Gv2[t++] = 2.0 * Gpilot[i * g.d + c];
+    }
+    HIPCHK(launch_ds_header(h, s), "dataset header");
+    HIPCHK(launch_linbin_xcd(X, n, g, L.counts, p.copies, L.n_out, s, bounds ? &L.rec->lo[0] : nullptr,
+                             bounds != nullptr),
+           "linbin");
+    HIPCHK(fft_prepare_nd(L.counts, L.spec, L.wmix, g, s), "count transform");
+    HIPCHK(fft_autocorr_nd(L.wmix, L.alag, g, s), "count autocorrelation");
+    if (with_const) {
         const RowLaunch rl = launch_for(FUN_PSI, g.d, 0, g.P[g.d - 1]);
         const RowGeom geo = make_geom(g, FUN_PSI, 0, 1, rl.variant);
         HIPCHK(launch_rows(FUN_PSI, g.d, 0, geo, p.prm, 1, p.partial, rl, s), "const-term rows");
@@ -966,9 +976,10 @@ int kdefft_dataset_prepare_auto(const double* X, int64_t n, int d, const int32_t
         volatile double pk = pad_sd * sd;   // the same product as kdefft_grid_auto
         pad[k] = pk;
     }
-    HIPCHK(launch_bounds(X, n, d, partial, (int)nb, bounds, s), "bounds");
-    HIPCHK(launch_grid_from_bounds(bounds, g, pad, &dl.rec->lo[0], s), "grid on the device");
-    rc = prepare_into(X, n, g, Gpilot_host, dl, p, true, s, true);
+    HIPCHK(launch_bounds(X, n, d, partial, (int)nb, bounds, s, p.copies,
+                         (size_t)(XCD_COPIES * sizes_of(g).prodM) * sizeof(int64_t)),
+           "bounds");
+    rc = prepare_into(X, n, g, Gpilot_host, dl, p, true, s, bounds, pad);
     if (rc) return rc;
     kdefft_dataset o;
     std::memset(&o, 0, sizeof(o));

@@ -10,8 +10,13 @@ namespace kdefft {
 // ------------------------------------------------------------------ bounds
 // Per-block min/max of each column of X [n, d]; min/max are exact, so the
 // result does not depend on the reduction order.
+// Also clears zero_words 32-bit words at zero_ptr (the binning's scratch), so
+// the preparation needs no separate clearing launch.
 __global__ __launch_bounds__(256) void k_bounds(const double* __restrict__ X, int64_t n, int d,
-                                                double* __restrict__ partial) {
+                                                double* __restrict__ partial, uint32_t* __restrict__ zero_ptr,
+                                                int64_t zero_words) {
+    for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < zero_words; i += (int64_t)gridDim.x * 256)
+        zero_ptr[i] = 0u;
     __shared__ double smin[4][256], smax[4][256];
     double mn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
     double mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
@@ -69,43 +74,11 @@ __global__ __launch_bounds__(256) void k_bounds_final(const double* __restrict__
     }
 }
 
-// Grid from data bounds on the device (one thread).  Same IEEE steps, in the
-// same order, as the host planner: lo = min - pad, hi = max + pad, a
-// degenerate axis gets a unit span, delta = (hi - lo) / (M - 1).
-struct PadArg {
-    double v[4];
-};
-__global__ void k_grid_from_bounds(const double* __restrict__ bounds, kdefft_grid g, PadArg pad,
-                                   double* __restrict__ gdev) {
-#pragma clang fp contract(off)
-    if (threadIdx.x != 0) return;
-    const double nan = __longlong_as_double(0x7ff8000000000000LL);
-    for (int k = 0; k < g.d; ++k) {
-        const double lo = bounds[k] - pad.v[k];
-        double hi = bounds[4 + k] + pad.v[k];
-        if (!isfinite(lo) || !isfinite(hi)) {
-            // non-finite data: a NaN spacing sends every point out of the grid
-            gdev[k] = nan;
-            gdev[4 + k] = nan;
-            continue;
-        }
-        if (!(hi > lo)) hi = lo + 1.0;
-        gdev[k] = lo;
-        gdev[4 + k] = (hi - lo) / (double)(g.M[k] - 1);
-    }
-}
-
-hipError_t launch_grid_from_bounds(const double* bounds, const kdefft_grid& g, const double* pad, double* gdev,
-                                   hipStream_t s) {
-    PadArg p{};
-    for (int k = 0; k < g.d; ++k) p.v[k] = pad[k];
-    hipLaunchKernelGGL(k_grid_from_bounds, dim3(1), dim3(64), 0, s, bounds, g, p, gdev);
-    return hipGetLastError();
-}
-
 hipError_t launch_bounds(const double* X, int64_t n, int d, double* partial, int nblk, double* out,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_bounds, dim3(nblk), dim3(256), 0, s, X, n, d, partial);
+                         hipStream_t s, void* zero_ptr, size_t zero_bytes) {
+    if (zero_bytes % 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bounds, dim3(nblk), dim3(256), 0, s, X, n, d, partial, static_cast<uint32_t*>(zero_ptr),
+                       (int64_t)(zero_bytes / 4));
     hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(256), 0, s, partial, nblk, d, out);
     return hipGetLastError();
 }
@@ -218,11 +191,14 @@ __global__ __launch_bounds__(256) void k_sum_copies(const unsigned long long* __
 }
 
 hipError_t launch_linbin_xcd(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts, int64_t* copies,
-                             int32_t* n_out, hipStream_t s, const double* gdev) {
+                             int32_t* n_out, hipStream_t s, const double* gdev, bool copies_zeroed) {
     int64_t prodM = 1;
     for (int k = 0; k < g.d; ++k) prodM *= g.M[k];
-    hipError_t e = launch_zero(copies, (size_t)(XCD_COPIES * prodM) * sizeof(int64_t), s);
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    if (!copies_zeroed) {
+        e = launch_zero(copies, (size_t)(XCD_COPIES * prodM) * sizeof(int64_t), s);
+        if (e != hipSuccess) return e;
+    }
     int64_t blocks = (n + 255) / 256;
     if (blocks > 16384) blocks = 16384;
     auto* c = reinterpret_cast<unsigned long long*>(copies);

@@ -89,7 +89,7 @@ int ng_of(int kind, int d, int r);   // number of kernel grids of a family
 hipError_t twiddles(const double2** out);  // per-device table e^{-2 pi i m/4096}
 
 hipError_t launch_bounds(const double* X, int64_t n, int d, double* partial, int nblk,
-                         double* out, hipStream_t s);
+                         double* out, hipStream_t s, void* zero_ptr = nullptr, size_t zero_bytes = 0);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // gdev: if not NULL, 8 device doubles (lo[4], delta[4]) that replace g's
 hipError_t launch_linbin(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts,
@@ -98,15 +98,29 @@ hipError_t launch_linbin(const double* X, int64_t n, const kdefft_grid& g, int64
 // their exact int64 sum into counts; copies: XCD_COPIES * prod M int64 scratch.
 constexpr int XCD_COPIES = 8;
 hipError_t launch_linbin_xcd(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts, int64_t* copies,
-                             int32_t* n_out, hipStream_t s, const double* gdev);
-// lo = min - pad, hi = max + pad (hi = lo + 1 for a degenerate axis),
-// delta = (hi - lo) / (M - 1) from the bounds written by launch_bounds, on the
-// device, into gdev (lo[4], delta[4]) -- the same IEEE steps as the host planner
-hipError_t launch_grid_from_bounds(const double* bounds, const kdefft_grid& g, const double* pad, double* gdev,
-                                   hipStream_t s);
+                             int32_t* n_out, hipStream_t s, const double* gdev, bool copies_zeroed);
+
+// One small launch at the start of a dataset's preparation: the record (with
+// the grid origin and spacing from the data bounds when `bounds` is set --
+// lo = min - pad, hi = max + pad, hi = lo + 1 for a degenerate axis,
+// delta = (hi - lo)/(M - 1), the same IEEE steps as the host planner), the
+// out-of-grid counter and scalar block cleared, and the parameter block of
+// the constant SCV term (psi_0 at 2G) when prm is set.
+struct HeaderArgs {
+    DsDev* rec;
+    DsDev val;
+    const double* bounds;
+    kdefft_grid g;
+    double pad[4];
+    int32_t* n_out;
+    double* scal;
+    double* prm;
+    double Gv2[10];   // vech of 2G (columns of the lower triangle)
+    double prodP;
+};
+hipError_t launch_ds_header(const HeaderArgs& h, hipStream_t s);
 hipError_t launch_fill_czp(const int64_t* counts, const kdefft_grid& g, double* czp, hipStream_t s);
-// keep_grid: leave the record's lo / delta (written on the device) as they are
-hipError_t launch_write_rec(DsDev* rec, const DsDev& val, bool keep_grid, hipStream_t s);
+
 
 // Multi-dimensional transforms over the circular-layout arrays.
 hipError_t fft_r2c_nd(const double* in, double2* out, const kdefft_grid& g, hipStream_t s);

@@ -316,13 +316,41 @@ hipError_t launch_scv_setup(const double* vechL, const ScvBatchArgs& a, int64_t 
     return hipGetLastError();
 }
 
-// One thread per dataset: P = G^{-1}, c = (-1)^r (2 pi)^{-d/2} |G|^{-1/2}
-// for the psi_r family at the given bandwidth (validated SPD on the host).
+// Parameter block of the psi_r family for bandwidth vech gv on dataset ds:
+// P = G^{-1}, c = (-1)^r (2 pi)^{-d/2} |G|^{-1/2} (even r: the sign is +1),
+// walk constants, lag array, spacing, n and the scale of the lag sums.
+template <int D>
+__device__ static void psi_params(const double* gv, const DsDev& ds, double prodP, double* p) {
+    constexpr int d = D;
+    double G[16], L[16];
+    for (int i = 0; i < 16; ++i) G[i] = 0.0;
+    int t = 0;
+    for (int jj = 0; jj < d; ++jj)
+        for (int i = jj; i < d; ++i) {
+            G[i * 4 + jj] = gv[t];
+            G[jj * 4 + i] = gv[t];
+            ++t;
+        }
+    for (int i = 0; i < PRM; ++i) p[i] = 0.0;
+    chol4<D>(G, L);
+    chol_inv4<D>(L, p + S_P1);
+    double det = 1.0;
+    for (int k = 0; k < d; ++k) det *= L[k * 4 + k];
+    p[S_C] = two_pi_pow(d) / det;
+    put_ptr(p + S_WMIX, ds.wmix);
+    put_ptr(p + S_ALAG, ds.alag);
+    for (int k = 0; k < d; ++k) p[S_DELTA + k] = ds.delta[k];
+    put_walk<D>(p, 0, p + S_P1, ds.delta[d - 1], p[S_C]);
+    p[S_N] = ds.n;
+    p[S_SCALE] = 1.0 / (ds.n * ds.n * prodP);
+}
+
+// One thread per dataset: the psi_r parameter block at its bandwidth
+// (validated SPD on the host).
 template <int D>
 __global__ void k_psi_setup(PsiBatchArgs a, double* __restrict__ prm) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= a.n_ds) return;
-    constexpr int d = D;
     const DsDev* dsp = a.rec[0];
     double gv[10];
     for (int t = 0; t < 10; ++t) gv[t] = a.Gv[0][t];
@@ -333,29 +361,7 @@ __global__ void k_psi_setup(PsiBatchArgs a, double* __restrict__ prm) {
 #pragma unroll
             for (int t = 0; t < 10; ++t) gv[t] = a.Gv[jj][t];
         }
-    const DsDev& ds = *dsp;
-    double G[16], L[16];
-    for (int i = 0; i < 16; ++i) G[i] = 0.0;
-    int t = 0;
-    for (int jj = 0; jj < d; ++jj)
-        for (int i = jj; i < d; ++i) {
-            G[i * 4 + jj] = gv[t];
-            G[jj * 4 + i] = gv[t];
-            ++t;
-        }
-    double* p = prm + (int64_t)j * PRM;
-    for (int i = 0; i < PRM; ++i) p[i] = 0.0;
-    chol4<D>(G, L);
-    chol_inv4<D>(L, p + S_P1);
-    double det = 1.0;
-    for (int k = 0; k < d; ++k) det *= L[k * 4 + k];
-    p[S_C] = two_pi_pow(d) / det;  // (-1)^r = 1: r is even
-    put_ptr(p + S_WMIX, ds.wmix);
-    put_ptr(p + S_ALAG, ds.alag);
-    for (int k = 0; k < d; ++k) p[S_DELTA + k] = ds.delta[k];
-    put_walk<D>(p, 0, p + S_P1, ds.delta[d - 1], p[S_C]);
-    p[S_N] = ds.n;
-    p[S_SCALE] = 1.0 / (ds.n * ds.n * a.prodP);
+    psi_params<D>(gv, *dsp, a.prodP, prm + (int64_t)j * PRM);
 }
 
 hipError_t launch_psi_setup(const PsiBatchArgs& a, double* prm, hipStream_t s) {
@@ -369,19 +375,44 @@ hipError_t launch_psi_setup(const PsiBatchArgs& a, double* prm, hipStream_t s) {
     return hipGetLastError();
 }
 
-__global__ void k_write_rec(DsDev* rec, DsDev val, int keep_grid) {
+// The preparation header (one thread): grid origin and spacing from the data
+// bounds (same IEEE steps and order as the host planner; non-finite data give
+// a NaN spacing, so every point counts as out of the grid), the record, the
+// cleared counter and scalar block, and the constant-term parameter block.
+template <int D>
+__global__ void k_ds_header(HeaderArgs h) {
+#pragma clang fp contract(off)
     if (threadIdx.x != 0) return;
-    if (keep_grid) {
-        for (int k = 0; k < 4; ++k) {
-            val.lo[k] = rec->lo[k];
-            val.delta[k] = rec->delta[k];
+    DsDev v = h.val;
+    if (h.bounds) {
+        const double nan = __longlong_as_double(0x7ff8000000000000LL);
+        for (int k = 0; k < D; ++k) {
+            const double lo = h.bounds[k] - h.pad[k];
+            double hi = h.bounds[4 + k] + h.pad[k];
+            if (!isfinite(lo) || !isfinite(hi)) {
+                v.lo[k] = nan;
+                v.delta[k] = nan;
+                continue;
+            }
+            if (!(hi > lo)) hi = lo + 1.0;
+            v.lo[k] = lo;
+            v.delta[k] = (hi - lo) / (double)(h.g.M[k] - 1);
         }
     }
-    *rec = val;
+    *h.rec = v;
+    if (h.n_out) *h.n_out = 0;
+    for (int k = 0; k < 4; ++k) h.scal[k] = 0.0;
+    if (h.prm) psi_params<D>(h.Gv2, v, h.prodP, h.prm);
 }
 
-hipError_t launch_write_rec(DsDev* rec, const DsDev& val, bool keep_grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_write_rec, dim3(1), dim3(64), 0, s, rec, val, keep_grid ? 1 : 0);
+hipError_t launch_ds_header(const HeaderArgs& h, hipStream_t s) {
+    switch (h.g.d) {
+        case 1: hipLaunchKernelGGL(k_ds_header<1>, dim3(1), dim3(64), 0, s, h); break;
+        case 2: hipLaunchKernelGGL(k_ds_header<2>, dim3(1), dim3(64), 0, s, h); break;
+        case 3: hipLaunchKernelGGL(k_ds_header<3>, dim3(1), dim3(64), 0, s, h); break;
+        case 4: hipLaunchKernelGGL(k_ds_header<4>, dim3(1), dim3(64), 0, s, h); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
