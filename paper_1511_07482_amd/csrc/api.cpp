@@ -392,7 +392,6 @@ int plan_bytes(const kdefft_grid& g, int op, int r, int64_t batch, Arena& a) {
         case KDEFFT_OP_GRID_AUTO: {
             const int64_t nb = std::min<int64_t>(std::max<int64_t>((batch + 255) / 256, 1), 1024);
             a.take<double>(nb * 8);
-            a.take<double>(8);
             return KDEFFT_OK;
         }
         case KDEFFT_OP_PSI_PLAIN: carve_plain(a, g, true); return KDEFFT_OK;
@@ -406,7 +405,6 @@ int plan_bytes(const kdefft_grid& g, int op, int r, int64_t batch, Arena& a) {
             carve_prepare(a, g);
             const int64_t nb = std::min<int64_t>(std::max<int64_t>((batch + 255) / 256, 1), 1024);
             a.take<double>(nb * 8);
-            a.take<double>(8);
             return KDEFFT_OK;
         }
         case KDEFFT_OP_PSI_BATCH: carve_batch(a, g, FUN_PSI, r, std::max<int64_t>(batch, 1)); return KDEFFT_OK;
@@ -466,13 +464,13 @@ PsiBatchArgs psi_args(const kdefft_grid& g, int r, int n_ds, const DsDev* const*
 }
 
 // Prepare a dataset whose buffers are described by L (in a caller buffer or
-// workspace).  bounds (device, 8 doubles: min[4], max[4]) and
-// pad: the grid's origin and spacing are computed on the device from the data
+// workspace).  partial (device, nblk per-block bound partials of X) and pad:
+// the grid's origin and spacing are computed on the device from the data
 // bounds (g then carries the shape only) and the binning scratch was already
 // cleared by the bounds kernel; otherwise g's origin and spacing are used.
 int prepare_into(const double* X, int64_t n, const kdefft_grid& g, const double* Gpilot, const DsLayout& L,
-                 const PrepScratch& p, bool with_const, hipStream_t s, const double* bounds = nullptr,
-                 const double* pad = nullptr) {
+                 const PrepScratch& p, bool with_const, hipStream_t s, const double* partial = nullptr,
+                 int nblk = 0, const double* pad = nullptr) {
     HeaderArgs h{};
     h.rec = L.rec;
     h.val.wmix = L.wmix;
@@ -486,7 +484,8 @@ int prepare_into(const double* X, int64_t n, const kdefft_grid& g, const double*
     if (Gpilot)
         for (int i = 0; i < g.d; ++i)
             for (int j = 0; j < g.d; ++j) h.val.G[i * 4 + j] = Gpilot[i * g.d + j];
-    h.bounds = bounds;
+    h.partial = partial;
+    h.nblk = nblk;
     h.g = g;
     for (int k = 0; k < g.d; ++k) h.pad[k] = pad ? pad[k] : 0.0;
     h.n_out = L.n_out;
@@ -500,10 +499,9 @@ int prepare_into(const double* X, int64_t n, const kdefft_grid& g, const double*
             for (int i = c; i < g.d; ++i) h.Gv2[t++] = 2.0 * Gpilot[i * g.d + c];
     }
     HIPCHK(launch_ds_header(h, s), "dataset header");
-    HIPCHK(launch_linbin_xcd(X, n, g, L.counts, p.copies, L.n_out, s, bounds ? &L.rec->lo[0] : nullptr,
-                             bounds != nullptr),
+    HIPCHK(launch_linbin_xcd(X, n, g, p.copies, L.n_out, s, partial ? &L.rec->lo[0] : nullptr, partial != nullptr),
            "linbin");
-    HIPCHK(fft_prepare_nd(L.counts, L.spec, L.wmix, g, s), "count transform");
+    HIPCHK(fft_prepare_nd(p.copies, XCD_COPIES, L.counts, L.spec, L.wmix, g, s), "count transform");
     HIPCHK(fft_autocorr_nd(L.wmix, L.alag, g, s), "count autocorrelation");
     if (with_const) {
         const RowLaunch rl = launch_for(FUN_PSI, g.d, 0, g.P[g.d - 1]);
@@ -966,7 +964,6 @@ int kdefft_dataset_prepare_auto(const double* X, int64_t n, int d, const int32_t
     const PrepScratch p = carve_prepare(a, g);
     const int64_t nb = std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 1024);
     double* partial = a.take<double>(nb * 8);
-    double* bounds = a.take<double>(8);
     rc = check_ws(a, ws_bytes);
     if (rc) return rc;
     hipStream_t s = S(stream);
@@ -976,10 +973,10 @@ int kdefft_dataset_prepare_auto(const double* X, int64_t n, int d, const int32_t
         volatile double pk = pad_sd * sd;   // the same product as kdefft_grid_auto
         pad[k] = pk;
     }
-    HIPCHK(launch_bounds(X, n, d, partial, (int)nb, bounds, s, p.copies,
-                         (size_t)(XCD_COPIES * sizes_of(g).prodM) * sizeof(int64_t)),
+    HIPCHK(launch_bounds_partial(X, n, d, partial, (int)nb, s, p.copies,
+                                 (size_t)(XCD_COPIES * sizes_of(g).prodM) * sizeof(int64_t)),
            "bounds");
-    rc = prepare_into(X, n, g, Gpilot_host, dl, p, true, s, bounds, pad);
+    rc = prepare_into(X, n, g, Gpilot_host, dl, p, true, s, partial, (int)nb, pad);
     if (rc) return rc;
     kdefft_dataset o;
     std::memset(&o, 0, sizeof(o));

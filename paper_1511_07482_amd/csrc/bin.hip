@@ -8,77 +8,88 @@
 namespace kdefft {
 
 // ------------------------------------------------------------------ bounds
-// Per-block min/max of each column of X [n, d]; min/max are exact, so the
-// result does not depend on the reduction order.
-// Also clears zero_words 32-bit words at zero_ptr (the binning's scratch), so
-// the preparation needs no separate clearing launch.
-__global__ __launch_bounds__(256) void k_bounds(const double* __restrict__ X, int64_t n, int d,
-                                                double* __restrict__ partial, uint32_t* __restrict__ zero_ptr,
-                                                int64_t zero_words) {
-    for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < zero_words; i += (int64_t)gridDim.x * 256)
-        zero_ptr[i] = 0u;
-    __shared__ double smin[4][256], smax[4][256];
-    double mn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
-    double mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
-    for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        for (int k = 0; k < d; ++k) {
-            const double v = X[i * d + k];
+// Per-block min/max of each column of X [n, D] into partial[block * 8 + k]
+// (min) and partial[block * 8 + 4 + k] (max); min/max are exact, so the
+// result does not depend on the reduction order.  Also clears zero16 16-byte
+// words at zero_ptr (the binning's scratch), so the preparation needs no
+// separate clearing launch.
+template <int D>
+__global__ __launch_bounds__(256) void k_bounds(const double* __restrict__ X, int64_t n,
+                                                double* __restrict__ partial, uint4* __restrict__ zero_ptr,
+                                                int64_t zero16) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < zero16; i += stride) zero_ptr[i] = make_uint4(0, 0, 0, 0);
+    double mn[D], mx[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        mn[k] = INFINITY;
+        mx[k] = -INFINITY;
+    }
+    for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += stride) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double v = X[i * D + k];
             mn[k] = fmin(mn[k], v);
             mx[k] = fmax(mx[k], v);
         }
     }
-    for (int k = 0; k < 4; ++k) {
-        smin[k][threadIdx.x] = mn[k];
-        smax[k][threadIdx.x] = mx[k];
+    __shared__ double sw[4][8];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            mn[k] = fmin(mn[k], __shfl_xor(mn[k], off, 64));
+            mx[k] = fmax(mx[k], __shfl_xor(mx[k], off, 64));
+        }
+        if (lane == 0) {
+            sw[wid][k] = mn[k];
+            sw[wid][4 + k] = mx[k];
+        }
     }
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s)
-            for (int k = 0; k < 4; ++k) {
-                smin[k][threadIdx.x] = fmin(smin[k][threadIdx.x], smin[k][threadIdx.x + s]);
-                smax[k][threadIdx.x] = fmax(smax[k][threadIdx.x], smax[k][threadIdx.x + s]);
-            }
-        __syncthreads();
-    }
-    if (threadIdx.x < (unsigned)d) {
-        partial[blockIdx.x * 8 + threadIdx.x] = smin[threadIdx.x][0];
-        partial[blockIdx.x * 8 + 4 + threadIdx.x] = smax[threadIdx.x][0];
+    if (threadIdx.x < (unsigned)D) {
+        const int k = threadIdx.x;
+        double a = sw[0][k], b = sw[0][4 + k];
+        for (int w = 1; w < 4; ++w) {
+            a = fmin(a, sw[w][k]);
+            b = fmax(b, sw[w][4 + k]);
+        }
+        partial[blockIdx.x * 8 + k] = a;
+        partial[blockIdx.x * 8 + 4 + k] = b;
     }
 }
 
+// Reduction of the per-block partials into out (min[4], max[4]); one block.
 __global__ __launch_bounds__(256) void k_bounds_final(const double* __restrict__ partial, int nblk, int d,
                                                       double* __restrict__ out) {
-    __shared__ double smin[4][256], smax[4][256];
-    for (int k = 0; k < 4; ++k) {
-        double mn = INFINITY, mx = -INFINITY;
-        if (k < d)
-            for (int b = threadIdx.x; b < nblk; b += 256) {
-                mn = fmin(mn, partial[b * 8 + k]);
-                mx = fmax(mx, partial[b * 8 + 4 + k]);
-            }
-        smin[k][threadIdx.x] = mn;
-        smax[k][threadIdx.x] = mx;
-    }
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s)
-            for (int k = 0; k < 4; ++k) {
-                smin[k][threadIdx.x] = fmin(smin[k][threadIdx.x], smin[k][threadIdx.x + s]);
-                smax[k][threadIdx.x] = fmax(smax[k][threadIdx.x], smax[k][threadIdx.x + s]);
-            }
-        __syncthreads();
-    }
+    __shared__ double scratch[32], red[8];
+    reduce_bounds(partial, nblk, d, scratch, red);
     if (threadIdx.x < (unsigned)d) {
-        out[threadIdx.x] = smin[threadIdx.x][0];
-        out[4 + threadIdx.x] = smax[threadIdx.x][0];
+        out[threadIdx.x] = red[threadIdx.x];
+        out[4 + threadIdx.x] = red[4 + threadIdx.x];
     }
+}
+
+hipError_t launch_bounds_partial(const double* X, int64_t n, int d, double* partial, int nblk, hipStream_t s,
+                                 void* zero_ptr, size_t zero_bytes) {
+    if (zero_bytes % 16 || (reinterpret_cast<uintptr_t>(zero_ptr) & 15)) return hipErrorInvalidValue;
+    uint4* z = static_cast<uint4*>(zero_ptr);
+    const int64_t z16 = (int64_t)(zero_bytes / 16);
+    switch (d) {
+        case 1: hipLaunchKernelGGL(k_bounds<1>, dim3(nblk), dim3(256), 0, s, X, n, partial, z, z16); break;
+        case 2: hipLaunchKernelGGL(k_bounds<2>, dim3(nblk), dim3(256), 0, s, X, n, partial, z, z16); break;
+        case 3: hipLaunchKernelGGL(k_bounds<3>, dim3(nblk), dim3(256), 0, s, X, n, partial, z, z16); break;
+        case 4: hipLaunchKernelGGL(k_bounds<4>, dim3(nblk), dim3(256), 0, s, X, n, partial, z, z16); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_bounds(const double* X, int64_t n, int d, double* partial, int nblk, double* out,
-                         hipStream_t s, void* zero_ptr, size_t zero_bytes) {
-    if (zero_bytes % 4) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_bounds, dim3(nblk), dim3(256), 0, s, X, n, d, partial, static_cast<uint32_t*>(zero_ptr),
-                       (int64_t)(zero_bytes / 4));
+                         hipStream_t s) {
+    hipError_t e = launch_bounds_partial(X, n, d, partial, nblk, s, nullptr, 0);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(256), 0, s, partial, nblk, d, out);
     return hipGetLastError();
 }
@@ -118,7 +129,8 @@ __device__ __forceinline__ unsigned xcd_id() {
 
 // copy_stride > 0: the counts are accumulated into XCD_COPIES grids of
 // copy_stride bins, one per XCD (chosen by the die the block runs on), so the
-// atomics of different dies never meet; k_sum_copies adds them afterwards.
+// atomics of different dies never meet; the count transform's first pass adds
+// them (exactly, in integers) while it reads them.
 template <int D>
 __global__ __launch_bounds__(256) void k_linbin(const double* __restrict__ X, int64_t n, kdefft_grid g,
                                                 const double* __restrict__ gdev,
@@ -180,18 +192,8 @@ __global__ __launch_bounds__(256) void k_linbin(const double* __restrict__ X, in
     }
 }
 
-__global__ __launch_bounds__(256) void k_sum_copies(const unsigned long long* __restrict__ copies, int64_t stride,
-                                                    unsigned long long* __restrict__ counts) {
-    for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < stride; i += (int64_t)gridDim.x * 256) {
-        unsigned long long t = 0;
-#pragma unroll
-        for (int c = 0; c < XCD_COPIES; ++c) t += copies[c * stride + i];
-        counts[i] = t;
-    }
-}
-
-hipError_t launch_linbin_xcd(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts, int64_t* copies,
-                             int32_t* n_out, hipStream_t s, const double* gdev, bool copies_zeroed) {
+hipError_t launch_linbin_xcd(const double* X, int64_t n, const kdefft_grid& g, int64_t* copies, int32_t* n_out,
+                             hipStream_t s, const double* gdev, bool copies_zeroed) {
     int64_t prodM = 1;
     for (int k = 0; k < g.d; ++k) prodM *= g.M[k];
     hipError_t e = hipSuccess;
@@ -209,12 +211,6 @@ hipError_t launch_linbin_xcd(const double* X, int64_t n, const kdefft_grid& g, i
         case 4: hipLaunchKernelGGL(k_linbin<4>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, prodM); break;
         default: return hipErrorInvalidValue;
     }
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    int64_t sb = (prodM + 255) / 256;
-    if (sb > 4096) sb = 4096;
-    hipLaunchKernelGGL(k_sum_copies, dim3((unsigned)sb), dim3(256), 0, s, c, prodM,
-                       reinterpret_cast<unsigned long long*>(counts));
     return hipGetLastError();
 }
 

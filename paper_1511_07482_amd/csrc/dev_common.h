@@ -192,4 +192,39 @@ __device__ __forceinline__ void block_sum(double* vals, double* scratch, double*
     __syncthreads();
 }
 
+// Min/max over nblk per-block bound partials (partial[b * 8 + k] = min,
+// partial[b * 8 + 4 + k] = max, k < d) by a block of 256 threads; result in
+// red[0..3] (min) and red[4..7] (max), valid in every thread on return.
+// scratch: 32 doubles of LDS.  min/max are exact: the order does not matter.
+__device__ __forceinline__ void reduce_bounds(const double* __restrict__ partial, int nblk, int d,
+                                              double* scratch, double* red) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double mn = INFINITY, mx = -INFINITY;
+        if (k < d)
+            for (int b = threadIdx.x; b < nblk; b += 256) {
+                mn = fmin(mn, partial[b * 8 + k]);
+                mx = fmax(mx, partial[b * 8 + 4 + k]);
+            }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            mn = fmin(mn, __shfl_xor(mn, off, 64));
+            mx = fmax(mx, __shfl_xor(mx, off, 64));
+        }
+        if (lane == 0) {
+            scratch[wid * 8 + k] = mn;
+            scratch[wid * 8 + 4 + k] = mx;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        const int k = threadIdx.x;
+        double v = scratch[k];
+        for (int w = 1; w < 4; ++w) v = k < 4 ? fmin(v, scratch[w * 8 + k]) : fmax(v, scratch[w * 8 + k]);
+        red[k] = v;
+    }
+    __syncthreads();
+}
+
 }  // namespace kdefft

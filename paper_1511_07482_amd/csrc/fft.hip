@@ -82,7 +82,21 @@ struct CountSrc {
     int d;
     int M[4];
     int P[4];
+    int ncopies;            // > 0: counts holds ncopies grids of `stride` bins, summed here
+    int64_t stride;
+    int64_t* sum_out;       // the summed grid, written when ncopies > 0
 };
+
+// Count of bin i (flat index into the M^d grid); sums the copies exactly
+// (unsigned 64-bit) and stores the sum when there are several.
+__device__ __forceinline__ int64_t load_count(const CountSrc& cs, int64_t i) {
+    if (cs.ncopies <= 0) return cs.counts[i];
+    uint64_t t = 0;
+#pragma unroll 8
+    for (int c = 0; c < cs.ncopies; ++c) t += static_cast<uint64_t>(cs.counts[c * cs.stride + i]);
+    cs.sum_out[i] = static_cast<int64_t>(t);
+    return static_cast<int64_t>(t);
+}
 struct RowFlip {
     int on;
     int nlead;
@@ -152,8 +166,8 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
             double2 v = make_double2(0.0, 0.0);
             if (base >= 0) {
                 const int p0 = 2 * m, p1 = 2 * m + 1;
-                if (p0 < Ml) v.x = (double)cs.counts[base + p0] * quantum;
-                if (p1 < Ml) v.y = (double)cs.counts[base + p1] * quantum;
+                if (p0 < Ml) v.x = (double)load_count(cs, base + p0) * quantum;
+                if (p1 < Ml) v.y = (double)load_count(cs, base + p1) * quantum;
             }
             buf[rr * PS + m] = v;
         }
@@ -371,7 +385,7 @@ static hipError_t run_c2c(double2* buf, double2* out2, int64_t outer, int64_t in
     }
 
 static hipError_t r2c_last(const double* in, double2* out, int64_t rows, int N, const double2* tw, hipStream_t s,
-                           CountSrc cs = CountSrc{nullptr, 0, {0, 0, 0, 0}, {0, 0, 0, 0}}) {
+                           CountSrc cs = CountSrc{nullptr, 0, {0, 0, 0, 0}, {0, 0, 0, 0}, 0, 0, nullptr}) {
 #define CALL(NN) run_r2c_last<NN>(in, out, rows, tw, s, cs)
     if (N < 4) return hipErrorInvalidValue;
     KDEFFT_SWITCH_N(ilog2i(N), CALL)
@@ -440,16 +454,18 @@ hipError_t fft_c2r_nd(double2* inout, double* out, const kdefft_grid& g, hipStre
     return c2r_last(inout, out, lead_count(g), g.P[g.d - 1], tw, s);
 }
 
-hipError_t fft_prepare_nd(const int64_t* counts, double2* spec, double2* wmix, const kdefft_grid& g,
-                          hipStream_t s) {
+hipError_t fft_prepare_nd(const int64_t* src, int ncopies, int64_t* counts, double2* spec, double2* wmix,
+                          const kdefft_grid& g, hipStream_t s) {
     const double2* tw;
     hipError_t e = twiddles(&tw);
     if (e != hipSuccess) return e;
-    CountSrc cs{counts, g.d, {1, 1, 1, 1}, {1, 1, 1, 1}};
+    CountSrc cs{src, g.d, {1, 1, 1, 1}, {1, 1, 1, 1}, ncopies, 1, counts};
     for (int k = 0; k < g.d; ++k) {
         cs.M[k] = g.M[k];
         cs.P[k] = g.P[k];
+        cs.stride *= g.M[k];
     }
+    if (ncopies > 0 && !counts) return hipErrorInvalidValue;
     e = r2c_last(nullptr, spec, lead_count(g), g.P[g.d - 1], tw, s, cs);
     if (e != hipSuccess) return e;
     if (g.d == 1) {

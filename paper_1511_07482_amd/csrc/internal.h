@@ -88,20 +88,27 @@ int ng_of(int kind, int d, int r);   // number of kernel grids of a family
 // All return hipSuccess or the first HIP error; they only enqueue work.
 hipError_t twiddles(const double2** out);  // per-device table e^{-2 pi i m/4096}
 
+// Data bounds: per-block partials (nblk blocks; 8 doubles each) then their
+// reduction into out (min[4], max[4]).
 hipError_t launch_bounds(const double* X, int64_t n, int d, double* partial, int nblk,
-                         double* out, hipStream_t s, void* zero_ptr = nullptr, size_t zero_bytes = 0);
+                         double* out, hipStream_t s);
+// The per-block partials only, clearing zero_bytes (a multiple of 16, 16-byte
+// aligned) at zero_ptr on the way.
+hipError_t launch_bounds_partial(const double* X, int64_t n, int d, double* partial, int nblk, hipStream_t s,
+                                 void* zero_ptr, size_t zero_bytes);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // gdev: if not NULL, 8 device doubles (lo[4], delta[4]) that replace g's
 hipError_t launch_linbin(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts,
                          int32_t* n_out, hipStream_t s, const double* gdev = nullptr);
-// Binning into XCD_COPIES private copies of the count grid (one per XCD), then
-// their exact int64 sum into counts; copies: XCD_COPIES * prod M int64 scratch.
+// Binning into XCD_COPIES private copies of the count grid (one per XCD);
+// copies: XCD_COPIES * prod M int64 (cleared here unless copies_zeroed).  The
+// count transform (fft_prepare_nd) sums them exactly.
 constexpr int XCD_COPIES = 8;
-hipError_t launch_linbin_xcd(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts, int64_t* copies,
-                             int32_t* n_out, hipStream_t s, const double* gdev, bool copies_zeroed);
+hipError_t launch_linbin_xcd(const double* X, int64_t n, const kdefft_grid& g, int64_t* copies, int32_t* n_out,
+                             hipStream_t s, const double* gdev, bool copies_zeroed);
 
 // One small launch at the start of a dataset's preparation: the record (with
-// the grid origin and spacing from the data bounds when `bounds` is set --
+// the grid origin and spacing from the data bounds when `partial` is set --
 // lo = min - pad, hi = max + pad, hi = lo + 1 for a degenerate axis,
 // delta = (hi - lo)/(M - 1), the same IEEE steps as the host planner), the
 // out-of-grid counter and scalar block cleared, and the parameter block of
@@ -109,7 +116,8 @@ hipError_t launch_linbin_xcd(const double* X, int64_t n, const kdefft_grid& g, i
 struct HeaderArgs {
     DsDev* rec;
     DsDev val;
-    const double* bounds;
+    const double* partial;   // per-block bound partials of the data (or NULL: keep val's grid)
+    int nblk;
     kdefft_grid g;
     double pad[4];
     int32_t* n_out;
@@ -126,10 +134,11 @@ hipError_t launch_fill_czp(const int64_t* counts, const kdefft_grid& g, double* 
 hipError_t fft_r2c_nd(const double* in, double2* out, const kdefft_grid& g, hipStream_t s);
 hipError_t fft_c2r_nd(double2* inout, double* out, const kdefft_grid& g, hipStream_t s);
 // Count spectrum of a prepared dataset: spec = R2C(czp); wmix = |spec|^2
-// transformed forward along the leading axes.
-// (the first pass reads the int64 counts directly)
-hipError_t fft_prepare_nd(const int64_t* counts, double2* spec, double2* wmix, const kdefft_grid& g,
-                          hipStream_t s);
+// transformed forward along the leading axes.  The first pass reads the int64
+// counts directly: src is the count grid itself (ncopies = 0) or ncopies grids
+// of prod M bins whose exact sum it also writes to counts.
+hipError_t fft_prepare_nd(const int64_t* src, int ncopies, int64_t* counts, double2* spec, double2* wmix,
+                          const kdefft_grid& g, hipStream_t s);
 // alag = inverse transform of |C|^2 = prod P times the count autocorrelation,
 // computed from the mixed spectrum (rows at negated leading indices).
 hipError_t fft_autocorr_nd(const double2* wmix, double* alag, const kdefft_grid& g, hipStream_t s);

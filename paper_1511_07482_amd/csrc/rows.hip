@@ -375,20 +375,23 @@ hipError_t launch_psi_setup(const PsiBatchArgs& a, double* prm, hipStream_t s) {
     return hipGetLastError();
 }
 
-// The preparation header (one thread): grid origin and spacing from the data
+// The preparation header (one block: the reduction of the bound partials uses
+// all its threads, the rest one thread): grid origin and spacing from the data
 // bounds (same IEEE steps and order as the host planner; non-finite data give
 // a NaN spacing, so every point counts as out of the grid), the record, the
 // cleared counter and scalar block, and the constant-term parameter block.
 template <int D>
-__global__ void k_ds_header(HeaderArgs h) {
+__global__ __launch_bounds__(256) void k_ds_header(HeaderArgs h) {
 #pragma clang fp contract(off)
+    __shared__ double scratch[32], red[8];
+    if (h.partial) reduce_bounds(h.partial, h.nblk, D, scratch, red);   // uniform branch
     if (threadIdx.x != 0) return;
     DsDev v = h.val;
-    if (h.bounds) {
+    if (h.partial) {
         const double nan = __longlong_as_double(0x7ff8000000000000LL);
         for (int k = 0; k < D; ++k) {
-            const double lo = h.bounds[k] - h.pad[k];
-            double hi = h.bounds[4 + k] + h.pad[k];
+            const double lo = red[k] - h.pad[k];
+            double hi = red[4 + k] + h.pad[k];
             if (!isfinite(lo) || !isfinite(hi)) {
                 v.lo[k] = nan;
                 v.delta[k] = nan;
@@ -407,10 +410,10 @@ __global__ void k_ds_header(HeaderArgs h) {
 
 hipError_t launch_ds_header(const HeaderArgs& h, hipStream_t s) {
     switch (h.g.d) {
-        case 1: hipLaunchKernelGGL(k_ds_header<1>, dim3(1), dim3(64), 0, s, h); break;
-        case 2: hipLaunchKernelGGL(k_ds_header<2>, dim3(1), dim3(64), 0, s, h); break;
-        case 3: hipLaunchKernelGGL(k_ds_header<3>, dim3(1), dim3(64), 0, s, h); break;
-        case 4: hipLaunchKernelGGL(k_ds_header<4>, dim3(1), dim3(64), 0, s, h); break;
+        case 1: hipLaunchKernelGGL(k_ds_header<1>, dim3(1), dim3(256), 0, s, h); break;
+        case 2: hipLaunchKernelGGL(k_ds_header<2>, dim3(1), dim3(256), 0, s, h); break;
+        case 3: hipLaunchKernelGGL(k_ds_header<3>, dim3(1), dim3(256), 0, s, h); break;
+        case 4: hipLaunchKernelGGL(k_ds_header<4>, dim3(1), dim3(256), 0, s, h); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
