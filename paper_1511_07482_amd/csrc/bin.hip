@@ -131,6 +131,13 @@ __device__ __forceinline__ unsigned xcd_id() {
 // copy_stride bins, one per XCD (chosen by the die the block runs on), so the
 // atomics of different dies never meet; the count transform's first pass adds
 // them (exactly, in integers) while it reads them.
+//
+// Scattered 64-bit atomics cost one memory-side request per distinct cache
+// line per instruction, so after the per-point arithmetic the wavefront's
+// 64 x 2^D corner increments are re-dealt through LDS: instruction `it` gives
+// lane l the increment number it * 64 + l, i.e. point (it * 64 + l) / 2^D and
+// corner (it * 64 + l) % 2^D in an order whose consecutive corners differ in
+// the last (contiguous) axis, so neighbouring lanes add to adjacent bins.
 template <int D>
 __global__ __launch_bounds__(256) void k_linbin(const double* __restrict__ X, int64_t n, kdefft_grid g,
                                                 const double* __restrict__ gdev,
@@ -138,6 +145,8 @@ __global__ __launch_bounds__(256) void k_linbin(const double* __restrict__ X, in
                                                 int32_t* __restrict__ n_out, int64_t copy_stride) {
 #pragma clang fp contract(off)
     constexpr int NC = 1 << D;
+    __shared__ long long qs[256 * NC];   // increments, per wavefront in issue order
+    __shared__ int64_t fbs[256];         // flat index of each point's lowest corner
     if (copy_stride > 0) counts += (int64_t)(xcd_id() % XCD_COPIES) * copy_stride;
     if (gdev) {   // origin and spacing computed on the device
 #pragma unroll
@@ -146,49 +155,78 @@ __global__ __launch_bounds__(256) void k_linbin(const double* __restrict__ X, in
             g.delta[k] = gdev[4 + k];
         }
     }
+    int64_t stride[D];
+    stride[D - 1] = 1;
+#pragma unroll
+    for (int k = D - 2; k >= 0; --k) stride[k] = stride[k + 1] * g.M[k + 1];
+    const int lane = threadIdx.x & 63, w0ff = threadIdx.x & ~63;
     const double one_q = 1099511627776.0;  // 2^40
-    for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        double w0[D], w1[D];
-        int64_t j[D];
-        bool ok = true;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const double t = (X[i * D + k] - g.lo[k]) / g.delta[k];
-            ok = ok && (t >= 0.0) && (t <= (double)(g.M[k] - 1));
-            double jf = floor(t);
-            if (jf == (double)(g.M[k] - 1)) jf = (double)(g.M[k] - 2);
-            const double f = t - jf;
-            w0[k] = 1.0 - f;
-            w1[k] = f;
-            j[k] = (int64_t)jf;
-        }
-        if (!ok) {
-            if (n_out) atomicAdd(n_out, 1);
-            continue;
-        }
+    for (int64_t i0 = blockIdx.x * 256LL; i0 < n; i0 += (int64_t)gridDim.x * 256) {   // block-uniform
+        const int64_t i = i0 + threadIdx.x;
         long long q[NC];
-        int best = 0;
+#pragma unroll
+        for (int b = 0; b < NC; ++b) q[b] = 0;
+        int64_t fb = 0;
+        if (i < n) {
+            double w0[D], w1[D];
+            int64_t j[D];
+            bool ok = true;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const double t = (X[i * D + k] - g.lo[k]) / g.delta[k];
+                ok = ok && (t >= 0.0) && (t <= (double)(g.M[k] - 1));
+                double jf = floor(t);
+                if (jf == (double)(g.M[k] - 1)) jf = (double)(g.M[k] - 2);
+                const double f = t - jf;
+                w0[k] = 1.0 - f;
+                w1[k] = f;
+                j[k] = (int64_t)jf;
+            }
+            if (!ok) {
+                if (n_out) atomicAdd(n_out, 1);
+            } else {
+                // corner b: bit k set = upper node along axis k
+                int best = 0;
+#pragma unroll
+                for (int b = 0; b < NC; ++b) {
+                    double w = (b & 1) ? w1[0] : w0[0];
+#pragma unroll
+                    for (int k = 1; k < D; ++k) w = w * (((b >> k) & 1) ? w1[k] : w0[k]);
+                    q[b] = (long long)rint(w * one_q);
+                    if (q[b] > q[best]) best = b;
+                }
+                long long rest = 0;
+#pragma unroll
+                for (int b = 0; b < NC; ++b)
+                    if (b != best) rest += q[b];
+                q[best] = (1LL << 40) - rest;
+#pragma unroll
+                for (int k = 0; k < D; ++k) fb += j[k] * stride[k];
+            }
+        }
+        // issue order c = bit-reversed b: bit 0 of c is the last axis
 #pragma unroll
         for (int b = 0; b < NC; ++b) {
-            double w = (b & 1) ? w1[0] : w0[0];
+            int c = 0;
 #pragma unroll
-            for (int k = 1; k < D; ++k) w = w * (((b >> k) & 1) ? w1[k] : w0[k]);
-            q[b] = (long long)rint(w * one_q);
-            if (q[b] > q[best]) best = b;
+            for (int k = 0; k < D; ++k) c |= ((b >> k) & 1) << (D - 1 - k);
+            qs[w0ff * NC + lane * NC + c] = q[b];
         }
-        long long rest = 0;
+        fbs[threadIdx.x] = fb;
+        __syncthreads();
 #pragma unroll
-        for (int b = 0; b < NC; ++b)
-            if (b != best) rest += q[b];
-        q[best] = (1LL << 40) - rest;
+        for (int it = 0; it < NC; ++it) {
+            const int a = it * 64 + lane;
+            const int pnt = a / NC, c = a % NC;
+            const long long v = qs[w0ff * NC + a];
+            if (v != 0) {
+                int64_t off = 0;
 #pragma unroll
-        for (int b = 0; b < NC; ++b) {
-            if (q[b] == 0) continue;
-            int64_t flat = 0;
-#pragma unroll
-            for (int k = 0; k < D; ++k) flat = flat * g.M[k] + j[k] + ((b >> k) & 1);
-            atomicAdd(counts + flat, (unsigned long long)q[b]);
+                for (int k = 0; k < D; ++k) off += ((c >> (D - 1 - k)) & 1) * stride[k];
+                atomicAdd(counts + fbs[w0ff + pnt] + off, (unsigned long long)v);
+            }
         }
+        __syncthreads();
     }
 }
 

@@ -3,7 +3,8 @@
 // * double2 complex helpers;
 // * an LDS-resident Stockham FFT (radix 8/4/2 stages, unnormalised, sign -1
 //   forward / +1 inverse) over a batch of pencils, with twiddles read from a
-//   table e^{-2 pi i m / TWN}, m < TWN, computed once per device on the host;
+//   table e^{-2 pi i m / TWN}, m < TWN (plus contiguous copies of its
+//   N-point subsets), computed once per device on the host;
 // * deterministic block reductions (wave64 xor-shuffles then a fixed-order
 //   pass over the waves).
 #pragma once
@@ -103,13 +104,15 @@ __host__ __device__ constexpr int next_radix(int rem, int sched) {
 // One radix-R Stockham stage, in place in LDS, on NPEN pencils of length N
 // (pencil p starts at buf + p * ps).  L = length of the sub-transforms
 // already formed.  Every thread first reads all its butterflies into
-// registers, then the block synchronises and writes them back.
-template <int N, int R, int L, int NPEN, int NT, int DIR>
+// registers, then the block synchronises and writes them back.  tw holds
+// e^{-2 pi i j / TL} for j < TL (the device table, TL = TWN, or a copy of the
+// N-point subset in LDS, TL = N or a multiple of it).
+template <int N, int R, int L, int NPEN, int NT, int DIR, int TL = TWN>
 __device__ __forceinline__ void stockham_stage(double2* buf, int ps, const double2* __restrict__ tw) {
     constexpr int NB = N / R;
     constexpr int TOT = NB * NPEN;
     constexpr int PER = (TOT + NT - 1) / NT;
-    constexpr int TWS = TWN / (R * L);
+    constexpr int TWS = TL / (R * L);
     double2 v[PER][R];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
@@ -145,21 +148,55 @@ __device__ __forceinline__ void stockham_stage(double2* buf, int ps, const doubl
     __syncthreads();
 }
 
-template <int N, int L, int NPEN, int NT, int DIR, int SCHED>
+template <int N, int L, int NPEN, int NT, int DIR, int SCHED, int TL>
 __device__ __forceinline__ void fft_stages(double2* buf, int ps, const double2* __restrict__ tw) {
     if constexpr (L < N) {
         constexpr int R = next_radix(N / L, SCHED);
-        stockham_stage<N, R, L, NPEN, NT, DIR>(buf, ps, tw);
-        fft_stages<N, L * R, NPEN, NT, DIR, SCHED>(buf, ps, tw);
+        stockham_stage<N, R, L, NPEN, NT, DIR, TL>(buf, ps, tw);
+        fft_stages<N, L * R, NPEN, NT, DIR, SCHED, TL>(buf, ps, tw);
     }
 }
 
 // Unnormalised DFT of NPEN pencils of length N held in LDS; ends synchronised.
-// Caller must have synchronised after filling the buffer.
-template <int N, int NPEN, int NT, int DIR, int SCHED = 0>
+// Caller must have synchronised after filling the buffer.  tw: a twiddle table
+// of length TL (see stockham_stage).
+template <int N, int NPEN, int NT, int DIR, int SCHED = 0, int TL = TWN>
 __device__ __forceinline__ void fft_lds(double2* buf, int ps, const double2* __restrict__ tw) {
-    if constexpr (N > 1) fft_stages<N, 1, NPEN, NT, DIR, SCHED>(buf, ps, tw);
+    static_assert(TL % N == 0, "twiddle table must hold the N-th roots");
+    if constexpr (N > 1) fft_stages<N, 1, NPEN, NT, DIR, SCHED, TL>(buf, ps, tw);
 }
+
+// Copy of e^{-2 pi i j / N}, j < N, from the device table (its contiguous
+// N-point subset at offset TWN + N) into LDS in two steps: fetch() issues the
+// loads into registers (at kernel start, so their latency overlaps the data
+// loads), store() writes them to LDS; the caller synchronises before use.
+// Subsets of more than 8 values per thread are loaded in store() directly.
+template <int N, int NT>
+struct TwiddleCopy {
+    static constexpr int PER = (N + NT - 1) / NT;
+    static constexpr bool PRE = PER <= 8;
+    double2 v[PRE ? PER : 1];
+    __device__ __forceinline__ void fetch(const double2* __restrict__ tw) {
+        if constexpr (PRE) {
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int j = threadIdx.x + u * NT;
+                if ((N % NT) == 0 || j < N) v[u] = tw[TWN + N + j];
+            }
+        }
+    }
+    __device__ __forceinline__ void store(double2* lds_tw, const double2* __restrict__ tw) {
+        if constexpr (PRE) {
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int j = threadIdx.x + u * NT;
+                if ((N % NT) == 0 || j < N) lds_tw[j] = v[u];
+            }
+        } else {
+            for (int j = threadIdx.x; j < N; j += NT) lds_tw[j] = tw[TWN + N + j];
+        }
+    }
+};
 
 // ------------------------------------------------------------------ reductions
 __device__ __forceinline__ double wave_sum(double v) {

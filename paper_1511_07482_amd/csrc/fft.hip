@@ -23,7 +23,10 @@ namespace kdefft {
 
 // ------------------------------------------------------------------ twiddles
 // One table per device; kernels receive its device address as an argument.
-static __device__ double2 g_twiddle[TWN];
+// [0, TWN): e^{-2 pi i m / TWN}; then, at offset TWN + N for each power of two
+// N <= TWN, the N-point subset e^{-2 pi i j / N}, j < N (the same values, stored
+// contiguously so a block can copy the subset it needs in whole cache lines).
+static __device__ double2 g_twiddle[3 * TWN];
 
 hipError_t twiddles(const double2** out) {
     static std::mutex mu;
@@ -36,7 +39,7 @@ hipError_t twiddles(const double2** out) {
     if (!ptr[dev]) {
         // cos/sin of 2 pi m / TWN from the first octant in long double, so that
         // symmetric entries are exactly symmetric and each value is rounded once.
-        static double2 host[TWN];
+        static double2 host[3 * TWN];
         const long double pi = 3.141592653589793238462643383279502884L;
         for (int m = 0; m < TWN; ++m) {
             int q = m / (TWN / 4), rr = m % (TWN / 4);  // quadrant, remainder
@@ -59,6 +62,8 @@ hipError_t twiddles(const double2** out) {
             }
             host[m] = make_double2((double)c2, -(double)s2);  // e^{-i theta}
         }
+        for (int N = 1; N <= TWN; N *= 2)
+            for (int j = 0; j < N; ++j) host[TWN + N + j] = host[j * (TWN / N)];
         e = hipMemcpyToSymbol(HIP_SYMBOL(g_twiddle), host, sizeof(host), 0, hipMemcpyHostToDevice);
         if (e != hipSuccess) return e;
         void* p = nullptr;
@@ -124,6 +129,9 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
     constexpr int H = N / 2, Q = H + 1;
     constexpr int PS = H + 1;
     __shared__ double2 buf[ROWS * PS];
+    __shared__ double2 twl[N];
+    TwiddleCopy<N, NT> twc;
+    twc.fetch(tw);
     const int64_t r0 = (int64_t)blockIdx.x * ROWS;
     const double2* src = reinterpret_cast<const double2*>(in);
     if (cs.counts) {
@@ -178,8 +186,9 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
             buf[rr * PS + m] = row < rows ? src[row * H + m] : make_double2(0.0, 0.0);
         }
     }
+    twc.store(twl, tw);
     __syncthreads();
-    fft_lds<H, ROWS, NT, -1>(buf, PS, tw);
+    fft_lds<H, ROWS, NT, -1, 0, N>(buf, PS, twl);
     for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
         const int rr = e / Q, k = e - rr * Q;
         const int64_t row = r0 + rr;
@@ -188,7 +197,7 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
         const double2 zc = c_conj(buf[rr * PS + (k == 0 ? 0 : H - k)]);
         const double2 E = c_scale(c_add(zk, zc), 0.5);
         const double2 O = c_rot<-1>(c_scale(c_sub(zk, zc), 0.5));  // (zk - zc)/(2i)
-        const double2 w = tw[k * (TWN / N)];
+        const double2 w = twl[k];
         out[row * Q + k] = c_add(E, c_mul(w, O));
     }
 }
@@ -199,7 +208,10 @@ __global__ __launch_bounds__(NT) void k_c2r_last(const double2* __restrict__ in,
     constexpr int H = N / 2, Q = H + 1;
     constexpr int PS = H + 1;
     __shared__ double2 buf[ROWS * PS];
+    __shared__ double2 twl[N];
     __shared__ int64_t rsrc[ROWS];   // source row of each row (-1: past the end), decoded once per row
+    TwiddleCopy<N, NT> twc;
+    twc.fetch(tw);
     const int64_t r0 = (int64_t)blockIdx.x * ROWS;
     for (int rr = threadIdx.x; rr < ROWS; rr += NT) {
         const int64_t row = r0 + rr;
@@ -211,6 +223,7 @@ __global__ __launch_bounds__(NT) void k_c2r_last(const double2* __restrict__ in,
         const int64_t src_row = rsrc[rr];
         buf[rr * PS + k] = src_row >= 0 ? in[src_row * Q + k] : make_double2(0.0, 0.0);
     }
+    twc.store(twl, tw);
     __syncthreads();
     constexpr int PER = (ROWS * H + NT - 1) / NT;
     double2 z[PER];
@@ -222,7 +235,7 @@ __global__ __launch_bounds__(NT) void k_c2r_last(const double2* __restrict__ in,
             const double2 xk = buf[rr * PS + k];
             const double2 xc = c_conj(buf[rr * PS + H - k]);
             const double2 E = c_scale(c_add(xk, xc), 0.5);
-            const double2 O = c_scale(c_mulc(c_sub(xk, xc), tw[k * (TWN / N)]), 0.5);  // * e^{+i..}
+            const double2 O = c_scale(c_mulc(c_sub(xk, xc), twl[k]), 0.5);  // * e^{+i..}
             z[u] = c_add(E, c_rot<1>(O));
         }
     }
@@ -236,7 +249,7 @@ __global__ __launch_bounds__(NT) void k_c2r_last(const double2* __restrict__ in,
         }
     }
     __syncthreads();
-    fft_lds<H, ROWS, NT, 1>(buf, PS, tw);
+    fft_lds<H, ROWS, NT, 1, 0, N>(buf, PS, twl);
     double2* dst = reinterpret_cast<double2*>(out);
     for (int e = threadIdx.x; e < ROWS * H; e += NT) {
         const int rr = e / H, m = e - rr * H;
@@ -262,6 +275,9 @@ __global__ __launch_bounds__(NT) void k_c2c_strided(double2* __restrict__ buf, d
                                                     const double2* __restrict__ tw) {
     constexpr int PS = T > 1 ? N + 1 : N;
     __shared__ double2 lds[T * PS];
+    __shared__ double2 twl[N];
+    TwiddleCopy<N, NT> twc;
+    twc.fetch(tw);
     const int64_t o = blockIdx.x / tiles;
     const int64_t i0 = (blockIdx.x - o * tiles) * T;
     double2* base = buf + o * N * inner + i0;
@@ -269,8 +285,9 @@ __global__ __launch_bounds__(NT) void k_c2c_strided(double2* __restrict__ buf, d
         const int t = e % T, p = e / T;
         lds[t * PS + p] = (i0 + t < inner) ? base[(int64_t)p * inner + t] : make_double2(0.0, 0.0);
     }
+    twc.store(twl, tw);
     __syncthreads();
-    fft_lds<N, T, NT, DIR>(lds, PS, tw);
+    fft_lds<N, T, NT, DIR, 0, N>(lds, PS, twl);
     for (int e = threadIdx.x; e < N * T; e += NT) {
         const int t = e % T, p = e / T;
         if (i0 + t < inner) base[(int64_t)p * inner + t] = lds[t * PS + p];
@@ -282,7 +299,7 @@ __global__ __launch_bounds__(NT) void k_c2c_strided(double2* __restrict__ buf, d
             lds[t * PS + p] = make_double2(v.x * v.x + v.y * v.y, 0.0);
         }
         __syncthreads();
-        fft_lds<N, T, NT, -1>(lds, PS, tw);
+        fft_lds<N, T, NT, -1, 0, N>(lds, PS, twl);
         double2* b2 = out2 + o * N * inner + i0;
         for (int e = threadIdx.x; e < N * T; e += NT) {
             const int t = e % T, p = e / T;

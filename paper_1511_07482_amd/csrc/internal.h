@@ -86,7 +86,7 @@ int ng_of(int kind, int d, int r);   // number of kernel grids of a family
 
 // -------------------------------------------------------------- launchers
 // All return hipSuccess or the first HIP error; they only enqueue work.
-hipError_t twiddles(const double2** out);  // per-device table e^{-2 pi i m/4096}
+hipError_t twiddles(const double2** out);  // per-device table e^{-2 pi i m/4096} + N-point subsets
 
 // Data bounds: per-block partials (nblk blocks; 8 doubles each) then their
 // reduction into out (min[4], max[4]).
