@@ -331,13 +331,15 @@ DsLayout carve_dataset(Arena& a, const kdefft_grid& g) {
 struct PrepScratch {
     double* prm;
     double* partial;
-    int64_t* copies;   // per-XCD count grids for the binning
+    int64_t* copies;    // per-XCD count grids for the binning
+    int32_t* counter;   // completion counter of the constant-term launch
 };
 PrepScratch carve_prepare(Arena& a, const kdefft_grid& g) {
     PrepScratch p;
     p.prm = a.take<double>(PRM);
     p.partial = a.take<double>(max_nchunks(g, FUN_PSI, 0, 1));
     p.copies = a.take<int64_t>(XCD_COPIES * sizes_of(g).prodM);
+    p.counter = a.take<int32_t>(1);
     return p;
 }
 
@@ -370,7 +372,22 @@ PlainScratch carve_plain(Arena& a, const kdefft_grid& g, bool with_counts) {
 struct BatchScratch {
     double* prm;
     double* partial;
+    int32_t* counters;   // completion counters, one per candidate
 };
+
+// Completion of a lag launch: fused into the row kernel for the lag-domain
+// variants, else (FIN_NONE) a separate final kernel.
+FinishArgs fin_psi(const RowLaunch& rl, int ng, int32_t* counters, double* psi, double* scal) {
+    FinishArgs f{};
+    if (rl.variant >= 3) {
+        f.mode = FIN_PSI;
+        f.ng = ng;
+        f.counters = counters;
+        f.out = psi;
+        f.scal = scal;
+    }
+    return f;
+}
 // Partial sums of the row kernels: sized for every family that may run in
 // this workspace (the SCV families differ in grids per item and chunking).
 BatchScratch carve_batch(Arena& a, const kdefft_grid& g, int kind, int r, int64_t ncand) {
@@ -384,6 +401,7 @@ BatchScratch carve_batch(Arena& a, const kdefft_grid& g, int kind, int r, int64_
             need = std::max<int64_t>(need, max_nchunks(g, k, 2, ncand) * ng_of(k, g.d, 2));
     }
     b.partial = a.take<double>(ncand * need);
+    b.counters = a.take<int32_t>(ncand);
     return b;
 }
 
@@ -491,12 +509,14 @@ int prepare_into(const double* X, int64_t n, const kdefft_grid& g, const double*
     h.n_out = L.n_out;
     h.scal = L.scal;
     h.prodP = (double)sizes_of(g).prodP;
+    const RowLaunch crl = launch_for(FUN_PSI, g.d, 0, g.P[g.d - 1]);
     if (with_const) {
         // constant SCV term: n^-2 sum sum phi_{2G}, the psi_0 functional at 2G
         h.prm = p.prm;
         int t = 0;
         for (int c = 0; c < g.d; ++c)
             for (int i = c; i < g.d; ++i) h.Gv2[t++] = 2.0 * Gpilot[i * g.d + c];
+        h.fin = fin_psi(crl, 1, p.counter, nullptr, L.scal);
     }
     HIPCHK(launch_ds_header(h, s), "dataset header");
     HIPCHK(launch_linbin_xcd(X, n, g, p.copies, L.n_out, s, partial ? &L.rec->lo[0] : nullptr, partial != nullptr),
@@ -504,10 +524,10 @@ int prepare_into(const double* X, int64_t n, const kdefft_grid& g, const double*
     HIPCHK(fft_prepare_nd(p.copies, XCD_COPIES, L.counts, L.spec, L.wmix, g, s), "count transform");
     HIPCHK(fft_autocorr_nd(L.wmix, L.alag, g, s), "count autocorrelation");
     if (with_const) {
-        const RowLaunch rl = launch_for(FUN_PSI, g.d, 0, g.P[g.d - 1]);
-        const RowGeom geo = make_geom(g, FUN_PSI, 0, 1, rl.variant);
-        HIPCHK(launch_rows(FUN_PSI, g.d, 0, geo, p.prm, 1, p.partial, rl, s), "const-term rows");
-        HIPCHK(launch_psi_final(p.partial, geo, 1, p.prm, 1, nullptr, L.scal, s), "const-term final");
+        const RowGeom geo = make_geom(g, FUN_PSI, 0, 1, crl.variant);
+        HIPCHK(launch_rows(FUN_PSI, g.d, 0, geo, p.prm, 1, p.partial, crl, s), "const-term rows");
+        if (h.fin.mode == FIN_NONE)
+            HIPCHK(launch_psi_final(p.partial, geo, 1, p.prm, 1, nullptr, L.scal, s), "const-term final");
     }
     return KDEFFT_OK;
 }
@@ -804,12 +824,14 @@ int kdefft_psi(const double* X, int64_t n, const kdefft_grid* g, const double* G
     rc = prepare_into(X, n, *g, G_host, L2, pp, false, s);
     if (rc) return rc;
     const DsDev* recs[1] = {L2.rec};
-    const PsiBatchArgs args = psi_args(*g, r, 1, recs, G_host);
-    HIPCHK(launch_psi_setup(args, b.prm, s), "psi setup");
+    PsiBatchArgs args = psi_args(*g, r, 1, recs, G_host);
     const RowLaunch rl = launch_for(FUN_PSI, d, r, g->P[d - 1]);
+    args.fin = fin_psi(rl, nu, b.counters, psi, nullptr);
+    HIPCHK(launch_psi_setup(args, b.prm, s), "psi setup");
     const RowGeom geo = make_geom(*g, FUN_PSI, r, 1, rl.variant);
     HIPCHK(timed_rows(FUN_PSI, d, r, geo, b.prm, 1, b.partial, rl, s), "psi rows");
-    HIPCHK(launch_psi_final(b.partial, geo, nu, b.prm, 1, psi, nullptr, s), "psi final");
+    if (args.fin.mode == FIN_NONE)
+        HIPCHK(launch_psi_final(b.partial, geo, nu, b.prm, 1, psi, nullptr, s), "psi final");
     return KDEFFT_OK;
 }
 
@@ -1041,13 +1063,16 @@ int kdefft_psi_batch(const kdefft_dataset* ds, int n_ds, const double* G_host, i
     if (rc) return rc;
     std::vector<const DsDev*> recs(n_ds);
     for (int j = 0; j < n_ds; ++j) recs[j] = static_cast<const DsDev*>(ds[j].rec);
-    const PsiBatchArgs args = psi_args(g, r, n_ds, recs.data(), Gs.data());
+    PsiBatchArgs args = psi_args(g, r, n_ds, recs.data(), Gs.data());
     hipStream_t s = S(stream);
-    HIPCHK(launch_psi_setup(args, b.prm, s), "psi setup");
     const RowLaunch rl = launch_for(FUN_PSI, d, r, g.P[d - 1]);
+    const int nu = (int)binom(d + r - 1, r);
+    args.fin = fin_psi(rl, nu, b.counters, psi, nullptr);
+    HIPCHK(launch_psi_setup(args, b.prm, s), "psi setup");
     const RowGeom geo = make_geom(g, FUN_PSI, r, n_ds, rl.variant);
     HIPCHK(timed_rows(FUN_PSI, d, r, geo, b.prm, n_ds, b.partial, rl, s), "psi rows");
-    HIPCHK(launch_psi_final(b.partial, geo, (int)binom(d + r - 1, r), b.prm, n_ds, psi, nullptr, s), "psi final");
+    if (args.fin.mode == FIN_NONE)
+        HIPCHK(launch_psi_final(b.partial, geo, nu, b.prm, n_ds, psi, nullptr, s), "psi final");
     return KDEFFT_OK;
 }
 
@@ -1100,6 +1125,9 @@ static int crit_common(const kdefft_dataset* ds, int n_ds, const int64_t* off, c
     const int ckey = crit == KDEFFT_CRIT_LSCV_EXACT ? KDEFFT_CRIT_LSCV : crit;
     const RowLaunch rl = force ? *force : launch_for(kind, g.d, kr, g.P[g.d - 1], ckey);
     const RowGeom geo = make_geom(g, kind, kr, B, rl.variant);
+    // the criteria complete in their own kernel: fused into the row kernel the
+    // assembly lengthens the dominant launch by about what the separate
+    // launch costs in a replayed graph
     HIPCHK(launch_scv_setup(vechL, a, B, b.prm, status, s), "criterion setup");
     HIPCHK(timed_rows(kind, g.d, kr, geo, b.prm, B, b.partial, rl, s), "criterion rows");
     HIPCHK(launch_scv_final(kind, b.partial, geo, b.prm, B, grad_out, obj, grad, s), "criterion final");

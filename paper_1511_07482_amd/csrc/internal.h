@@ -10,7 +10,7 @@
 
 namespace kdefft {
 
-constexpr int PRM = 80;     // doubles per candidate parameter block
+constexpr int PRM = 96;     // doubles per candidate parameter block
 constexpr int NT_DEF = 256;  // threads per block of the simple kernels
 
 // Parameter block layout (float64 slots) shared by setup, row and finalize kernels.
@@ -23,7 +23,23 @@ constexpr int NT_DEF = 256;  // threads per block of the simple kernels
 //   lag walk of Gaussian k (k = 0, 1) at [64 + 8k, 72 + 8k): dz[0..3] = delta_last P_k[i][last],
 //         [4] hpl = delta_last^2 P_k[last][last] / 2, [5] sig = exp(-2 hpl), [6] log(1e-290 / c_k)
 enum Slot { S_P1 = 0, S_C = 16, S_P2 = 16, S_C1 = 32, S_C2 = 33, S_FIRST = 34, S_R = 35, S_SIGN = 36, S_ALAG = 38,
-            S_WMIX = 39, S_DELTA = 40, S_N = 44, S_SCALE = 45, S_CONST = 46, S_SING = 47, S_L = 48, S_WALK = 64 };
+            S_WMIX = 39, S_DELTA = 40, S_N = 44, S_SCALE = 45, S_CONST = 46, S_SING = 47, S_L = 48, S_WALK = 64,
+            // fused completion (FinishArgs): mode, grids, counter and output pointers
+            S_FIN_MODE = 80, S_FIN_NG = 81, S_FIN_CNT = 82, S_FIN_OUT = 83, S_FIN_SCAL = 84 };
+
+// How a psi lag launch completes (written into every candidate's parameter
+// block by the setup kernels): FIN_NONE = a separate final kernel assembles
+// the results; FIN_PSI = the block that finishes a candidate's last work item
+// writes its psi entries.  counters: one int per candidate, cleared by the
+// setup kernel.
+enum FinMode { FIN_NONE = 0, FIN_PSI = 1 };
+struct FinishArgs {
+    int mode;
+    int ng;
+    int32_t* counters;
+    double* out;    // psi [n_ds, ng]
+    double* scal;   // psi[0, 0] also stored here (constant SCV term)
+};
 
 // Per-dataset record kept in the dataset's own device buffer (written by a
 // kernel at prepare time); batched calls pass pointers to these records.
@@ -54,6 +70,7 @@ struct PsiBatchArgs {
     double prodP;
     const DsDev* rec[KDEFFT_MAX_PSI_DS];
     double Gv[KDEFFT_MAX_PSI_DS][10];   // vech (columns of the lower triangle)
+    FinishArgs fin;
 };
 struct PiArgs {
     int n_ds;
@@ -125,6 +142,7 @@ struct HeaderArgs {
     double* prm;
     double Gv2[10];   // vech of 2G (columns of the lower triangle)
     double prodP;
+    FinishArgs fin;   // completion of the constant-term launch
 };
 hipError_t launch_ds_header(const HeaderArgs& h, hipStream_t s);
 hipError_t launch_fill_czp(const int64_t* counts, const kdefft_grid& g, double* czp, hipStream_t s);

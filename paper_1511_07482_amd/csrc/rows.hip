@@ -6,6 +6,7 @@
 
 #include "dev_common.h"
 #include "dev_kernels.h"
+#include "finish.h"
 #include "internal.h"
 
 namespace kdefft {
@@ -121,60 +122,6 @@ hipError_t launch_rows(int kind, int d, int r, const RowGeom& geo, const double*
     }
 }
 
-// ------------------------------------------------------------------ small dense linear algebra (d <= 4)
-// Cholesky A = L L^T of a symmetric d x d (row stride 4); false if not positive definite.
-template <int D>
-__device__ __forceinline__ static bool chol4(const double* A, double* L) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) L[i] = 0.0;
-    bool ok = true;
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-        double s = A[j * 4 + j];
-#pragma unroll
-        for (int k = 0; k < j; ++k) s -= L[j * 4 + k] * L[j * 4 + k];
-        ok = ok && (s > 0.0);
-        const double ljj = sqrt(s > 0.0 ? s : 1.0);
-        L[j * 4 + j] = ljj;
-#pragma unroll
-        for (int i = j + 1; i < D; ++i) {
-            double t = A[i * 4 + j];
-#pragma unroll
-            for (int k = 0; k < j; ++k) t -= L[i * 4 + k] * L[j * 4 + k];
-            L[i * 4 + j] = t / ljj;
-        }
-    }
-    return ok;
-}
-
-// Inverse of L L^T from the lower factor L (row stride 4).
-template <int D>
-__device__ __forceinline__ static void chol_inv4(const double* L, double* Ainv) {
-    double Li[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) Li[i] = 0.0;
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-        Li[j * 4 + j] = 1.0 / L[j * 4 + j];
-#pragma unroll
-        for (int i = j + 1; i < D; ++i) {
-            double s = 0.0;
-#pragma unroll
-            for (int k = j; k < i; ++k) s -= L[i * 4 + k] * Li[k * 4 + j];
-            Li[i * 4 + j] = s / L[i * 4 + i];
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < D; ++i)
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            double s = 0.0;
-#pragma unroll
-            for (int k = (i > j ? i : j); k < D; ++k) s += Li[k * 4 + i] * Li[k * 4 + j];
-            Ainv[i * 4 + j] = s;
-        }
-}
-
 __device__ static double two_pi_pow(int d) {  // (2 pi)^{-d/2}
     const double c = 0.39894228040143267794;      // (2 pi)^{-1/2}
     double r = 1.0;
@@ -196,6 +143,16 @@ __device__ static void put_walk(double* p, int k, const double* P, double dl, do
 
 __device__ static void put_ptr(double* slot, const void* p) {
     *slot = __longlong_as_double(static_cast<long long>(reinterpret_cast<uintptr_t>(p)));
+}
+
+// Completion slots of candidate h's block; clears its counter when fused.
+__device__ static void put_finish(double* p, const FinishArgs& f, int64_t h) {
+    p[S_FIN_MODE] = (double)f.mode;
+    p[S_FIN_NG] = (double)f.ng;
+    put_ptr(p + S_FIN_CNT, f.counters);
+    put_ptr(p + S_FIN_OUT, f.out);
+    put_ptr(p + S_FIN_SCAL, f.scal);
+    if (f.mode != FIN_NONE) f.counters[h] = 0;
 }
 
 // One thread per candidate: H = L L^T from vechL, then per criterion
@@ -362,6 +319,7 @@ __global__ void k_psi_setup(PsiBatchArgs a, double* __restrict__ prm) {
             for (int t = 0; t < 10; ++t) gv[t] = a.Gv[jj][t];
         }
     psi_params<D>(gv, *dsp, a.prodP, prm + (int64_t)j * PRM);
+    put_finish(prm + (int64_t)j * PRM, a.fin, j);
 }
 
 hipError_t launch_psi_setup(const PsiBatchArgs& a, double* prm, hipStream_t s) {
@@ -405,7 +363,10 @@ __global__ __launch_bounds__(256) void k_ds_header(HeaderArgs h) {
     *h.rec = v;
     if (h.n_out) *h.n_out = 0;
     for (int k = 0; k < 4; ++k) h.scal[k] = 0.0;
-    if (h.prm) psi_params<D>(h.Gv2, v, h.prodP, h.prm);
+    if (h.prm) {
+        psi_params<D>(h.Gv2, v, h.prodP, h.prm);
+        put_finish(h.prm, h.fin, 0);
+    }
 }
 
 hipError_t launch_ds_header(const HeaderArgs& h, hipStream_t s) {
@@ -419,17 +380,7 @@ hipError_t launch_ds_header(const HeaderArgs& h, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Sum of the partial sums of candidate h, grid g over its chunks, by one
-// wavefront: lane t takes chunks t, t+64, ... in order, then a fixed xor tree.
-__device__ static double chunk_sum(const double* __restrict__ partial, int64_t h, int64_t nchunks, int ng, int g) {
-    const int lane = threadIdx.x & 63;
-    double s = 0.0;
-    for (int64_t c = lane; c < nchunks; c += 64) s += partial[(h * nchunks + c) * ng + g];
-    return wave_sum(s);
-}
-
-// Criterion assembly, one wavefront per candidate.  kind: FUN_SCV_OBJ or FUN_ETA* (obj only),
-// FUN_SCV_OBJGRAD (obj + grad), FUN_SCV_GRAD (adjoint: grad scaled by grad_out).
+// Criterion assembly, one wavefront per candidate (see crit_finish).
 template <int D>
 __global__ __launch_bounds__(64) void k_scv_final(int kind, const double* __restrict__ partial, int64_t nchunks,
                                                   int ng, const double* __restrict__ prm, int64_t ncand,
@@ -437,40 +388,7 @@ __global__ __launch_bounds__(64) void k_scv_final(int kind, const double* __rest
                                                   double* __restrict__ grad) {
     const int64_t h = blockIdx.x;
     if (h >= ncand) return;
-    constexpr int d = D;
-    const double* p = prm + h * PRM;
-    constexpr int q = d * (d + 1) / 2;
-    double T[1 + q];
-#pragma unroll
-    for (int g = 0; g < 1 + q; ++g) T[g] = g < ng ? chunk_sum(partial, h, nchunks, ng, g) * p[S_SCALE] : 0.0;
-    if (threadIdx.x != 0) return;
-    const bool sing = p[S_SING] != 0.0;
-    const double nan = __longlong_as_double(0x7ff8000000000000LL);
-    const double* L = p + S_L;
-    // closed-form term: proportional to |H|^{-1/2} for every criterion with a
-    // gradient, so its matrix gradient is -1/2 first H^{-1}
-    const double first = p[S_FIRST];
-    if (kind != FUN_SCV_GRAD) obj[h] = sing ? nan : first + T[0] + p[S_CONST];
-    if (kind == FUN_SCV_OBJ || kind == FUN_ETA1 || kind == FUN_ETA2 || grad == nullptr) return;
-    const int off = kind == FUN_SCV_OBJGRAD ? 1 : 0;
-    double Hinv[16];
-    chol_inv4<D>(L, Hinv);
-    double gH[16];
-    int t = off;
-    for (int i = 0; i < d; ++i)
-        for (int j = i; j < d; ++j) {
-            const double v = -0.5 * first * Hinv[i * 4 + j] + T[t++];
-            gH[i * 4 + j] = v;
-            gH[j * 4 + i] = v;
-        }
-    const double sc = kind == FUN_SCV_GRAD ? grad_out[h] : 1.0;
-    int o = 0;
-    for (int j = 0; j < d; ++j)
-        for (int i = j; i < d; ++i) {
-            double s = 0.0;
-            for (int k = 0; k < d; ++k) s += gH[i * 4 + k] * L[k * 4 + j];
-            grad[h * q + o++] = sing ? nan : 2.0 * s * sc;
-        }
+    crit_finish<D>(kind, partial, nchunks, ng, prm + h * PRM, h, grad_out, obj, grad);
 }
 
 hipError_t launch_scv_final(int kind, const double* partial, const RowGeom& geo, const double* prm, int64_t ncand,
@@ -608,11 +526,7 @@ __global__ __launch_bounds__(64) void k_psi_final(const double* __restrict__ par
     const int64_t e = blockIdx.x;
     if (e >= ncand * ng) return;
     const int64_t h = e / ng;
-    const int g = (int)(e - h * ng);
-    const double v = chunk_sum(partial, h, nchunks, ng, g) * prm[h * PRM + S_SCALE];
-    if (threadIdx.x != 0) return;
-    if (psi) psi[h * ng + g] = v;
-    if (scal_out && e == 0) scal_out[0] = v;
+    psi_finish(partial, nchunks, ng, prm + h * PRM, h, (int)(e - h * ng), psi, scal_out);
 }
 
 hipError_t launch_psi_final(const double* partial, const RowGeom& geo, int ng, const double* prm, int64_t ncand,

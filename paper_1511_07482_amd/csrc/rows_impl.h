@@ -29,6 +29,7 @@
 
 #include "dev_common.h"
 #include "dev_kernels.h"
+#include "finish.h"
 #include "internal.h"
 
 namespace kdefft {
@@ -453,10 +454,8 @@ __global__ __launch_bounds__(NT) void k_lag(const double* __restrict__ prm, RowG
         }
         double outv[NG];
         block_sum<NG, NT>(acc, red, outv);
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int g = 0; g < NG; ++g) partial[item * NG + g] = outv[g];
-        }
+        if (threadIdx.x == 0) store_item<NG>(pr, partial + item * NG, outv);
+        fused_finish<D>(pr, partial, geo.nchunks, h);
     }
 }
 
@@ -637,10 +636,8 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
         }
         double outv[NG];
         block_sum<NG, NT>(acc, red, outv);
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int g = 0; g < NG; ++g) partial[item * NG + g] = outv[g];
-        }
+        if (threadIdx.x == 0) store_item<NG>(pr, partial + item * NG, outv);
+        fused_finish<D>(pr, partial, geo.nchunks, h);
     }
 }
 
