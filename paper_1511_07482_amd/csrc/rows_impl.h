@@ -462,25 +462,33 @@ __global__ __launch_bounds__(NT) void k_lag(const double* __restrict__ prm, RowG
 // Lag-domain evaluation for the families with a moment form (SCV / LSCV):
 // runs of RL consecutive array positions of the circular row (see below),
 // their RL autocorrelation values loaded as one aligned block, and per run
-// only the moments sum_t t^p e(t) A(t) of each Gaussian (Fun::fold).
+// only the moments sum_t t^p e(t) A(t) of each Gaussian (Fun::fold).  A thread
+// walks a segment of SEG consecutive runs of one row: the values e and ratios
+// rho reached at the end of a run are those of the next run's start, so only
+// the segment's first run (or a run after one that needed special handling)
+// evaluates exponentials.
 template <int D, int N, class Fun, int NT, int RUN, bool SCALED>
 __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, RowGeom geo, int64_t nitems,
                                             double* __restrict__ partial) {
     constexpr int NG = Fun::NG;
     constexpr int NGS = Fun::NGAUSS;
     // Runs of RL consecutive array positions of the circular row: p in [0, N/2)
-    // holds lags p, p in [N/2, N) lags p - N; N/2 is a multiple of RL, so a run
-    // never mixes the two sides, its lags are consecutive, and its RL values of
-    // the autocorrelation form one aligned block that is loaded at once.
-    // Positions outside |lag| <= M-1 (the zero slots) get weight 0.
+    // holds lags p, p in [N/2, N) lags p - N; N/2 is a multiple of RL * SEG, so
+    // neither a run nor a segment mixes the two sides, their lags are
+    // consecutive, and a run's RL values of the autocorrelation form one
+    // aligned block that is loaded at once.  Positions outside |lag| <= M-1
+    // (the zero slots) get weight 0.
     constexpr int RL = RUN < N / 2 ? RUN : N / 2;
-    constexpr int nrun = N / RL;
+    // long rows (dense in live lags) walk 4 runs per thread; short rows keep
+    // one, so that a row's few live runs are spread over several threads
+    constexpr int SEG = N >= 256 && (N / 2) / RL >= 4 ? 4 : 1;
+    constexpr int nseg = N / (RL * SEG);
     __shared__ double red[(NT / 64) * NG];
     const int M_last = geo.M[D - 1];
-    // thread t takes the (row, run) pairs t, t + NT, ... of its item in row-major
-    // order; the pair is advanced incrementally (no division in the loop)
-    constexpr int step_ro = NT / nrun, step_j = NT % nrun;
-    const int ro0 = (int)threadIdx.x / nrun, j0 = (int)threadIdx.x % nrun;
+    // thread t takes the (row, segment) pairs t, t + NT, ... of its item in
+    // row-major order; the pair is advanced incrementally (no division in the loop)
+    constexpr int step_ro = NT / nseg, step_j = NT % nseg;
+    const int ro0 = (int)threadIdx.x / nseg, j0 = (int)threadIdx.x % nseg;
     for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int64_t h = item / geo.nchunks;
         const int64_t ch = item - h * geo.nchunks;
@@ -493,7 +501,6 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
         const double* __restrict__ A =
             reinterpret_cast<const double*>(static_cast<uintptr_t>(__double_as_longlong(pr[S_ALAG])));
         const double dl = delta[D - 1];
-        // walk constants written by the setup kernel (uniform: scalar loads)
         double dz[NGS][D], sig[NGS], hpl[NGS], lcut[NGS];
 #pragma unroll
         for (int k = 0; k < NGS; ++k) {
@@ -510,128 +517,167 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
         const int64_t rbeg = ch * geo.chunk;
         const int64_t rend = rbeg + geo.chunk < geo.nrows ? rbeg + geo.chunk : geo.nrows;
         const int nro = (int)(rend - rbeg);   // rows of one item < 2^31
-        for (int ro = ro0, j = j0; ro < nro; ro += step_ro + (j + step_j >= nrun ? 1 : 0),
-                 j = j + step_j >= nrun ? j + step_j - nrun : j + step_j) {
-            const int p0 = j * RL;
-            const bool pos = p0 < N / 2;
-            const int lag0 = pos ? p0 : p0 - N;
-            // runs that lie wholly in the zero slots
-            if (pos ? lag0 > M_last - 1 : lag0 + RL - 1 < -(M_last - 1)) continue;
+        for (int ro = ro0, sg = j0; ro < nro; ro += step_ro + (sg + step_j >= nseg ? 1 : 0),
+                 sg = sg + step_j >= nseg ? sg + step_j - nseg : sg + step_j) {
             const RowInfo ri = row_info<D>(rbeg + ro, rend, geo, delta, nullptr);
-            const double* __restrict__ Arow = A + ri.wr * N + p0;
-            double av[RL];
-            if constexpr (RL % 2 == 0) {
-                const double2* a2 = reinterpret_cast<const double2*>(Arow);
-#pragma unroll
-                for (int t = 0; t < RL / 2; ++t) {
-                    const double2 v = a2[t];
-                    av[2 * t] = v.x;
-                    av[2 * t + 1] = v.y;
-                }
-            } else {
-#pragma unroll
-                for (int t = 0; t < RL; ++t) av[t] = Arow[t];
-            }
-#pragma unroll
-            for (int t = 0; t < RL; ++t) {
-                const int lag = lag0 + t;
-                const bool ok = pos ? lag <= M_last - 1 : lag >= -(M_last - 1);
-                av[t] = ok ? ri.rw * av[t] : 0.0;
-            }
-            double x[D];
-#pragma unroll
-            for (int k = 0; k < D - 1; ++k) x[k] = ri.x[k];
-            x[D - 1] = dl * (double)lag0;
+            // walk state carried from run to run: z at the run start, e, rho
             double z[NGS][D], ev[NGS], rho[NGS];
-            bool scl[NGS];
-            bool direct = false, alive = false;
-#pragma unroll
-            for (int k = 0; k < NGS; ++k) {
-                const double* P = f.Pm(k);
-                double q = 0.0;
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int jj = 0; jj < D; ++jj) s += P[i * D + jj] * x[jj];
-                    z[k][i] = s;
-                    q += x[i] * s;
+            bool carried = false;
+#pragma unroll 1
+            for (int c = 0; c < SEG; ++c) {
+                const int p0 = (sg * SEG + c) * RL;
+                const bool pos = p0 < N / 2;
+                const int lag0 = pos ? p0 : p0 - N;
+                // runs that lie wholly in the zero slots
+                if (pos ? lag0 > M_last - 1 : lag0 + RL - 1 < -(M_last - 1)) {
+                    carried = false;
+                    continue;
                 }
-                // A run starting below 1e-290 with ratios rho, rho sig, ... <= 1
-                // (sig < 1) stays there and adds nothing a float64 sum can hold
-                // next to the lag-0 term.  A run that rises from there is walked
-                // with values scaled by e^600 (kept in the normal range) and its
-                // moments scaled back at the end (SCALED), or evaluated lag by lag.
-                const double ea = -0.5 * q;
-                rho[k] = exp(-(dl * z[k][D - 1] + hpl[k]));
-                if constexpr (SCALED) {
-                    const bool low = ea < lcut[k];
-                    scl[k] = low;
-                    if (low && rho[k] <= 1.0) {
-                        ev[k] = 0.0;
-                    } else {
-                        ev[k] = f.cn(k) * exp(low ? ea + 600.0 : ea);
-                        direct = direct || !(rho[k] <= 1e200);
-                        alive = true;
+                const double* __restrict__ Arow = A + ri.wr * N + p0;
+                double av[RL];
+                if constexpr (RL % 2 == 0) {
+                    const double2* a2 = reinterpret_cast<const double2*>(Arow);
+#pragma unroll
+                    for (int t = 0; t < RL / 2; ++t) {
+                        const double2 v = a2[t];
+                        av[2 * t] = v.x;
+                        av[2 * t + 1] = v.y;
                     }
                 } else {
-                    scl[k] = false;
-                    ev[k] = f.cn(k) * exp(ea);
-                    if (!(ev[k] >= 1e-290) && rho[k] <= 1.0) {
-                        ev[k] = 0.0;
-                    } else {
-                        direct = direct || !(ev[k] >= 1e-290) || !(rho[k] <= 1e200);
-                        alive = true;
-                    }
+#pragma unroll
+                    for (int t = 0; t < RL; ++t) av[t] = Arow[t];
                 }
-            }
-            if (!alive) continue;
-            if (direct) {
-                // exact evaluation lag by lag (values near the float64 range
-                // limits; rare): a rolled loop keeps one copy of the evaluation
-#pragma unroll 1
+#pragma unroll
                 for (int t = 0; t < RL; ++t) {
                     const int lag = lag0 + t;
                     const bool ok = pos ? lag <= M_last - 1 : lag >= -(M_last - 1);
-                    if (ok) {
-                        double vals[NG];
-                        x[D - 1] = dl * (double)lag;
-                        eval_direct<Fun, D>(f, x, vals);
-                        const double a = ri.rw * Arow[t];
-#pragma unroll
-                        for (int g = 0; g < NG; ++g) acc[g] += vals[g] * a;
-                    }
+                    av[t] = ok ? ri.rw * av[t] : 0.0;
                 }
-                continue;
-            }
-            {
-                constexpr int NM = Fun::NMOM;
-                double m[NGS][3];
-#pragma unroll
-                for (int k = 0; k < NGS; ++k) m[k][0] = m[k][1] = m[k][2] = 0.0;
-#pragma unroll
-                for (int t = 0; t < RL; ++t) {
+                bool scl[NGS];
+                bool direct = false, alive = false;
+                if (carried) {
+                    // continue the walk: values at or above 1e-290 (or dead and
+                    // decreasing) go on; a Gaussian rising from below restarts
 #pragma unroll
                     for (int k = 0; k < NGS; ++k) {
-                        const double w = ev[k] * av[t];
-                        m[k][0] += w;
-                        if constexpr (NM > 1) {
-                            m[k][1] += (double)t * w;
-                            m[k][2] += (double)(t * t) * w;
+                        scl[k] = false;
+#pragma unroll
+                        for (int i = 0; i < D; ++i) z[k][i] += (double)RL * dz[k][i];
+                        if (!(ev[k] >= 1e-290)) {
+                            if (rho[k] <= 1.0) ev[k] = 0.0;
+                            else carried = false;
+                        } else {
+                            direct = direct || !(rho[k] <= 1e200);
                         }
-                        ev[k] *= rho[k];
-                        rho[k] *= sig[k];
+                        alive = alive || ev[k] != 0.0;
                     }
                 }
+                if (!carried) {
+                    double x[D];
 #pragma unroll
-                for (int k = 0; k < NGS; ++k)
-                    if (SCALED && scl[k]) {
-                        constexpr double E_M600 = 2.6503965530043108e-261;   // e^-600
-                        m[k][0] *= E_M600;
-                        m[k][1] *= E_M600;
-                        m[k][2] *= E_M600;
+                    for (int k = 0; k < D - 1; ++k) x[k] = ri.x[k];
+                    x[D - 1] = dl * (double)lag0;
+                    direct = false;
+                    alive = false;
+#pragma unroll
+                    for (int k = 0; k < NGS; ++k) {
+                        const double* P = f.Pm(k);
+                        double q = 0.0;
+#pragma unroll
+                        for (int i = 0; i < D; ++i) {
+                            double s = 0.0;
+#pragma unroll
+                            for (int jj = 0; jj < D; ++jj) s += P[i * D + jj] * x[jj];
+                            z[k][i] = s;
+                            q += x[i] * s;
+                        }
+                        // A run starting below 1e-290 with ratios rho, rho sig, ... <= 1
+                        // (sig < 1) stays there and adds nothing a float64 sum can hold
+                        // next to the lag-0 term.  A run that rises from there is walked
+                        // with values scaled by e^600 (kept in the normal range) and its
+                        // moments scaled back at the end (SCALED), or evaluated lag by lag.
+                        const double ea = -0.5 * q;
+                        rho[k] = exp(-(dl * z[k][D - 1] + hpl[k]));
+                        if constexpr (SCALED) {
+                            const bool low = ea < lcut[k];
+                            scl[k] = low;
+                            if (low && rho[k] <= 1.0) {
+                                ev[k] = 0.0;
+                            } else {
+                                ev[k] = f.cn(k) * exp(low ? ea + 600.0 : ea);
+                                direct = direct || !(rho[k] <= 1e200);
+                                alive = true;
+                            }
+                        } else {
+                            scl[k] = false;
+                            ev[k] = f.cn(k) * exp(ea);
+                            if (!(ev[k] >= 1e-290) && rho[k] <= 1.0) {
+                                ev[k] = 0.0;
+                            } else {
+                                direct = direct || !(ev[k] >= 1e-290) || !(rho[k] <= 1e200);
+                                alive = true;
+                            }
+                        }
                     }
-                f.fold(z, dz, m, acc);
+                }
+                // every Gaussian below 1e-290 and decreasing: so are the rest
+                // of the segment's runs (further along the same direction)
+                if (!alive) break;
+                // the next run continues this one's walk unless this one is
+                // evaluated directly or walked scaled
+                carried = !direct;
+#pragma unroll
+                for (int k = 0; k < NGS; ++k) carried = carried && !scl[k];
+                if (direct) {
+                    // exact evaluation lag by lag (values near the float64 range
+                    // limits; rare): a rolled loop keeps one copy of the evaluation
+                    double x[D];
+#pragma unroll
+                    for (int k = 0; k < D - 1; ++k) x[k] = ri.x[k];
+#pragma unroll 1
+                    for (int t = 0; t < RL; ++t) {
+                        const int lag = lag0 + t;
+                        const bool ok = pos ? lag <= M_last - 1 : lag >= -(M_last - 1);
+                        if (ok) {
+                            double vals[NG];
+                            x[D - 1] = dl * (double)lag;
+                            eval_direct<Fun, D>(f, x, vals);
+                            const double a = ri.rw * Arow[t];
+#pragma unroll
+                            for (int g = 0; g < NG; ++g) acc[g] += vals[g] * a;
+                        }
+                    }
+                    continue;
+                }
+                {
+                    constexpr int NM = Fun::NMOM;
+                    double m[NGS][3];
+#pragma unroll
+                    for (int k = 0; k < NGS; ++k) m[k][0] = m[k][1] = m[k][2] = 0.0;
+#pragma unroll
+                    for (int t = 0; t < RL; ++t) {
+#pragma unroll
+                        for (int k = 0; k < NGS; ++k) {
+                            const double w = ev[k] * av[t];
+                            m[k][0] += w;
+                            if constexpr (NM > 1) {
+                                m[k][1] += (double)t * w;
+                                m[k][2] += (double)(t * t) * w;
+                            }
+                            ev[k] *= rho[k];
+                            rho[k] *= sig[k];
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < NGS; ++k)
+                        if (SCALED && scl[k]) {
+                            constexpr double E_M600 = 2.6503965530043108e-261;   // e^-600
+                            m[k][0] *= E_M600;
+                            m[k][1] *= E_M600;
+                            m[k][2] *= E_M600;
+                        }
+                    f.fold(z, dz, m, acc);
+                }
             }
         }
         double outv[NG];
