@@ -35,7 +35,7 @@ import numpy as np  # noqa: E402
 METRIC = "psi_r evals/s and SCV objective+grad evals/s, batched+adjoint vs plain, FP64"
 PEAK_FP64_VECTOR = 78.6e12          # MI355X FP64 vector FLOP/s (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
 EXP_FLOPS = 20                      # flops charged per exp (the device exp is ~13 FMA + 4 other FP64 ops)
-ROW_KERNEL_SOURCES = ["rows_impl.h", "dev_kernels.h", "dev_common.h", "rows_dispatch.h", "rows_d2.hip"]
+ROW_KERNEL_SOURCES = ["rows_impl.h", "dev_kernels.h", "dev_common.h", "finish.h", "rows_dispatch.h", "rows_d2.hip"]
 
 
 def parse():
@@ -73,25 +73,50 @@ def gen_flops_per_lag(d=2):
     return 2 * (2 * d * d + 2 * d + 2 + EXP_FLOPS) + 2 + 7 * d * (d + 1) // 2
 
 
-def algorithmic_flops_per_candidate(M, N, d=2, variant=0):
-    """FP64 flops of one candidate in the batched objective+gradient kernel.
+def moment_walk_layout(N):
+    """Run length and runs per segment of the lag moment kernel for rows of
+    N positions (as compiled: 16-lag runs in 32-lag segments for N >= 256,
+    else single runs of 8)."""
+    if N >= 256:
+        return 16, 2
+    return min(8, N // 2), 1
 
-    Both forms visit the rows of the half lag set, M of them (l_0 = 0..M-1),
-    and generate the kernel at the 2M-1 nonzero lags of each row.
-    Spectral form (variants 0-2), per row: two complex FFTs of length N (the 4
-    real grids packed two per transform) at 5 N log2 N flops each and the
-    contraction over the full last axis, 8 flops per complex multiply-add per
-    transform.  Lag form (variants 3, 4), per lag: one multiply-add per grid
-    against the autocorrelation (4 grids, 2 flops each).  Generation is
-    charged at its direct-evaluation cost in both forms (the lag kernel's
-    exponential recurrence does fewer operations for the same work)."""
-    gen = (2 * M - 1) * gen_flops_per_lag(d)
+
+def algorithmic_flops_per_candidate(M, N, d=2, variant=0):
+    """FP64 flops of one candidate in the batched objective+gradient kernel
+    (d = 2: M rows of the half lag set, l_0 = 0..M-1, N positions each).
+
+    Lag form (variants 3, 4), the algorithm as designed: per position, per
+    Gaussian, the walk e*A, the three moment sums (1 add + 2 FMA) and the two
+    recurrence products = 8 flops, plus the row weight (1); per run of RL
+    positions the fold of the moments into the objective (3) and the q
+    Hessian sums (25 each), and the advance of z (4d); per segment a fresh
+    start per Gaussian: S^-1 x (2d^2), x^T S^-1 x (2d), exponent arguments
+    (4), two exponentials (EXP_FLOPS each).  Runs whose Gaussians are all
+    below the float64 cut-off are skipped by the kernel and still counted here
+    (case 4 has almost none).
+    Spectral form (variants 0-2), per row: generation at direct-evaluation cost
+    at the 2M-1 nonzero lags, two complex FFTs of length N (the 4 real grids
+    packed two per transform) at 5 N log2 N flops each and the contraction,
+    8 flops per complex multiply-add per transform."""
+    q = d * (d + 1) // 2
     if variant >= 3:
-        return M * (gen + (2 * M - 1) * 2 * 4)
+        RL, SEG = moment_walk_layout(N)
+        per_run = (RL * (2 * 8 + 1) + (3 + 25 * q) + 4 * d * (SEG - 1) / SEG
+                   + 2 * (2 * d * d + 2 * d + 4 + 2 * EXP_FLOPS) / SEG)
+        return M * (N // RL) * per_run
+    gen = (2 * M - 1) * gen_flops_per_lag(d)
     log2n = int(np.log2(N))
     fft = 2 * 5 * N * log2n
     contraction = 2 * N * 8
     return M * (fft + contraction + gen)
+
+
+def direct_equivalent_flops_per_candidate(M, d=2):
+    """The same sums evaluated lag by lag (kernel generation at its direct
+    cost at each of the (2M-1) lags of the M rows, then 2 flops per grid):
+    the work the walk replaces."""
+    return M * (2 * M - 1) * (gen_flops_per_lag(d) + 2 * (1 + d * (d + 1) // 2))
 
 
 def main():
@@ -276,13 +301,16 @@ def main():
             ent = rec.get("launches", {}).get(f"{variant},{grid_blocks}")
             if ent:
                 traffic = ent["hbm_bytes_per_launch"]
-    kname = (f"k_lag_mom<2,512,ScvFun<2,1>,256,8,{'true' if variant == 4 else 'false'}>" if variant >= 3
-             else f"k_rows<2,512,ScvFun<2,1>> variant {variant}")
+    kname = (f"k_lag_mom<2,{N},ScvFun<2,1>,256,{moment_walk_layout(N)[0]},{'true' if variant == 4 else 'false'}>"
+             if variant >= 3 else f"k_rows<2,{N},ScvFun<2,1>> variant {variant}")
     kname += " (grid: one block per work item)" if grid_blocks < 0 else " (grid: resident blocks)"
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic,
                 "kernel": kname, "launch_ms": scv_ms, "call_ms": scv_call_ms,
-                "flops_per_launch": flops, "variant": variant}
+                "flops_per_launch": flops, "variant": variant,
+                "direct_evaluation_equivalent": {
+                    "flops_per_launch": direct_equivalent_flops_per_candidate(M, d) * B,
+                    "rate_tflops": direct_equivalent_flops_per_candidate(M, d) * B / (scv_ms * 1e-3) / 1e12}}
     fft_route = {"kernel": f"k_rows<2,512,ScvFun<2,1>> variant {spec_variant} (per-candidate last-axis FFTs in LDS)",
                  "launch_ms": spec_ms, "evals_per_s": B / (spec_ms * 1e-3), "flops_per_launch": spec_flops,
                  "achieved_tflops": spec_flops / (spec_ms * 1e-3) / 1e12,

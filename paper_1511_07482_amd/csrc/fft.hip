@@ -106,6 +106,7 @@ struct RowFlip {
     int on;
     int nlead;
     int P[3];
+    int mlast;   // > 0: positions of the last axis with |lag| > mlast - 1 are written as exact zeros
 };
 
 __device__ __forceinline__ int64_t flip_row(int64_t r, const RowFlip& f) {
@@ -254,7 +255,15 @@ __global__ __launch_bounds__(NT) void k_c2r_last(const double2* __restrict__ in,
     for (int e = threadIdx.x; e < ROWS * H; e += NT) {
         const int rr = e / H, m = e - rr * H;
         const int64_t row = r0 + rr;
-        if (row < rows) dst[row * H + m] = c_scale(buf[rr * PS + m], 2.0);
+        if (row >= rows) continue;
+        double2 v = c_scale(buf[rr * PS + m], 2.0);
+        if (fl.mlast > 0) {
+            // positions 2m, 2m + 1 hold lags p (p < N/2) or p - N
+            const int p0 = 2 * m, p1 = 2 * m + 1;
+            if (p0 > fl.mlast - 1 && p0 < N - (fl.mlast - 1)) v.x = 0.0;
+            if (p1 > fl.mlast - 1 && p1 < N - (fl.mlast - 1)) v.y = 0.0;
+        }
+        dst[row * H + m] = v;
     }
 }
 
@@ -409,7 +418,7 @@ static hipError_t r2c_last(const double* in, double2* out, int64_t rows, int N, 
 #undef CALL
 }
 static hipError_t c2r_last(const double2* in, double* out, int64_t rows, int N, const double2* tw, hipStream_t s,
-                           RowFlip fl = RowFlip{0, 0, {1, 1, 1}}) {
+                           RowFlip fl = RowFlip{0, 0, {1, 1, 1}, 0}) {
 #define CALL(NN) run_c2r_last<NN>(in, out, rows, tw, s, fl)
     if (N < 4) return hipErrorInvalidValue;
     KDEFFT_SWITCH_N(ilog2i(N), CALL)
@@ -514,8 +523,10 @@ hipError_t fft_autocorr_nd(const double2* wmix, double* alag, const kdefft_grid&
     hipError_t e = twiddles(&tw);
     if (e != hipSuccess) return e;
     // inverting |C|^2 along the leading axes = the forward transform (wmix)
-    // read at negated leading indices; then the last-axis inverse
-    RowFlip fl{g.d > 1 ? 1 : 0, g.d - 1, {1, 1, 1}};
+    // read at negated leading indices; then the last-axis inverse.  Lags with
+    // |l| >= M along the last axis are zero in exact arithmetic (the counts
+    // occupy [0, M)) and are stored as exact zeros.
+    RowFlip fl{g.d > 1 ? 1 : 0, g.d - 1, {1, 1, 1}, g.M[g.d - 1]};
     for (int k = 0; k + 1 < g.d; ++k) fl.P[k] = g.P[k];
     return c2r_last(wmix, alag, lead_count(g), g.P[g.d - 1], tw, s, fl);
 }

@@ -32,7 +32,7 @@ hipError_t rows_var(int var, const double* prm, RowGeom geo, int64_t nitems, dou
 // Rows one block transforms per pass (rows per wavefront x wavefronts).
 template <int D, int N, class Fun>
 constexpr int rows_per_iter_t(int var) {
-    return var >= 3 ? lag_rows_per_pass<N>() : var == 1 ? rows_for<N, Fun::NG, 1>() * waves_for<N, Fun::NG, rows_for<N, Fun::NG, 1>()>()
+    return var >= 3 ? (HasMoments<Fun>::value ? mom_rows_per_pass<N>() : lag_rows_per_pass<N>()) : var == 1 ? rows_for<N, Fun::NG, 1>() * waves_for<N, Fun::NG, rows_for<N, Fun::NG, 1>()>()
                     : rows_for<N, Fun::NG, 0>() * waves_for<N, Fun::NG, rows_for<N, Fun::NG, 0>()>();
 }
 

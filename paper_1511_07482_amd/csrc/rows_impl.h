@@ -459,6 +459,16 @@ __global__ __launch_bounds__(NT) void k_lag(const double* __restrict__ prm, RowG
     }
 }
 
+constexpr int LAG_RUN = 8;
+
+// Moment families: long rows use runs of 16 lags (one fold per 16 lags) ...
+template <int N>
+constexpr int mom_run_of() { return N >= 256 ? 16 : LAG_RUN; }
+// ... walked in segments of 32 lags per thread; short rows one run per
+// thread, so that a row's few live runs are spread over several threads.
+template <int N, int RL>
+constexpr int mom_seg_of() { return N >= 256 && RL <= 32 && (N / 2) % 32 == 0 ? 32 / RL : 1; }
+
 // Lag-domain evaluation for the families with a moment form (SCV / LSCV):
 // runs of RL consecutive array positions of the circular row (see below),
 // their RL autocorrelation values loaded as one aligned block, and per run
@@ -479,9 +489,7 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
     // aligned block that is loaded at once.  Positions outside |lag| <= M-1
     // (the zero slots) get weight 0.
     constexpr int RL = RUN < N / 2 ? RUN : N / 2;
-    // long rows (dense in live lags) walk 4 runs per thread; short rows keep
-    // one, so that a row's few live runs are spread over several threads
-    constexpr int SEG = N >= 256 && (N / 2) / RL >= 4 ? 4 : 1;
+    constexpr int SEG = mom_seg_of<N, RL>();
     constexpr int nseg = N / (RL * SEG);
     __shared__ double red[(NT / 64) * NG];
     const int M_last = geo.M[D - 1];
@@ -547,30 +555,29 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
 #pragma unroll
                     for (int t = 0; t < RL; ++t) av[t] = Arow[t];
                 }
+                // the lag array is exactly zero at |lag| > M - 1 (stored so by
+                // the preparation), so no position needs masking here
 #pragma unroll
-                for (int t = 0; t < RL; ++t) {
-                    const int lag = lag0 + t;
-                    const bool ok = pos ? lag <= M_last - 1 : lag >= -(M_last - 1);
-                    av[t] = ok ? ri.rw * av[t] : 0.0;
-                }
+                for (int t = 0; t < RL; ++t) av[t] = ri.rw * av[t];
                 bool scl[NGS];
                 bool direct = false, alive = false;
                 if (carried) {
-                    // continue the walk: values at or above 1e-290 (or dead and
-                    // decreasing) go on; a Gaussian rising from below restarts
+                    // continue the walk: values at or above 1e-290 go on, values
+                    // below it that decrease are dropped; a Gaussian rising from
+                    // below restarts the run with exponentials (the ratios only
+                    // decrease along a walk, so none can newly exceed 1e200)
+                    bool rise = false;
 #pragma unroll
                     for (int k = 0; k < NGS; ++k) {
                         scl[k] = false;
 #pragma unroll
                         for (int i = 0; i < D; ++i) z[k][i] += (double)RL * dz[k][i];
-                        if (!(ev[k] >= 1e-290)) {
-                            if (rho[k] <= 1.0) ev[k] = 0.0;
-                            else carried = false;
-                        } else {
-                            direct = direct || !(rho[k] <= 1e200);
-                        }
-                        alive = alive || ev[k] != 0.0;
+                        const bool low = !(ev[k] >= 1e-290);
+                        rise = rise || (low && rho[k] > 1.0);
+                        ev[k] = low ? 0.0 : ev[k];
+                        alive = alive || !low;
                     }
+                    carried = !rise;
                 }
                 if (!carried) {
                     double x[D];
@@ -687,17 +694,16 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
     }
 }
 
-constexpr int LAG_RUN = 8;
-
 // Families whose combine step dominates (many Hermite outputs) gain nothing
 // from the exponential recurrence and lose registers to it: runs of one lag.
 template <class Fun>
 constexpr int lag_run_of() { return Fun::NG > 12 ? 1 : LAG_RUN; }
 
+
 template <int D, int N, class Fun, int NT, bool SCALED>
 constexpr auto select_lag() {
     if constexpr (HasMoments<Fun>::value)
-        return k_lag_mom<D, N, Fun, NT, lag_run_of<Fun>(), SCALED>;
+        return k_lag_mom<D, N, Fun, NT, mom_run_of<N>(), SCALED>;
     else
         return k_lag<D, N, Fun, NT, lag_run_of<Fun>()>;
 }
@@ -729,9 +735,16 @@ hipError_t run_lag_t(const double* prm, RowGeom geo, int64_t nitems, double* par
     return hipGetLastError();
 }
 
-// rows covered by one pass of a 256-thread block (runs of LAG_RUN lags)
+// rows covered by one pass of a 256-thread block (runs of LAG_RUN lags, or
+// for the moment families segments of mom_seg_of x mom_run_of lags)
 template <int N>
 constexpr int lag_rows_per_pass() { return (256 * LAG_RUN) / N >= 1 ? (256 * LAG_RUN) / N : 1; }
+template <int N>
+constexpr int mom_rows_per_pass() {
+    constexpr int RL = mom_run_of<N>() < N / 2 ? mom_run_of<N>() : N / 2;
+    constexpr int per = 256 * RL * mom_seg_of<N, RL>() / N;
+    return per >= 1 ? per : 1;
+}
 
 // Rows per wavefront per pass: enough butterflies for one per lane in a radix-8
 // stage (variant 0, 2) or twice that (variant 1); at most 8.
