@@ -375,11 +375,14 @@ struct BatchScratch {
     int32_t* counters;   // completion counters, one per candidate
 };
 
-// Completion of a lag launch: fused into the row kernel for the lag-domain
-// variants, else (FIN_NONE) a separate final kernel.
-FinishArgs fin_psi(const RowLaunch& rl, int ng, int32_t* counters, double* psi, double* scal) {
+// Completion of a psi launch: fused into the row kernel for the lag-domain
+// variants when a candidate has few work items (every item of a candidate
+// counts on one device-scope counter, so thousands of items would queue on
+// it), else (FIN_NONE) a separate final kernel.
+constexpr int64_t FUSED_MAX_CHUNKS = 128;
+FinishArgs fin_psi(const RowLaunch& rl, const RowGeom& geo, int ng, int32_t* counters, double* psi, double* scal) {
     FinishArgs f{};
-    if (rl.variant >= 3) {
+    if (rl.variant >= 3 && geo.nchunks <= FUSED_MAX_CHUNKS) {
         f.mode = FIN_PSI;
         f.ng = ng;
         f.counters = counters;
@@ -510,13 +513,14 @@ int prepare_into(const double* X, int64_t n, const kdefft_grid& g, const double*
     h.scal = L.scal;
     h.prodP = (double)sizes_of(g).prodP;
     const RowLaunch crl = launch_for(FUN_PSI, g.d, 0, g.P[g.d - 1]);
+    const RowGeom cgeo = make_geom(g, FUN_PSI, 0, 1, crl.variant);
     if (with_const) {
         // constant SCV term: n^-2 sum sum phi_{2G}, the psi_0 functional at 2G
         h.prm = p.prm;
         int t = 0;
         for (int c = 0; c < g.d; ++c)
             for (int i = c; i < g.d; ++i) h.Gv2[t++] = 2.0 * Gpilot[i * g.d + c];
-        h.fin = fin_psi(crl, 1, p.counter, nullptr, L.scal);
+        h.fin = fin_psi(crl, cgeo, 1, p.counter, nullptr, L.scal);
     }
     HIPCHK(launch_ds_header(h, s), "dataset header");
     HIPCHK(launch_linbin_xcd(X, n, g, p.copies, L.n_out, s, partial ? &L.rec->lo[0] : nullptr, partial != nullptr),
@@ -524,10 +528,9 @@ int prepare_into(const double* X, int64_t n, const kdefft_grid& g, const double*
     HIPCHK(fft_prepare_nd(p.copies, XCD_COPIES, L.counts, L.spec, L.wmix, g, s), "count transform");
     HIPCHK(fft_autocorr_nd(L.wmix, L.alag, g, s), "count autocorrelation");
     if (with_const) {
-        const RowGeom geo = make_geom(g, FUN_PSI, 0, 1, crl.variant);
-        HIPCHK(launch_rows(FUN_PSI, g.d, 0, geo, p.prm, 1, p.partial, crl, s), "const-term rows");
+        HIPCHK(launch_rows(FUN_PSI, g.d, 0, cgeo, p.prm, 1, p.partial, crl, s), "const-term rows");
         if (h.fin.mode == FIN_NONE)
-            HIPCHK(launch_psi_final(p.partial, geo, 1, p.prm, 1, nullptr, L.scal, s), "const-term final");
+            HIPCHK(launch_psi_final(p.partial, cgeo, 1, p.prm, 1, nullptr, L.scal, s), "const-term final");
     }
     return KDEFFT_OK;
 }
@@ -826,9 +829,9 @@ int kdefft_psi(const double* X, int64_t n, const kdefft_grid* g, const double* G
     const DsDev* recs[1] = {L2.rec};
     PsiBatchArgs args = psi_args(*g, r, 1, recs, G_host);
     const RowLaunch rl = launch_for(FUN_PSI, d, r, g->P[d - 1]);
-    args.fin = fin_psi(rl, nu, b.counters, psi, nullptr);
-    HIPCHK(launch_psi_setup(args, b.prm, s), "psi setup");
     const RowGeom geo = make_geom(*g, FUN_PSI, r, 1, rl.variant);
+    args.fin = fin_psi(rl, geo, nu, b.counters, psi, nullptr);
+    HIPCHK(launch_psi_setup(args, b.prm, s), "psi setup");
     HIPCHK(timed_rows(FUN_PSI, d, r, geo, b.prm, 1, b.partial, rl, s), "psi rows");
     if (args.fin.mode == FIN_NONE)
         HIPCHK(launch_psi_final(b.partial, geo, nu, b.prm, 1, psi, nullptr, s), "psi final");
@@ -1067,9 +1070,9 @@ int kdefft_psi_batch(const kdefft_dataset* ds, int n_ds, const double* G_host, i
     hipStream_t s = S(stream);
     const RowLaunch rl = launch_for(FUN_PSI, d, r, g.P[d - 1]);
     const int nu = (int)binom(d + r - 1, r);
-    args.fin = fin_psi(rl, nu, b.counters, psi, nullptr);
-    HIPCHK(launch_psi_setup(args, b.prm, s), "psi setup");
     const RowGeom geo = make_geom(g, FUN_PSI, r, n_ds, rl.variant);
+    args.fin = fin_psi(rl, geo, nu, b.counters, psi, nullptr);
+    HIPCHK(launch_psi_setup(args, b.prm, s), "psi setup");
     HIPCHK(timed_rows(FUN_PSI, d, r, geo, b.prm, n_ds, b.partial, rl, s), "psi rows");
     if (args.fin.mode == FIN_NONE)
         HIPCHK(launch_psi_final(b.partial, geo, nu, b.prm, n_ds, psi, nullptr, s), "psi final");
