@@ -381,11 +381,31 @@ static void launch_c2c_t(double2* buf, double2* out2, int64_t outer, int64_t inn
         hipLaunchKernelGGL((k_c2c_strided<N, NT, 1, 0, T>), grid, dim3(NT), 0, s, buf, out2, inner, tiles, tw);
 }
 
+// Slab tiles: when the axis is the last leading one its inner extent is the
+// half-spectrum length Q = P/2 + 1 (17, 33, 65, ...), which T-column tiles
+// cover raggedly (33 = 16 + 16 + 1).  For Q = 17 and 33 one block takes the
+// whole contiguous [N][Q] slab instead (fully coalesced, no partial tile)
+// while it fits 80 KiB of LDS.
+template <int N, int Q>
+constexpr bool slab_fits() { return N >= 8 && Q * (N + 1) * 16 <= 81920; }
+
 template <int N>
 static hipError_t run_c2c(double2* buf, double2* out2, int64_t outer, int64_t inner, int dir, int mode,
                           const double2* tw, hipStream_t s) {
     constexpr int T = tile_cols<N>();
     constexpr int TS = N >= 64 ? 1 : (64 / N > 16 ? 16 : 64 / N);  // one radix pass per lane
+    if constexpr (slab_fits<N, 33>()) {
+        if (inner == 33 && outer >= kMinBlocks) {
+            launch_c2c_t<N, 256, 33>(buf, out2, outer, inner, dir, mode, tw, s);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (slab_fits<N, 17>()) {
+        if (inner == 17 && outer >= kMinBlocks) {
+            launch_c2c_t<N, 256, 17>(buf, out2, outer, inner, dir, mode, tw, s);
+            return hipGetLastError();
+        }
+    }
     if (outer * ((inner + T - 1) / T) < kMinBlocks && TS < T)
         launch_c2c_t<N, 64, TS>(buf, out2, outer, inner, dir, mode, tw, s);
     else
