@@ -90,7 +90,9 @@ typedef struct kdefft_grid {
  *                                           axes 0..d-2 (mixed-domain spectrum)
  *   alag    float64 [P_0, ..., P_{d-1}]     prod P times the autocorrelation of the
  *                                           counts, A_l = sum_i c_i c_{i+l}, lag l at
- *                                           index l mod P (inverse transform of |C|^2)
+ *                                           index l mod P (inverse transform of |C|^2);
+ *                                           exact zeros where the last-axis lag has
+ *                                           |l_{d-1}| > M_{d-1} - 1 (zero exactly)
  *   scal    float64 [4]                     scal[0] = n^-2 sum sum phi_{2G} (binned)
  *   n_out   int32 [1]                       number of points outside the grid
  *   rec     opaque device record (pointers, n, spacing, pilot) read by the
@@ -238,7 +240,9 @@ int kdefft_dataset_prepare_auto(const double* X, int64_t n, int d, const int32_t
 int kdefft_dataset_grid(const kdefft_dataset* ds_host, kdefft_grid* out, void* stream);
 
 /* psi_r at bandwidth G_host + 16*j (row-major d x d) for each of n_ds prepared
- * datasets, one launch (Parseval form against the prepared spectra; Sec. 5).
+ * datasets, one launch: the binned double sum of Eq. (13) as sum_l k(l) A(l)
+ * over the prepared lag array (or, for the spectral launch variants, the
+ * Parseval form against the prepared spectra; Sec. 5).
  * psi: device float64 [n_ds, kdefft_unique_count(d, r)].  All datasets must
  * share d and the grid lengths P. Workspace: KDEFFT_OP_PSI_BATCH, batch = n_ds. */
 int kdefft_psi_batch(const kdefft_dataset* ds_host, int n_ds, const double* G_host,
@@ -248,7 +252,8 @@ int kdefft_psi_batch(const kdefft_dataset* ds_host, int n_ds, const double* G_ho
  * belonging to dataset j when h_offsets_host[j] <= b < h_offsets_host[j+1]:
  *   SCV(H) = n^-1 (4 pi)^{-d/2} |H|^{-1/2}
  *          + n^-2 sum sum [phi_{2H+2G} - 2 phi_{H+2G} + phi_{2G}](X_i - X_j)
- * with the double sum binned and evaluated by the FFT route (the SCV selector
+ * with the double sum binned and evaluated against the dataset's prepared
+ * transforms (lag array or spectra, by launch variant; the SCV selector
  * of Sec. 3 and Sec. 5, V-statistic form).  vechL [B, q] parametrises H = L L^T.
  * obj: device [B].  grad: device [B, q] or NULL; if given it receives
  * d SCV / d vechL.  status: device int32 [B] or NULL; 0 = ok, 1 = H singular
