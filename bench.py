@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default=None, metavar="VARIANT,GRID",
                     help="pin the SCV row launch (e.g. 3,-1) instead of tuning; used for counter runs")
-    ap.add_argument("--cpu-h", type=int, default=48, help="candidates in the CPU oracle sample")
+    ap.add_argument("--cpu-h", type=int, default=160, help="candidates in the CPU oracle sample")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy (counter calibration for rocprofv3 --pmc runs)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner (library defaults)")
