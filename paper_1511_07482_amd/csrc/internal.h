@@ -23,7 +23,7 @@ constexpr int NT_DEF = 256;  // threads per block of the simple kernels
 //   lag walk of Gaussian k (k = 0, 1) at [64 + 8k, 72 + 8k): dz[0..3] = delta_last P_k[i][last],
 //         [4] hpl = delta_last^2 P_k[last][last] / 2, [5] sig = exp(-2 hpl), [6] log(1e-290 / c_k)
 enum Slot { S_P1 = 0, S_C = 16, S_P2 = 16, S_C1 = 32, S_C2 = 33, S_FIRST = 34, S_R = 35, S_SIGN = 36, S_ALAG = 38,
-            S_WMIX = 39, S_DELTA = 40, S_N = 44, S_SCALE = 45, S_CONST = 46, S_SING = 47, S_L = 48, S_WALK = 64,
+            S_WMIX = 39, S_DELTA = 40, S_N = 44, S_SCALE = 45, S_CONST = 46, S_SING = 47, S_L = 48,
             // fused completion (FinishArgs): mode, grids, counter and output pointers
             S_FIN_MODE = 80, S_FIN_NG = 81, S_FIN_CNT = 82, S_FIN_OUT = 83, S_FIN_SCAL = 84 };
 

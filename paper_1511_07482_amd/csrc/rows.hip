@@ -129,18 +129,6 @@ __device__ static double two_pi_pow(int d) {  // (2 pi)^{-d/2}
     return r;
 }
 
-// Constants of the lag-domain walk along the last axis for inverse covariance
-// P (row stride 4) and spacing dl; read by the lag kernels as uniform values.
-template <int D>
-__device__ static void put_walk(double* p, int k, const double* P, double dl, double c) {
-    double* w = p + S_WALK + 8 * k;
-    for (int i = 0; i < D; ++i) w[i] = dl * P[i * 4 + D - 1];
-    const double hpl = 0.5 * dl * dl * P[(D - 1) * 4 + D - 1];
-    w[4] = hpl;
-    w[5] = exp(-2.0 * hpl);
-    w[6] = -667.74967696827317 - log(c);   // exponents below this give c e^x < 1e-290
-}
-
 __device__ static void put_ptr(double* slot, const void* p) {
     *slot = __longlong_as_double(static_cast<long long>(reinterpret_cast<uintptr_t>(p)));
 }
@@ -206,7 +194,11 @@ __global__ void k_scv_setup(const double* __restrict__ vechL, ScvBatchArgs a, in
             S2[i * 4 + k2] = H[i * 4 + k2] + gw * ds.G[i * 4 + k2];
         }
     double* p = prm + h * PRM;
-    for (int i = 0; i < PRM; ++i) p[i] = 0.0;
+    // every slot the row and final kernels read is written below; these three
+    // default to zero (no closed-form or constant term, separate final kernel)
+    p[S_FIRST] = 0.0;
+    p[S_CONST] = 0.0;
+    p[S_FIN_MODE] = 0.0;
     const bool ok1 = chol4<D>(S1, L1);
     const bool ok2 = chol4<D>(S2, L2);
     const bool ok = !sing && ok1 && ok2;
@@ -251,8 +243,6 @@ __global__ void k_scv_setup(const double* __restrict__ vechL, ScvBatchArgs a, in
     put_ptr(p + S_WMIX, ds.wmix);
     put_ptr(p + S_ALAG, ds.alag);
     for (int k = 0; k < d; ++k) p[S_DELTA + k] = ds.delta[k];
-    put_walk<D>(p, 0, p + S_P1, ds.delta[d - 1], p[S_C1]);
-    put_walk<D>(p, 1, p + S_P2, ds.delta[d - 1], p[S_C2]);
     p[S_N] = n;
     p[S_SCALE] = 1.0 / (n * n * a.prodP);
     p[S_SING] = sing ? 1.0 : 0.0;
@@ -275,7 +265,7 @@ hipError_t launch_scv_setup(const double* vechL, const ScvBatchArgs& a, int64_t 
 
 // Parameter block of the psi_r family for bandwidth vech gv on dataset ds:
 // P = G^{-1}, c = (-1)^r (2 pi)^{-d/2} |G|^{-1/2} (even r: the sign is +1),
-// walk constants, lag array, spacing, n and the scale of the lag sums.
+// lag array, spacing, n and the scale of the lag sums.
 template <int D>
 __device__ static void psi_params(const double* gv, const DsDev& ds, double prodP, double* p) {
     constexpr int d = D;
@@ -297,7 +287,6 @@ __device__ static void psi_params(const double* gv, const DsDev& ds, double prod
     put_ptr(p + S_WMIX, ds.wmix);
     put_ptr(p + S_ALAG, ds.alag);
     for (int k = 0; k < d; ++k) p[S_DELTA + k] = ds.delta[k];
-    put_walk<D>(p, 0, p + S_P1, ds.delta[d - 1], p[S_C]);
     p[S_N] = ds.n;
     p[S_SCALE] = 1.0 / (ds.n * ds.n * prodP);
 }
