@@ -234,6 +234,15 @@ class Dataset:
             _lib.check(rc, "kdefft_check_binning")
         return int(v.value)
 
+    def lag_array(self) -> torch.Tensor:
+        """Copy of the prepared lag array: prod P times the count
+        autocorrelation, lag l at index l mod P (float64 [P_0, ..., P_{d-1}];
+        exact zeros where the last-axis lag exceeds M - 1)."""
+        shape = tuple(self.shape_grid.P[:self.d])
+        numel = int(np.prod(shape))
+        start = self.desc.alag - self.mem.data_ptr()
+        return self.mem[start:start + 8 * numel].view(torch.float64).view(shape).clone()
+
     def counts(self) -> torch.Tensor:
         """Copy of the int64 grid counts."""
         shape = tuple(self.shape_grid.M[:self.d])

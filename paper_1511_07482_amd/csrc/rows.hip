@@ -278,7 +278,7 @@ __device__ static void psi_params(const double* gv, const DsDev& ds, double prod
             G[jj * 4 + i] = gv[t];
             ++t;
         }
-    for (int i = 0; i < PRM; ++i) p[i] = 0.0;
+    // every slot the psi kernels read is written here or by put_finish
     chol4<D>(G, L);
     chol_inv4<D>(L, p + S_P1);
     double det = 1.0;

@@ -93,6 +93,29 @@ def test_prepare_auto_nonfinite_data(kf, gpu):
         ds.grid
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_lag_array_vs_oracle(kf, gpu, name):
+    """The prepared lag array against the oracle's direct autocorrelation of
+    the same counts (every lag with |l_k| <= M_k - 1), and exact zeros at the
+    last-axis positions beyond M - 1."""
+    X, G, M = CASES[name]()
+    log(f"[lag array] case={name} n={X.shape[0]} d={X.shape[1]} M={M}")
+    _, _, _, _, A = _case(name, X, G, M)
+    Xd = _to_dev(X, gpu)
+    g = kf.grid_auto(Xd, G, M)
+    ds = kf.Dataset(Xd, G, grid=g)
+    al = ds.lag_array().cpu().numpy()
+    d = X.shape[1]
+    P = [int(p) for p in g.P[:d]]
+    Mv = [int(m) for m in g.M[:d]]
+    idx = [np.arange(-(m - 1), m) % p for m, p in zip(Mv, P)]
+    got = al[np.ix_(*idx)] / float(np.prod(P))
+    np.testing.assert_allclose(got, A, rtol=0, atol=1e-12 * np.abs(A).max())
+    zero = np.arange(P[-1])
+    zero = zero[(zero > Mv[-1] - 1) & (zero < P[-1] - (Mv[-1] - 1))]
+    assert zero.size > 0 and np.all(al[..., zero] == 0.0)
+
+
 def test_linbin_fixture(kf, gpu, repo_root):
     from test_oracle_linbin import _read_fixture
     cases = _read_fixture(os.path.join(repo_root, "tests", "golden", "linbin_tiny.txt"))

@@ -204,6 +204,28 @@ def test_case4_full_sampled(kf, gpu):
     np.testing.assert_allclose(pl[1:], g[77], rtol=1e-9, atol=1e-10 * np.abs(g[77]).max())
 
 
+def test_case5_shape_sampled(kf, gpu):
+    """A case-5-shaped dataset (d=4, n=2e5, M=32, P=64): thousands of row
+    chunks per candidate, so the constant term completes in its own final
+    kernel; two candidates against the oracle's binned objective and gradient."""
+    w = synth.case5(n_datasets=1, B=2, n_lo=200_000, n_hi=200_000)
+    X, Gp, H = w.X[0], w.G_pilot[0], w.H[0]
+    log("[scv-full] case5 shape d=4 n=2e5 M=32")
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=32)
+    obj, g = kf.scv([ds], torch.from_numpy(_vech(H)).to(gpu))
+    obj, g = obj.cpu().numpy(), g.cpu().numpy()
+    # the oracle's objective (its gradient over 63^4 lags and 10 Hessian grids
+    # takes about a minute per candidate on the host: the gradient is checked
+    # against the paper-literal FFT path instead)
+    log("[scv-full] case5 shape: oracle objective")
+    g_o, A = _oracle("case5_shape", X, Gp, 32)
+    o, _ = scv.objective_binned(A, X.shape[0], g_o, H[0], Gp, with_grad=False)
+    assert abs(obj[0] - o) <= 1e-11 * abs(o), (obj[0], o)
+    pl = kf.scv_plain(ds, H[1]).cpu().numpy()
+    np.testing.assert_allclose(pl[0], obj[1], rtol=1e-11)
+    np.testing.assert_allclose(pl[1:], g[1], rtol=1e-9, atol=1e-10 * np.abs(g[1]).max())
+
+
 def test_psi_batch(kf, gpu):
     d, M, r = 2, 24, 4
     dss, Gs, Xs = [], [], []
