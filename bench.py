@@ -495,6 +495,11 @@ def main_case5(a):
     t_bin, _ = ev_time(lambda: kf.linbin(Xs[big], gbig), 3)
     t_prep1, _ = ev_time(lambda: kf.Dataset(Xs[big], w.G_pilot[big], grid=gbig), 3)
     P = int(gbig.P[0])
+    if a.calib_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     out = {"metric": "case5 (extra line): d=4, 32 datasets n~U[1e4,1e6], M=32 (P=64), 64 H each",
            "n_total": int(sum(ns)), "candidates": B,
            "prepare_all_ms": t_prep, "psi4_batch_ms": t_psi, "scv_objgrad_batch_ms": t_scv,
