@@ -10,7 +10,8 @@
 * uneven multi-dataset batches, every compiled launch variant, a singular
   candidate (status 1, NaN), bitwise repeatability;
 * the full case-4 workload (d=2, n=1e5, M=256, 256 candidates) on sampled
-  candidates.
+  candidates; a case-5-shaped dataset (d=4, n=2e5, M=32) against the
+  oracle's objective and the paper-literal path's gradient.
 """
 import numpy as np
 import pytest
