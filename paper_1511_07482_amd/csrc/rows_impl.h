@@ -611,8 +611,12 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
                             if (low && rho[k] <= 1.0) {
                                 ev[k] = 0.0;
                             } else {
-                                ev[k] = f.cn(k) * exp(low ? ea + 600.0 : ea);
-                                direct = direct || !(rho[k] <= 1e200);
+                                const double es = low ? ea + 600.0 : ea;
+                                ev[k] = f.cn(k) * exp(es);
+                                // a start still below 1e-290 after the e^600 scaling
+                                // (the values rise by more than that along the run,
+                                // and would start from zero): lag by lag instead
+                                direct = direct || !(rho[k] <= 1e200) || !(es >= lcut[k]);
                                 alive = true;
                             }
                         } else {

@@ -174,6 +174,26 @@ def test_launch_variants_agree(kf, gpu):
         kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, 0, 0)
 
 
+@pytest.mark.parametrize("d,M", [(1, 2), (1, 3), (2, 2), (2, 3), (3, 2), (2, 5)])
+def test_tiny_grids(kf, gpu, d, M):
+    """Grids of 2-5 nodes per axis (last-axis rows of 4-16 positions: runs
+    shorter than the nominal 8 lags) in both lag-domain launches."""
+    X = mixture_sample(400, d, 40 + d)
+    Gp = spd(d, 41 + d, 0.05)
+    H = _Hs(d, 3, 42 + d)
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
+    v = torch.from_numpy(_vech(H)).to(gpu)
+    N = ds.grid.P[d - 1]
+    log(f"[scv-tiny] d={d} M={M} P={N}")
+    try:
+        for var in (3, 4):
+            kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, var, 0)
+            obj, g = kf.scv([ds], v)
+            _check_against_oracle(kf, f"tiny{d}_{M}", d, X, Gp, M, H, obj.cpu().numpy(), g.cpu().numpy())
+    finally:
+        kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, 4, 0)
+
+
 def test_singular_candidate_and_determinism(kf, gpu):
     d, X, Gp, M, H, _ = _setup("d2", gpu)
     ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
