@@ -31,6 +31,7 @@ CASES = {
     "d2_ragged": (2, 2500, 29, 5),
     "d3": (3, 3000, 16, 5),
     "d4": (4, 2000, 8, 4),
+    "d2_tiny": (2, 400, 5, 4),   # coarse grid: runs rising by more than e^600 along 8 lags
 }
 _AC = {}
 
@@ -96,7 +97,8 @@ def test_lscv_adjoint_and_autograd(kf, gpu):
     np.testing.assert_allclose(out.detach().cpu().numpy(), obj.cpu().numpy(), rtol=1e-13)
 
 
-RS = {"d1": [1, 2, 4, 8], "d2": [1, 2, 3, 6, 8], "d2_ragged": [2, 5], "d3": [1, 2, 4], "d4": [1, 2, 3]}
+RS = {"d1": [1, 2, 4, 8], "d2": [1, 2, 3, 6, 8], "d2_ragged": [2, 5], "d3": [1, 2, 4], "d4": [1, 2, 3],
+      "d2_tiny": [1, 2, 4]}
 
 
 @pytest.mark.parametrize("name", list(RS))
