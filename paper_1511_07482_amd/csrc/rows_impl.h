@@ -377,7 +377,7 @@ __global__ __launch_bounds__(NT) void k_lag(const double* __restrict__ prm, RowG
         const double* __restrict__ A =
             reinterpret_cast<const double*>(static_cast<uintptr_t>(__double_as_longlong(pr[S_ALAG])));
         const double dl = delta[D - 1];
-        double dz[NGS][D], sig[NGS], hpl[NGS];
+        double dz[NGS][D], sig[NGS], hpl[NGS], lcut[NGS];
 #pragma unroll
         for (int k = 0; k < NGS; ++k) {
             const double* P = f.Pm(k);
@@ -385,6 +385,7 @@ __global__ __launch_bounds__(NT) void k_lag(const double* __restrict__ prm, RowG
             for (int i = 0; i < D; ++i) dz[k][i] = dl * P[i * D + D - 1];
             hpl[k] = 0.5 * dl * dl * P[(D - 1) * D + D - 1];
             sig[k] = exp(-2.0 * hpl[k]);
+            lcut[k] = -667.74967696827317 - log(f.cn(k));   // c e^x < 1e-290 below
         }
         double acc[NG];
 #pragma unroll
@@ -415,12 +416,15 @@ __global__ __launch_bounds__(NT) void k_lag(const double* __restrict__ prm, RowG
                     z[k][i] = s;
                     q += x[i] * s;
                 }
-                ev[k] = f.cn(k) * exp(-0.5 * q);
-                rho[k] = exp(-(dl * z[k][D - 1] + hpl[k]));
-                // ratios along the run are rho, rho sig, ... with sig < 1: if the
-                // first value is below 1e-290 and rho <= 1 the whole run is, and
-                // it adds nothing a float64 sum can hold next to the lag-0 term
-                if (!(ev[k] >= 1e-290) && rho[k] <= 1.0) {
+                const double ea = -0.5 * q;
+                const double lr = -(dl * z[k][D - 1] + hpl[k]);
+                ev[k] = f.cn(k) * exp(ea);
+                rho[k] = exp(lr);
+                // ratios along the run are rho, rho sig, ... with sig < 1, so the
+                // exponent stays below ea + (RUN - 1) max(lr, 0): when that is
+                // under the 1e-290 cut the run adds nothing a float64 sum can
+                // hold next to the lag-0 term
+                if (!(ev[k] >= 1e-290) && (rho[k] <= 1.0 || ea + (double)(RUN - 1) * lr < lcut[k])) {
                     ev[k] = 0.0;
                 } else {
                     direct = direct || !(ev[k] >= 1e-290) || !(rho[k] <= 1e200);
@@ -517,7 +521,7 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
             for (int i = 0; i < D; ++i) dz[k][i] = dl * P[i * D + D - 1];
             hpl[k] = 0.5 * dl * dl * P[(D - 1) * D + D - 1];
             sig[k] = exp(-2.0 * hpl[k]);
-            if constexpr (SCALED) lcut[k] = -667.74967696827317 - log(f.cn(k));   // c e^x < 1e-290 below
+            lcut[k] = -667.74967696827317 - log(f.cn(k));   // c e^x < 1e-290 below
         }
         double acc[NG];
 #pragma unroll
@@ -560,7 +564,7 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
 #pragma unroll
                 for (int t = 0; t < RL; ++t) av[t] = ri.rw * av[t];
                 bool scl[NGS];
-                bool direct = false, alive = false;
+                bool direct = false, alive = false, rising = false;
                 if (carried) {
                     // continue the walk: values at or above 1e-290 go on, values
                     // below it that decrease are dropped; a Gaussian rising from
@@ -604,12 +608,18 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
                         // with values scaled by e^600 (kept in the normal range) and its
                         // moments scaled back at the end (SCALED), or evaluated lag by lag.
                         const double ea = -0.5 * q;
-                        rho[k] = exp(-(dl * z[k][D - 1] + hpl[k]));
+                        const double lr = -(dl * z[k][D - 1] + hpl[k]);
+                        rho[k] = exp(lr);
+                        // a run below the cut that rises: its exponent stays below
+                        // ea + (RL - 1) lr (the log-ratios only decrease); if that
+                        // bound is below the cut too, the run is negligible
+                        const bool low = ea < lcut[k];
+                        const bool negl = low && ea + (double)(RL - 1) * lr < lcut[k];
                         if constexpr (SCALED) {
-                            const bool low = ea < lcut[k];
                             scl[k] = low;
-                            if (low && rho[k] <= 1.0) {
+                            if (low && (rho[k] <= 1.0 || negl)) {
                                 ev[k] = 0.0;
+                                rising = rising || rho[k] > 1.0;
                             } else {
                                 const double es = low ? ea + 600.0 : ea;
                                 ev[k] = f.cn(k) * exp(es);
@@ -622,8 +632,9 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
                         } else {
                             scl[k] = false;
                             ev[k] = f.cn(k) * exp(ea);
-                            if (!(ev[k] >= 1e-290) && rho[k] <= 1.0) {
+                            if (!(ev[k] >= 1e-290) && (rho[k] <= 1.0 || negl)) {
                                 ev[k] = 0.0;
+                                rising = rising || rho[k] > 1.0;
                             } else {
                                 direct = direct || !(ev[k] >= 1e-290) || !(rho[k] <= 1e200);
                                 alive = true;
@@ -631,9 +642,14 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
                         }
                     }
                 }
-                // every Gaussian below 1e-290 and decreasing: so are the rest
-                // of the segment's runs (further along the same direction)
-                if (!alive) break;
+                if (!alive) {
+                    // every Gaussian below 1e-290 and decreasing: so are the
+                    // rest of the segment's runs (further along the same
+                    // direction); one still rising is looked at again next run
+                    if (!rising) break;
+                    carried = false;
+                    continue;
+                }
                 // the next run continues this one's walk unless this one is
                 // evaluated directly or walked scaled
                 carried = !direct;
