@@ -194,6 +194,45 @@ def test_tiny_grids(kf, gpu, d, M):
         kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, 4, 0)
 
 
+@pytest.mark.parametrize("d,M", [(2, 3), (2, 5), (3, 4), (1, 6)])
+@pytest.mark.parametrize("r", [0, 2, 4])
+def test_psi_batch_coarse_grids(kf, gpu, d, M, r):
+    """psi_r from the batched lag kernel on coarse grids with narrow G (the
+    Gaussian changes by many orders of magnitude from one lag to the next)."""
+    from _gpu_util import assert_psi_close
+    from oracle import multiindex
+    X = mixture_sample(500, d, 60 + d)
+    Gp = spd(d, 61 + d, 0.05)
+    G = spd(d, 62 + d, 0.01)
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
+    got = kf.psi_batch([ds], [G], r).cpu().numpy()[0]
+    g_o = grid.plan_auto(X, Gp, [M] * d)
+    co, _ = linbin.linbin(X, g_o)
+    A = binned.autocorr_direct(linbin.counts_to_real(co))
+    want = binned.psi(A, X.shape[0], g_o, G, r)
+    sabs = binned.abs_scale(A, X.shape[0], g_o, G, multiindex.unique_alphas(d, r))
+    assert_psi_close(got, want, sabs, what=f"d={d} M={M} r={r}")
+
+
+@pytest.mark.parametrize("scale", [1e-3, 30.0])
+def test_extreme_candidates(kf, gpu, scale):
+    """Candidates far narrower and far wider than the pilot on an ordinary
+    grid, in both lag-domain launches."""
+    d, X, Gp, M, H, _ = _setup("d2", gpu)
+    Hs = H * scale
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
+    v = torch.from_numpy(_vech(Hs)).to(gpu)
+    N = ds.grid.P[d - 1]
+    log(f"[scv-extreme] H x {scale}")
+    try:
+        for var in (3, 4):
+            kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, var, 0)
+            obj, g = kf.scv([ds], v)
+            _check_against_oracle(kf, "d2", d, X, Gp, M, Hs, obj.cpu().numpy(), g.cpu().numpy())
+    finally:
+        kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, 4, 0)
+
+
 def test_singular_candidate_and_determinism(kf, gpu):
     d, X, Gp, M, H, _ = _setup("d2", gpu)
     ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
