@@ -434,7 +434,8 @@ def fftl_section(kf, torch, dev, X, Gpsi, g):
         vt, L, P = trunc()
         vt = vt.cpu().numpy()
         t.update({"L": L, "P_fft_L": P, "P_fft_M": [int(p) for p in gg.P[:gg.d]],
-                  "max_rel_diff": float(np.max(np.abs(vt - vf) / np.abs(vf)))})
+                  "max_rel_diff": float(np.max(np.abs(vt - vf) / np.abs(vf))),
+                  "max_diff_over_max_abs": float(np.max(np.abs(vt - vf)) / np.max(np.abs(vf)))})
         res[label] = t
     return res
 

@@ -1082,7 +1082,8 @@ int kdefft_psi_batch(const kdefft_dataset* ds, int n_ds, const double* G_host, i
 // Row-kernel family of a criterion: the two-Gaussian SCV families (with the
 // Hessian grids for gradients) serve SCV and LSCV at r = 0; LSCV_r for r > 0 and
 // Q_r use the scalar eta_r families.  The dispatch order passed to the row
-// kernels is 2 for the SCV families and 0 (unused) for the eta families.
+// kernels is 2 for the SCV families and r for the eta families (which pick the
+// kernel compiled for r's order class).
 static int crit_kind(int crit, int r, bool want_grad, bool adjoint) {
     if (crit == KDEFFT_CRIT_QR) return FUN_ETA1;
     if (r > 0) return FUN_ETA2;
@@ -1108,7 +1109,7 @@ static int crit_common(const kdefft_dataset* ds, int n_ds, const int64_t* off, c
     if (crit == KDEFFT_CRIT_LSCV_EXACT)
         for (int j = 0; j < n_ds; ++j)
             if (ds[j].n < 2) return fail(KDEFFT_E_ARG, "the leave-one-out form needs n >= 2 (dataset %d)", j);
-    const int kr = (kind == FUN_ETA1 || kind == FUN_ETA2) ? 0 : 2;
+    const int kr = (kind == FUN_ETA1 || kind == FUN_ETA2) ? r : 2;
     rc = check_rows(kind, g.d, kr, g.P[g.d - 1]);
     if (rc) return rc;
     ScvBatchArgs a{};

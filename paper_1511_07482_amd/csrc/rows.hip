@@ -6,6 +6,7 @@
 
 #include "dev_common.h"
 #include "dev_kernels.h"
+#include "eta_fun.h"
 #include "finish.h"
 #include "internal.h"
 
@@ -19,10 +20,10 @@ hipError_t launch_rows_d3(int, int, int, int, const double*, RowGeom, int64_t, d
                           hipStream_t);
 hipError_t launch_rows_d4(int, int, int, int, const double*, RowGeom, int64_t, double*, int, const double2*,
                           hipStream_t);
-hipError_t launch_rows_eta_d1(int, int, int, const double*, RowGeom, int64_t, double*, int, hipStream_t);
-hipError_t launch_rows_eta_d2(int, int, int, const double*, RowGeom, int64_t, double*, int, hipStream_t);
-hipError_t launch_rows_eta_d3(int, int, int, const double*, RowGeom, int64_t, double*, int, hipStream_t);
-hipError_t launch_rows_eta_d4(int, int, int, const double*, RowGeom, int64_t, double*, int, hipStream_t);
+hipError_t launch_rows_eta_d1(int, int, int, int, const double*, RowGeom, int64_t, double*, int, hipStream_t);
+hipError_t launch_rows_eta_d2(int, int, int, int, const double*, RowGeom, int64_t, double*, int, hipStream_t);
+hipError_t launch_rows_eta_d3(int, int, int, int, const double*, RowGeom, int64_t, double*, int, hipStream_t);
+hipError_t launch_rows_eta_d4(int, int, int, int, const double*, RowGeom, int64_t, double*, int, hipStream_t);
 int rows_iter_eta_d1(int, int, int);
 int rows_iter_eta_d2(int, int, int);
 int rows_iter_eta_d3(int, int, int);
@@ -106,10 +107,10 @@ hipError_t launch_rows(int kind, int d, int r, const RowGeom& geo, const double*
     const int N = geo.P[d - 1];
     if (kind == FUN_ETA1 || kind == FUN_ETA2) {
         switch (d) {
-            case 1: return launch_rows_eta_d1(kind, N, rl.variant, prm, geo, nitems, partial, rl.grid_blocks, s);
-            case 2: return launch_rows_eta_d2(kind, N, rl.variant, prm, geo, nitems, partial, rl.grid_blocks, s);
-            case 3: return launch_rows_eta_d3(kind, N, rl.variant, prm, geo, nitems, partial, rl.grid_blocks, s);
-            case 4: return launch_rows_eta_d4(kind, N, rl.variant, prm, geo, nitems, partial, rl.grid_blocks, s);
+            case 1: return launch_rows_eta_d1(kind, r, N, rl.variant, prm, geo, nitems, partial, rl.grid_blocks, s);
+            case 2: return launch_rows_eta_d2(kind, r, N, rl.variant, prm, geo, nitems, partial, rl.grid_blocks, s);
+            case 3: return launch_rows_eta_d3(kind, r, N, rl.variant, prm, geo, nitems, partial, rl.grid_blocks, s);
+            case 4: return launch_rows_eta_d4(kind, r, N, rl.variant, prm, geo, nitems, partial, rl.grid_blocks, s);
             default: return hipErrorInvalidValue;
         }
     }

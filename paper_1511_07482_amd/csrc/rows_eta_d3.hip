@@ -1,5 +1,6 @@
 // Scalar eta_r families (Q_r, LSCV_r) for d = 3: lag-domain kernel only (variants 3 and 4
 // coincide for them; see rows_impl.h).
+#include "eta_fun.h"
 #include "rows_dispatch.h"
 
 namespace kdefft {
@@ -18,12 +19,26 @@ static hipError_t lag_3(int N, const double* prm, RowGeom geo, int64_t nitems, d
     }
 }
 
-hipError_t launch_rows_eta_d3(int kind, int N, int var, const double* prm, RowGeom geo, int64_t nitems,
+// One kernel per order class of r (eta_bound), so the per-lag work is that
+// of the class bound rather than of the largest order.
+template <int NGS>
+static hipError_t eta_3(int r, int N, const double* prm, RowGeom geo, int64_t nitems, double* partial, int gb,
+                         hipStream_t s) {
+    switch (eta_bound(r)) {
+        case 2: return lag_3<EtaFun<3, NGS, 2>>(N, prm, geo, nitems, partial, gb, s);
+        case 4: return lag_3<EtaFun<3, NGS, 4>>(N, prm, geo, nitems, partial, gb, s);
+        case 6: return lag_3<EtaFun<3, NGS, 6>>(N, prm, geo, nitems, partial, gb, s);
+        default: return lag_3<EtaFun<3, NGS, ETA_RMAX>>(N, prm, geo, nitems, partial, gb, s);
+    }
+}
+
+hipError_t launch_rows_eta_d3(int kind, int r, int N, int var, const double* prm, RowGeom geo, int64_t nitems,
                                double* partial, int gb, hipStream_t s) {
     if (var != 3 && var != 4) return hipErrorInvalidValue;
+    if (r < 0 || r > ETA_RMAX) return hipErrorInvalidValue;
     switch (kind) {
-        case FUN_ETA1: return lag_3<EtaFun<3, 1>>(N, prm, geo, nitems, partial, gb, s);
-        case FUN_ETA2: return lag_3<EtaFun<3, 2>>(N, prm, geo, nitems, partial, gb, s);
+        case FUN_ETA1: return eta_3<1>(r, N, prm, geo, nitems, partial, gb, s);
+        case FUN_ETA2: return eta_3<2>(r, N, prm, geo, nitems, partial, gb, s);
         default: return hipErrorInvalidValue;
     }
 }

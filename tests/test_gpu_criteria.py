@@ -97,7 +97,7 @@ def test_lscv_adjoint_and_autograd(kf, gpu):
     np.testing.assert_allclose(out.detach().cpu().numpy(), obj.cpu().numpy(), rtol=1e-13)
 
 
-RS = {"d1": [1, 2, 4, 8], "d2": [1, 2, 3, 6, 8], "d2_ragged": [2, 5], "d3": [1, 2, 4], "d4": [1, 2, 3],
+RS = {"d1": [1, 2, 4, 8], "d2": [1, 2, 3, 6, 7, 8], "d2_ragged": [2, 5], "d3": [1, 2, 4], "d4": [1, 2, 3],
       "d2_tiny": [1, 2, 4]}
 
 
