@@ -21,15 +21,19 @@ static hipError_t lag_2(int N, const double* prm, RowGeom geo, int64_t nitems, d
     }
 }
 
-// One kernel per order class of r (eta_bound), so the per-lag work is that
-// of the class bound rather than of the largest order.
+// One kernel per order r, so a lag costs the work of its own order.
 template <int NGS>
 static hipError_t eta_2(int r, int N, const double* prm, RowGeom geo, int64_t nitems, double* partial, int gb,
                          hipStream_t s) {
-    switch (eta_bound(r)) {
+    switch (r) {
+        case 0: return lag_2<EtaFun<2, NGS, 0>>(N, prm, geo, nitems, partial, gb, s);
+        case 1: return lag_2<EtaFun<2, NGS, 1>>(N, prm, geo, nitems, partial, gb, s);
         case 2: return lag_2<EtaFun<2, NGS, 2>>(N, prm, geo, nitems, partial, gb, s);
+        case 3: return lag_2<EtaFun<2, NGS, 3>>(N, prm, geo, nitems, partial, gb, s);
         case 4: return lag_2<EtaFun<2, NGS, 4>>(N, prm, geo, nitems, partial, gb, s);
+        case 5: return lag_2<EtaFun<2, NGS, 5>>(N, prm, geo, nitems, partial, gb, s);
         case 6: return lag_2<EtaFun<2, NGS, 6>>(N, prm, geo, nitems, partial, gb, s);
+        case 7: return lag_2<EtaFun<2, NGS, 7>>(N, prm, geo, nitems, partial, gb, s);
         default: return lag_2<EtaFun<2, NGS, ETA_RMAX>>(N, prm, geo, nitems, partial, gb, s);
     }
 }
