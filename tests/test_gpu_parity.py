@@ -160,6 +160,35 @@ def test_linbin_full_sizes(kf, gpu):
         assert int(counts.sum().item()) == X.shape[0] << 40
 
 
+def test_linbin_max_n(kf, gpu):
+    """The largest accepted n (2^23 - 1): random points bin bit-identically, and
+    the same point repeated n times fills its largest corner to within 2^40 of
+    2^63 without overflow (every bin equals n times the one-point quanta)."""
+    n = (1 << 23) - 1
+    rng = np.random.default_rng(151107482 + 23)
+    X = rng.standard_normal((n, 2))
+    G = np.array([[0.01, 0.002], [0.002, 0.02]])
+    log(f"[linbin-max] random n={n}")
+    g_o = grid.plan_auto(X, G, [256, 256])
+    co, sk = linbin.linbin(X, g_o)
+    Xd = _to_dev(X, gpu)
+    g = kf.grid_auto(Xd, G, 256)
+    counts, nout = kf.linbin(Xd, g)
+    np.testing.assert_array_equal(counts.cpu().numpy(), co)
+    assert int(nout.item()) == sk == 0
+    del Xd, counts
+    log(f"[linbin-max] repeated point n={n}")
+    g1 = kf.grid_plan([5, 4], [0.0, -1.0], [1.0, 2.0])
+    p1 = np.array([[0.5 + 1e-3, 0.25 - 2e-3]])
+    g1o = {"d": 2, "M": np.array([5, 4]), "lo": np.array([0.0, -1.0]), "delta": g1.to_dict()["delta"]}
+    one, _ = linbin.linbin(p1, g1o)
+    Xr = _to_dev(np.repeat(p1, n, axis=0), gpu)
+    counts, nout = kf.linbin(Xr, g1)
+    got = counts.cpu().numpy()
+    np.testing.assert_array_equal(got, one * n)
+    assert int(got.max()) > (1 << 62) and int(got.sum()) == n << 40
+
+
 PSI_CASES = [("d1", 0), ("d1", 4), ("d1", 8), ("d2_case1", 0), ("d2_ragged", 2), ("d2_ragged", 4),
              ("d2_ragged", 8), ("d3", 2), ("d3", 4), ("d3", 6), ("d4", 2), ("d4", 4), ("d4_m12", 2)]
 

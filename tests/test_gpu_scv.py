@@ -89,6 +89,22 @@ def test_scv_batch_vs_oracle(kf, gpu, name):
     np.testing.assert_allclose(obj_only, obj, rtol=1e-13)
 
 
+@pytest.mark.parametrize("B", [1, 4097])
+def test_batch_sizes(kf, gpu, B):
+    """One candidate, and 4097 candidates (several waves of items over the
+    resident grid, a ragged last wave): the first, last and a random sample of
+    candidates against the oracle."""
+    name = "d2_ragged"
+    d, X, Gp, M, _, _ = _setup(name, gpu)
+    H = _Hs(d, B, 900 + B)
+    log(f"[scv] batch B={B}")
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
+    obj, g = kf.scv([ds], torch.from_numpy(_vech(H)).to(gpu))
+    obj, g = obj.cpu().numpy(), g.cpu().numpy()
+    idx = sorted(set([0, B - 1] + list(np.random.default_rng(B).integers(0, B, size=min(B, 12)))))
+    _check_against_oracle(kf, name, d, X, Gp, M, H[idx], obj[idx], g[idx])
+
+
 @pytest.mark.parametrize("name", ["d1", "d2_ragged", "d3", "d4"])
 def test_scv_plain_vs_oracle(kf, gpu, name):
     d, X, Gp, M, H, _ = _setup(name, gpu)
