@@ -123,7 +123,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
-              "(the path shards by candidates/datasets with no exchange; see DESIGN.md)", file=sys.stderr)
+              "(the path shards by candidates or datasets with no exchange between GPUs)", file=sys.stderr)
         sys.exit(2)
     if a.case5:
         return main_case5(a)
