@@ -237,6 +237,22 @@ def main():
     t_psi_plain, _ = timed(lambda: kf.psi(X, Gpsi, 4, grid=g, mode="plain"), 5)
     t_scv_only, _ = timed(lambda: kf.scv([ds], vechL), 10)
 
+    # binning alone (the standalone entry: zero fill of one int64 grid, then the
+    # points), HIP events on the stream: n points x 2^d lane atomics each
+    kf.linbin(X, g)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(20):
+        kf.linbin(X, g)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_bin = e0.elapsed_time(e1) / 20 * 1e-3
+    binning = {"call_ms": t_bin * 1e3, "points_per_s": n / t_bin, "lane_atomics_per_s": n * 2 ** d / t_bin,
+               "x_read_GB_per_s": n * d * 8 / t_bin / 1e9,
+               "what": "kdefft_linbin on the case-4 grid: fill of the 256^2 int64 grid plus binning of the "
+                       "1e5 points (the step's own binning adds into per-XCD copies cleared by the bounds pass)"}
+
     def autograd_step():
         v = vechL.clone().requires_grad_(True)
         o = kf.SCV.apply(v, ds)
@@ -347,6 +363,7 @@ def main():
         "cpu_baseline": cpu,
         "row_kernels_in_timed_steps_ms": {"scv_objgrad_256": scv_ms, "psi4": float(np.mean(psi_k)),
                                           "scv_call_with_setup_final": scv_call_ms},
+        "binning": binning,
         "components_ms": {"dataset_prepare": t_prep * 1e3, "psi4_batched": t_psi_batched * 1e3,
                           "scv_objgrad_batched_256": t_scv_only * 1e3, "scv_autograd_fwd_adjoint_256": t_autograd * 1e3,
                           "psi4_plain_with_binning": t_psi_plain * 1e3, "scv_plain_per_H": t_plain * 1e3,
