@@ -1,0 +1,45 @@
+"""The benchmark's work model (CPU): the algorithmic flop and byte counts that
+the roofline figures divide by, pinned to hand counts of the same formulas."""
+import os
+import sys
+
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402
+
+
+def test_walk_flops_case4():
+    # d = 2, N = 512: runs of 16 lags in segments of 2 runs; per run
+    # 16 * (2 * 8 + 1) walk flops, 3 + 25 * 3 fold flops, z advance 4d / 2,
+    # and a fresh start per segment: 2 * (2 d^2 + 2 d + 4 + 2 * 20) / 2
+    assert bench.moment_walk_layout(512) == (16, 2)
+    per_run = 16 * 17 + (3 + 75) + 8 / 2 + 2 * (8 + 4 + 4 + 40) / 2
+    assert per_run == 410.0
+    per_cand = bench.algorithmic_flops_per_candidate(256, 512, d=2, variant=3)
+    assert per_cand == 256 * 32 * per_run
+    assert per_cand * 256 == 859_832_320
+
+
+def test_direct_equivalent_flops_case4():
+    # generation at a lag: 2 * (2 d^2 + 2 d + 2 + 20) + 2 + 7 * 3 = 91 at d = 2,
+    # plus 2 flops for each of the 4 grids' sums: 99 per lag
+    assert bench.gen_flops_per_lag(2) == 2 * (8 + 4 + 2 + 20) + 2 + 21 == 91
+    assert bench.direct_equivalent_flops_per_candidate(256, 2) == 256 * 511 * (91 + 8)
+    assert bench.direct_equivalent_flops_per_candidate(256, 2) * 256 == 3_315_400_704
+
+
+@pytest.mark.parametrize("N,layout", [(64, (8, 1)), (128, (8, 1)), (256, (16, 2)), (1024, (16, 2)), (8, (4, 1))])
+def test_walk_layout(N, layout):
+    assert bench.moment_walk_layout(N) == layout
+
+
+def test_fft_stage_bytes():
+    # case 5 (P = 64, d = 4): real grid 8 P^4, half spectrum 16 P^3 (P/2 + 1)
+    real, half = 8 * 64 ** 4, 16 * 64 ** 3 * 33
+    fwd = real + half + 3 * 2 * half + half + 2 * 2 * half
+    auto = 2 * half + 3 * 2 * half + half + real
+    assert bench.fft_stage_bytes(64, 4) == fwd + auto == 3_175_088_128
+    # d = 2 (P = 512): no middle passes
+    real, half = 8 * 512 ** 2, 16 * 512 * 257
+    assert bench.fft_stage_bytes(512, 2) == (real + half) + 2 * half + half + 2 * half + 2 * half + half + real
