@@ -75,11 +75,11 @@ def gen_flops_per_lag(d=2):
 
 def moment_walk_layout(N):
     """Run length and runs per segment of the lag moment kernel for rows of
-    N positions (as compiled: 16-lag runs in 32-lag segments for N >= 256,
-    else single runs of 8)."""
-    if N >= 256:
-        return 16, 2
-    return min(8, N // 2), 1
+    N positions, as the library was compiled (kdefft_lag_layout; 16-lag runs
+    in 32-lag segments for N >= 256, else single runs of up to 8)."""
+    import paper_1511_07482_amd as kf
+    run, seg, _ = kf.lag_layout(N, True)
+    return run, seg
 
 
 def algorithmic_flops_per_candidate(M, N, d=2, variant=0):

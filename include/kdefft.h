@@ -348,6 +348,17 @@ int kdefft_scv_plain(const kdefft_dataset* ds_host, const double* H_host, double
  * kdefft_autotune and by tests that cover every variant.  Host only. */
 int kdefft_set_row_launch(int kind, int d, int r, int N, int variant, int grid_blocks);
 
+/* Layout of the compiled lag-domain kernels (variants 3 and 4) for a last-axis
+ * length N (a power of two in [4, 2048]): *run_len = lags per run (one
+ * exponential recurrence start per run, or per segment for the moment
+ * families), *runs_per_seg = consecutive runs one thread walks carrying the
+ * recurrence (moment families; 1 otherwise), *rows_per_pass = rows one
+ * 256-thread block covers per pass.  moments = 1 for the SCV / LSCV families
+ * (moment form), 0 for the psi_r and eta_r families with at most 12 outputs
+ * per lag.  Lets a caller's work model use the constants the kernels were
+ * compiled with.  Host only; KDEFFT_E_ARG for other N or NULL outputs. */
+int kdefft_lag_layout(int N, int moments, int* run_len, int* runs_per_seg, int* rows_per_pass);
+
 /* Measurement hook for the batched row kernels (the dominant launches of
  * kdefft_psi, kdefft_psi_batch, kdefft_scv_batch, kdefft_scv_adjoint and
  * kdefft_autotune).  kdefft_timing_start arms it for up to max_launches

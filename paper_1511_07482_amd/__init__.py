@@ -525,6 +525,15 @@ class SCV(torch.autograd.Function):
         return g, None, None
 
 
+def lag_layout(N: int, moments: bool = True):
+    """(lags per run, runs per segment, rows per block pass) of the compiled
+    lag-domain kernels for last-axis length N."""
+    run, seg, rows = C.c_int(), C.c_int(), C.c_int()
+    _lib.check(_L().kdefft_lag_layout(int(N), int(bool(moments)), C.byref(run), C.byref(seg), C.byref(rows)),
+               "kdefft_lag_layout")
+    return run.value, seg.value, rows.value
+
+
 def set_row_launch(kind: int, d: int, r: int, N: int, variant: int, grid_blocks: int = 0):
     _lib.check(_L().kdefft_set_row_launch(kind, d, r, N, variant, grid_blocks), "kdefft_set_row_launch")
 

@@ -1295,6 +1295,14 @@ int kdefft_scv_plain(const kdefft_dataset* ds, const double* H_host, double* out
     return KDEFFT_OK;
 }
 
+int kdefft_lag_layout(int N, int moments, int* run_len, int* runs_per_seg, int* rows_per_pass) {
+    if (!run_len || !runs_per_seg || !rows_per_pass) return fail(KDEFFT_E_ARG, "NULL output");
+    if (moments != 0 && moments != 1) return fail(KDEFFT_E_ARG, "moments=%d", moments);
+    if (!lag_layout(N, moments, run_len, runs_per_seg, rows_per_pass))
+        return fail(KDEFFT_E_ARG, "N=%d is not a power of two in [4, 2048]", N);
+    return KDEFFT_OK;
+}
+
 int kdefft_set_row_launch(int kind, int d, int r, int N, int variant, int grid_blocks) {
     if (kind < 0 || kind > FUN_ETA2) return fail(KDEFFT_E_ARG, "kind=%d", kind);
     if (variant < 0 || variant >= ROW_VARIANTS) return fail(KDEFFT_E_ARG, "variant=%d", variant);

@@ -182,6 +182,8 @@ struct RowLaunch {
 hipError_t launch_rows(int kind, int d, int r, const RowGeom& geo, const double* prm, int64_t ncand,
                        double* partial, const RowLaunch& rl, hipStream_t s);
 int rows_per_iter(int kind, int d, int r, int N, int variant);
+// compiled lag-kernel layout for last-axis length N (0 = unsupported N)
+int lag_layout(int N, int moments, int* run_len, int* runs_per_seg, int* rows_per_pass);
 constexpr int ROW_VARIANTS = 5;   // 0-2: spectral (per-candidate FFT), 3, 4: lag domain (4: scaled walk)
 hipError_t launch_scv_setup(const double* vechL, const ScvBatchArgs& a, int64_t ncand, double* prm,
                             int32_t* status, hipStream_t s);

@@ -9,6 +9,7 @@
 #include "eta_fun.h"
 #include "finish.h"
 #include "internal.h"
+#include "rows_impl.h"
 
 namespace kdefft {
 
@@ -37,6 +38,37 @@ static int binom_h(int n, int k) {
     int r = 1;
     for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
     return r;
+}
+
+template <int N>
+static int layout_of(int moments, int* run_len, int* runs_per_seg, int* rows_per_pass) {
+    if (moments) {
+        constexpr int RL = mom_run_of<N>() < N / 2 ? mom_run_of<N>() : N / 2;
+        *run_len = RL;
+        *runs_per_seg = mom_seg_of<N, RL>();
+        *rows_per_pass = mom_rows_per_pass<N>();
+    } else {
+        *run_len = LAG_RUN;
+        *runs_per_seg = 1;
+        *rows_per_pass = lag_rows_per_pass<N>();
+    }
+    return 1;
+}
+
+int lag_layout(int N, int moments, int* run_len, int* runs_per_seg, int* rows_per_pass) {
+    switch (N) {
+        case 4: return layout_of<4>(moments, run_len, runs_per_seg, rows_per_pass);
+        case 8: return layout_of<8>(moments, run_len, runs_per_seg, rows_per_pass);
+        case 16: return layout_of<16>(moments, run_len, runs_per_seg, rows_per_pass);
+        case 32: return layout_of<32>(moments, run_len, runs_per_seg, rows_per_pass);
+        case 64: return layout_of<64>(moments, run_len, runs_per_seg, rows_per_pass);
+        case 128: return layout_of<128>(moments, run_len, runs_per_seg, rows_per_pass);
+        case 256: return layout_of<256>(moments, run_len, runs_per_seg, rows_per_pass);
+        case 512: return layout_of<512>(moments, run_len, runs_per_seg, rows_per_pass);
+        case 1024: return layout_of<1024>(moments, run_len, runs_per_seg, rows_per_pass);
+        case 2048: return layout_of<2048>(moments, run_len, runs_per_seg, rows_per_pass);
+        default: return 0;
+    }
 }
 
 int ng_of(int kind, int d, int r) {

@@ -29,9 +29,23 @@ def test_direct_equivalent_flops_case4():
     assert bench.direct_equivalent_flops_per_candidate(256, 2) * 256 == 3_315_400_704
 
 
-@pytest.mark.parametrize("N,layout", [(64, (8, 1)), (128, (8, 1)), (256, (16, 2)), (1024, (16, 2)), (8, (4, 1))])
+@pytest.mark.parametrize("N,layout", [(4, (2, 1, 128)), (8, (4, 1, 128)), (64, (8, 1, 32)), (128, (8, 1, 16)),
+                                      (256, (16, 2, 32)), (512, (16, 2, 16)), (1024, (16, 2, 8))])
 def test_walk_layout(N, layout):
-    assert bench.moment_walk_layout(N) == layout
+    """The compiled layout the model reads from the library (runs of up to 8
+    lags below N = 256, runs of 16 in segments of 2 from there; a 256-thread
+    block covers 256 * run * seg / N rows per pass)."""
+    assert bench.moment_walk_layout(N) == layout[:2]
+    import paper_1511_07482_amd as kf
+    assert kf.lag_layout(N, True) == layout
+    assert layout[2] == 256 * layout[0] * layout[1] // N
+
+
+def test_lag_layout_rejects_bad_length():
+    import paper_1511_07482_amd as kf
+    for N in (2, 3, 96, 4096):
+        with pytest.raises(RuntimeError):
+            kf.lag_layout(N)
 
 
 def test_fft_stage_bytes():
