@@ -1,5 +1,6 @@
 """The whole hot-path step (device-planned grid, binning, count transform,
-psi_4, SCV objective + gradient, LSCV, PI) captured in a HIP graph.
+psi_4, SCV objective + gradient and adjoint, LSCV, LSCV_4, Q_2, PI, and the
+single-call psi_2 routes) captured in a HIP graph.
 
 Every replay must reproduce the eager results bit for bit; replays are
 interleaved with unrelated eager work on the same device (the capture must not
@@ -22,13 +23,21 @@ def test_step_graph_replays_match_eager(kf, gpu):
     Gp, Gpsi = spd(d, 4243, 0.05), spd(d, 4244, 0.08)
     v = torch.from_numpy(synth.vech_chol(synth.random_H_2d(B, np.random.default_rng(4245)))).to(gpu)
 
+    g = kf.grid_auto(X, Gpsi, M)   # reads the bounds back: planned outside the capture
+    w = torch.linspace(0.5, 1.5, B, dtype=torch.float64, device=gpu)
+
     def step():
         ds = kf.Dataset(X, Gp, M=M)
         p4 = kf.psi_batch([ds], [Gpsi], 4)
         so, sg = kf.scv([ds], v)
         lo, lg = kf.crit([ds], v, "lscv")
         po, pg = kf.pi(p4, [n], v)
-        return p4, so, sg, lo, lg, po, pg
+        adj = kf.scv_adjoint([ds], v, w)
+        l4 = kf.crit([ds], v, "lscv", 4, grad=False)
+        q2 = kf.crit([ds], v, "qr", 2, grad=False)
+        p2f = kf.psi(X, Gpsi, 2, grid=g, mode="fused")
+        p2p = kf.psi(X, Gpsi, 2, grid=g, mode="plain")
+        return p4, so, sg, lo, lg, po, pg, adj, l4, q2, p2f, p2p
 
     want = [t.clone() for t in step()]
     side = torch.cuda.Stream(gpu)
