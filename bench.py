@@ -82,9 +82,10 @@ def moment_walk_layout(N):
     return run, seg
 
 
-def algorithmic_flops_per_candidate(M, N, d=2, variant=0):
+def algorithmic_flops_per_candidate(M, N, d=2, variant=0, rows=None):
     """FP64 flops of one candidate in the batched objective+gradient kernel
-    (d = 2: M rows of the half lag set, l_0 = 0..M-1, N positions each).
+    over `rows` rows of the half lag set, N positions each (default M rows,
+    l_0 = 0..M-1, the d = 2 set; in general M_0 prod_{0<k<d-1} (2 M_k - 1)).
 
     Lag form (variants 3, 4), the algorithm as designed: per position, per
     Gaussian, the walk e*A, the three moment sums (1 add + 2 FMA) and the two
@@ -100,16 +101,17 @@ def algorithmic_flops_per_candidate(M, N, d=2, variant=0):
     packed two per transform) at 5 N log2 N flops each and the contraction,
     8 flops per complex multiply-add per transform."""
     q = d * (d + 1) // 2
+    rows = M if rows is None else rows
     if variant >= 3:
         RL, SEG = moment_walk_layout(N)
         per_run = (RL * (2 * 8 + 1) + (3 + 25 * q) + 4 * d * (SEG - 1) / SEG
                    + 2 * (2 * d * d + 2 * d + 4 + 2 * EXP_FLOPS) / SEG)
-        return M * (N // RL) * per_run
+        return rows * (N // RL) * per_run
     gen = (2 * M - 1) * gen_flops_per_lag(d)
     log2n = int(np.log2(N))
     fft = 2 * 5 * N * log2n
     contraction = 2 * N * 8
-    return M * (fft + contraction + gen)
+    return rows * (fft + contraction + gen)
 
 
 def direct_equivalent_flops_per_candidate(M, d=2):
@@ -507,6 +509,26 @@ def main_case5(a):
     t_psi, _ = ev_time(lambda: kf.psi_batch(dss, w.G_psi, 4), 3)
     t_scv, (obj, grad) = ev_time(lambda: kf.scv(dss, vech, per_ds=per), 3)
     assert torch.isfinite(obj).all() and torch.isfinite(grad).all()
+    # the lag kernel of the SCV launch alone (library HIP events), against the
+    # walk's algorithmic flops over every run (all runs of these grids are above
+    # the 1e-290 cut, so the kernel walks each one)
+    kf.timing_start(16)
+    for _ in range(3):
+        kf.scv(dss, vech, per_ds=per)
+    torch.cuda.synchronize()
+    lag_ms = float(np.mean([ms for ms, fam, r in kf.timing_stop() if fam == kf.FUN_SCV_OBJGRAD]))
+    variant = 4
+    for line in (tuned or "").splitlines():
+        if line.startswith("best: variant"):
+            variant = int(line.split()[2])
+    P_last = int(dss[0].grid.P[d - 1])
+    roofline = None
+    if variant >= 3:
+        rows = M * (2 * M - 1) ** (d - 2)
+        flops = B * algorithmic_flops_per_candidate(M, P_last, d=d, variant=variant, rows=rows)
+        roofline = {"bound": "alu", "kernel": f"k_lag_mom<{d},{P_last},ScvFun<{d},1>> variant {variant}",
+                    "launch_ms": lag_ms, "flops_per_launch": flops, "achieved": flops / (lag_ms * 1e-3) / 1e12,
+                    "peak": 78.6, "unit": "TFLOP/s", "frac": flops / (lag_ms * 1e-3) / 1e12 / 78.6}
     # one large dataset: binning alone vs full preparation -> count-transform time
     big = int(np.argmax(ns))
     gbig = dss[big].grid
@@ -523,7 +545,7 @@ def main_case5(a):
            "prepare_all_ms": t_prep, "psi4_batch_ms": t_psi, "scv_objgrad_batch_ms": t_scv,
            "scv_evals_per_s": B / (t_scv * 1e-3), "psi4_evals_per_s": len(dss) / (t_psi * 1e-3),
            "largest_n": ns[big], "linbin_largest_ms": t_bin, "prepare_largest_ms": t_prep1,
-           "fft_stage_bytes_per_dataset": fft_stage_bytes(P, d), "tuned": tuned}
+           "fft_stage_bytes_per_dataset": fft_stage_bytes(P, d), "scv_roofline": roofline, "tuned": tuned}
     print(json.dumps(out))
 
 
