@@ -344,9 +344,17 @@ int kdefft_scv_plain(const kdefft_dataset* ds_host, const double* H_host, double
  * (identical sums, no per-candidate transform); for the SCV families, runs of
  * lags that start below 1e-290 and rise are evaluated lag by lag (3) or
  * walked with values scaled by e^600 (4, the untuned default); the psi and eta
- * families treat 3 and 4 alike and have no spectral variants for eta.  Used by
- * kdefft_autotune and by tests that cover every variant.  Host only. */
+ * families treat 3 and 4 alike and have no spectral variants for eta.
+ * variant = -1 drops the pinned (or tuned) choice of that key, so the untuned
+ * default applies again.  Used by kdefft_autotune and by tests that cover
+ * every variant.  Host only. */
 int kdefft_set_row_launch(int kind, int d, int r, int N, int variant, int grid_blocks);
+
+/* The launch the batched calls of that key (kind, d, r, N as in
+ * kdefft_set_row_launch) use now on the current device: pinned, tuned or the
+ * untuned default.  Lets a caller restore a choice after pinning another.
+ * Host only. */
+int kdefft_get_row_launch(int kind, int d, int r, int N, int* variant, int* grid_blocks);
 
 /* Layout of the compiled lag-domain kernels (variants 3 and 4) for a last-axis
  * length N (a power of two in [4, 2048]): *run_len = lags per run (one

@@ -12,8 +12,9 @@ full symmetric lag range l in [-(M-1), M-1]^d.  Writing the inner sums out,
 (A is the autocorrelation of the counts; only i with both i and i+l on the grid
 contribute).  That is the plain definition the FFT route must reproduce up to
 rounding; here A is built from shifted-slice dot products and the final sum
-is taken with math.fsum.  ``autocorr_fft`` (numpy.fft, test-only cross check)
-is provided for grids where the direct product is too slow.
+is taken with math.fsum.  ``autocorr_gemm`` computes the same A for large
+grids (matrix products of shifted slabs, still no FFT); ``autocorr_fft``
+(numpy.fft) is a test-only cross check.
 """
 from __future__ import annotations
 
@@ -43,6 +44,51 @@ def autocorr_direct(c):
         A[tuple(x + m - 1 for x, m in zip(neg, M))] = v
     assert d == len(M)
     return A
+
+
+def autocorr_gemm(c):
+    """The same A_l = sum_i c_i c_{i+l} as ``autocorr_direct`` (same layout),
+    arranged for large grids and still FFT-free.  The axes are split into
+    leading axes a and trailing axes t (the last axis for d <= 3, the last two
+    for d = 4).  For one trailing lag l_t the two overlapping slabs S1 = c[:, i_t]
+    and S2 = c[:, i_t + l_t] give, by one matrix product (library primitive),
+    G[a, b] = sum_{i_t} c[a, i_t] c[b, i_t + l_t]; then
+    A(l_a, l_t) = sum_a G[a, a + l_a], i.e. the entries of G summed by their
+    leading-axes lag b - a (np.bincount).  Trailing lags with l_t < 0
+    (lexicographically) follow from A_{-l} = A_l."""
+    c = np.asarray(c, dtype=np.float64)
+    M = c.shape
+    d = c.ndim
+    if d == 1:
+        return autocorr_direct(c)
+    t = 1 if d <= 3 else 2
+    lead, trail = M[:d - t], M[d - t:]
+    nlead = int(np.prod(lead))
+    coords = np.indices(lead).reshape(d - t, -1)
+    key = np.zeros((nlead, nlead), dtype=np.int64)
+    for k in range(d - t):
+        diff = coords[k][None, :] - coords[k][:, None] + (lead[k] - 1)
+        key = key * (2 * lead[k] - 1) + diff
+    key = key.ravel()
+    nkey = int(np.prod([2 * m - 1 for m in lead]))
+    tshape = tuple(2 * m - 1 for m in trail)
+    A = np.zeros((nkey,) + tshape)
+    zero = (0,) * t
+    for lt in itertools.product(*[range(-(m - 1), m) for m in trail]):
+        if lt < zero:
+            continue
+        s1 = tuple(slice(max(0, -l), m - max(0, l)) for l, m in zip(lt, trail))
+        s2 = tuple(slice(max(0, l), m + min(0, l)) for l, m in zip(lt, trail))
+        S1 = c[(Ellipsis,) + s1].reshape(nlead, -1)
+        S2 = c[(Ellipsis,) + s2].reshape(nlead, -1)
+        col = np.bincount(key, weights=(S1 @ S2.T).ravel(), minlength=nkey)
+        if lt == zero:
+            # A_{-l} = A_l within this column: keep the half with l_a >= 0
+            half = nkey // 2
+            col[:half] = col[::-1][:half]
+        A[(slice(None),) + tuple(l + m - 1 for l, m in zip(lt, trail))] = col
+        A[(slice(None),) + tuple(-l + m - 1 for l, m in zip(lt, trail))] = col[::-1]
+    return A.reshape(tuple(2 * m - 1 for m in M))
 
 
 def autocorr_fft(c):
@@ -115,3 +161,15 @@ def vstat(A, n, g, terms, alphas):
 def abs_scale(A, n, g, G, alphas):
     """S_abs = n^-2 sum_l |k_l| A_l per entry: scale for near-zero entries."""
     return _chunked_dot(g, A, lambda x: np.abs(gauss.dphi_many(x, G, alphas)), len(alphas)) / float(n) ** 2
+
+
+def vstat_abs(A, n, g, terms, alphas):
+    """n^-2 sum_l |sum_t coef_t D^alpha phi_{S_t}(delta o l)| |A_l| for each alpha:
+    the absolute-value sum that scales the comparison of near-zero entries."""
+    def fn(x):
+        out = None
+        for c, S in terms:
+            v = c * gauss.dphi_many(x, S, alphas)
+            out = v if out is None else out + v
+        return np.abs(out)
+    return _chunked_dot(g, np.abs(A), fn, len(alphas)) / float(n) ** 2

@@ -93,3 +93,20 @@ def objective_binned_parts(A, n, g, H, G):
     var = binned.vstat(A, n, g, [(1.0, 2 * H + 2 * G), (-2.0, H + 2 * G)], zero)[0]
     const = binned.vstat(A, n, g, [(1.0, 2 * G)], zero)[0]
     return first_term(H, n), var, const
+
+
+def objective_binned_scales(A, n, g, H, G):
+    """Absolute-value scales of the binned objective and of each entry of its
+    vech gradient: |closed-form term| + n^-2 sum_l |kernel_l| A_l for the
+    objective and for every Hessian entry, carried through the chain rule
+    dSCV/dL = lower(2 grad_H L) with absolute values.  Used to judge entries
+    that nearly cancel (relative error against this scale)."""
+    d = g["d"]
+    zero = [(0,) * d]
+    s_obj = abs(first_term(H, n)) + binned.vstat_abs(A, n, g, _terms_obj(H, G), zero)[0]
+    alphas2 = multiindex.unique_alphas(d, 2)
+    hv = binned.vstat_abs(A, n, g, _terms_hess(H, G), alphas2)
+    sH = np.abs(first_term_grad(H, n)) + _hess_from_unique(hv, d)
+    L = np.abs(np.linalg.cholesky(H))
+    sL = np.tril(2.0 * sH @ L)
+    return s_obj, np.concatenate([sL[j:, j] for j in range(d)])

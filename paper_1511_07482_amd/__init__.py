@@ -21,12 +21,14 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import FUN_PSI, FUN_SCV_GRAD, FUN_SCV_OBJ, FUN_SCV_OBJGRAD, Grid, KdefftError  # noqa: F401
+from ._lib import (FUN_ETA1, FUN_ETA2, FUN_PSI, FUN_SCV_GRAD, FUN_SCV_OBJ, FUN_SCV_OBJGRAD, Grid,  # noqa: F401
+                   KdefftError)
 
 __all__ = ["Grid", "Dataset", "KdefftError", "grid_plan", "grid_auto", "linbin", "psi", "psi_batch", "scv",
            "scv_adjoint", "scv_plain", "SCV", "unique_tuples", "autotune", "set_row_launch", "library_path",
            "timing_start", "timing_stop", "crit", "crit_adjoint", "pi", "expand_full", "Criterion", "PI",
-           "CRIT_SCV", "CRIT_LSCV", "CRIT_LSCV_EXACT", "CRIT_QR", "fftl_plan", "psi_fftl"]
+           "CRIT_SCV", "CRIT_LSCV", "CRIT_LSCV_EXACT", "CRIT_QR", "fftl_plan", "psi_fftl",
+           "get_row_launch", "row_launch", "lag_layout"]
 
 
 def library_path():
@@ -216,11 +218,15 @@ class Dataset:
 
     @property
     def grid(self) -> Grid:
+        """The grid with its origin and spacing; a device-planned grid is read
+        back once (one stream synchronisation) and kept in the descriptor, so
+        later calls that need it on the host (the plain path) do not wait."""
         if self._grid is None:
             g = Grid()
             _lib.check(_L().kdefft_dataset_grid(C.byref(self.desc), C.byref(g), _stream(self.device)),
                        "kdefft_dataset_grid")
             self._grid = g
+            self.desc.grid = g
         return self._grid
 
     @property
@@ -535,7 +541,39 @@ def lag_layout(N: int, moments: bool = True):
 
 
 def set_row_launch(kind: int, d: int, r: int, N: int, variant: int, grid_blocks: int = 0):
+    """Pin the batched launch of one kernel family and shape (variant -1 drops the pin)."""
     _lib.check(_L().kdefft_set_row_launch(kind, d, r, N, variant, grid_blocks), "kdefft_set_row_launch")
+
+
+def get_row_launch(kind: int, d: int, r: int, N: int):
+    """(variant, grid_blocks) the batched calls of this family and shape use now."""
+    v, gb = C.c_int(), C.c_int()
+    _lib.check(_L().kdefft_get_row_launch(kind, d, r, N, C.byref(v), C.byref(gb)), "kdefft_get_row_launch")
+    return v.value, gb.value
+
+
+class row_launch:
+    """Context manager: pin (variant, grid_blocks) for the given families of
+    one shape, and restore the previous choices on exit."""
+
+    def __init__(self, kinds, d: int, r: int, N: int, variant: int, grid_blocks: int = 0):
+        self.kinds = [kinds] if isinstance(kinds, int) else list(kinds)
+        self.key = (d, r, N)
+        self.launch = (variant, grid_blocks)
+        self.saved = []
+
+    def __enter__(self):
+        d, r, N = self.key
+        self.saved = [(k, get_row_launch(k, d, r, N)) for k in self.kinds]
+        for k in self.kinds:
+            set_row_launch(k, d, r, N, *self.launch)
+        return self
+
+    def __exit__(self, *exc):
+        d, r, N = self.key
+        for k, (v, gb) in self.saved:
+            set_row_launch(k, d, r, N, v, gb)
+        return False
 
 
 def autotune(dataset: Dataset, cache_path: Optional[str] = None) -> str:

@@ -14,7 +14,7 @@ E_ARG, E_NOT_SPD, E_ODD_R, E_OUT_OF_GRID, E_OVERFLOW, E_WORKSPACE, E_HIP, E_UNSU
 OP_GRID_AUTO, OP_PSI_PLAIN, OP_PSI_FUSED, OP_PREPARE, OP_PSI_BATCH, OP_SCV_BATCH, OP_SCV_PLAIN, OP_AUTOTUNE, \
     OP_PSI_FFTL, OP_PREPARE_AUTO = range(1, 11)
 PSI_PLAIN, PSI_FUSED = 0, 1
-FUN_PSI, FUN_SCV_OBJ, FUN_SCV_OBJGRAD, FUN_SCV_GRAD = range(4)
+FUN_PSI, FUN_SCV_OBJ, FUN_SCV_OBJGRAD, FUN_SCV_GRAD, FUN_ETA1, FUN_ETA2 = range(6)
 MAX_BATCH_DS = 64
 MAX_PSI_DS = 32
 MAX_TIMED = 4096
@@ -67,6 +67,8 @@ EXPORTS = {
     "kdefft_scv_plain": (C.c_int, [C.POINTER(Dataset), C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                    C.c_void_p]),
     "kdefft_set_row_launch": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
+    "kdefft_get_row_launch": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int),
+                                        C.POINTER(C.c_int)]),
     "kdefft_lag_layout": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "kdefft_autotune": (C.c_int, [C.POINTER(Dataset), C.c_void_p, C.c_size_t, C.c_char_p, C.c_void_p]),
     "kdefft_crit_batch": (C.c_int, [C.POINTER(Dataset), C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int,

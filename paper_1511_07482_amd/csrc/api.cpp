@@ -305,6 +305,13 @@ void set_launch(int kind, int d, int r, int N, RowLaunch rl) {
     g_launch[LaunchKey{dev, kind, d, r, N, 0}] = rl;
 }
 
+void clear_launch(int kind, int d, int r, int N) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_launch_mu);
+    g_launch.erase(LaunchKey{dev, kind, d, r, N, 0});
+}
+
 // ---------------------------------------------------------------- workspace plans
 struct DsLayout {
     int64_t* counts;
@@ -621,6 +628,31 @@ hipError_t timed_rows(int kind, int d, int r, const RowGeom& geo, const double* 
 }
 
 }  // namespace
+
+// ==================================================================== internal helpers for other units
+namespace kdefft {
+
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
+int scv_batch_ws_need(const kdefft_dataset* ds, int n_ds, const int64_t* off, size_t* need) {
+    int rc = check_batch_ds(ds, n_ds, KDEFFT_MAX_BATCH_DS);
+    if (rc) return rc;
+    if (!off || !need) return fail(KDEFFT_E_ARG, "NULL h_offsets or size output");
+    const int64_t B = off[n_ds];
+    if (B < 1) return fail(KDEFFT_E_ARG, "no candidate bandwidths");
+    if (B > (1LL << 24)) return fail(KDEFFT_E_ARG, "too many candidates in one call");
+    kdefft_grid g = ds[0].grid;   // the shape decides the layout; origin and spacing may be NaN
+    for (int k = 0; k < 4; ++k) {
+        g.lo[k] = 0.0;
+        g.delta[k] = 1.0;
+    }
+    Arena a(nullptr, 0, true);
+    carve_batch(a, g, FUN_SCV_OBJGRAD, 2, B);
+    *need = a.off + 256;
+    return KDEFFT_OK;
+}
+
+}  // namespace kdefft
 
 // ==================================================================== exports
 extern "C" {
@@ -1305,11 +1337,24 @@ int kdefft_lag_layout(int N, int moments, int* run_len, int* runs_per_seg, int* 
 
 int kdefft_set_row_launch(int kind, int d, int r, int N, int variant, int grid_blocks) {
     if (kind < 0 || kind > FUN_ETA2) return fail(KDEFFT_E_ARG, "kind=%d", kind);
+    if (variant == -1) {
+        clear_launch(kind, d, r, N);
+        return KDEFFT_OK;
+    }
     if (variant < 0 || variant >= ROW_VARIANTS) return fail(KDEFFT_E_ARG, "variant=%d", variant);
     if (grid_blocks < -1) return fail(KDEFFT_E_ARG, "grid_blocks=%d", grid_blocks);
     if (rows_per_iter(kind, d, r, N, variant) < 1)
         return fail(KDEFFT_E_UNSUPPORTED, "no compiled row kernel for kind=%d d=%d r=%d N=%d", kind, d, r, N);
     set_launch(kind, d, r, N, RowLaunch{variant, grid_blocks});
+    return KDEFFT_OK;
+}
+
+int kdefft_get_row_launch(int kind, int d, int r, int N, int* variant, int* grid_blocks) {
+    if (kind < 0 || kind > FUN_ETA2) return fail(KDEFFT_E_ARG, "kind=%d", kind);
+    if (!variant || !grid_blocks) return fail(KDEFFT_E_ARG, "NULL output");
+    const RowLaunch rl = launch_for(kind, d, r, N);
+    *variant = rl.variant;
+    *grid_blocks = rl.grid_blocks;
     return KDEFFT_OK;
 }
 

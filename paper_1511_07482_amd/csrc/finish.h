@@ -68,8 +68,10 @@ __device__ __forceinline__ static void chol_inv4(const double* L, double* Ainv) 
 
 // Sum of the partial sums of candidate h, grid g over its chunks, by one
 // wavefront: lane t takes chunks t, t+64, ... in order, then a fixed xor tree.
-// COHERENT: read each value with a device-scope atomic (partial sums stored
-// with device-scope atomics by other blocks of the running launch).
+// COHERENT: the partial sums were stored by other blocks of the running launch
+// (agent-scope atomic stores, ordered before their counter increments by
+// release); each value is read with an agent-scope atomic load after the
+// reading lane's own acquire of the counter.
 template <bool COHERENT = false>
 __device__ static double chunk_sum(const double* __restrict__ partial, int64_t h, int64_t nchunks, int ng, int g) {
     const int lane = threadIdx.x & 63;
@@ -77,10 +79,7 @@ __device__ static double chunk_sum(const double* __restrict__ partial, int64_t h
     for (int64_t c = lane; c < nchunks; c += 64) {
         const double* q = partial + (h * nchunks + c) * ng + g;
         if constexpr (COHERENT) {
-            // read at the point where device-scope atomics are performed
-            // (adding zero to the bit pattern leaves it unchanged)
-            auto* qb = reinterpret_cast<unsigned long long*>(const_cast<double*>(q));
-            s += __longlong_as_double((long long)atomicAdd(qb, 0ULL));
+            s += __hip_atomic_load(const_cast<double*>(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             s += *q;
         }
@@ -148,9 +147,9 @@ __device__ __forceinline__ static void* slot_ptr(double v) {
 }
 
 // Partial sums of one work item (thread 0).  When the launch completes fused,
-// they are written with device-scope atomic exchanges, so the block that
-// finishes the candidate (possibly on another die) reads them with atomics
-// too, and no cache write-back is needed.
+// they are written with agent-scope atomic stores (write-through to the
+// coherence point shared by all dies), and the same thread's release on the
+// candidate's counter (fused_finish) orders them before its increment.
 template <int NG>
 __device__ __forceinline__ static void store_item(const double* __restrict__ p, double* dst, const double* v) {
     if ((int)p[S_FIN_MODE] == 0) {
@@ -158,31 +157,33 @@ __device__ __forceinline__ static void store_item(const double* __restrict__ p, 
         for (int g = 0; g < NG; ++g) dst[g] = v[g];
     } else {
 #pragma unroll
-        for (int g = 0; g < NG; ++g)
-            atomicExch(reinterpret_cast<unsigned long long*>(dst + g),
-                       static_cast<unsigned long long>(__double_as_longlong(v[g])));
+        for (int g = 0; g < NG; ++g) __hip_atomic_store(dst + g, v[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
 // Fused completion of the psi launches, called by every thread of a lag
-// kernel's block after thread 0 stored the item's partial sums (store_item):
-// the first wavefront counts the item for its candidate h (counter set to zero
-// by the setup kernel) once those atomics are performed, and if it was the
-// candidate's last of nchunks items, writes the candidate's psi entries.  The other wavefronts go on at
-// once.  Does nothing when the parameter block asks for no fusion.
+// kernel's block after thread 0 stored the item's partial sums (store_item).
+// Thread 0 counts the item on its candidate h's counter (set to zero by the
+// setup kernel) with an acquire-release read-modify-write at agent scope: the
+// release makes its partial-sum stores visible before the increment, and the
+// increments of all items form one release sequence.  If the item was the
+// candidate's last of nchunks, every lane of the first wavefront takes an
+// acquire load of the counter (it reads the final value, so it synchronizes
+// with every item's release) and the wavefront writes the candidate's psi
+// entries.  The other wavefronts go on at once.  Does nothing when the
+// parameter block asks for no fusion.
 template <int D>
 __device__ __forceinline__ static void fused_finish(const double* __restrict__ p, const double* partial,
                                                     int64_t nchunks, int64_t h) {
     const int mode = (int)p[S_FIN_MODE];
     if (mode == 0 || threadIdx.x >= 64) return;
+    int32_t* cnt = static_cast<int32_t*>(slot_ptr(p[S_FIN_CNT]));
     int last = 0;
-    if (threadIdx.x == 0) {
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the exchanges above have been performed
-        int32_t* cnt = static_cast<int32_t*>(slot_ptr(p[S_FIN_CNT]));
-        last = atomicAdd(cnt + h, 1) == (int)(nchunks - 1);
-    }
+    if (threadIdx.x == 0)
+        last = __hip_atomic_fetch_add(cnt + h, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == (int)(nchunks - 1);
     last = __shfl(last, 0, 64);
     if (!last) return;
+    (void)__hip_atomic_load(cnt + h, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
     const int ng = (int)p[S_FIN_NG];
     double* psi = static_cast<double*>(slot_ptr(p[S_FIN_OUT]));
     double* scal = static_cast<double*>(slot_ptr(p[S_FIN_SCAL]));

@@ -200,4 +200,10 @@ hipError_t launch_pi(const PiArgs& a, const double* psi4, const double* vechL, i
 
 RowGeom make_geom(const kdefft_grid& g, int kind, int r, int64_t ncand, int variant);
 
+// Host helpers of the C-ABI layer shared with other units: record an error
+// (returned code, message for kdefft_last_error_detail), and the workspace
+// bytes kdefft_scv_batch needs for a batch (validates the datasets and offsets).
+int set_error(int code, const char* msg);
+int scv_batch_ws_need(const kdefft_dataset* ds, int n_ds, const int64_t* off, size_t* need);
+
 }  // namespace kdefft

@@ -132,9 +132,12 @@ RowGeom make_geom(const kdefft_grid& g, int kind, int r, int64_t ncand, int vari
 
 hipError_t launch_rows(int kind, int d, int r, const RowGeom& geo, const double* prm, int64_t ncand,
                        double* partial, const RowLaunch& rl, hipStream_t s) {
-    const double2* tw;
-    hipError_t e = twiddles(&tw);
-    if (e != hipSuccess) return e;
+    // only the spectral variants read the twiddle table (set up on first use)
+    const double2* tw = nullptr;
+    if (rl.variant < 3 && kind != FUN_ETA1 && kind != FUN_ETA2) {
+        hipError_t e = twiddles(&tw);
+        if (e != hipSuccess) return e;
+    }
     const int64_t nitems = ncand * geo.nchunks;
     const int N = geo.P[d - 1];
     if (kind == FUN_ETA1 || kind == FUN_ETA2) {

@@ -27,6 +27,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "dev_common.h"
 #include "dev_kernels.h"
 #include "finish.h"
@@ -520,9 +522,21 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
 #pragma unroll
             for (int i = 0; i < D; ++i) dz[k][i] = dl * P[i * D + D - 1];
             hpl[k] = 0.5 * dl * dl * P[(D - 1) * D + D - 1];
-            sig[k] = exp(-2.0 * hpl[k]);
             lcut[k] = -667.74967696827317 - log(f.cn(k));   // c e^x < 1e-290 below
         }
+        // The ratio update rho <- rho sigma, sigma = exp(-2 hpl), compounds the
+        // representation error of sigma t(t-1)/2 times by lag t of a walk, the
+        // same way for every run.  When every sigma is close to 1 (wide kernels,
+        // whose runs stay near their start value), sig holds sigma - 1 and the
+        // update is rho + rho (sigma - 1), one FMA, so the compounded error is
+        // that of the small number sigma - 1.  Otherwise (sigma < 1/2: values
+        // fall by half a decade per lag or faster, and only the first few lags
+        // of a walk matter) sig holds sigma itself.
+        bool near1 = true;
+#pragma unroll
+        for (int k = 0; k < NGS; ++k) near1 = near1 && 2.0 * hpl[k] < 0.69314718055994531;
+#pragma unroll
+        for (int k = 0; k < NGS; ++k) sig[k] = near1 ? expm1(-2.0 * hpl[k]) : exp(-2.0 * hpl[k]);
         double acc[NG];
 #pragma unroll
         for (int g = 0; g < NG; ++g) acc[g] = 0.0;
@@ -681,20 +695,31 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
                     double m[NGS][3];
 #pragma unroll
                     for (int k = 0; k < NGS; ++k) m[k][0] = m[k][1] = m[k][2] = 0.0;
+                    // one walk of the run per regime of sig (item-uniform branch)
+                    auto walk = [&](auto near1_tag) {
+                        constexpr bool NEAR1 = decltype(near1_tag)::value;
 #pragma unroll
-                    for (int t = 0; t < RL; ++t) {
+                        for (int t = 0; t < RL; ++t) {
 #pragma unroll
-                        for (int k = 0; k < NGS; ++k) {
-                            const double w = ev[k] * av[t];
-                            m[k][0] += w;
-                            if constexpr (NM > 1) {
-                                m[k][1] += (double)t * w;
-                                m[k][2] += (double)(t * t) * w;
+                            for (int k = 0; k < NGS; ++k) {
+                                const double w = ev[k] * av[t];
+                                m[k][0] += w;
+                                if constexpr (NM > 1) {
+                                    m[k][1] += (double)t * w;
+                                    m[k][2] += (double)(t * t) * w;
+                                }
+                                ev[k] *= rho[k];
+                                if constexpr (NEAR1)
+                                    rho[k] = fma(rho[k], sig[k], rho[k]);
+                                else
+                                    rho[k] *= sig[k];
                             }
-                            ev[k] *= rho[k];
-                            rho[k] *= sig[k];
                         }
-                    }
+                    };
+                    if (near1)
+                        walk(std::true_type{});
+                    else
+                        walk(std::false_type{});
 #pragma unroll
                     for (int k = 0; k < NGS; ++k)
                         if (SCALED && scl[k]) {

@@ -53,11 +53,12 @@ def oracle_counts(X, G, M, pad=4.0):
 
 
 def oracle_autocorr(c, direct_limit=70_000):
-    """Direct shifted-slice autocorrelation when affordable, else numpy.fft
-    (pinned equal to the direct form at small sizes)."""
+    """The oracle's FFT-free autocorrelation of the counts: shifted-slice dot
+    products when affordable, else slab products summed by lag (pinned equal
+    to the shifted-slice form)."""
     if c.size <= direct_limit:
         return binned.autocorr_direct(c)
-    return binned.autocorr_fft(c)
+    return binned.autocorr_gemm(c)
 
 
 def assert_psi_close(got, want, scale_abs, rtol=RTOL_PSI, what=""):
@@ -69,3 +70,23 @@ def assert_psi_close(got, want, scale_abs, rtol=RTOL_PSI, what=""):
         ref = abs(b) if abs(b) >= 1e-3 * s else s
         err = abs(a - b) / ref
         assert err <= rtol, f"{what} entry {k}: got {a!r} want {b!r} rel err {err:.3e}"
+
+
+def z16_errors(got, want, scale):
+    """Per-entry relative errors under the near-zero rule: |a - b| / |b|, or
+    |a - b| / S when |b| < 1e-3 S (S the entry's absolute-value scale)."""
+    want = np.asarray(want, dtype=np.float64)
+    got = np.asarray(got, dtype=np.float64).reshape(want.shape).ravel()
+    scale = np.broadcast_to(np.asarray(scale, dtype=np.float64), want.shape).ravel()
+    want = want.ravel()
+    ref = np.where(np.abs(want) >= 1e-3 * scale, np.abs(want), scale)
+    return np.abs(got - want) / ref
+
+
+def assert_z16(got, want, scale, rtol=1e-11, what=""):
+    """Every entry within rtol under the near-zero rule (z16_errors)."""
+    err = z16_errors(got, want, scale)
+    k = int(np.argmax(err))
+    log(f"  {what}: worst entry {k} rel err {err[k]:.2e} (bar {rtol:.0e})")
+    assert err[k] <= rtol, (f"{what} entry {k}: got {np.ravel(got)[k]!r} want {np.ravel(want)[k]!r} "
+                            f"rel err {err[k]:.3e}")

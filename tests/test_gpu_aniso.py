@@ -95,3 +95,28 @@ def test_criteria_anisotropic(kf, gpu, name):
                what=f"lscv_2 {name} b={b}")
         _close(q2[b], eta.qr_binned(A, n, g_o, H[b], 2),
                eta.vstat_binned(A, n, g_o, [(1.0, H[b])], 2, absval=True), what=f"Q_2 {name} b={b}")
+
+
+@pytest.mark.parametrize("launch", [(3, 0), (3, -1), (4, 0), (4, -1)])
+def test_long_last_axis_all_launches(kf, gpu, launch):
+    """d2_long_last (last-axis P = 256: 16-lag runs walked in 32-lag segments,
+    several runs per segment) with 256 candidates in each lag-domain launch:
+    objective and every gradient entry per entry (near-zero rule, 1e-11)."""
+    from _gpu_util import assert_z16
+    name = "d2_long_last"
+    d, M, X, Gp, _ = _data(name)
+    n = X.shape[0]
+    H = synth.random_H_2d(256, np.random.default_rng(65))
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
+    N = ds.grid.P[d - 1]
+    assert N == 256
+    g_o, A = _oracle(X, Gp, M)
+    v = torch.from_numpy(synth.vech_chol(H)).to(gpu)
+    log(f"[aniso] {name} 256 candidates, launch {launch}")
+    with kf.row_launch((kf.FUN_SCV_OBJ, kf.FUN_SCV_OBJGRAD, kf.FUN_SCV_GRAD), d, 2, N, *launch):
+        obj, gr = kf.scv([ds], v)
+    obj, gr = obj.cpu().numpy(), gr.cpu().numpy()
+    want = [scv.objective_binned(A, n, g_o, H[b], Gp) for b in range(256)]
+    scales = [scv.objective_binned_scales(A, n, g_o, H[b], Gp) for b in range(256)]
+    assert_z16(obj, [o for o, _ in want], [s for s, _ in scales], what=f"objective {launch}")
+    assert_z16(gr, np.array([g for _, g in want]), np.array([s for _, s in scales]), what=f"gradient {launch}")

@@ -177,17 +177,14 @@ def test_launch_variants_agree(kf, gpu):
     v = torch.from_numpy(_vech(H)).to(gpu)
     N = ds.grid.P[d - 1]
     ref = None
-    try:
-        for var in range(4):
-            for gb in (0, -1, 7):
-                kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, var, gb)
+    for var in range(5):
+        for gb in (0, -1, 7):
+            with kf.row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, var, gb):
                 obj, g = kf.scv([ds], v)
-                cur = np.concatenate([obj.cpu().numpy(), g.cpu().numpy().ravel()])
-                if ref is None:
-                    ref = cur
-                np.testing.assert_allclose(cur, ref, rtol=1e-12, atol=1e-15)
-    finally:
-        kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, 0, 0)
+            cur = np.concatenate([obj.cpu().numpy(), g.cpu().numpy().ravel()])
+            if ref is None:
+                ref = cur
+            np.testing.assert_allclose(cur, ref, rtol=1e-12, atol=1e-15)
 
 
 @pytest.mark.parametrize("d,M", [(1, 2), (1, 3), (2, 2), (2, 3), (3, 2), (2, 5)])
@@ -201,13 +198,10 @@ def test_tiny_grids(kf, gpu, d, M):
     v = torch.from_numpy(_vech(H)).to(gpu)
     N = ds.grid.P[d - 1]
     log(f"[scv-tiny] d={d} M={M} P={N}")
-    try:
-        for var in (3, 4):
-            kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, var, 0)
+    for var in (3, 4):
+        with kf.row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, var, 0):
             obj, g = kf.scv([ds], v)
-            _check_against_oracle(kf, f"tiny{d}_{M}", d, X, Gp, M, H, obj.cpu().numpy(), g.cpu().numpy())
-    finally:
-        kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, 4, 0)
+        _check_against_oracle(kf, f"tiny{d}_{M}", d, X, Gp, M, H, obj.cpu().numpy(), g.cpu().numpy())
 
 
 @pytest.mark.parametrize("d,M", [(2, 3), (2, 5), (3, 4), (1, 6)])
@@ -240,13 +234,10 @@ def test_extreme_candidates(kf, gpu, scale):
     v = torch.from_numpy(_vech(Hs)).to(gpu)
     N = ds.grid.P[d - 1]
     log(f"[scv-extreme] H x {scale}")
-    try:
-        for var in (3, 4):
-            kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, var, 0)
+    for var in (3, 4):
+        with kf.row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, var, 0):
             obj, g = kf.scv([ds], v)
-            _check_against_oracle(kf, "d2", d, X, Gp, M, Hs, obj.cpu().numpy(), g.cpu().numpy())
-    finally:
-        kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, 4, 0)
+        _check_against_oracle(kf, "d2", d, X, Gp, M, Hs, obj.cpu().numpy(), g.cpu().numpy())
 
 
 def test_singular_candidate_and_determinism(kf, gpu):
@@ -331,16 +322,11 @@ def test_every_variant_vs_oracle(kf, gpu, name, variant):
     N = ds.grid.P[d - 1]
     v = torch.from_numpy(_vech(H)).to(gpu)
     kinds = (kf.FUN_SCV_OBJ, kf.FUN_SCV_OBJGRAD, kf.FUN_SCV_GRAD)
-    try:
-        for k in kinds:
-            kf.set_row_launch(k, d, 2, N, variant, 0)
+    with kf.row_launch(kinds, d, 2, N, variant, 0):
         obj, g = kf.scv([ds], v)
         obj_only = kf.scv([ds], v, grad=False)
         w = torch.ones(H.shape[0], dtype=torch.float64, device=gpu)
         adj = kf.scv_adjoint([ds], v, w)
-    finally:
-        for k in kinds:
-            kf.set_row_launch(k, d, 2, N, 4, 0)
     obj, g = obj.cpu().numpy(), g.cpu().numpy()
     _check_against_oracle(kf, name, d, X, Gp, M, H, obj, g)
     np.testing.assert_allclose(obj_only.cpu().numpy(), obj, rtol=1e-13)
@@ -355,11 +341,8 @@ def test_psi_batch_variants(kf, gpu, variant):
     Gpsi = spd(d, 952, 0.08)
     ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
     N = ds.grid.P[d - 1]
-    try:
-        kf.set_row_launch(kf.FUN_PSI, d, r, N, variant, 0)
+    with kf.row_launch(kf.FUN_PSI, d, r, N, variant, 0):
         out = kf.psi_batch([ds], [Gpsi], r).cpu().numpy()[0]
-    finally:
-        kf.set_row_launch(kf.FUN_PSI, d, r, N, 3, 0)
     g_o = grid.plan_auto(X, Gp, [M] * d)
     co, _ = linbin.linbin(X, g_o)
     A = binned.autocorr_direct(linbin.counts_to_real(co))
@@ -379,11 +362,8 @@ def test_narrow_kernels_recurrence_fallback(kf, gpu, variant):
     ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
     v = torch.from_numpy(_vech(H)).to(gpu)
     N = ds.grid.P[d - 1]
-    try:
-        kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, variant, 0)
+    with kf.row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, variant, 0):
         obj, g = kf.scv([ds], v)
-    finally:
-        kf.set_row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, 4, 0)
     _check_against_oracle(kf, "narrow", d, X, Gp, M, H, obj.cpu().numpy(), g.cpu().numpy())
 
 

@@ -2,8 +2,8 @@
 
 * literal Eq. (14): the quadruple sum over node pairs at tiny grids equals the
   lag-domain form;
-* autocorrelation by shifted slices equals a brute-force double loop and the
-  numpy.fft route;
+* autocorrelation by shifted slices and by slab products equals a
+  brute-force double loop and the numpy.fft route;
 * data on grid nodes: binned psi equals the unbinned psi of oracle.direct;
 * the paper's zero-padded layout (P = 2^ceil(log2(3M-1))) and the circular
   P = 2M layout both equal the lag-domain form;
@@ -54,7 +54,7 @@ def test_literal_eq14(d, M, r):
     np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-14 * np.abs(want).max())
 
 
-@pytest.mark.parametrize("shape", [(7,), (5, 6), (3, 4, 5)])
+@pytest.mark.parametrize("shape", [(7,), (5, 6), (3, 4, 5), (3, 2, 4, 3)])
 def test_autocorr_routes(shape):
     rng = np.random.default_rng(2)
     c = rng.random(shape)
@@ -67,7 +67,23 @@ def test_autocorr_routes(shape):
             brute[tuple(l + m - 1 for l, m in zip(lag, shape))] += c[i] * c[j]
     np.testing.assert_allclose(A, brute, rtol=1e-13)
     np.testing.assert_allclose(binned.autocorr_fft(c), brute, rtol=1e-12, atol=1e-12 * brute.max())
+    np.testing.assert_allclose(binned.autocorr_gemm(c), brute, rtol=1e-13)
     assert d == A.ndim
+
+
+@pytest.mark.parametrize("shape", [(9, 5), (6, 7, 5), (5, 4, 6, 3), (4, 4, 4, 4)])
+def test_autocorr_gemm_matches_slices(shape):
+    """The slab-product route (used for the large grids of the GPU parity
+    tests) equals the shifted-slice definition on sparse ragged grids, and is
+    exactly centrally symmetric (A_{-l} = A_l bit for bit)."""
+    rng = np.random.default_rng(sum(shape))
+    c = rng.random(shape) * (rng.random(shape) < 0.6)
+    A = binned.autocorr_direct(c)
+    B = binned.autocorr_gemm(c)
+    np.testing.assert_allclose(B, A, rtol=1e-13, atol=1e-15 * A.max())
+    assert np.array_equal(B, B[tuple(slice(None, None, -1) for _ in shape)])
+    # zero lag: the sum of squares
+    assert B[tuple(m - 1 for m in shape)] == pytest.approx(float(np.sum(c * c)), rel=1e-14)
 
 
 @pytest.mark.parametrize("d,r", [(1, 6), (2, 0), (2, 4), (3, 2)])

@@ -104,3 +104,26 @@ def test_constant_term_and_on_nodes():
     od, gd = scv.objective_direct(X, H1, G)
     assert ob == pytest.approx(od, rel=1e-13)
     np.testing.assert_allclose(gb, gd, rtol=1e-12)
+
+
+def test_abs_scales_bound_the_values():
+    """The absolute-value scales that judge near-cancelling entries: for one
+    positive kernel (psi_0) the scale equals the value; for the SCV objective
+    and every gradient entry it bounds the value (triangle inequality) and is
+    strictly larger where the Hessian kernels change sign."""
+    rng = np.random.default_rng(31)
+    d, n, M = 2, 300, 12
+    X = rng.standard_normal((n, d)) @ np.array([[1.0, 0.0], [0.5, 0.8]])
+    G = np.array([[0.06, 0.02], [0.02, 0.09]])
+    g = grid.plan_auto(X, G, [M, M])
+    counts, _ = linbin.linbin(X, g)
+    A = binned.autocorr_direct(linbin.counts_to_real(counts))
+    zero = [(0, 0)]
+    v = binned.vstat(A, n, g, [(1.0, G)], zero)
+    s = binned.vstat_abs(A, n, g, [(1.0, G)], zero)
+    assert s[0] == pytest.approx(v[0], rel=1e-14)
+    H = np.array([[0.2, -0.05], [-0.05, 0.1]])
+    obj, gr = scv.objective_binned(A, n, g, H, G)
+    s_obj, s_gr = scv.objective_binned_scales(A, n, g, H, G)
+    assert s_obj >= abs(obj)
+    assert np.all(s_gr >= np.abs(gr)) and np.all(s_gr > np.abs(gr) * (1 + 1e-6))
