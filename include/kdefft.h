@@ -395,6 +395,23 @@ int kdefft_timing_stop(float* ms_out, int32_t* tag_out, int cap, int* count_out)
 int kdefft_autotune(const kdefft_dataset* ds_host, void* ws, size_t ws_bytes,
                     const char* cache_path, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the batched
+ * SCV objective (+ gradient) of kdefft_scv_batch with the same arguments,
+ * kernels and results, but no workspace argument.  Its workspace is a fixed
+ * device array of KDEFFT_NOALLOC_BYTES bytes inside the library; each GPU the
+ * library runs on holds one for the rest of the process.  The call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine); a batch whose
+ * workspace (kdefft_ws_bytes, KDEFFT_OP_SCV_BATCH) exceeds the array is
+ * rejected with KDEFFT_E_WORKSPACE before anything is launched.  Every call on
+ * one GPU shares that GPU's array, which keeps the last call's contents
+ * (nothing in it needs to start at zero): calls that overlap on one GPU --
+ * on different streams, or from several threads -- race and must be
+ * serialized by the caller. */
+#define KDEFFT_NOALLOC_BYTES (16u << 20)
+int kdefft_scv_batch_noalloc(const kdefft_dataset* ds_host, int n_ds, const int64_t* h_offsets_host,
+                             const double* vechL, double* obj, double* grad, int32_t* status, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,7 +28,7 @@ __all__ = ["Grid", "Dataset", "KdefftError", "grid_plan", "grid_auto", "linbin",
            "scv_adjoint", "scv_plain", "SCV", "unique_tuples", "autotune", "set_row_launch", "library_path",
            "timing_start", "timing_stop", "crit", "crit_adjoint", "pi", "expand_full", "Criterion", "PI",
            "CRIT_SCV", "CRIT_LSCV", "CRIT_LSCV_EXACT", "CRIT_QR", "fftl_plan", "psi_fftl",
-           "get_row_launch", "row_launch", "lag_layout"]
+           "get_row_launch", "row_launch", "lag_layout", "scv_batch_noalloc"]
 
 
 def library_path():
@@ -409,6 +409,22 @@ def scv(datasets: Sequence[Dataset], vechL: torch.Tensor, per_ds=None, grad: boo
     if status:
         return obj, g, st
     return (obj, g) if grad else obj
+
+
+def scv_batch_noalloc(datasets: Sequence[Dataset], vechL: torch.Tensor, obj: torch.Tensor,
+                      grad: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None, per_ds=None):
+    """kdefft_scv_batch_noalloc: the batched SCV objective (and gradient) into the
+    caller's obj [B] (and grad [B, q], status [B]) with the library's fixed
+    device scratch as workspace; allocates nothing (up to 64 datasets)."""
+    datasets = list(datasets)
+    if len(datasets) > _lib.MAX_BATCH_DS:
+        raise ValueError(f"at most {_lib.MAX_BATCH_DS} datasets per call")
+    dev = datasets[0].device
+    per_ds = _split_counts(datasets, vechL, per_ds)
+    off = _offsets(datasets, per_ds)
+    arr = _ds_array(datasets)
+    _lib.check(_L().kdefft_scv_batch_noalloc(arr, len(datasets), off.ctypes.data, _ptr(vechL), _ptr(obj),
+                                             _ptr(grad), _ptr(status), _stream(dev)), "kdefft_scv_batch_noalloc")
 
 
 def scv_adjoint(datasets: Sequence[Dataset], vechL: torch.Tensor, grad_out: torch.Tensor, per_ds=None):

@@ -18,6 +18,7 @@ FUN_PSI, FUN_SCV_OBJ, FUN_SCV_OBJGRAD, FUN_SCV_GRAD, FUN_ETA1, FUN_ETA2 = range(
 MAX_BATCH_DS = 64
 MAX_PSI_DS = 32
 MAX_TIMED = 4096
+NOALLOC_BYTES = 16 << 20
 
 
 class Grid(C.Structure):
@@ -81,6 +82,8 @@ EXPORTS = {
     "kdefft_fftl_plan": (C.c_int, [C.POINTER(Grid), C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
     "kdefft_psi_fftl": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(Grid), C.c_void_p, C.c_int, C.c_double,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "kdefft_scv_batch_noalloc": (C.c_int, [C.POINTER(Dataset), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_void_p, C.c_void_p]),
     "kdefft_timing_start": (C.c_int, [C.c_int]),
     "kdefft_timing_stop": (C.c_int, [C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int)]),
 }
