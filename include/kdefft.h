@@ -335,7 +335,7 @@ int kdefft_scv_plain(const kdefft_dataset* ds_host, const double* H_host, double
  * 1 SCV objective, 2 SCV objective+gradient, 3 SCV gradient, 4 Q_r, 5 LSCV_r
  * for r > 0), dimension d, order r (2 for the SCV families) and last-axis
  * length N for the rest of the process, for the psi / SCV / Q_r calls (LSCV
- * keeps its own choice): variant in [0, 5): 0, 1, 2 run the per-candidate
+ * keeps its own choice): variant in [0, 7): 0, 1, 2 run the per-candidate
  * last-axis FFTs in LDS (0: one radix-8 butterfly per lane per stage, radix-8
  * first; 1: twice the rows per wavefront; 2: radix-4 first); grid_blocks =
  * persistent grid size, 0 = resident blocks per CU x CUs, -1 = one block per
@@ -345,6 +345,11 @@ int kdefft_scv_plain(const kdefft_dataset* ds_host, const double* H_host, double
  * lags that start below 1e-290 and rise are evaluated lag by lag (3) or
  * walked with values scaled by e^600 (4, the untuned default); the psi and eta
  * families treat 3 and 4 alike and have no spectral variants for eta.
+ * Variants 5 and 6 are 3 and 4 with the work compacted: each row's lags whose
+ * Gaussians all stay below 1e-30 of their peak are bounded analytically and
+ * skipped, and only the remaining runs are dealt to the threads (the dropped
+ * terms are far below float64 rounding of the result; the psi and eta
+ * families treat 5 and 6 as 3).
  * variant = -1 drops the pinned (or tuned) choice of that key, so the untuned
  * default applies again.  Used by kdefft_autotune and by tests that cover
  * every variant.  Host only. */

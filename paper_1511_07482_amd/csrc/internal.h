@@ -184,7 +184,9 @@ hipError_t launch_rows(int kind, int d, int r, const RowGeom& geo, const double*
 int rows_per_iter(int kind, int d, int r, int N, int variant);
 // compiled lag-kernel layout for last-axis length N (0 = unsupported N)
 int lag_layout(int N, int moments, int* run_len, int* runs_per_seg, int* rows_per_pass);
-constexpr int ROW_VARIANTS = 5;   // 0-2: spectral (per-candidate FFT), 3, 4: lag domain (4: scaled walk)
+// 0-2: spectral (per-candidate FFT); 3, 4: lag domain (4: scaled walk of rising
+// runs); 5, 6: as 3, 4 with only the live runs of each row dealt to the threads
+constexpr int ROW_VARIANTS = 7;
 hipError_t launch_scv_setup(const double* vechL, const ScvBatchArgs& a, int64_t ncand, double* prm,
                             int32_t* status, hipStream_t s);
 hipError_t launch_psi_setup(const PsiBatchArgs& a, double* prm, hipStream_t s);

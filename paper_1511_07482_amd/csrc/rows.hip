@@ -103,6 +103,20 @@ int rows_per_iter(int kind, int d, int r, int N, int variant) {
     }
 }
 
+// Resident blocks of the compacted lag kernels on the current device: their
+// launch bounds ask for 3 blocks of 256 threads per CU at d <= 2, 2 above.
+static int compact_slots(int d) {
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (cus[dev] <= 0) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1) c = 256;
+        cus[dev] = c;
+    }
+    return cus[dev] * (d <= 2 ? 3 : 2);
+}
+
 RowGeom make_geom(const kdefft_grid& g, int kind, int r, int64_t ncand, int variant) {
     RowGeom geo{};
     geo.d = g.d;
@@ -119,6 +133,24 @@ RowGeom make_geom(const kdefft_grid& g, int kind, int r, int64_t ncand, int vari
     geo.Q = g.P[g.d - 1] / 2 + 1;
     int ri = rows_per_iter(kind, g.d, r, g.P[g.d - 1], variant);
     if (ri < 1) ri = 1;
+    const bool mom = kind == FUN_SCV_OBJ || kind == FUN_SCV_OBJGRAD || kind == FUN_SCV_GRAD;
+    if (variant >= 5 && mom) {
+        // compacted walk: the live runs of a whole item are dealt over the
+        // block at once, so items are sized to the resident blocks instead:
+        // the fewest whole rounds of items over the resident slots that keep an
+        // item at most 4096 rows, the items split evenly over the candidates
+        const int64_t slots = (int64_t)compact_slots(g.d);
+        const int64_t maxrows = 4096;
+        int64_t rounds = (nrows * ncand + slots * maxrows - 1) / (slots * maxrows);
+        if (rounds < 1) rounds = 1;
+        int64_t per = slots * rounds / ncand;
+        if (per < 1) per = 1;
+        if (per > nrows) per = nrows;
+        const int64_t chunk = (nrows + per - 1) / per;
+        geo.chunk = chunk;
+        geo.nchunks = (nrows + chunk - 1) / chunk;
+        return geo;
+    }
     // lag kernel: larger items amortise the per-item set-up and block reduction
     const int64_t target = variant >= 3 ? 2048 : 8192;
     int64_t iters = (nrows * ncand + (int64_t)ri * target - 1) / ((int64_t)ri * target);

@@ -22,8 +22,10 @@ hipError_t rows_var(int var, const double* prm, RowGeom geo, int64_t nitems, dou
             case 0: return run_rows_t<D, N, Fun, 0>(prm, geo, nitems, partial, grid_blocks, tw, s);
             case 1: return run_rows_t<D, N, Fun, 1>(prm, geo, nitems, partial, grid_blocks, tw, s);
             case 2: return run_rows_t<D, N, Fun, 2>(prm, geo, nitems, partial, grid_blocks, tw, s);
-            case 3: return run_lag_t<D, N, Fun>(prm, geo, nitems, partial, grid_blocks, s, false);
-            case 4: return run_lag_t<D, N, Fun>(prm, geo, nitems, partial, grid_blocks, s, true);
+            case 3:
+            case 4:
+            case 5:
+            case 6: return run_lag_t<D, N, Fun>(prm, geo, nitems, partial, grid_blocks, s, var);
             default: return hipErrorInvalidValue;
         }
     }

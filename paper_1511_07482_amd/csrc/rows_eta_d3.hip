@@ -8,13 +8,13 @@ namespace kdefft {
 template <class Fun>
 static hipError_t lag_3(int N, const double* prm, RowGeom geo, int64_t nitems, double* partial, int gb, hipStream_t s) {
     switch (N) {
-        case 4: return run_lag_t<3, 4, Fun>(prm, geo, nitems, partial, gb, s, false);
-        case 8: return run_lag_t<3, 8, Fun>(prm, geo, nitems, partial, gb, s, false);
-        case 16: return run_lag_t<3, 16, Fun>(prm, geo, nitems, partial, gb, s, false);
-        case 32: return run_lag_t<3, 32, Fun>(prm, geo, nitems, partial, gb, s, false);
-        case 64: return run_lag_t<3, 64, Fun>(prm, geo, nitems, partial, gb, s, false);
-        case 128: return run_lag_t<3, 128, Fun>(prm, geo, nitems, partial, gb, s, false);
-        case 256: return run_lag_t<3, 256, Fun>(prm, geo, nitems, partial, gb, s, false);
+        case 4: return run_lag_t<3, 4, Fun>(prm, geo, nitems, partial, gb, s, 3);
+        case 8: return run_lag_t<3, 8, Fun>(prm, geo, nitems, partial, gb, s, 3);
+        case 16: return run_lag_t<3, 16, Fun>(prm, geo, nitems, partial, gb, s, 3);
+        case 32: return run_lag_t<3, 32, Fun>(prm, geo, nitems, partial, gb, s, 3);
+        case 64: return run_lag_t<3, 64, Fun>(prm, geo, nitems, partial, gb, s, 3);
+        case 128: return run_lag_t<3, 128, Fun>(prm, geo, nitems, partial, gb, s, 3);
+        case 256: return run_lag_t<3, 256, Fun>(prm, geo, nitems, partial, gb, s, 3);
         default: return hipErrorInvalidValue;
     }
 }

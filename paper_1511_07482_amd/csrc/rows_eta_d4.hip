@@ -8,12 +8,12 @@ namespace kdefft {
 template <class Fun>
 static hipError_t lag_4(int N, const double* prm, RowGeom geo, int64_t nitems, double* partial, int gb, hipStream_t s) {
     switch (N) {
-        case 4: return run_lag_t<4, 4, Fun>(prm, geo, nitems, partial, gb, s, false);
-        case 8: return run_lag_t<4, 8, Fun>(prm, geo, nitems, partial, gb, s, false);
-        case 16: return run_lag_t<4, 16, Fun>(prm, geo, nitems, partial, gb, s, false);
-        case 32: return run_lag_t<4, 32, Fun>(prm, geo, nitems, partial, gb, s, false);
-        case 64: return run_lag_t<4, 64, Fun>(prm, geo, nitems, partial, gb, s, false);
-        case 128: return run_lag_t<4, 128, Fun>(prm, geo, nitems, partial, gb, s, false);
+        case 4: return run_lag_t<4, 4, Fun>(prm, geo, nitems, partial, gb, s, 3);
+        case 8: return run_lag_t<4, 8, Fun>(prm, geo, nitems, partial, gb, s, 3);
+        case 16: return run_lag_t<4, 16, Fun>(prm, geo, nitems, partial, gb, s, 3);
+        case 32: return run_lag_t<4, 32, Fun>(prm, geo, nitems, partial, gb, s, 3);
+        case 64: return run_lag_t<4, 64, Fun>(prm, geo, nitems, partial, gb, s, 3);
+        case 128: return run_lag_t<4, 128, Fun>(prm, geo, nitems, partial, gb, s, 3);
         default: return hipErrorInvalidValue;
     }
 }

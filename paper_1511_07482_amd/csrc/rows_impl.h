@@ -475,6 +475,111 @@ constexpr int mom_run_of() { return N >= 256 ? 16 : LAG_RUN; }
 template <int N, int RL>
 constexpr int mom_seg_of() { return N >= 256 && RL <= 32 && (N / 2) % 32 == 0 ? 32 / RL : 1; }
 
+// Relative cut of the compacted lag walk: a run is walked only if some of its
+// lags x has c_k exp(-x^T S_k^{-1} x / 2) >= 1e-30 c_k for some Gaussian k of
+// the family (log 1e-30 below).  The dropped values are each below 1e-30 of
+// their Gaussian's peak, so all of them together (times the moment-form
+// polynomial factors, at most a few hundred times P) stay below 1e-30 x (number
+// of lags) x (largest autocorrelation) x 10^3 -- more than ten orders of
+// magnitude under float64 rounding of the lag-0 term alone.
+constexpr double LOG_REL_CUT = -69.077552789821368;
+
+// Compacted dealing of an item's rows [rbeg, rend): the rows are taken NT at a
+// time; thread t bounds row t's live lag interval (for every Gaussian of the
+// family the lags l with exponent above LOG_REL_CUT, an interval because the
+// exponent is a concave quadratic in l along the row; the hull over the
+// Gaussians, widened by one lag each side), turns it into runs of RL positions
+// on each side of the circular row and segments of up to SEG runs; a block
+// scan numbers the segments, and the threads take segments t, t + NT, ... of
+// that list (rows in order, runs in order within a row, so neighbouring lanes
+// read neighbouring blocks of the autocorrelation).  seg_walk(ri, j, nruns)
+// walks one segment.
+template <int D, int N, int RL, int SEG, int NT, class Fun, class Walk>
+__device__ __forceinline__ void live_segments(const Fun& f, const RowGeom& geo, int64_t rbeg, int64_t rend,
+                                              const double* delta, Walk&& seg_walk) {
+    constexpr int NGS = Fun::NGAUSS;
+    constexpr int NW = NT / 64;
+    constexpr int NRUN = N / RL;                               // runs per row
+    constexpr int UPR = 2 * ((NRUN / 2 + SEG - 1) / SEG);     // segments per row, at most (both sides)
+    constexpr int RB = NT < 4096 / UPR ? NT : 4096 / UPR;      // rows per pass: at most 4096 segments
+    constexpr int MAXU = RB * UPR;
+    static_assert(NRUN <= 256 && NT <= 256 && RB >= 1, "unit word layout");
+    __shared__ RowInfo s_ri[RB];
+    __shared__ uint32_t s_unit[MAXU];   // row << 16 | first run << 8 | runs
+    __shared__ int s_wsum[NW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int M_last = geo.M[D - 1];
+    const double dl = delta[D - 1];
+    for (int64_t rb = rbeg; rb < rend; rb += RB) {
+        const int nb = rend - rb < RB ? (int)(rend - rb) : RB;
+        int pf = 0, pn = 0, nf = 0, nn = 0;
+        if ((int)threadIdx.x < nb) {
+            const RowInfo ri = row_info<D>(rb + threadIdx.x, rend, geo, delta, nullptr);
+            double la = INFINITY, lb = -INFINITY;
+#pragma unroll
+            for (int k = 0; k < NGS; ++k) {
+                const double* P = f.Pm(k);
+                double b = 0.0, ql = 0.0;
+#pragma unroll
+                for (int i = 0; i < D - 1; ++i) {
+                    b += P[(D - 1) * D + i] * ri.x[i];
+#pragma unroll
+                    for (int jj = 0; jj < D - 1; ++jj) ql += ri.x[i] * P[i * D + jj] * ri.x[jj];
+                }
+                const double pll = P[(D - 1) * D + D - 1];
+                const double emax = -0.5 * (ql - b * b / pll);   // largest exponent along the row
+                if (emax > LOG_REL_CUT) {
+                    const double ls = -b / (dl * pll);
+                    const double w = sqrt(2.0 * (emax - LOG_REL_CUT) / (dl * dl * pll));
+                    la = fmin(la, ls - w);
+                    lb = fmax(lb, ls + w);
+                }
+            }
+            const double lim = (double)(M_last - 1);
+            const double fa = fmax(floor(la) - 1.0, -lim), fb = fmin(ceil(lb) + 1.0, lim);
+            if (fa <= fb) {   // false for an empty (or NaN) interval
+                const int ia = (int)fa, ib = (int)fb;
+                if (ib >= 0) {
+                    pf = (ia > 0 ? ia : 0) / RL;
+                    pn = ib / RL - pf + 1;
+                }
+                if (ia <= -1) {
+                    nf = (ia + N) / RL;
+                    nn = ((ib < -1 ? ib : -1) + N) / RL - nf + 1;
+                }
+            }
+            s_ri[threadIdx.x] = ri;
+        }
+        const int units = (pn + SEG - 1) / SEG + (nn + SEG - 1) / SEG;
+        // exclusive block scan of the segment counts, then each row writes its
+        // segments into the block's list
+        int x = units;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) s_wsum[wave] = x;
+        __syncthreads();
+        int pre = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            pre += w < wave ? s_wsum[w] : 0;
+            total += s_wsum[w];
+        }
+        int o = pre + x - units;
+        const uint32_t rw = (uint32_t)threadIdx.x << 16;
+        for (int a = 0; a < pn; a += SEG, ++o) s_unit[o] = rw | (uint32_t)(pf + a) << 8 | (uint32_t)(pn - a < SEG ? pn - a : SEG);
+        for (int a = 0; a < nn; a += SEG, ++o) s_unit[o] = rw | (uint32_t)(nf + a) << 8 | (uint32_t)(nn - a < SEG ? nn - a : SEG);
+        __syncthreads();
+        for (int k = threadIdx.x; k < total; k += NT) {
+            const uint32_t u = s_unit[k];
+            seg_walk(s_ri[u >> 16], (int)((u >> 8) & 255u), (int)(u & 255u));
+        }
+        __syncthreads();
+    }
+}
+
 // Lag-domain evaluation for the families with a moment form (SCV / LSCV):
 // runs of RL consecutive array positions of the circular row (see below),
 // their RL autocorrelation values loaded as one aligned block, and per run
@@ -483,8 +588,8 @@ constexpr int mom_seg_of() { return N >= 256 && RL <= 32 && (N / 2) % 32 == 0 ? 
 // rho reached at the end of a run are those of the next run's start, so only
 // the segment's first run (or a run after one that needed special handling)
 // evaluates exponentials.
-template <int D, int N, class Fun, int NT, int RUN, bool SCALED>
-__global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, RowGeom geo, int64_t nitems,
+template <int D, int N, class Fun, int NT, int RUN, bool SCALED, bool COMPACT>
+__global__ __launch_bounds__(NT, D <= 2 ? (COMPACT ? 3 : 1) : 2) void k_lag_mom(const double* __restrict__ prm, RowGeom geo, int64_t nitems,
                                             double* __restrict__ partial) {
     constexpr int NG = Fun::NG;
     constexpr int NGS = Fun::NGAUSS;
@@ -526,32 +631,34 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
         }
         // The ratio update rho <- rho sigma, sigma = exp(-2 hpl), compounds the
         // representation error of sigma t(t-1)/2 times by lag t of a walk, the
-        // same way for every run.  When every sigma is close to 1 (wide kernels,
-        // whose runs stay near their start value), sig holds sigma - 1 and the
-        // update is rho + rho (sigma - 1), one FMA, so the compounded error is
-        // that of the small number sigma - 1.  Otherwise (sigma < 1/2: values
-        // fall by half a decade per lag or faster, and only the first few lags
-        // of a walk matter) sig holds sigma itself.
+        // same way for every run.  sig holds sigma - 1 (expm1) and the update is
+        // rho + rho (sigma - 1), one FMA, so the compounded error is that of the
+        // small number sigma - 1.  That needs sigma near 1: with some sigma below
+        // 1/2 (kernels narrower than about a grid step, whose values fall by half
+        // a decade per lag or faster and cover only a few lags of a row) every
+        // run of the item is evaluated lag by lag instead.
         bool near1 = true;
 #pragma unroll
-        for (int k = 0; k < NGS; ++k) near1 = near1 && 2.0 * hpl[k] < 0.69314718055994531;
-#pragma unroll
-        for (int k = 0; k < NGS; ++k) sig[k] = near1 ? expm1(-2.0 * hpl[k]) : exp(-2.0 * hpl[k]);
+        for (int k = 0; k < NGS; ++k) {
+            near1 = near1 && 2.0 * hpl[k] < 0.69314718055994531;
+            sig[k] = expm1(-2.0 * hpl[k]);
+        }
         double acc[NG];
 #pragma unroll
         for (int g = 0; g < NG; ++g) acc[g] = 0.0;
         const int64_t rbeg = ch * geo.chunk;
         const int64_t rend = rbeg + geo.chunk < geo.nrows ? rbeg + geo.chunk : geo.nrows;
         const int nro = (int)(rend - rbeg);   // rows of one item < 2^31
-        for (int ro = ro0, sg = j0; ro < nro; ro += step_ro + (sg + step_j >= nseg ? 1 : 0),
-                 sg = sg + step_j >= nseg ? sg + step_j - nseg : sg + step_j) {
-            const RowInfo ri = row_info<D>(rbeg + ro, rend, geo, delta, nullptr);
+        // One segment of a row: nruns consecutive runs from run index j (runs
+        // of RL array positions, j < N / RL; all on one side of the row),
+        // carrying the walk state from run to run.
+        auto seg_walk = [&](const RowInfo& ri, int j, int nruns) {
             // walk state carried from run to run: z at the run start, e, rho
             double z[NGS][D], ev[NGS], rho[NGS];
             bool carried = false;
 #pragma unroll 1
-            for (int c = 0; c < SEG; ++c) {
-                const int p0 = (sg * SEG + c) * RL;
+            for (int c = 0; c < nruns; ++c) {
+                const int p0 = (j + c) * RL;
                 const bool pos = p0 < N / 2;
                 const int lag0 = pos ? p0 : p0 - N;
                 // runs that lie wholly in the zero slots
@@ -560,6 +667,10 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
                     continue;
                 }
                 const double* __restrict__ Arow = A + ri.wr * N + p0;
+                // the run's autocorrelation values, one aligned block, loaded
+                // first so that their latency overlaps the run start; the lag
+                // array is exactly zero at |lag| > M - 1 (stored so by the
+                // preparation), so no position needs masking here
                 double av[RL];
                 if constexpr (RL % 2 == 0) {
                     const double2* a2 = reinterpret_cast<const double2*>(Arow);
@@ -573,10 +684,6 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
 #pragma unroll
                     for (int t = 0; t < RL; ++t) av[t] = Arow[t];
                 }
-                // the lag array is exactly zero at |lag| > M - 1 (stored so by
-                // the preparation), so no position needs masking here
-#pragma unroll
-                for (int t = 0; t < RL; ++t) av[t] = ri.rw * av[t];
                 bool scl[NGS];
                 bool direct = false, alive = false, rising = false;
                 if (carried) {
@@ -656,6 +763,7 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
                         }
                     }
                 }
+                direct = direct || !near1;
                 if (!alive) {
                     // every Gaussian below 1e-290 and decreasing: so are the
                     // rest of the segment's runs (further along the same
@@ -695,42 +803,39 @@ __global__ __launch_bounds__(NT) void k_lag_mom(const double* __restrict__ prm, 
                     double m[NGS][3];
 #pragma unroll
                     for (int k = 0; k < NGS; ++k) m[k][0] = m[k][1] = m[k][2] = 0.0;
-                    // one walk of the run per regime of sig (item-uniform branch)
-                    auto walk = [&](auto near1_tag) {
-                        constexpr bool NEAR1 = decltype(near1_tag)::value;
 #pragma unroll
-                        for (int t = 0; t < RL; ++t) {
+                    for (int t = 0; t < RL; ++t) {
 #pragma unroll
-                            for (int k = 0; k < NGS; ++k) {
-                                const double w = ev[k] * av[t];
-                                m[k][0] += w;
-                                if constexpr (NM > 1) {
-                                    m[k][1] += (double)t * w;
-                                    m[k][2] += (double)(t * t) * w;
-                                }
-                                ev[k] *= rho[k];
-                                if constexpr (NEAR1)
-                                    rho[k] = fma(rho[k], sig[k], rho[k]);
-                                else
-                                    rho[k] *= sig[k];
+                        for (int k = 0; k < NGS; ++k) {
+                            const double w = ev[k] * av[t];
+                            m[k][0] += w;
+                            if constexpr (NM > 1) {
+                                m[k][1] += (double)t * w;
+                                m[k][2] += (double)(t * t) * w;
                             }
+                            ev[k] *= rho[k];
+                            rho[k] = fma(rho[k], sig[k], rho[k]);   // rho sigma, sig = sigma - 1
                         }
-                    };
-                    if (near1)
-                        walk(std::true_type{});
-                    else
-                        walk(std::false_type{});
+                    }
+                    // row weight (mirror rows count twice), and the e^600 scaling undone
 #pragma unroll
-                    for (int k = 0; k < NGS; ++k)
-                        if (SCALED && scl[k]) {
-                            constexpr double E_M600 = 2.6503965530043108e-261;   // e^-600
-                            m[k][0] *= E_M600;
-                            m[k][1] *= E_M600;
-                            m[k][2] *= E_M600;
-                        }
+                    for (int k = 0; k < NGS; ++k) {
+                        constexpr double E_M600 = 2.6503965530043108e-261;   // e^-600
+                        const double wk = (SCALED && scl[k]) ? ri.rw * E_M600 : ri.rw;
+                        m[k][0] *= wk;
+                        m[k][1] *= wk;
+                        m[k][2] *= wk;
+                    }
                     f.fold(z, dz, m, acc);
                 }
             }
+        };
+        if constexpr (!COMPACT) {
+            for (int ro = ro0, sg = j0; ro < nro; ro += step_ro + (sg + step_j >= nseg ? 1 : 0),
+                     sg = sg + step_j >= nseg ? sg + step_j - nseg : sg + step_j)
+                seg_walk(row_info<D>(rbeg + ro, rend, geo, delta, nullptr), sg * SEG, SEG);
+        } else {
+            live_segments<D, N, RL, SEG, NT>(f, geo, rbeg, rend, delta, seg_walk);
         }
         double outv[NG];
         block_sum<NG, NT>(acc, red, outv);
@@ -745,20 +850,26 @@ template <class Fun>
 constexpr int lag_run_of() { return Fun::NG > 12 ? 1 : LAG_RUN; }
 
 
-template <int D, int N, class Fun, int NT, bool SCALED>
+template <int D, int N, class Fun, int NT, bool SCALED, bool COMPACT>
 constexpr auto select_lag() {
     if constexpr (HasMoments<Fun>::value)
-        return k_lag_mom<D, N, Fun, NT, mom_run_of<N>(), SCALED>;
+        return k_lag_mom<D, N, Fun, NT, mom_run_of<N>(), SCALED, COMPACT>;
     else
         return k_lag<D, N, Fun, NT, lag_run_of<Fun>()>;
 }
 
+// variant 3: lag walk, runs that rise from below the float64 range evaluated
+// lag by lag; 4: the same runs walked scaled by e^600; 5, 6: as 3, 4 with the
+// live runs of each row dealt to the threads (compacted).  The psi and eta
+// families (no moment form) run one lag-walk kernel for all four.
 template <int D, int N, class Fun>
 hipError_t run_lag_t(const double* prm, RowGeom geo, int64_t nitems, double* partial, int grid_blocks,
-                     hipStream_t s, bool scaled) {
+                     hipStream_t s, int variant) {
     constexpr int NT = 256;
-    // variant 4 (scaled walk) differs from variant 3 only for the moment families
-    auto kern = scaled ? select_lag<D, N, Fun, NT, true>() : select_lag<D, N, Fun, NT, false>();
+    auto kern = variant == 4   ? select_lag<D, N, Fun, NT, true, false>()
+                : variant == 5 ? select_lag<D, N, Fun, NT, false, true>()
+                : variant == 6 ? select_lag<D, N, Fun, NT, true, true>()
+                               : select_lag<D, N, Fun, NT, false, false>();
     int64_t blocks = nitems;
     if (grid_blocks > 0) {
         blocks = grid_blocks;

@@ -97,7 +97,7 @@ def test_criteria_anisotropic(kf, gpu, name):
                eta.vstat_binned(A, n, g_o, [(1.0, H[b])], 2, absval=True), what=f"Q_2 {name} b={b}")
 
 
-@pytest.mark.parametrize("launch", [(3, 0), (3, -1), (4, 0), (4, -1)])
+@pytest.mark.parametrize("launch", [(3, 0), (3, -1), (4, 0), (4, -1), (5, 0), (5, -1), (6, 0), (6, -1)])
 def test_long_last_axis_all_launches(kf, gpu, launch):
     """d2_long_last (last-axis P = 256: 16-lag runs walked in 32-lag segments,
     several runs per segment) with 256 candidates in each lag-domain launch:

@@ -6,14 +6,14 @@ FFT-free binned sums of Eq. (17)-(18) on the same seeded inputs).
   device-planned dataset; psi_4 at the psi pilot on that grid through the
   batched lag launch that completes inside the kernel; the SCV objective and
   every gradient entry of all 256 candidates in each lag-domain launch
-  (variants 3 and 4, resident and one-block-per-item grids) and each spectral
+  (variants 3-6, resident and one-block-per-item grids) and each spectral
   launch (variants 0-2): 1e-11 per entry under the near-zero rule;
 * case 4: the GPU gradient against central differences of the GPU objective
   with Richardson extrapolation, 8 candidates, 1e-7;
 * case 3 (d=3, n=2e5, M=64): psi_2 (plain, fused and batched routes) and the
   SCV objective + gradient at four bandwidths;
 * case-5 shape (d=4, n=2e5, M=32, P=64): the 35-entry psi_4 batch launch, the
-  SCV objective + gradient of two candidates in both lag-domain launches, and
+  SCV objective + gradient of two candidates in every lag-domain launch, and
   the gradient against central differences (Richardson) of the GPU objective;
 * case-5 uneven batch: four d=4 datasets of uneven n in one SCV launch and one
   psi_4 launch.
@@ -34,7 +34,6 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 RTOL = 1e-11
-SCV_KINDS = None   # filled from kf (objective, objective+gradient, adjoint families)
 
 
 def _golden(name):
@@ -105,7 +104,8 @@ def test_case4_grid_counts_psi4(kf, gpu, case4):
         assert_z16(got, gold["psi4"]["values"], gold["psi4"]["scales"], RTOL, what=f"case4 psi_4 variant {var}")
 
 
-@pytest.mark.parametrize("launch", [(3, 0), (3, -1), (4, 0), (4, -1), (0, 0), (1, 0), (2, 0)])
+@pytest.mark.parametrize("launch", [(3, 0), (3, -1), (4, 0), (4, -1), (5, 0), (5, -1), (6, 0), (6, -1),
+                                    (0, 0), (1, 0), (2, 0)])
 def test_case4_all_candidates(kf, gpu, case4, launch):
     w, gold, ds, v = case4
     N = gold["grid"]["P"][1]
@@ -186,7 +186,7 @@ def test_case5_shape_psi4_batch(kf, gpu, case5_shape):
     assert_z16(got, gold["psi4"]["values"], gold["psi4"]["scales"], RTOL, what="case5 shape psi_4")
 
 
-@pytest.mark.parametrize("variant", [3, 4])
+@pytest.mark.parametrize("variant", [3, 4, 5, 6])
 def test_case5_shape_scv(kf, gpu, case5_shape, variant):
     w, gold, ds = case5_shape
     log(f"[full] case5 shape SCV obj+grad, launch variant {variant}")

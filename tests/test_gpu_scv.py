@@ -177,7 +177,7 @@ def test_launch_variants_agree(kf, gpu):
     v = torch.from_numpy(_vech(H)).to(gpu)
     N = ds.grid.P[d - 1]
     ref = None
-    for var in range(5):
+    for var in range(7):
         for gb in (0, -1, 7):
             with kf.row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, var, gb):
                 obj, g = kf.scv([ds], v)
@@ -198,7 +198,7 @@ def test_tiny_grids(kf, gpu, d, M):
     v = torch.from_numpy(_vech(H)).to(gpu)
     N = ds.grid.P[d - 1]
     log(f"[scv-tiny] d={d} M={M} P={N}")
-    for var in (3, 4):
+    for var in (3, 4, 5, 6):
         with kf.row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, var, 0):
             obj, g = kf.scv([ds], v)
         _check_against_oracle(kf, f"tiny{d}_{M}", d, X, Gp, M, H, obj.cpu().numpy(), g.cpu().numpy())
@@ -234,7 +234,7 @@ def test_extreme_candidates(kf, gpu, scale):
     v = torch.from_numpy(_vech(Hs)).to(gpu)
     N = ds.grid.P[d - 1]
     log(f"[scv-extreme] H x {scale}")
-    for var in (3, 4):
+    for var in (3, 4, 5, 6):
         with kf.row_launch(kf.FUN_SCV_OBJGRAD, d, 2, N, var, 0):
             obj, g = kf.scv([ds], v)
         _check_against_oracle(kf, "d2", d, X, Gp, M, Hs, obj.cpu().numpy(), g.cpu().numpy())
@@ -312,7 +312,7 @@ def test_psi_batch(kf, gpu):
         np.testing.assert_allclose(out[j], want, rtol=1e-10, atol=1e-12 * np.abs(want).max())
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("name", ["d1", "d2_ragged", "d3", "d4"])
 def test_every_variant_vs_oracle(kf, gpu, name, variant):
     """Each compiled launch variant (three spectral, two lag-domain) against the
@@ -350,7 +350,7 @@ def test_psi_batch_variants(kf, gpu, variant):
     np.testing.assert_allclose(out, want, rtol=1e-10, atol=1e-11 * np.abs(want).max())
 
 
-@pytest.mark.parametrize("variant", [3, 4])
+@pytest.mark.parametrize("variant", [3, 4, 5, 6])
 def test_narrow_kernels_recurrence_fallback(kf, gpu, variant):
     """Kernels much narrower than the bins: the far lags underflow, so the
     lag-domain kernel's recurrence falls back to direct evaluation (variant 3)
