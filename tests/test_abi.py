@@ -153,7 +153,8 @@ def test_dataset_entry_validation(kf):
     ds[0].n = 10
     off = np.array([0, 4], dtype=np.int64)
     assert lib.kdefft_scv_batch(ds, 1, off.ctypes.data, fake, fake, None, None, fake, 1 << 30, None) == L.E_ARG
-    assert lib.kdefft_set_row_launch(2, 2, 2, 512, 5, 0) == L.E_ARG
+    assert lib.kdefft_set_row_launch(2, 2, 2, 512, 7, 0) == L.E_ARG
+    assert lib.kdefft_set_row_launch(2, 2, 2, 512, -2, 0) == L.E_ARG
     assert lib.kdefft_set_row_launch(2, 2, 2, 3, 0, 0) == L.E_UNSUPPORTED
 
 
