@@ -93,7 +93,10 @@ typedef struct kdefft_grid {
  *                                           index l mod P (inverse transform of |C|^2);
  *                                           exact zeros where the last-axis lag has
  *                                           |l_{d-1}| > M_{d-1} - 1 (zero exactly)
- *   scal    float64 [4]                     scal[0] = n^-2 sum sum phi_{2G} (binned)
+ *   scal    float64 [4]                     scal[0] = n^-2 sum sum phi_{2G} (binned), the
+ *                                           constant SCV term, written by every batched
+ *                                           SCV objective call on the dataset (0 after
+ *                                           preparation)
  *   n_out   int32 [1]                       number of points outside the grid
  *   rec     opaque device record (pointers, n, spacing, pilot) read by the
  *           batched kernels, so batch calls need no host-to-device copies */
@@ -212,9 +215,10 @@ int kdefft_check_binning(const int32_t* n_out_dev, int32_t* n_out_host, void* st
 /* Device bytes of the buffer that holds one prepared dataset on grid g. */
 int kdefft_dataset_bytes(const kdefft_grid* g, size_t* out);
 
-/* Bin X onto g, transform the counts once (C = R2C(counts), then |C|^2 and its
- * transform along the leading axes) and evaluate the constant SCV term with
- * the pilot Gpilot_host.  ds_mem: device buffer of kdefft_dataset_bytes(g)
+/* Bin X onto g and transform the counts once (C = R2C(counts), then |C|^2 and
+ * its transform along the leading axes, and the lag array); the pilot
+ * Gpilot_host is kept for the SCV calls (which also evaluate the constant
+ * phi_{2G} term).  ds_mem: device buffer of kdefft_dataset_bytes(g)
  * bytes, 256-byte aligned; *out receives the descriptor.  Workspace:
  * KDEFFT_OP_PREPARE. */
 int kdefft_dataset_prepare(const double* X, int64_t n, const kdefft_grid* g,

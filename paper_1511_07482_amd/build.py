@@ -34,7 +34,8 @@ HOST_EXTRA = ["-ffp-contract=off"]
 UNITS = ["api.cpp", "noalloc.hip", "fft.hip", "bin.hip", "plain.hip", "rows.hip",
          "rows_d1.hip", "rows_d2.hip", "rows_d3.hip", "rows_d4.hip",
          "rows_eta_d1.hip", "rows_eta_d2.hip", "rows_eta_d3.hip", "rows_eta_d4.hip"]
-HEADERS = ["dev_common.h", "dev_kernels.h", "eta_fun.h", "finish.h", "internal.h", "rows_impl.h", "rows_dispatch.h"]
+HEADERS = ["dev_common.h", "dev_kernels.h", "eta_fun.h", "finish.h", "internal.h", "params.h", "rows_impl.h",
+           "rows_dispatch.h"]
 
 
 def _newest_header():

@@ -224,6 +224,10 @@ Sizes sizes_of(const kdefft_grid& g) {
     return s;
 }
 
+// Blocks of the bounds pass of the device-planned preparation: every block of
+// the binning launch reduces their partials again, so they are kept few.
+int64_t bound_blocks(int64_t n) { return std::min<int64_t>(std::max<int64_t>((n + 1023) / 1024, 1), 128); }
+
 int nblk_dot(const kdefft_grid& g) {
     const int64_t b = (sizes_of(g).prodM + 255) / 256;
     return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 1024);
@@ -380,6 +384,8 @@ struct BatchScratch {
     double* prm;
     double* partial;
     int32_t* counters;   // completion counters, one per candidate
+    int32_t* wc;         // live segment counts per candidate (balanced plan)
+    int32_t* item_off;   // first item of each candidate (balanced plan)
 };
 
 // Completion of a psi launch: fused into the row kernel for the lag-domain
@@ -402,6 +408,8 @@ FinishArgs fin_psi(const RowLaunch& rl, const RowGeom& geo, int ng, int32_t* cou
 // this workspace (the SCV families differ in grids per item and chunking).
 BatchScratch carve_batch(Arena& a, const kdefft_grid& g, int kind, int r, int64_t ncand) {
     BatchScratch b;
+    // the criteria add one constant-term candidate per dataset (SCV)
+    if (kind != FUN_PSI) ncand += KDEFFT_MAX_BATCH_DS;
     b.prm = a.take<double>(ncand * PRM);
     int64_t need = 0;
     if (kind == FUN_PSI) {
@@ -412,6 +420,8 @@ BatchScratch carve_batch(Arena& a, const kdefft_grid& g, int kind, int r, int64_
     }
     b.partial = a.take<double>(ncand * need);
     b.counters = a.take<int32_t>(ncand);
+    b.wc = a.take<int32_t>(ncand);
+    b.item_off = a.take<int32_t>(ncand + 1);
     return b;
 }
 
@@ -431,8 +441,7 @@ int plan_bytes(const kdefft_grid& g, int op, int r, int64_t batch, Arena& a) {
         case KDEFFT_OP_PREPARE: carve_prepare(a, g); return KDEFFT_OK;
         case KDEFFT_OP_PREPARE_AUTO: {
             carve_prepare(a, g);
-            const int64_t nb = std::min<int64_t>(std::max<int64_t>((batch + 255) / 256, 1), 1024);
-            a.take<double>(nb * 8);
+            a.take<double>(bound_blocks(batch) * 8);
             return KDEFFT_OK;
         }
         case KDEFFT_OP_PSI_BATCH: carve_batch(a, g, FUN_PSI, r, std::max<int64_t>(batch, 1)); return KDEFFT_OK;
@@ -519,26 +528,20 @@ int prepare_into(const double* X, int64_t n, const kdefft_grid& g, const double*
     h.n_out = L.n_out;
     h.scal = L.scal;
     h.prodP = (double)sizes_of(g).prodP;
-    const RowLaunch crl = launch_for(FUN_PSI, g.d, 0, g.P[g.d - 1]);
-    const RowGeom cgeo = make_geom(g, FUN_PSI, 0, 1, crl.variant);
-    if (with_const) {
-        // constant SCV term: n^-2 sum sum phi_{2G}, the psi_0 functional at 2G
-        h.prm = p.prm;
-        int t = 0;
-        for (int c = 0; c < g.d; ++c)
-            for (int i = c; i < g.d; ++i) h.Gv2[t++] = 2.0 * Gpilot[i * g.d + c];
-        h.fin = fin_psi(crl, cgeo, 1, p.counter, nullptr, L.scal);
+    // the constant SCV term n^-2 sum sum phi_{2G} is evaluated by the batched SCV
+    // calls themselves (one more candidate per dataset), so the header writes
+    // no parameter block here
+    (void)with_const;
+    if (partial) {
+        // grid from the bound partials and the header inside the binning launch
+        // (the bounds launch cleared the counter, the scalar block and the copies)
+        HIPCHK(launch_linbin_xcd(X, n, g, p.copies, L.n_out, s, nullptr, true, &h), "linbin");
+    } else {
+        HIPCHK(launch_ds_header(h, s), "dataset header");
+        HIPCHK(launch_linbin_xcd(X, n, g, p.copies, L.n_out, s, nullptr, false), "linbin");
     }
-    HIPCHK(launch_ds_header(h, s), "dataset header");
-    HIPCHK(launch_linbin_xcd(X, n, g, p.copies, L.n_out, s, partial ? &L.rec->lo[0] : nullptr, partial != nullptr),
-           "linbin");
     HIPCHK(fft_prepare_nd(p.copies, XCD_COPIES, L.counts, L.spec, L.wmix, g, s), "count transform");
     HIPCHK(fft_autocorr_nd(L.wmix, L.alag, g, s), "count autocorrelation");
-    if (with_const) {
-        HIPCHK(launch_rows(FUN_PSI, g.d, 0, cgeo, p.prm, 1, p.partial, crl, s), "const-term rows");
-        if (h.fin.mode == FIN_NONE)
-            HIPCHK(launch_psi_final(p.partial, cgeo, 1, p.prm, 1, nullptr, L.scal, s), "const-term final");
-    }
     return KDEFFT_OK;
 }
 
@@ -1019,7 +1022,7 @@ int kdefft_dataset_prepare_auto(const double* X, int64_t n, int d, const int32_t
     if (!da.fits()) return fail(KDEFFT_E_WORKSPACE, "dataset buffer of %zu bytes, need %zu", ds_bytes, da.off);
     Arena a(ws, ws_bytes, false);
     const PrepScratch p = carve_prepare(a, g);
-    const int64_t nb = std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 1024);
+    const int64_t nb = bound_blocks(n);
     double* partial = a.take<double>(nb * 8);
     rc = check_ws(a, ws_bytes);
     if (rc) return rc;
@@ -1031,7 +1034,7 @@ int kdefft_dataset_prepare_auto(const double* X, int64_t n, int d, const int32_t
         pad[k] = pk;
     }
     HIPCHK(launch_bounds_partial(X, n, d, partial, (int)nb, s, p.copies,
-                                 (size_t)(XCD_COPIES * sizes_of(g).prodM) * sizeof(int64_t)),
+                                 (size_t)(XCD_COPIES * sizes_of(g).prodM) * sizeof(int64_t), dl.n_out, dl.scal),
            "bounds");
     rc = prepare_into(X, n, g, Gpilot_host, dl, p, true, s, partial, (int)nb, pad);
     if (rc) return rc;
@@ -1116,6 +1119,14 @@ int kdefft_psi_batch(const kdefft_dataset* ds, int n_ds, const double* G_host, i
 // Q_r use the scalar eta_r families.  The dispatch order passed to the row
 // kernels is 2 for the SCV families and r for the eta families (which pick the
 // kernel compiled for r's order class).
+// The balanced plan of the compacted moment walk (variants 5, 6): for
+// candidates with a few thousand rows each and at most MAX_PLAN candidates, on
+// the resident grid (its items are numbered on the device).
+static bool balanced_ok(const RowGeom& geo, int kind, const RowLaunch& rl, int64_t nc) {
+    const bool mom = kind == FUN_SCV_OBJ || kind == FUN_SCV_OBJGRAD || kind == FUN_SCV_GRAD;
+    return mom && rl.variant >= 5 && rl.grid_blocks == 0 && nc <= 1024 && geo.nrows <= 4096;
+}
+
 static int crit_kind(int crit, int r, bool want_grad, bool adjoint) {
     if (crit == KDEFFT_CRIT_QR) return FUN_ETA1;
     if (r > 0) return FUN_ETA2;
@@ -1160,13 +1171,23 @@ static int crit_common(const kdefft_dataset* ds, int n_ds, const int64_t* off, c
     hipStream_t s = S(stream);
     const int ckey = crit == KDEFFT_CRIT_LSCV_EXACT ? KDEFFT_CRIT_LSCV : crit;
     const RowLaunch rl = force ? *force : launch_for(kind, g.d, kr, g.P[g.d - 1], ckey);
-    const RowGeom geo = make_geom(g, kind, kr, B, rl.variant);
+    // SCV objectives: each dataset's constant phi_{2G} term is evaluated in the
+    // same launch, as one more candidate per dataset after the real ones
+    const int npseudo = (crit == KDEFFT_CRIT_SCV && kind != FUN_SCV_GRAD) ? n_ds : 0;
+    const int64_t nc = B + npseudo;
+    RowGeom geo = make_geom(g, kind, kr, nc, rl.variant);
+    if (balanced_ok(geo, kind, rl, nc)) {
+        geo.nplan = (int)nc;
+        geo.wc = b.wc;
+        geo.item_off = b.item_off;
+    }
     // the criteria complete in their own kernel: fused into the row kernel the
     // assembly lengthens the dominant launch by about what the separate
     // launch costs in a replayed graph
-    HIPCHK(launch_scv_setup(vechL, a, B, b.prm, status, s), "criterion setup");
-    HIPCHK(timed_rows(kind, g.d, kr, geo, b.prm, B, b.partial, rl, s), "criterion rows");
-    HIPCHK(launch_scv_final(kind, b.partial, geo, b.prm, B, grad_out, obj, grad, s), "criterion final");
+    HIPCHK(launch_scv_setup(vechL, a, B, npseudo, b.prm, status, geo, geo.nplan > 0 ? b.wc : nullptr, s),
+           "criterion setup");
+    HIPCHK(timed_rows(kind, g.d, kr, geo, b.prm, nc, b.partial, rl, s), "criterion rows");
+    HIPCHK(launch_scv_final(kind, b.partial, geo, b.prm, B, npseudo, grad_out, obj, grad, s), "criterion final");
     return KDEFFT_OK;
 }
 

@@ -4,6 +4,7 @@
 
 #include "dev_common.h"
 #include "internal.h"
+#include "params.h"
 
 namespace kdefft {
 
@@ -16,9 +17,14 @@ namespace kdefft {
 template <int D>
 __global__ __launch_bounds__(256) void k_bounds(const double* __restrict__ X, int64_t n,
                                                 double* __restrict__ partial, uint4* __restrict__ zero_ptr,
-                                                int64_t zero16) {
+                                                int64_t zero16, int32_t* __restrict__ n_out,
+                                                double* __restrict__ scal) {
     const int64_t stride = (int64_t)gridDim.x * 256;
     for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < zero16; i += stride) zero_ptr[i] = make_uint4(0, 0, 0, 0);
+    if (blockIdx.x == 0 && threadIdx.x < 4) {   // the dataset's out-of-grid counter and scalar block
+        if (n_out && threadIdx.x == 0) *n_out = 0;
+        if (scal) scal[threadIdx.x] = 0.0;
+    }
     double mn[D], mx[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -72,15 +78,15 @@ __global__ __launch_bounds__(256) void k_bounds_final(const double* __restrict__
 }
 
 hipError_t launch_bounds_partial(const double* X, int64_t n, int d, double* partial, int nblk, hipStream_t s,
-                                 void* zero_ptr, size_t zero_bytes) {
+                                 void* zero_ptr, size_t zero_bytes, int32_t* n_out, double* scal) {
     if (zero_bytes % 16 || (reinterpret_cast<uintptr_t>(zero_ptr) & 15)) return hipErrorInvalidValue;
     uint4* z = static_cast<uint4*>(zero_ptr);
     const int64_t z16 = (int64_t)(zero_bytes / 16);
     switch (d) {
-        case 1: hipLaunchKernelGGL(k_bounds<1>, dim3(nblk), dim3(256), 0, s, X, n, partial, z, z16); break;
-        case 2: hipLaunchKernelGGL(k_bounds<2>, dim3(nblk), dim3(256), 0, s, X, n, partial, z, z16); break;
-        case 3: hipLaunchKernelGGL(k_bounds<3>, dim3(nblk), dim3(256), 0, s, X, n, partial, z, z16); break;
-        case 4: hipLaunchKernelGGL(k_bounds<4>, dim3(nblk), dim3(256), 0, s, X, n, partial, z, z16); break;
+        case 1: hipLaunchKernelGGL(k_bounds<1>, dim3(nblk), dim3(256), 0, s, X, n, partial, z, z16, n_out, scal); break;
+        case 2: hipLaunchKernelGGL(k_bounds<2>, dim3(nblk), dim3(256), 0, s, X, n, partial, z, z16, n_out, scal); break;
+        case 3: hipLaunchKernelGGL(k_bounds<3>, dim3(nblk), dim3(256), 0, s, X, n, partial, z, z16, n_out, scal); break;
+        case 4: hipLaunchKernelGGL(k_bounds<4>, dim3(nblk), dim3(256), 0, s, X, n, partial, z, z16, n_out, scal); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -88,7 +94,7 @@ hipError_t launch_bounds_partial(const double* X, int64_t n, int d, double* part
 
 hipError_t launch_bounds(const double* X, int64_t n, int d, double* partial, int nblk, double* out,
                          hipStream_t s) {
-    hipError_t e = launch_bounds_partial(X, n, d, partial, nblk, s, nullptr, 0);
+    hipError_t e = launch_bounds_partial(X, n, d, partial, nblk, s, nullptr, 0, nullptr, nullptr);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(256), 0, s, partial, nblk, d, out);
     return hipGetLastError();
@@ -138,11 +144,47 @@ __device__ __forceinline__ unsigned xcd_id() {
 // lane l the increment number it * 64 + l, i.e. point (it * 64 + l) / 2^D and
 // corner (it * 64 + l) % 2^D in an order whose consecutive corners differ in
 // the last (contiguous) axis, so neighbouring lanes add to adjacent bins.
+// Grid origin and spacing from the data bounds (per-block partials of the
+// bounds kernel), by the same IEEE steps and order as the host planner:
+// lo = min - pad, hi = max + pad, hi = lo + 1 for a degenerate axis,
+// delta = (hi - lo) / (M - 1); non-finite data give a NaN spacing, so every
+// point counts as out of the grid.  Called by all threads of a block.
+template <int D>
+__device__ __forceinline__ void grid_from_bounds(const HeaderArgs& h, double* lo, double* delta) {
+#pragma clang fp contract(off)
+    __shared__ double scratch[32], red[8], sg[8];
+    reduce_bounds(h.partial, h.nblk, D, scratch, red);
+    if (threadIdx.x < (unsigned)D) {
+        const int k = threadIdx.x;
+        const double nan = __longlong_as_double(0x7ff8000000000000LL);
+        const double l = red[k] - h.pad[k];
+        double hi = red[4 + k] + h.pad[k];
+        if (!isfinite(l) || !isfinite(hi)) {
+            sg[k] = nan;
+            sg[4 + k] = nan;
+        } else {
+            if (!(hi > l)) hi = l + 1.0;
+            sg[k] = l;
+            sg[4 + k] = (hi - l) / (double)(h.g.M[k] - 1);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        lo[k] = sg[k];
+        delta[k] = sg[4 + k];
+    }
+}
+
+// hdr.partial set: the dataset header is computed here, not by a separate
+// launch: every block derives the grid origin and spacing from the bound
+// partials (grid_from_bounds), and block 0 writes the dataset record and the
+// parameter block of the constant SCV term for the later launches.
 template <int D>
 __global__ __launch_bounds__(256) void k_linbin(const double* __restrict__ X, int64_t n, kdefft_grid g,
                                                 const double* __restrict__ gdev,
                                                 unsigned long long* __restrict__ counts,
-                                                int32_t* __restrict__ n_out, int64_t copy_stride) {
+                                                int32_t* __restrict__ n_out, int64_t copy_stride, HeaderArgs hdr) {
 #pragma clang fp contract(off)
     constexpr int NC = 1 << D;
     __shared__ long long qs[256 * NC];   // increments, per wavefront in issue order
@@ -153,6 +195,21 @@ __global__ __launch_bounds__(256) void k_linbin(const double* __restrict__ X, in
         for (int k = 0; k < D; ++k) {
             g.lo[k] = gdev[k];
             g.delta[k] = gdev[4 + k];
+        }
+    }
+    if (hdr.partial) {   // block-uniform
+        grid_from_bounds<D>(hdr, g.lo, g.delta);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            DsDev v = hdr.val;
+            for (int k = 0; k < D; ++k) {
+                v.lo[k] = g.lo[k];
+                v.delta[k] = g.delta[k];
+            }
+            *hdr.rec = v;
+            if (hdr.prm) {
+                psi_params<D>(hdr.Gv2, v, hdr.prodP, hdr.prm);
+                put_finish(hdr.prm, hdr.fin, 0);
+            }
         }
     }
     int64_t stride[D];
@@ -231,7 +288,7 @@ __global__ __launch_bounds__(256) void k_linbin(const double* __restrict__ X, in
 }
 
 hipError_t launch_linbin_xcd(const double* X, int64_t n, const kdefft_grid& g, int64_t* copies, int32_t* n_out,
-                             hipStream_t s, const double* gdev, bool copies_zeroed) {
+                             hipStream_t s, const double* gdev, bool copies_zeroed, const HeaderArgs* hdr) {
     int64_t prodM = 1;
     for (int k = 0; k < g.d; ++k) prodM *= g.M[k];
     hipError_t e = hipSuccess;
@@ -242,11 +299,13 @@ hipError_t launch_linbin_xcd(const double* X, int64_t n, const kdefft_grid& g, i
     int64_t blocks = (n + 255) / 256;
     if (blocks > 16384) blocks = 16384;
     auto* c = reinterpret_cast<unsigned long long*>(copies);
+    HeaderArgs h{};
+    if (hdr) h = *hdr;
     switch (g.d) {
-        case 1: hipLaunchKernelGGL(k_linbin<1>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, prodM); break;
-        case 2: hipLaunchKernelGGL(k_linbin<2>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, prodM); break;
-        case 3: hipLaunchKernelGGL(k_linbin<3>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, prodM); break;
-        case 4: hipLaunchKernelGGL(k_linbin<4>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, prodM); break;
+        case 1: hipLaunchKernelGGL(k_linbin<1>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, prodM, h); break;
+        case 2: hipLaunchKernelGGL(k_linbin<2>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, prodM, h); break;
+        case 3: hipLaunchKernelGGL(k_linbin<3>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, prodM, h); break;
+        case 4: hipLaunchKernelGGL(k_linbin<4>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, prodM, h); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -258,11 +317,12 @@ hipError_t launch_linbin(const double* X, int64_t n, const kdefft_grid& g, int64
     if (blocks > 16384) blocks = 16384;
     if (blocks < 1) blocks = 1;
     auto* c = reinterpret_cast<unsigned long long*>(counts);
+    const HeaderArgs h{};
     switch (g.d) {
-        case 1: hipLaunchKernelGGL(k_linbin<1>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, (int64_t)0); break;
-        case 2: hipLaunchKernelGGL(k_linbin<2>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, (int64_t)0); break;
-        case 3: hipLaunchKernelGGL(k_linbin<3>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, (int64_t)0); break;
-        case 4: hipLaunchKernelGGL(k_linbin<4>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, (int64_t)0); break;
+        case 1: hipLaunchKernelGGL(k_linbin<1>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, (int64_t)0, h); break;
+        case 2: hipLaunchKernelGGL(k_linbin<2>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, (int64_t)0, h); break;
+        case 3: hipLaunchKernelGGL(k_linbin<3>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, (int64_t)0, h); break;
+        case 4: hipLaunchKernelGGL(k_linbin<4>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, (int64_t)0, h); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

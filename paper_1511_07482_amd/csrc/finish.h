@@ -87,6 +87,15 @@ __device__ static double chunk_sum(const double* __restrict__ partial, int64_t h
     return wave_sum(s);
 }
 
+// Sum of grid g of the count items from item `first` (partial sums of NG = ng
+// values per item), by one wavefront in the same fixed order as chunk_sum.
+__device__ static double item_sum(const double* __restrict__ partial, int64_t first, int64_t count, int ng, int g) {
+    const int lane = threadIdx.x & 63;
+    double s = 0.0;
+    for (int64_t c = lane; c < count; c += 64) s += partial[(first + c) * ng + g];
+    return wave_sum(s);
+}
+
 // psi[h, g] = scale * chunk sum, by one wavefront; scal_out (if set) receives
 // psi[0, 0] (the constant SCV term of a dataset).  p: candidate h's block.
 template <bool COHERENT = false>
@@ -102,24 +111,26 @@ __device__ __forceinline__ static void psi_finish(const double* __restrict__ par
 // Criterion assembly for candidate h by one wavefront (p: its parameter
 // block).  kind: FUN_SCV_OBJ or FUN_ETA* (obj only), FUN_SCV_OBJGRAD (obj +
 // grad), FUN_SCV_GRAD (adjoint: grad scaled by grad_out).
+// The candidate's work items are `count` items from `first`; cst is the
+// constant term added to the objective (the SCV phi_{2G} sum, else 0).
 template <int D>
-__device__ __forceinline__ static void crit_finish(int kind, const double* __restrict__ partial, int64_t nchunks,
-                                                   int ng, const double* __restrict__ p, int64_t h,
-                                                   const double* __restrict__ grad_out, double* __restrict__ obj,
-                                                   double* __restrict__ grad) {
+__device__ __forceinline__ static void crit_finish(int kind, const double* __restrict__ partial, int64_t first,
+                                                   int64_t count, int ng, const double* __restrict__ p, int64_t h,
+                                                   double cst, const double* __restrict__ grad_out,
+                                                   double* __restrict__ obj, double* __restrict__ grad) {
     constexpr int d = D;
     constexpr int q = d * (d + 1) / 2;
     double T[1 + q];
 #pragma unroll
-    for (int g = 0; g < 1 + q; ++g) T[g] = g < ng ? chunk_sum(partial, h, nchunks, ng, g) * p[S_SCALE] : 0.0;
+    for (int g = 0; g < 1 + q; ++g) T[g] = g < ng ? item_sum(partial, first, count, ng, g) * p[S_SCALE] : 0.0;
     if ((threadIdx.x & 63) != 0) return;
     const bool sing = p[S_SING] != 0.0;
     const double nan = __longlong_as_double(0x7ff8000000000000LL);
     const double* L = p + S_L;
     // closed-form term: proportional to |H|^{-1/2} for every criterion with a
     // gradient, so its matrix gradient is -1/2 first H^{-1}
-    const double first = p[S_FIRST];
-    if (kind != FUN_SCV_GRAD) obj[h] = sing ? nan : first + T[0] + p[S_CONST];
+    const double t0 = p[S_FIRST];
+    if (kind != FUN_SCV_GRAD) obj[h] = sing ? nan : t0 + T[0] + cst;
     if (kind == FUN_SCV_OBJ || kind == FUN_ETA1 || kind == FUN_ETA2 || grad == nullptr) return;
     const int off = kind == FUN_SCV_OBJGRAD ? 1 : 0;
     double Hinv[16];
@@ -128,7 +139,7 @@ __device__ __forceinline__ static void crit_finish(int kind, const double* __res
     int t = off;
     for (int i = 0; i < d; ++i)
         for (int j = i; j < d; ++j) {
-            const double v = -0.5 * first * Hinv[i * 4 + j] + T[t++];
+            const double v = -0.5 * t0 * Hinv[i * 4 + j] + T[t++];
             gH[i * 4 + j] = v;
             gH[j * 4 + i] = v;
         }

@@ -20,9 +20,11 @@ constexpr int NT_DEF = 256;  // threads per block of the simple kernels
 //   both: [38] alag pointer bits  [39] wmix pointer bits  [40,44) delta  [44] n  [45] 1/(n^2 prod P)
 //         [46] constant term  [47] singular flag  [48,64) L (scv) / P3 (plain scv)
 //   criteria: [34] first (closed-form) term  [35] r of eta_r  [36] sign (-1)^r
+//         [37] SCV: the candidate index whose objective sum is the dataset's constant phi_{2G} term
 //   lag walk of Gaussian k (k = 0, 1) at [64 + 8k, 72 + 8k): dz[0..3] = delta_last P_k[i][last],
 //         [4] hpl = delta_last^2 P_k[last][last] / 2, [5] sig = exp(-2 hpl), [6] log(1e-290 / c_k)
-enum Slot { S_P1 = 0, S_C = 16, S_P2 = 16, S_C1 = 32, S_C2 = 33, S_FIRST = 34, S_R = 35, S_SIGN = 36, S_ALAG = 38,
+enum Slot { S_P1 = 0, S_C = 16, S_P2 = 16, S_C1 = 32, S_C2 = 33, S_FIRST = 34, S_R = 35, S_SIGN = 36, S_PSEUDO = 37,
+            S_ALAG = 38,
             S_WMIX = 39, S_DELTA = 40, S_N = 44, S_SCALE = 45, S_CONST = 46, S_SING = 47, S_L = 48,
             // fused completion (FinishArgs): mode, grids, counter and output pointers
             S_FIN_MODE = 80, S_FIN_NG = 81, S_FIN_CNT = 82, S_FIN_OUT = 83, S_FIN_SCAL = 84 };
@@ -90,8 +92,15 @@ struct RowGeom {
     int P[4];
     int64_t nrows;     // rows of the half lag set with nonzero kernel values
     int64_t chunk;     // rows per work item
-    int64_t nchunks;   // work items per candidate
+    int64_t nchunks;   // work items per candidate (balanced plan: an upper bound of items / candidates)
     int Q;             // P[d-1]/2 + 1
+    // Balanced plan of the compacted moment walk (nplan > 0): the nplan
+    // candidates' live segment counts wc (from the set-up kernel) set how many
+    // items each gets; the launch writes the first item of each candidate to
+    // item_off [nplan + 1] for the final kernel.
+    int nplan;
+    const int32_t* wc;
+    int32_t* item_off;
 };
 
 // Kinds of kernel families generated on the lag grid.
@@ -112,7 +121,7 @@ hipError_t launch_bounds(const double* X, int64_t n, int d, double* partial, int
 // The per-block partials only, clearing zero_bytes (a multiple of 16, 16-byte
 // aligned) at zero_ptr on the way.
 hipError_t launch_bounds_partial(const double* X, int64_t n, int d, double* partial, int nblk, hipStream_t s,
-                                 void* zero_ptr, size_t zero_bytes);
+                                 void* zero_ptr, size_t zero_bytes, int32_t* n_out = nullptr, double* scal = nullptr);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // gdev: if not NULL, 8 device doubles (lo[4], delta[4]) that replace g's
 hipError_t launch_linbin(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts,
@@ -121,8 +130,11 @@ hipError_t launch_linbin(const double* X, int64_t n, const kdefft_grid& g, int64
 // copies: XCD_COPIES * prod M int64 (cleared here unless copies_zeroed).  The
 // count transform (fft_prepare_nd) sums them exactly.
 constexpr int XCD_COPIES = 8;
+struct HeaderArgs;
+// hdr (may be NULL): with hdr->partial set, the binning launch also computes
+// the grid from the bound partials and writes the dataset header (block 0).
 hipError_t launch_linbin_xcd(const double* X, int64_t n, const kdefft_grid& g, int64_t* copies, int32_t* n_out,
-                             hipStream_t s, const double* gdev, bool copies_zeroed);
+                             hipStream_t s, const double* gdev, bool copies_zeroed, const HeaderArgs* hdr = nullptr);
 
 // One small launch at the start of a dataset's preparation: the record (with
 // the grid origin and spacing from the data bounds when `partial` is set --
@@ -187,11 +199,13 @@ int lag_layout(int N, int moments, int* run_len, int* runs_per_seg, int* rows_pe
 // 0-2: spectral (per-candidate FFT); 3, 4: lag domain (4: scaled walk of rising
 // runs); 5, 6: as 3, 4 with only the live runs of each row dealt to the threads
 constexpr int ROW_VARIANTS = 7;
-hipError_t launch_scv_setup(const double* vechL, const ScvBatchArgs& a, int64_t ncand, double* prm,
-                            int32_t* status, hipStream_t s);
+// ncand real candidates, then npseudo constant-term candidates (SCV: one per
+// dataset); wc (may be NULL): live segment counts for the balanced plan.
+hipError_t launch_scv_setup(const double* vechL, const ScvBatchArgs& a, int64_t ncand, int npseudo, double* prm,
+                            int32_t* status, const RowGeom& geo, int32_t* wc, hipStream_t s);
 hipError_t launch_psi_setup(const PsiBatchArgs& a, double* prm, hipStream_t s);
 hipError_t launch_scv_final(int kind, const double* partial, const RowGeom& geo,
-                            const double* prm, int64_t ncand, const double* grad_out,
+                            const double* prm, int64_t ncand, int npseudo, const double* grad_out,
                             double* obj, double* grad, hipStream_t s);
 hipError_t launch_psi_final(const double* partial, const RowGeom& geo, int ng,
                             const double* prm, int64_t ncand, double* psi, double* scal_out,

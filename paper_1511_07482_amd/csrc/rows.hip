@@ -9,6 +9,7 @@
 #include "eta_fun.h"
 #include "finish.h"
 #include "internal.h"
+#include "params.h"
 #include "rows_impl.h"
 
 namespace kdefft {
@@ -134,6 +135,18 @@ RowGeom make_geom(const kdefft_grid& g, int kind, int r, int64_t ncand, int vari
     int ri = rows_per_iter(kind, g.d, r, g.P[g.d - 1], variant);
     if (ri < 1) ri = 1;
     const bool mom = kind == FUN_SCV_OBJ || kind == FUN_SCV_OBJGRAD || kind == FUN_SCV_GRAD;
+    if (variant >= 5 && mom && nrows <= 4096 && ncand <= 1024) {
+        // compacted walk with a balanced plan (items numbered on the device,
+        // at most one per resident block): candidates x nchunks covers the
+        // resident blocks; the same row chunks serve the launch without a plan
+        const int64_t slots = (int64_t)compact_slots(g.d);
+        int64_t per = (slots + ncand - 1) / ncand;
+        if (per > nrows) per = nrows;
+        const int64_t chunk = (nrows + per - 1) / per;
+        geo.chunk = chunk;
+        geo.nchunks = (nrows + chunk - 1) / chunk;
+        return geo;
+    }
     if (variant >= 5 && mom) {
         // compacted walk: the live runs of a whole item are dealt over the
         // block at once, so items are sized to the resident blocks instead:
@@ -190,30 +203,10 @@ hipError_t launch_rows(int kind, int d, int r, const RowGeom& geo, const double*
     }
 }
 
-__device__ static double two_pi_pow(int d) {  // (2 pi)^{-d/2}
-    const double c = 0.39894228040143267794;      // (2 pi)^{-1/2}
-    double r = 1.0;
-    for (int k = 0; k < d; ++k) r *= c;
-    return r;
-}
-
-__device__ static void put_ptr(double* slot, const void* p) {
-    *slot = __longlong_as_double(static_cast<long long>(reinterpret_cast<uintptr_t>(p)));
-}
-
-// Completion slots of candidate h's block; clears its counter when fused.
-__device__ static void put_finish(double* p, const FinishArgs& f, int64_t h) {
-    p[S_FIN_MODE] = (double)f.mode;
-    p[S_FIN_NG] = (double)f.ng;
-    put_ptr(p + S_FIN_CNT, f.counters);
-    put_ptr(p + S_FIN_OUT, f.out);
-    put_ptr(p + S_FIN_SCAL, f.scal);
-    if (f.mode != FIN_NONE) f.counters[h] = 0;
-}
-
-// One thread per candidate: H = L L^T from vechL, then per criterion
+// Parameter block of candidate h: H = L L^T from vechL, then per criterion
 //   SCV:          S1 = 2H + 2G, S2 = H + 2G, first = n^-1 (4 pi)^{-d/2} |H|^{-1/2},
-//                 constant = the dataset's phi_{2G} sum;
+//                 and the index of the dataset's constant-term candidate
+//                 (npseudo > 0; see pseudo_params);
 //   LSCV (r):     S1 = 2H, S2 = H with the S2 weight a/2 folded into c2
 //                 (a = 2, or 2n/(n-1) for the leave-one-out form), sign (-1)^r,
 //                 first = (-1)^r b eta_r(0; H) (b = 2/n, or 2/(n-1));
@@ -221,19 +214,21 @@ __device__ static void put_finish(double* p, const FinishArgs& f, int64_t h) {
 // their inverses and normal constants, grid spacing, n and the scale of the
 // lag sums.  status 1 = singular candidate.
 template <int D>
-__global__ void k_scv_setup(const double* __restrict__ vechL, ScvBatchArgs a, int64_t ncand,
-                            double* __restrict__ prm, int32_t* __restrict__ status) {
-    const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (h >= ncand) return;
-    constexpr int d = D;
-    const int q = d * (d + 1) / 2;
+__device__ static void scv_params(const double* __restrict__ vechL, const ScvBatchArgs& a, int64_t h, int64_t ncand,
+                                  int npseudo, double* __restrict__ p, int32_t* __restrict__ status) {
     // dataset of candidate h; unrolled with constant indices so the by-value
     // argument arrays stay in scalar registers
     const DsDev* dsp = a.rec[0];
+    int ds_index = 0;
 #pragma unroll
     for (int jj = 1; jj < KDEFFT_MAX_BATCH_DS; ++jj)
-        if (jj < a.n_ds && h >= a.off[jj]) dsp = a.rec[jj];
+        if (jj < a.n_ds && h >= a.off[jj]) {
+            dsp = a.rec[jj];
+            ds_index = jj;
+        }
     const DsDev& ds = *dsp;
+    constexpr int d = D;
+    const int q = d * (d + 1) / 2;
     double L[16], H[16], S1[16], S2[16], L1[16], L2[16];
     for (int i = 0; i < 16; ++i) L[i] = 0.0;
     int t = 0;
@@ -261,12 +256,12 @@ __global__ void k_scv_setup(const double* __restrict__ vechL, ScvBatchArgs a, in
             S1[i * 4 + k2] = hw * H[i * 4 + k2] + gw * ds.G[i * 4 + k2];
             S2[i * 4 + k2] = H[i * 4 + k2] + gw * ds.G[i * 4 + k2];
         }
-    double* p = prm + h * PRM;
     // every slot the row and final kernels read is written below; these three
     // default to zero (no closed-form or constant term, separate final kernel)
     p[S_FIRST] = 0.0;
     p[S_CONST] = 0.0;
     p[S_FIN_MODE] = 0.0;
+    p[S_PSEUDO] = npseudo > 0 ? (double)(ncand + ds_index) : -1.0;
     const bool ok1 = chol4<D>(S1, L1);
     const bool ok2 = chol4<D>(S2, L2);
     const bool ok = !sing && ok1 && ok2;
@@ -295,7 +290,6 @@ __global__ void k_scv_setup(const double* __restrict__ vechL, ScvBatchArgs a, in
         double c4 = 1.0;  // (4 pi)^{-d/2}
         for (int k = 0; k < d; ++k) c4 *= 0.28209479177387814347;
         p[S_FIRST] = c4 / (n * ldet);
-        p[S_CONST] = ds.scal[0];
     } else if (!qr) {
         const bool exact = crit == KDEFFT_CRIT_LSCV_EXACT;
         const double b = exact ? 2.0 / (n - 1.0) : 2.0 / n;
@@ -318,45 +312,102 @@ __global__ void k_scv_setup(const double* __restrict__ vechL, ScvBatchArgs a, in
     if (status) status[h] = sing ? 1 : 0;
 }
 
-hipError_t launch_scv_setup(const double* vechL, const ScvBatchArgs& a, int64_t ncand, double* prm,
-                            int32_t* status, hipStream_t s) {
-    const int64_t blocks = (ncand + 63) / 64;
-    switch (a.d) {
-        case 1: hipLaunchKernelGGL(k_scv_setup<1>, dim3((unsigned)blocks), dim3(64), 0, s, vechL, a, ncand, prm, status); break;
-        case 2: hipLaunchKernelGGL(k_scv_setup<2>, dim3((unsigned)blocks), dim3(64), 0, s, vechL, a, ncand, prm, status); break;
-        case 3: hipLaunchKernelGGL(k_scv_setup<3>, dim3((unsigned)blocks), dim3(64), 0, s, vechL, a, ncand, prm, status); break;
-        case 4: hipLaunchKernelGGL(k_scv_setup<4>, dim3((unsigned)blocks), dim3(64), 0, s, vechL, a, ncand, prm, status); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
 
-// Parameter block of the psi_r family for bandwidth vech gv on dataset ds:
-// P = G^{-1}, c = (-1)^r (2 pi)^{-d/2} |G|^{-1/2} (even r: the sign is +1),
-// lag array, spacing, n and the scale of the lag sums.
+// Parameter block of the constant SCV term of dataset j (a candidate after
+// the real ones): n^-2 sum sum phi_{2G} evaluated by the same walk as a
+// candidate, with the first Gaussian phi_{2G} (its normal constant c1 > 0, as
+// the walk's magnitude tests assume) and the second switched off (c2 = 0), so
+// that the walk's objective sum (first minus twice the second) is the phi_{2G}
+// sum.  Both carry (2G)^{-1} (the live intervals use them).  No status or first
+// term; the final kernel stores the term in the dataset's scalar block (slot
+// S_FIN_SCAL).
 template <int D>
-__device__ static void psi_params(const double* gv, const DsDev& ds, double prodP, double* p) {
+__device__ static void pseudo_params(const ScvBatchArgs& a, int j, double* __restrict__ p) {
     constexpr int d = D;
-    double G[16], L[16];
-    for (int i = 0; i < 16; ++i) G[i] = 0.0;
-    int t = 0;
-    for (int jj = 0; jj < d; ++jj)
-        for (int i = jj; i < d; ++i) {
-            G[i * 4 + jj] = gv[t];
-            G[jj * 4 + i] = gv[t];
-            ++t;
-        }
-    // every slot the psi kernels read is written here or by put_finish
-    chol4<D>(G, L);
+    const DsDev* dsp = a.rec[0];
+#pragma unroll
+    for (int jj = 1; jj < KDEFFT_MAX_BATCH_DS; ++jj)
+        if (jj == j) dsp = a.rec[jj];
+    const DsDev& ds = *dsp;
+    double S[16], L[16];
+    for (int i = 0; i < 16; ++i) S[i] = 0.0;
+    for (int i = 0; i < d; ++i)
+        for (int k2 = 0; k2 < d; ++k2) S[i * 4 + k2] = 2.0 * ds.G[i * 4 + k2];
+    chol4<D>(S, L);   // the pilot was validated positive definite when the dataset was prepared
     chol_inv4<D>(L, p + S_P1);
+    chol_inv4<D>(L, p + S_P2);
     double det = 1.0;
     for (int k = 0; k < d; ++k) det *= L[k * 4 + k];
-    p[S_C] = two_pi_pow(d) / det;
+    p[S_C1] = two_pi_pow(d) / det;
+    p[S_C2] = 0.0;
+    p[S_FIRST] = 0.0;
+    p[S_CONST] = 0.0;
+    p[S_R] = 0.0;
+    p[S_SIGN] = 1.0;
+    p[S_PSEUDO] = -1.0;
+    p[S_FIN_MODE] = 0.0;
+    put_ptr(p + S_FIN_SCAL, ds.scal);
     put_ptr(p + S_WMIX, ds.wmix);
     put_ptr(p + S_ALAG, ds.alag);
     for (int k = 0; k < d; ++k) p[S_DELTA + k] = ds.delta[k];
     p[S_N] = ds.n;
-    p[S_SCALE] = 1.0 / (ds.n * ds.n * prodP);
+    p[S_SCALE] = 1.0 / (ds.n * ds.n * a.prodP);
+    p[S_SING] = 0.0;
+    for (int i = 0; i < 16; ++i) p[S_L + i] = i % 5 == 0 ? 1.0 : 0.0;
+}
+
+// One wavefront per candidate (real ones, then npseudo constant-term
+// candidates): lane 0 writes the parameter block; with wc set, the wavefront
+// then counts the candidate's live segments over all rows of the half lag set
+// (row_live with the moment walk's run length rl and segment length seg) into
+// wc[c] for the balanced plan of the compacted walk.
+template <int D>
+__global__ __launch_bounds__(256) void k_scv_setup(const double* __restrict__ vechL, ScvBatchArgs a, int64_t ncand,
+                                                   int npseudo, double* __restrict__ prm,
+                                                   int32_t* __restrict__ status, RowGeom geo, int rl, int seg,
+                                                   int32_t* __restrict__ wc) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * 4 + wave;
+    const bool active = c < ncand + npseudo;
+    if (active && lane == 0) {
+        if (c < ncand)
+            scv_params<D>(vechL, a, c, ncand, npseudo, prm + c * PRM, status);
+        else
+            pseudo_params<D>(a, (int)(c - ncand), prm + c * PRM);
+    }
+    if (!wc) return;   // grid-uniform
+    __syncthreads();   // the blocks written by lane 0 are visible to the block
+    if (!active) return;
+    const double* p = prm + c * PRM;
+    ScvFun<D, 1> f;
+    f.load(p);
+    double delta[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) delta[k] = p[S_DELTA + k];
+    const int M_last = geo.M[D - 1], N = geo.P[D - 1];
+    int units = 0;
+    for (int64_t row = lane; row < geo.nrows; row += 64) {
+        const LiveRuns lr = row_live<D>(f, row_info<D>(row, geo.nrows, geo, delta, nullptr), M_last, N, rl, delta[D - 1]);
+        units += (lr.pn + seg - 1) / seg + (lr.nn + seg - 1) / seg;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) units += __shfl_xor(units, off, 64);
+    if (lane == 0) wc[c] = units;
+}
+
+hipError_t launch_scv_setup(const double* vechL, const ScvBatchArgs& a, int64_t ncand, int npseudo, double* prm,
+                            int32_t* status, const RowGeom& geo, int32_t* wc, hipStream_t s) {
+    const int64_t blocks = (ncand + npseudo + 3) / 4;
+    int rl = 1, seg = 1, rows = 1;
+    if (wc && !lag_layout(geo.P[geo.d - 1], 1, &rl, &seg, &rows)) return hipErrorInvalidValue;
+    switch (a.d) {
+        case 1: hipLaunchKernelGGL(k_scv_setup<1>, dim3((unsigned)blocks), dim3(256), 0, s, vechL, a, ncand, npseudo, prm, status, geo, rl, seg, wc); break;
+        case 2: hipLaunchKernelGGL(k_scv_setup<2>, dim3((unsigned)blocks), dim3(256), 0, s, vechL, a, ncand, npseudo, prm, status, geo, rl, seg, wc); break;
+        case 3: hipLaunchKernelGGL(k_scv_setup<3>, dim3((unsigned)blocks), dim3(256), 0, s, vechL, a, ncand, npseudo, prm, status, geo, rl, seg, wc); break;
+        case 4: hipLaunchKernelGGL(k_scv_setup<4>, dim3((unsigned)blocks), dim3(256), 0, s, vechL, a, ncand, npseudo, prm, status, geo, rl, seg, wc); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 // One thread per dataset: the psi_r parameter block at its bandwidth
@@ -437,26 +488,44 @@ hipError_t launch_ds_header(const HeaderArgs& h, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Criterion assembly, one wavefront per candidate (see crit_finish).
+// Criterion assembly, one wavefront per candidate (see crit_finish); the
+// npseudo constant-term candidates after the real ones store their term in
+// their dataset's scalar block.  Work items of candidate c: item_off[c] ..
+// item_off[c + 1] (balanced plan) or c * nchunks + [0, nchunks).
 template <int D>
 __global__ __launch_bounds__(64) void k_scv_final(int kind, const double* __restrict__ partial, int64_t nchunks,
-                                                  int ng, const double* __restrict__ prm, int64_t ncand,
+                                                  const int32_t* __restrict__ item_off, int ng,
+                                                  const double* __restrict__ prm, int64_t ncand, int npseudo,
                                                   const double* __restrict__ grad_out, double* __restrict__ obj,
                                                   double* __restrict__ grad) {
     const int64_t h = blockIdx.x;
-    if (h >= ncand) return;
-    crit_finish<D>(kind, partial, nchunks, ng, prm + h * PRM, h, grad_out, obj, grad);
+    if (h >= ncand + npseudo) return;
+    auto first_of = [&](int64_t c) { return item_off ? (int64_t)item_off[c] : c * nchunks; };
+    auto count_of = [&](int64_t c) { return item_off ? (int64_t)(item_off[c + 1] - item_off[c]) : nchunks; };
+    const double* p = prm + h * PRM;
+    if (h >= ncand) {
+        const double v = item_sum(partial, first_of(h), count_of(h), ng, 0) * p[S_SCALE];
+        if (threadIdx.x == 0) static_cast<double*>(slot_ptr(p[S_FIN_SCAL]))[0] = v;
+        return;
+    }
+    double cst = 0.0;
+    if (p[S_PSEUDO] >= 0.0) {
+        const int64_t c = (int64_t)p[S_PSEUDO];
+        cst = item_sum(partial, first_of(c), count_of(c), ng, 0) * prm[c * PRM + S_SCALE];
+    }
+    crit_finish<D>(kind, partial, first_of(h), count_of(h), ng, p, h, cst, grad_out, obj, grad);
 }
 
 hipError_t launch_scv_final(int kind, const double* partial, const RowGeom& geo, const double* prm, int64_t ncand,
-                            const double* grad_out, double* obj, double* grad, hipStream_t s) {
+                            int npseudo, const double* grad_out, double* obj, double* grad, hipStream_t s) {
     const int ng = ng_of(kind, geo.d, 2);
-    const dim3 grid((unsigned)ncand);
+    const dim3 grid((unsigned)(ncand + npseudo));
+    const int32_t* off = geo.nplan > 0 ? geo.item_off : nullptr;
     switch (geo.d) {
-        case 1: hipLaunchKernelGGL(k_scv_final<1>, grid, dim3(64), 0, s, kind, partial, geo.nchunks, ng, prm, ncand, grad_out, obj, grad); break;
-        case 2: hipLaunchKernelGGL(k_scv_final<2>, grid, dim3(64), 0, s, kind, partial, geo.nchunks, ng, prm, ncand, grad_out, obj, grad); break;
-        case 3: hipLaunchKernelGGL(k_scv_final<3>, grid, dim3(64), 0, s, kind, partial, geo.nchunks, ng, prm, ncand, grad_out, obj, grad); break;
-        case 4: hipLaunchKernelGGL(k_scv_final<4>, grid, dim3(64), 0, s, kind, partial, geo.nchunks, ng, prm, ncand, grad_out, obj, grad); break;
+        case 1: hipLaunchKernelGGL(k_scv_final<1>, grid, dim3(64), 0, s, kind, partial, geo.nchunks, off, ng, prm, ncand, npseudo, grad_out, obj, grad); break;
+        case 2: hipLaunchKernelGGL(k_scv_final<2>, grid, dim3(64), 0, s, kind, partial, geo.nchunks, off, ng, prm, ncand, npseudo, grad_out, obj, grad); break;
+        case 3: hipLaunchKernelGGL(k_scv_final<3>, grid, dim3(64), 0, s, kind, partial, geo.nchunks, off, ng, prm, ncand, npseudo, grad_out, obj, grad); break;
+        case 4: hipLaunchKernelGGL(k_scv_final<4>, grid, dim3(64), 0, s, kind, partial, geo.nchunks, off, ng, prm, ncand, npseudo, grad_out, obj, grad); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -484,100 +484,246 @@ constexpr int mom_seg_of() { return N >= 256 && RL <= 32 && (N / 2) % 32 == 0 ? 
 // magnitude under float64 rounding of the lag-0 term alone.
 constexpr double LOG_REL_CUT = -69.077552789821368;
 
-// Compacted dealing of an item's rows [rbeg, rend): the rows are taken NT at a
-// time; thread t bounds row t's live lag interval (for every Gaussian of the
-// family the lags l with exponent above LOG_REL_CUT, an interval because the
-// exponent is a concave quadratic in l along the row; the hull over the
-// Gaussians, widened by one lag each side), turns it into runs of RL positions
-// on each side of the circular row and segments of up to SEG runs; a block
-// scan numbers the segments, and the threads take segments t, t + NT, ... of
-// that list (rows in order, runs in order within a row, so neighbouring lanes
-// read neighbouring blocks of the autocorrelation).  seg_walk(ri, j, nruns)
-// walks one segment.
+// Live runs of one row: for every Gaussian of the family the lags l with
+// exponent above LOG_REL_CUT form an interval (the exponent is a concave
+// quadratic in l along the row); their hull, widened by one lag each side and
+// clipped to |l| <= M - 1, as runs of RL array positions on the two sides of
+// the circular row: pn runs from run pf (lags >= 0), nn runs from run nf
+// (lags < 0).
+struct LiveRuns {
+    int pf, pn, nf, nn;
+};
+
+template <int D, class Fun>
+__device__ __forceinline__ LiveRuns row_live(const Fun& f, const RowInfo& ri, int M_last, int N, int RL, double dl) {
+    double la = INFINITY, lb = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < Fun::NGAUSS; ++k) {
+        const double* P = f.Pm(k);
+        double b = 0.0, ql = 0.0;
+#pragma unroll
+        for (int i = 0; i < D - 1; ++i) {
+            b += P[(D - 1) * D + i] * ri.x[i];
+#pragma unroll
+            for (int jj = 0; jj < D - 1; ++jj) ql += ri.x[i] * P[i * D + jj] * ri.x[jj];
+        }
+        const double pll = P[(D - 1) * D + D - 1];
+        const double emax = -0.5 * (ql - b * b / pll);   // largest exponent along the row
+        if (emax > LOG_REL_CUT) {
+            const double ls = -b / (dl * pll);
+            const double w = sqrt(2.0 * (emax - LOG_REL_CUT) / (dl * dl * pll));
+            la = fmin(la, ls - w);
+            lb = fmax(lb, ls + w);
+        }
+    }
+    LiveRuns lr{0, 0, 0, 0};
+    const double lim = (double)(M_last - 1);
+    const double fa = fmax(floor(la) - 1.0, -lim), fb = fmin(ceil(lb) + 1.0, lim);
+    if (fa <= fb) {   // false for an empty (or NaN) interval
+        const int ia = (int)fa, ib = (int)fb;
+        if (ib >= 0) {
+            lr.pf = (ia > 0 ? ia : 0) / RL;
+            lr.pn = ib / RL - lr.pf + 1;
+        }
+        if (ia <= -1) {
+            lr.nf = (ia + N) / RL;
+            lr.nn = ((ib < -1 ? ib : -1) + N) / RL - lr.nf + 1;
+        }
+    }
+    return lr;
+}
+
+// Segments (of up to SEG runs) of a row's live runs.
+template <int SEG>
+__device__ __forceinline__ int live_units(const LiveRuns& lr) {
+    return (lr.pn + SEG - 1) / SEG + (lr.nn + SEG - 1) / SEG;
+}
+
+// Exclusive block scan of v (all NT threads); *total receives the sum.  Ends
+// with a barrier, so s_wsum can be reused right away.
+template <int NT>
+__device__ __forceinline__ int block_scan_excl(int v, int* s_wsum, int* total) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) s_wsum[wave] = x;
+    __syncthreads();
+    int pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        pre += w < wave ? s_wsum[w] : 0;
+        tot += s_wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + x - v;
+}
+
+// Unit word of the per-item segment lists: row << 16 | first run << 8 | runs.
+__device__ __forceinline__ uint32_t unit_word(int row, int run, int nruns) {
+    return (uint32_t)row << 16 | (uint32_t)run << 8 | (uint32_t)nruns;
+}
+
+// Append the segments of a row with live runs lr to the list (positive side,
+// then negative side), numbered from first; only those with numbers in
+// [lo, hi) are written, at s_unit[number - lo].
+template <int SEG>
+__device__ __forceinline__ void write_units(uint32_t* s_unit, int row, const LiveRuns& lr, int first, int lo, int hi) {
+    int o = first;
+    for (int a = 0; a < lr.pn; a += SEG, ++o)
+        if (o >= lo && o < hi) s_unit[o - lo] = unit_word(row, lr.pf + a, lr.pn - a < SEG ? lr.pn - a : SEG);
+    for (int a = 0; a < lr.nn; a += SEG, ++o)
+        if (o >= lo && o < hi) s_unit[o - lo] = unit_word(row, lr.nf + a, lr.nn - a < SEG ? lr.nn - a : SEG);
+}
+
+// Largest number of segments one item's list holds in LDS, and of candidates
+// in a balanced plan.
+constexpr int UNIT_CAP = 4096;
+constexpr int MAX_PLAN = 1024;
+
+// Compacted dealing of an item's rows [rbeg, rend): the rows are taken RB at a
+// time; thread t finds row t's live runs (row_live), a block scan numbers their
+// segments, the segments are listed in LDS (rows in order, runs in order within
+// a row, so neighbouring lanes read neighbouring blocks of the
+// autocorrelation), and the threads walk segments t, t + NT, ... of the list
+// with seg_walk(ri, first run, runs).
 template <int D, int N, int RL, int SEG, int NT, class Fun, class Walk>
 __device__ __forceinline__ void live_segments(const Fun& f, const RowGeom& geo, int64_t rbeg, int64_t rend,
                                               const double* delta, Walk&& seg_walk) {
-    constexpr int NGS = Fun::NGAUSS;
-    constexpr int NW = NT / 64;
     constexpr int NRUN = N / RL;                               // runs per row
     constexpr int UPR = 2 * ((NRUN / 2 + SEG - 1) / SEG);     // segments per row, at most (both sides)
-    constexpr int RB = NT < 4096 / UPR ? NT : 4096 / UPR;      // rows per pass: at most 4096 segments
-    constexpr int MAXU = RB * UPR;
+    constexpr int RB = NT < UNIT_CAP / UPR ? NT : UNIT_CAP / UPR;   // rows per pass
     static_assert(NRUN <= 256 && NT <= 256 && RB >= 1, "unit word layout");
-    __shared__ RowInfo s_ri[RB];
-    __shared__ uint32_t s_unit[MAXU];   // row << 16 | first run << 8 | runs
-    __shared__ int s_wsum[NW];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ uint32_t s_unit[RB * UPR];
+    __shared__ int s_wsum[NT / 64];
     const int M_last = geo.M[D - 1];
-    const double dl = delta[D - 1];
     for (int64_t rb = rbeg; rb < rend; rb += RB) {
         const int nb = rend - rb < RB ? (int)(rend - rb) : RB;
-        int pf = 0, pn = 0, nf = 0, nn = 0;
-        if ((int)threadIdx.x < nb) {
-            const RowInfo ri = row_info<D>(rb + threadIdx.x, rend, geo, delta, nullptr);
-            double la = INFINITY, lb = -INFINITY;
-#pragma unroll
-            for (int k = 0; k < NGS; ++k) {
-                const double* P = f.Pm(k);
-                double b = 0.0, ql = 0.0;
-#pragma unroll
-                for (int i = 0; i < D - 1; ++i) {
-                    b += P[(D - 1) * D + i] * ri.x[i];
-#pragma unroll
-                    for (int jj = 0; jj < D - 1; ++jj) ql += ri.x[i] * P[i * D + jj] * ri.x[jj];
-                }
-                const double pll = P[(D - 1) * D + D - 1];
-                const double emax = -0.5 * (ql - b * b / pll);   // largest exponent along the row
-                if (emax > LOG_REL_CUT) {
-                    const double ls = -b / (dl * pll);
-                    const double w = sqrt(2.0 * (emax - LOG_REL_CUT) / (dl * dl * pll));
-                    la = fmin(la, ls - w);
-                    lb = fmax(lb, ls + w);
-                }
-            }
-            const double lim = (double)(M_last - 1);
-            const double fa = fmax(floor(la) - 1.0, -lim), fb = fmin(ceil(lb) + 1.0, lim);
-            if (fa <= fb) {   // false for an empty (or NaN) interval
-                const int ia = (int)fa, ib = (int)fb;
-                if (ib >= 0) {
-                    pf = (ia > 0 ? ia : 0) / RL;
-                    pn = ib / RL - pf + 1;
-                }
-                if (ia <= -1) {
-                    nf = (ia + N) / RL;
-                    nn = ((ib < -1 ? ib : -1) + N) / RL - nf + 1;
-                }
-            }
-            s_ri[threadIdx.x] = ri;
-        }
-        const int units = (pn + SEG - 1) / SEG + (nn + SEG - 1) / SEG;
-        // exclusive block scan of the segment counts, then each row writes its
-        // segments into the block's list
-        int x = units;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int y = __shfl_up(x, off, 64);
-            if (lane >= off) x += y;
-        }
-        if (lane == 63) s_wsum[wave] = x;
-        __syncthreads();
-        int pre = 0, total = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            pre += w < wave ? s_wsum[w] : 0;
-            total += s_wsum[w];
-        }
-        int o = pre + x - units;
-        const uint32_t rw = (uint32_t)threadIdx.x << 16;
-        for (int a = 0; a < pn; a += SEG, ++o) s_unit[o] = rw | (uint32_t)(pf + a) << 8 | (uint32_t)(pn - a < SEG ? pn - a : SEG);
-        for (int a = 0; a < nn; a += SEG, ++o) s_unit[o] = rw | (uint32_t)(nf + a) << 8 | (uint32_t)(nn - a < SEG ? nn - a : SEG);
+        LiveRuns lr{0, 0, 0, 0};
+        if ((int)threadIdx.x < nb)
+            lr = row_live<D>(f, row_info<D>(rb + threadIdx.x, rend, geo, delta, nullptr), M_last, N, RL, delta[D - 1]);
+        int total = 0;
+        const int first = block_scan_excl<NT>(live_units<SEG>(lr), s_wsum, &total);
+        if ((int)threadIdx.x < nb) write_units<SEG>(s_unit, (int)threadIdx.x, lr, first, 0, total);
         __syncthreads();
         for (int k = threadIdx.x; k < total; k += NT) {
             const uint32_t u = s_unit[k];
-            seg_walk(s_ri[u >> 16], (int)((u >> 8) & 255u), (int)(u & 255u));
+            seg_walk(row_info<D>(rb + (u >> 16), rend, geo, delta, nullptr), (int)((u >> 8) & 255u), (int)(u & 255u));
         }
         __syncthreads();
     }
+}
+
+// Balanced dealing: the item is the window [k W / parts, (k + 1) W / parts) of
+// its candidate's list of W live segments over all nrows rows (rows in order).
+// The rows are scanned in passes of NT (a first sweep counts W when the rows
+// span several passes); the window's segments are listed in LDS, UNIT_CAP at a
+// time, and walked as in live_segments.
+template <int D, int N, int RL, int SEG, int NT, class Fun, class Walk>
+__device__ __forceinline__ void live_window(const Fun& f, const RowGeom& geo, int k, int parts,
+                                            const double* delta, Walk&& seg_walk) {
+    static_assert(N / RL <= 256 && NT <= 256, "unit word layout");
+    __shared__ uint32_t s_unit[UNIT_CAP];
+    __shared__ int s_wsum[NT / 64];
+    const int M_last = geo.M[D - 1];
+    const int64_t nrows = geo.nrows;
+    int64_t wtot = -1;
+    if (nrows > NT) {
+        wtot = 0;
+        for (int64_t rb = 0; rb < nrows; rb += NT) {
+            LiveRuns lr{0, 0, 0, 0};
+            if (rb + threadIdx.x < nrows)
+                lr = row_live<D>(f, row_info<D>(rb + threadIdx.x, nrows, geo, delta, nullptr), M_last, N, RL,
+                                 delta[D - 1]);
+            int total = 0;
+            (void)block_scan_excl<NT>(live_units<SEG>(lr), s_wsum, &total);
+            wtot += total;
+        }
+    }
+    int64_t lo = -1, hi = -1;
+    for (int64_t sub = 0;; sub += UNIT_CAP) {
+        int64_t seen = 0, sl = 0, sh = 0;
+        for (int64_t rb = 0; rb < nrows; rb += NT) {
+            LiveRuns lr{0, 0, 0, 0};
+            if (rb + threadIdx.x < nrows)
+                lr = row_live<D>(f, row_info<D>(rb + threadIdx.x, nrows, geo, delta, nullptr), M_last, N, RL,
+                                 delta[D - 1]);
+            int total = 0;
+            const int first = block_scan_excl<NT>(live_units<SEG>(lr), s_wsum, &total);
+            if (wtot < 0) wtot = total;   // all rows in this one pass
+            if (lo < 0) {
+                lo = (int64_t)k * wtot / parts;
+                hi = (int64_t)(k + 1) * wtot / parts;
+            }
+            sl = lo + sub;
+            sh = hi < sl + UNIT_CAP ? hi : sl + UNIT_CAP;
+            if (rb + threadIdx.x < nrows && seen + first < sh)
+                write_units<SEG>(s_unit, (int)(rb + threadIdx.x), lr, (int)(seen + first - sl), 0, (int)(sh - sl));
+            seen += total;
+            if (seen >= sh) break;   // block-uniform
+        }
+        __syncthreads();
+        for (int u = threadIdx.x; u < sh - sl; u += NT) {
+            const uint32_t w = s_unit[u];
+            seg_walk(row_info<D>(w >> 16, nrows, geo, delta, nullptr), (int)((w >> 8) & 255u), (int)(w & 255u));
+        }
+        __syncthreads();
+        if (sh >= hi) break;
+    }
+}
+
+// Items of the balanced plan (every block computes the same plan from the
+// candidates' live segment counts wc): with W the total, the smallest U (from
+// ceil(W / slots), raised by 1/16 steps) for which giving candidate c
+// max(1, ceil(wc / U)) items keeps the total within max(slots, candidates) (the
+// loop ends: once U exceeds every count each candidate has one item);
+// s_off[c] is candidate c's first item, s_off[nplan] the number of items.
+// Block 0 also stores the offsets for the final kernel.
+template <int NT>
+__device__ __forceinline__ int balanced_plan(const RowGeom& geo, int slots, int* s_off, int* s_wsum) {
+    const int nc = geo.nplan;
+    const int target = slots > nc ? slots : nc;
+    int64_t wl = 0;
+    for (int c = threadIdx.x; c < nc; c += NT) wl += geo.wc[c];
+    int wtot = 0;
+    (void)block_scan_excl<NT>((int)wl, s_wsum, &wtot);
+    int64_t U = (wtot + (int64_t)slots - 1) / slots;
+    if (U < 1) U = 1;
+    for (;;) {
+        int tl = 0;
+        for (int c = threadIdx.x; c < nc; c += NT) {
+            const int64_t n = (geo.wc[c] + U - 1) / U;
+            tl += n > 1 ? (int)n : 1;
+        }
+        int t = 0;
+        (void)block_scan_excl<NT>(tl, s_wsum, &t);
+        if (t <= target) break;   // block-uniform
+        U += U / 16 > 1 ? U / 16 : 1;
+    }
+    // offsets: thread t takes candidates [t * per, (t + 1) * per)
+    const int per = (nc + NT - 1) / NT;
+    int cnt = 0;
+    for (int c = threadIdx.x * per; c < nc && c < (int)(threadIdx.x + 1) * per; ++c) {
+        const int64_t n = (geo.wc[c] + U - 1) / U;
+        cnt += n > 1 ? (int)n : 1;
+    }
+    int total = 0;
+    int o = block_scan_excl<NT>(cnt, s_wsum, &total);
+    for (int c = threadIdx.x * per; c < nc && c < (int)(threadIdx.x + 1) * per; ++c) {
+        const int64_t n = (geo.wc[c] + U - 1) / U;
+        s_off[c] = o;
+        o += n > 1 ? (int)n : 1;
+    }
+    if (threadIdx.x == 0) s_off[nc] = total;
+    __syncthreads();
+    if (blockIdx.x == 0)
+        for (int c = threadIdx.x; c <= nc; c += NT) geo.item_off[c] = s_off[c];
+    return total;
 }
 
 // Lag-domain evaluation for the families with a moment form (SCV / LSCV):
@@ -608,9 +754,33 @@ __global__ __launch_bounds__(NT, D <= 2 ? (COMPACT ? 3 : 1) : 2) void k_lag_mom(
     // row-major order; the pair is advanced incrementally (no division in the loop)
     constexpr int step_ro = NT / nseg, step_j = NT % nseg;
     const int ro0 = (int)threadIdx.x / nseg, j0 = (int)threadIdx.x % nseg;
-    for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
-        const int64_t h = item / geo.nchunks;
-        const int64_t ch = item - h * geo.nchunks;
+    // balanced plan (compacted walk, geo.nplan candidates): items are windows of
+    // the candidates' live segment lists, numbered by the plan
+    __shared__ int s_off[COMPACT ? MAX_PLAN + 1 : 1];
+    __shared__ int s_pw[NT / 64];
+    int64_t nit = nitems;
+    if constexpr (COMPACT) {
+        if (geo.nplan > 0) nit = balanced_plan<NT>(geo, (int)gridDim.x, s_off, s_pw);
+    }
+    for (int64_t item = blockIdx.x; item < nit; item += gridDim.x) {
+        int64_t h, ch = 0;
+        int part = 0, parts = 1;
+        if (COMPACT && geo.nplan > 0) {
+            int lo = 0, hi = geo.nplan - 1;   // the last candidate whose first item is <= item
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= item)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            h = lo;
+            part = (int)(item - s_off[lo]);
+            parts = s_off[lo + 1] - s_off[lo];
+        } else {
+            h = item / geo.nchunks;
+            ch = item - h * geo.nchunks;
+        }
         const double* pr = prm + h * PRM;
         Fun f;
         f.load(pr);
@@ -835,7 +1005,10 @@ __global__ __launch_bounds__(NT, D <= 2 ? (COMPACT ? 3 : 1) : 2) void k_lag_mom(
                      sg = sg + step_j >= nseg ? sg + step_j - nseg : sg + step_j)
                 seg_walk(row_info<D>(rbeg + ro, rend, geo, delta, nullptr), sg * SEG, SEG);
         } else {
-            live_segments<D, N, RL, SEG, NT>(f, geo, rbeg, rend, delta, seg_walk);
+            if (geo.nplan > 0)
+                live_window<D, N, RL, SEG, NT>(f, geo, part, parts, delta, seg_walk);
+            else
+                live_segments<D, N, RL, SEG, NT>(f, geo, rbeg, rend, delta, seg_walk);
         }
         double outv[NG];
         block_sum<NG, NT>(acc, red, outv);
