@@ -322,6 +322,47 @@ int kdefft_pi_batch(int d, int n_ds, const int64_t* n_host, const double* psi4,
                     const int64_t* h_offsets_host, const double* vechL, double* obj, double* grad,
                     int32_t* status, void* stream);
 
+/* Gradient-based minimisation of a selector criterion over vech(L), H = L L^T
+ * (Sec. 5 names the PI and SCV selectors; Sec. 6 minimises them numerically
+ * without derivatives).  Each of the B = h_offsets_host[n_ds] starting points
+ * vechL0 [B, q] is its own problem: quasi-Newton steps (BFGS update of an
+ * inverse-Hessian approximation, started from the identity scaled by the
+ * first step's curvature) with a backtracking Armijo line search (sufficient
+ * decrease 1e-4; rejected steps shortened to the minimiser of the quadratic
+ * through the two values and the slope, within [0.1, 0.5] of the step; a new
+ * direction's first step moves no entry by more than 1/4 of max |vechL|).
+ * Every evaluation is one batched criterion + gradient launch at all B trial
+ * points followed by one small update launch; `evals` evaluations are enqueued
+ * on `stream` without host synchronisation (the sequence can be captured in a
+ * graph).  A candidate stops when max|grad| * max|vechL| <= tol * |crit|
+ * (converged); as stalled (no decrease left in float64) after 60 shortenings
+ * of one step or two accepted steps in a row that lower crit by no more than
+ * 4 roundings; or when the evaluations run out.  The inverse-Hessian update is
+ * skipped when s.y <= 1e-10 |s| |y| (s the step, y the gradient change).
+ *   crit KDEFFT_CRIT_SCV, KDEFFT_CRIT_LSCV, KDEFFT_CRIT_LSCV_EXACT: ds_host,
+ *       n_ds and h_offsets_host as in kdefft_crit_batch (r = 0); n_host, psi4
+ *       and d unused;
+ *   crit KDEFFT_CRIT_PI: the plug-in criterion of kdefft_pi_batch; d, n_host
+ *       and psi4 as there, ds_host unused (NULL), n_ds and h_offsets_host group
+ *       the candidates.
+ * vechL_out: device [B, q], the final points; obj_out: device [B] or NULL,
+ * their criterion values; info: device int32 [B, 2] or NULL: outcome
+ * (KDEFFT_MIN_*) and the number of accepted steps.  evals in [1, 100000],
+ * tol > 0.  Workspace: kdefft_minimize_ws_bytes. */
+#define KDEFFT_CRIT_PI 4
+#define KDEFFT_MIN_CONVERGED 0
+#define KDEFFT_MIN_RUNNING 1    /* evaluations ran out first */
+#define KDEFFT_MIN_STALLED 2
+#define KDEFFT_MIN_BAD_START 3  /* the criterion is not finite at the start (singular H) */
+int kdefft_minimize(const kdefft_dataset* ds_host, int n_ds, const int64_t* h_offsets_host, int crit,
+                    int d, const int64_t* n_host, const double* psi4, const double* vechL0, int evals,
+                    double tol, double* vechL_out, double* obj_out, int32_t* info, void* ws,
+                    size_t ws_bytes, void* stream);
+
+/* Workspace bytes of kdefft_minimize for B candidates: g is the datasets'
+ * grid (SCV / LSCV), or NULL for KDEFFT_CRIT_PI with dimension d. */
+int kdefft_minimize_ws_bytes(const kdefft_grid* g, int d, int64_t B, size_t* out);
+
 /* Fill the d^r Kronecker-ordered vector (first index slowest) from the unique
  * entries (sorted index tuples in lexicographic order; Sec. 5): full_host
  * [d^r] from unique_host [kdefft_unique_count(d, r)].  Host only. */

@@ -28,7 +28,8 @@ __all__ = ["Grid", "Dataset", "KdefftError", "grid_plan", "grid_auto", "linbin",
            "scv_adjoint", "scv_plain", "SCV", "unique_tuples", "autotune", "set_row_launch", "library_path",
            "timing_start", "timing_stop", "crit", "crit_adjoint", "pi", "expand_full", "Criterion", "PI",
            "CRIT_SCV", "CRIT_LSCV", "CRIT_LSCV_EXACT", "CRIT_QR", "fftl_plan", "psi_fftl",
-           "get_row_launch", "row_launch", "lag_layout", "scv_batch_noalloc"]
+           "get_row_launch", "row_launch", "lag_layout", "scv_batch_noalloc", "minimize", "CRIT_PI",
+           "MIN_CONVERGED", "MIN_RUNNING", "MIN_STALLED", "MIN_BAD_START"]
 
 
 def library_path():
@@ -301,8 +302,10 @@ def _split_counts(datasets, vechL, per_ds):
     return per_ds
 
 
-CRIT_SCV, CRIT_LSCV, CRIT_LSCV_EXACT, CRIT_QR = 0, 1, 2, 3
-_CRIT_NAMES = {"scv": CRIT_SCV, "lscv": CRIT_LSCV, "lscv_exact": CRIT_LSCV_EXACT, "qr": CRIT_QR}
+CRIT_SCV, CRIT_LSCV, CRIT_LSCV_EXACT, CRIT_QR, CRIT_PI = 0, 1, 2, 3, 4
+_CRIT_NAMES = {"scv": CRIT_SCV, "lscv": CRIT_LSCV, "lscv_exact": CRIT_LSCV_EXACT, "qr": CRIT_QR, "pi": CRIT_PI}
+# outcomes of minimize (include/kdefft.h KDEFFT_MIN_*)
+MIN_CONVERGED, MIN_RUNNING, MIN_STALLED, MIN_BAD_START = 0, 1, 2, 3
 
 
 def _crit_code(crit):
@@ -429,6 +432,60 @@ def scv_batch_noalloc(datasets: Sequence[Dataset], vechL: torch.Tensor, obj: tor
 
 def scv_adjoint(datasets: Sequence[Dataset], vechL: torch.Tensor, grad_out: torch.Tensor, per_ds=None):
     return crit_adjoint(datasets, vechL, grad_out, "scv", per_ds)
+
+
+def minimize(vechL0: torch.Tensor, crit="scv", datasets: Optional[Sequence[Dataset]] = None, per_ds=None,
+             psi4: Optional[torch.Tensor] = None, ns: Optional[Sequence[int]] = None, evals: int = 80,
+             tol: float = 1e-9):
+    """kdefft_minimize: quasi-Newton minimisation of the criterion ("scv",
+    "lscv", "lscv_exact" on prepared datasets, or "pi" from psi4 [n_ds, C(d+3,4)]
+    and sample sizes ns) from each starting point vechL0 [B, q] independently,
+    `evals` batched evaluations enqueued without host synchronisation.
+    Returns (vechL [B, q], crit values [B], info [B, 2] = (outcome, accepted
+    steps)); outcomes MIN_CONVERGED / MIN_RUNNING / MIN_STALLED / MIN_BAD_START."""
+    import ctypes as C
+    code = _crit_code(crit)
+    if code == CRIT_PI:
+        if psi4 is None or ns is None:
+            raise ValueError("the PI criterion needs psi4 and ns")
+        dev = psi4.device
+        psi4 = psi4.to(dtype=torch.float64).contiguous()
+        nn = np.array([int(v) for v in ns], dtype=np.int64)
+        nds = len(nn)
+        arr, grid_p = None, None
+    else:
+        datasets = list(datasets)
+        if len(datasets) > _lib.MAX_BATCH_DS:
+            raise ValueError(f"at most {_lib.MAX_BATCH_DS} datasets per call")
+        dev = datasets[0].device
+        nds = len(datasets)
+        arr = _ds_array(datasets)
+        grid_p = C.byref(datasets[0].shape_grid)
+        nn = None
+    x0 = vechL0.to(device=dev, dtype=torch.float64).contiguous()
+    B, q = x0.shape
+    d = int(round((np.sqrt(8 * q + 1) - 1) / 2))
+    if per_ds is None:
+        if nds != 1:
+            raise ValueError("give per_ds (candidates per dataset) for several datasets")
+        per_ds = [B]
+    per_ds = [int(c) for c in per_ds]
+    if sum(per_ds) != B or len(per_ds) != nds:
+        raise ValueError("per_ds must have one count per dataset and add up to B")
+    off = np.zeros(nds + 1, dtype=np.int64)
+    off[1:] = np.cumsum(per_ds)
+    need = C.c_size_t()
+    _lib.check(_L().kdefft_minimize_ws_bytes(grid_p, d, B, C.byref(need)), "kdefft_minimize_ws_bytes")
+    ws = torch.empty(max(int(need.value), 256), dtype=torch.uint8, device=dev)
+    x = torch.empty((B, q), dtype=torch.float64, device=dev)
+    f = torch.empty(B, dtype=torch.float64, device=dev)
+    info = torch.empty((B, 2), dtype=torch.int32, device=dev)
+    _lib.check(_L().kdefft_minimize(arr, nds, off.ctypes.data, code, d,
+                                    nn.ctypes.data if nn is not None else None,
+                                    _ptr(psi4) if code == CRIT_PI else None, _ptr(x0), int(evals), float(tol),
+                                    _ptr(x), _ptr(f), _ptr(info), _ptr(ws), ws.numel(), _stream(dev)),
+               "kdefft_minimize")
+    return x, f, info
 
 
 def pi(psi4: torch.Tensor, ns: Sequence[int], vechL: torch.Tensor, per_ds=None, grad: bool = True,

@@ -84,6 +84,10 @@ EXPORTS = {
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "kdefft_scv_batch_noalloc": (C.c_int, [C.POINTER(Dataset), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.c_void_p, C.c_void_p, C.c_void_p]),
+    "kdefft_minimize": (C.c_int, [C.POINTER(Dataset), C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "kdefft_minimize_ws_bytes": (C.c_int, [C.POINTER(Grid), C.c_int, C.c_int64, C.POINTER(C.c_size_t)]),
     "kdefft_timing_start": (C.c_int, [C.c_int]),
     "kdefft_timing_stop": (C.c_int, [C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int)]),
 }

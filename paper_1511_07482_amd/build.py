@@ -31,7 +31,7 @@ COMMON = [
 # host-side arithmetic must round exactly like the CPU reference
 HOST_EXTRA = ["-ffp-contract=off"]
 
-UNITS = ["api.cpp", "noalloc.hip", "fft.hip", "bin.hip", "plain.hip", "rows.hip",
+UNITS = ["api.cpp", "noalloc.hip", "minimize.hip", "fft.hip", "bin.hip", "plain.hip", "rows.hip",
          "rows_d1.hip", "rows_d2.hip", "rows_d3.hip", "rows_d4.hip",
          "rows_eta_d1.hip", "rows_eta_d2.hip", "rows_eta_d3.hip", "rows_eta_d4.hip"]
 HEADERS = ["dev_common.h", "dev_kernels.h", "eta_fun.h", "finish.h", "internal.h", "params.h", "rows_impl.h",

@@ -1255,6 +1255,111 @@ int kdefft_pi_batch(int d, int n_ds, const int64_t* n_host, const double* psi4, 
     return KDEFFT_OK;
 }
 
+// ---------------------------------------------------------------- minimiser
+
+namespace {
+
+struct MinScratch {
+    double* st;
+    int32_t* ist;
+    double* ft;
+    double* gt;
+    int32_t* stt;
+    double* xt;
+};
+
+MinScratch carve_min(Arena& a, int q, int64_t B) {
+    MinScratch m;
+    m.st = a.take<double>((size_t)B * min_state_doubles(q));
+    m.ist = a.take<int32_t>((size_t)B * min_state_ints());
+    m.ft = a.take<double>((size_t)B);
+    m.gt = a.take<double>((size_t)B * q);
+    m.stt = a.take<int32_t>((size_t)B);
+    m.xt = a.take<double>((size_t)B * q);
+    return m;
+}
+
+// workspace of the minimiser: its state, then the criterion's workspace (g =
+// the datasets' grid, whose shape alone sizes it; NULL for PI)
+int min_ws_need(const kdefft_grid* g, int q, int64_t B, size_t* out) {
+    Arena a(nullptr, 0, true);
+    (void)carve_min(a, q, B);
+    size_t crit = 0;
+    if (g) {
+        Arena c(nullptr, 0, true);
+        const int rc = plan_bytes(*g, KDEFFT_OP_SCV_BATCH, 0, B, c);
+        if (rc) return rc;
+        crit = c.off + 256;
+    }
+    *out = ((a.off + 255) & ~size_t(255)) + crit + 256;
+    return KDEFFT_OK;
+}
+
+}  // namespace
+
+int kdefft_minimize_ws_bytes(const kdefft_grid* g, int d, int64_t B, size_t* out) {
+    if (!out) return fail(KDEFFT_E_ARG, "out is NULL");
+    if (B < 1 || B > (1LL << 24)) return fail(KDEFFT_E_ARG, "B=%lld", (long long)B);
+    if (g) {
+        const int rc = check_grid(g);
+        if (rc) return rc;
+        d = g->d;
+    }
+    if (d < 1 || d > KDEFFT_MAX_D) return fail(KDEFFT_E_ARG, "d=%d outside [1,4]", d);
+    return min_ws_need(g, d * (d + 1) / 2, B, out);
+}
+
+int kdefft_minimize(const kdefft_dataset* ds, int n_ds, const int64_t* off, int crit, int d, const int64_t* n_host,
+                    const double* psi4, const double* vechL0, int evals, double tol, double* vechL_out,
+                    double* obj_out, int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+    if (!off || !vechL0 || !vechL_out) return fail(KDEFFT_E_ARG, "NULL h_offsets, vechL0 or vechL_out");
+    if (evals < 1 || evals > 100000) return fail(KDEFFT_E_ARG, "evals=%d outside [1, 100000]", evals);
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(KDEFFT_E_ARG, "tol must be finite and > 0");
+    if (n_ds < 1 || n_ds > KDEFFT_MAX_BATCH_DS) return fail(KDEFFT_E_ARG, "n_ds=%d", n_ds);
+    if (off[0] != 0) return fail(KDEFFT_E_ARG, "h_offsets[0] must be 0");
+    for (int j = 0; j < n_ds; ++j)
+        if (off[j + 1] < off[j]) return fail(KDEFFT_E_ARG, "h_offsets must be non-decreasing");
+    const int64_t B = off[n_ds];
+    if (B < 1 || B > (1LL << 24)) return fail(KDEFFT_E_ARG, "B=%lld", (long long)B);
+    const bool pi = crit == KDEFFT_CRIT_PI;
+    if (!pi && crit != KDEFFT_CRIT_SCV && crit != KDEFFT_CRIT_LSCV && crit != KDEFFT_CRIT_LSCV_EXACT)
+        return fail(KDEFFT_E_ARG, "crit=%d has no gradient to minimise with", crit);
+    const kdefft_grid* g = nullptr;
+    if (pi) {
+        if (!n_host || !psi4) return fail(KDEFFT_E_ARG, "the PI criterion needs n_host and psi4");
+        if (d < 1 || d > KDEFFT_MAX_D) return fail(KDEFFT_E_ARG, "d=%d outside [1,4]", d);
+    } else {
+        const int rc = check_batch_ds(ds, n_ds, KDEFFT_MAX_BATCH_DS);
+        if (rc) return rc;
+        g = &ds[0].grid;
+        d = g->d;
+    }
+    const int q = d * (d + 1) / 2;
+    size_t need = 0;
+    int rc = min_ws_need(g, q, B, &need);
+    if (rc) return rc;
+    if (!ws) return fail(KDEFFT_E_ARG, "workspace is NULL");
+    if (ws_bytes < need) return fail(KDEFFT_E_WORKSPACE, "workspace %zu bytes < %zu", ws_bytes, need);
+    Arena a(ws, ws_bytes, false);
+    const MinScratch m = carve_min(a, q, B);
+    char* crit_ws = static_cast<char*>(ws) + ((a.off + 255) & ~size_t(255));
+    const size_t crit_bytes = ws_bytes - (size_t)(crit_ws - static_cast<char*>(ws));
+    hipStream_t s = S(stream);
+    HIPCHK(launch_min_init(B, q, vechL0, m.xt, m.ist, s), "minimiser init");
+    for (int e = 0; e < evals; ++e) {
+        if (pi) {
+            rc = kdefft_pi_batch(d, n_ds, n_host, psi4, off, m.xt, m.ft, m.gt, m.stt, stream);
+        } else {
+            rc = crit_common(ds, n_ds, off, m.xt, crit, 0, FUN_SCV_OBJGRAD, nullptr, m.ft, m.gt, m.stt, crit_ws,
+                             crit_bytes, stream, nullptr);
+        }
+        if (rc) return rc;
+        HIPCHK(launch_min_step(B, q, tol, m.st, m.ist, m.ft, m.gt, m.stt, m.xt, s), "minimiser step");
+    }
+    HIPCHK(launch_min_final(B, q, m.st, m.ist, vechL_out, obj_out, info, s), "minimiser final");
+    return KDEFFT_OK;
+}
+
 int kdefft_expand_full(int d, int r, const double* unique_host, double* full_host) {
     if (d < 1 || d > 4 || r < 0 || r > 8) return fail(KDEFFT_E_ARG, "d=%d r=%d", d, r);
     if (!unique_host || !full_host) return fail(KDEFFT_E_ARG, "NULL argument");

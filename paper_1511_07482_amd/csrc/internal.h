@@ -211,6 +211,15 @@ hipError_t launch_psi_final(const double* partial, const RowGeom& geo, int ng,
                             const double* prm, int64_t ncand, double* psi, double* scal_out,
                             hipStream_t s);
 
+// batched quasi-Newton minimiser (minimize.hip): per-candidate state of
+// min_state_doubles(q) doubles and min_state_ints() int32
+int min_state_doubles(int q);
+int min_state_ints();
+hipError_t launch_min_init(int64_t B, int q, const double* x0, double* xt, int32_t* ist, hipStream_t s);
+hipError_t launch_min_step(int64_t B, int q, double tol, double* st, int32_t* ist, const double* ft,
+                           const double* gt, const int32_t* stt, double* xt, hipStream_t s);
+hipError_t launch_min_final(int64_t B, int q, const double* st, const int32_t* ist, double* x_out, double* f_out,
+                            int32_t* info, hipStream_t s);
 hipError_t launch_pi(const PiArgs& a, const double* psi4, const double* vechL, int64_t ncand, double* obj,
                      double* grad, int32_t* status, hipStream_t s);
 

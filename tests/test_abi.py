@@ -214,6 +214,42 @@ def test_criterion_entry_validation(kf):
     assert pb(2, 1, n0.ctypes.data, fake, off.ctypes.data, fake, fake, None, None, None) == L.E_ARG
 
 
+def test_minimize_entry_validation(kf):
+    lib = kf._lib.load()
+    L = kf._lib
+    ds = _fake_prepared(kf)
+    fake = C.c_void_p(0x1000)
+    off = np.array([0, 4], dtype=np.int64)
+    nn = np.array([100], dtype=np.int64)
+    mz = lib.kdefft_minimize
+    big = 1 << 30
+
+    def call(crit=kf.CRIT_SCV, d=2, evals=10, tol=1e-9, ws_bytes=big, psi4=fake, offs=off, x_out=fake, dsa=ds):
+        return mz(dsa, 1, offs.ctypes.data, crit, d, nn.ctypes.data, psi4, fake, evals, tol, x_out, None, None,
+                  fake, ws_bytes, None)
+
+    assert call(evals=0) == L.E_ARG
+    assert call(evals=100001) == L.E_ARG
+    assert call(tol=0.0) == L.E_ARG
+    assert call(tol=float("nan")) == L.E_ARG
+    assert call(crit=kf.CRIT_QR) == L.E_ARG       # no gradient
+    assert call(crit=9) == L.E_ARG
+    assert call(x_out=None) == L.E_ARG
+    assert call(offs=np.array([1, 4], dtype=np.int64)) == L.E_ARG
+    assert call(offs=np.array([0, 0], dtype=np.int64)) == L.E_ARG
+    assert call(ws_bytes=64) == L.E_WORKSPACE
+    assert call(crit=kf.CRIT_PI, d=5, dsa=None) == L.E_ARG
+    assert call(crit=kf.CRIT_PI, psi4=None, dsa=None) == L.E_ARG
+    assert call(crit=kf.CRIT_PI, ws_bytes=64, dsa=None) == L.E_WORKSPACE
+    n = C.c_size_t()
+    assert lib.kdefft_minimize_ws_bytes(None, 2, 8, C.byref(n)) == L.OK and n.value > 8 * 8 * 8
+    pi_only = n.value
+    g = kf.grid_plan([32, 32], lo=[0.0, 0.0], hi=[1.0, 1.0])
+    assert lib.kdefft_minimize_ws_bytes(C.byref(g), 0, 8, C.byref(n)) == L.OK and n.value > pi_only
+    assert lib.kdefft_minimize_ws_bytes(None, 0, 8, C.byref(n)) == L.E_ARG
+    assert lib.kdefft_minimize_ws_bytes(None, 2, 0, C.byref(n)) == L.E_ARG
+
+
 @pytest.mark.parametrize("d,r", [(1, 0), (1, 4), (2, 0), (2, 4), (3, 2), (3, 4), (4, 4), (2, 8), (4, 3)])
 def test_expand_full_matches_oracle(kf, d, r):
     u = np.arange(1, multiindex.n_unique(d, r) + 1, dtype=np.float64) * 1.5
