@@ -434,14 +434,39 @@ int kdefft_lag_layout(int N, int moments, int* run_len, int* runs_per_seg, int* 
 int kdefft_timing_start(int max_launches);
 int kdefft_timing_stop(float* ms_out, int32_t* tag_out, int cap, int* count_out);
 
-/* Time the compiled launch variants of the batched kernels (rows per block
- * iteration / LDS footprint, radix schedule of the row transforms, persistent
- * grid size) for this dataset's grid shape on the current device, keep the
- * fastest for the rest of the process, and append the choice to cache_path
- * (one JSON object per line; NULL = no file).  Each launch is timed on 256
- * candidates H = s G (s spread over [0.5, 8], G the dataset's matrix); the
- * default (variant 4, grid 0) is kept unless another launch is more than 3%
- * faster.  Workspace: KDEFFT_OP_AUTOTUNE.  Synchronizes `stream`. */
+/* FFT-stage schedule of the count transform (Sec. 4, Eq. (19)-(23): the
+ * R2C, leading-axis and C2R passes of dataset preparation) for grids of shape
+ * (d, P_host[0..d-1]) on the current device, for the rest of the process:
+ *   0 (default) one-wavefront blocks when the 256-thread shape would give
+ *     fewer than 512 blocks, else 256-thread blocks of ~2048 values; radix-8
+ *     Stockham stages first (radix 4 or 2 for the remainder);
+ *   1 the same shapes with radix-4 stages (one radix-8 or 2 when log2 P is odd);
+ *   2 256-thread blocks for every pass (strided passes on 16-column tiles, or
+ *     whole [P][Q] slabs for Q = 17, 33);
+ *   3 one-wavefront blocks for every pass that has them;
+ *   4 strided passes on half-width tiles (twice the blocks).
+ * All schedules compute the same transform (they differ in rounding order
+ * only).  sched = -1 drops the pinned or tuned choice.  Host only. */
+#define KDEFFT_FFT_SCHEDULES 5
+int kdefft_set_fft_schedule(int d, const int32_t* P_host, int sched);
+int kdefft_get_fft_schedule(int d, const int32_t* P_host, int* sched);
+
+/* Time the compiled launch choices for this dataset's grid shape on the
+ * current device, keep the fastest of each for the rest of the process, and
+ * append the choices to cache_path (one JSON object per line; NULL = no file;
+ * the file named by the environment variable KDEFFT_TUNE_CACHE is read back at
+ * the first batched call of a process):
+ *   the count transform's FFT schedule (kdefft_set_fft_schedule), re-running
+ *     the dataset's transform, which is left computed by the chosen schedule;
+ *   the SCV families and the same kernels serving LSCV (row-kernel variant and
+ *     persistent grid size, as kdefft_set_row_launch), timed on 256 candidates
+ *     H = s G (s spread over [0.5, 8], G the dataset's matrix);
+ *   LSCV_4 (the scalar eta family: grid size) on the same candidates;
+ *   psi_4 at the dataset's pilot (variants 0-3, grid size).
+ * Each default (FFT schedule 0; variant 4 grid 0 for SCV / LSCV; variant 3
+ * grid 0 otherwise) is kept unless another choice is more than 3% faster.
+ * kdefft_last_error_detail() returns the timings afterwards.  Workspace:
+ * KDEFFT_OP_AUTOTUNE.  Synchronizes `stream`. */
 int kdefft_autotune(const kdefft_dataset* ds_host, void* ws, size_t ws_bytes,
                     const char* cache_path, void* stream);
 

@@ -29,7 +29,8 @@ __all__ = ["Grid", "Dataset", "KdefftError", "grid_plan", "grid_auto", "linbin",
            "timing_start", "timing_stop", "crit", "crit_adjoint", "pi", "expand_full", "Criterion", "PI",
            "CRIT_SCV", "CRIT_LSCV", "CRIT_LSCV_EXACT", "CRIT_QR", "fftl_plan", "psi_fftl",
            "get_row_launch", "row_launch", "lag_layout", "scv_batch_noalloc", "minimize", "CRIT_PI",
-           "MIN_CONVERGED", "MIN_RUNNING", "MIN_STALLED", "MIN_BAD_START"]
+           "MIN_CONVERGED", "MIN_RUNNING", "MIN_STALLED", "MIN_BAD_START", "set_fft_schedule",
+           "get_fft_schedule", "fft_schedule", "FFT_SCHEDULES"]
 
 
 def library_path():
@@ -623,6 +624,42 @@ def get_row_launch(kind: int, d: int, r: int, N: int):
     v, gb = C.c_int(), C.c_int()
     _lib.check(_L().kdefft_get_row_launch(kind, d, r, N, C.byref(v), C.byref(gb)), "kdefft_get_row_launch")
     return v.value, gb.value
+
+
+FFT_SCHEDULES = _lib.FFT_SCHEDULES
+
+
+def set_fft_schedule(P, sched: int):
+    """Pin the count transform's FFT schedule for grids with last-axis lengths
+    P (one entry per axis); sched -1 drops the pin (include/kdefft.h)."""
+    Pa = np.asarray(P, dtype=np.int32)
+    _lib.check(_L().kdefft_set_fft_schedule(len(Pa), Pa.ctypes.data, int(sched)), "kdefft_set_fft_schedule")
+
+
+def get_fft_schedule(P) -> int:
+    """The FFT schedule the count transform uses now for grids of lengths P."""
+    Pa = np.asarray(P, dtype=np.int32)
+    out = C.c_int()
+    _lib.check(_L().kdefft_get_fft_schedule(len(Pa), Pa.ctypes.data, C.byref(out)), "kdefft_get_fft_schedule")
+    return out.value
+
+
+class fft_schedule:
+    """Context manager: pin an FFT schedule for one grid shape, restore on exit."""
+
+    def __init__(self, P, sched: int):
+        self.P = list(P)
+        self.sched = sched
+        self.saved = None
+
+    def __enter__(self):
+        self.saved = get_fft_schedule(self.P)
+        set_fft_schedule(self.P, self.sched)
+        return self
+
+    def __exit__(self, *exc):
+        set_fft_schedule(self.P, self.saved)
+        return False
 
 
 class row_launch:

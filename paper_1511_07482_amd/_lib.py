@@ -10,6 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkdefft.so")
 
 OK = 0
+FFT_SCHEDULES = 5
 E_ARG, E_NOT_SPD, E_ODD_R, E_OUT_OF_GRID, E_OVERFLOW, E_WORKSPACE, E_HIP, E_UNSUPPORTED = range(-1, -9, -1)
 OP_GRID_AUTO, OP_PSI_PLAIN, OP_PSI_FUSED, OP_PREPARE, OP_PSI_BATCH, OP_SCV_BATCH, OP_SCV_PLAIN, OP_AUTOTUNE, \
     OP_PSI_FFTL, OP_PREPARE_AUTO = range(1, 11)
@@ -88,6 +89,8 @@ EXPORTS = {
                                   C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "kdefft_minimize_ws_bytes": (C.c_int, [C.POINTER(Grid), C.c_int, C.c_int64, C.POINTER(C.c_size_t)]),
+    "kdefft_set_fft_schedule": (C.c_int, [C.c_int, C.c_void_p, C.c_int]),
+    "kdefft_get_fft_schedule": (C.c_int, [C.c_int, C.c_void_p, C.POINTER(C.c_int)]),
     "kdefft_timing_start": (C.c_int, [C.c_int]),
     "kdefft_timing_stop": (C.c_int, [C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int)]),
 }

@@ -22,6 +22,7 @@ namespace {
 
 // Candidates per timed launch in kdefft_autotune.
 constexpr int TUNE_B = 256;
+constexpr int TUNE_PSI_OUT = 64;   // psi_4 outputs of one dataset (35 for d = 4)
 
 thread_local std::string g_err;
 
@@ -269,6 +270,8 @@ int json_int(const std::string& line, const char* key, int dflt) {
     return std::atoi(line.c_str() + p);
 }
 
+void fft_cache_entry(int dev, int d, const int32_t* P, int fs);
+
 void load_cache_locked(int dev) {
     if (g_cache_loaded) return;
     g_cache_loaded = true;
@@ -281,8 +284,15 @@ void load_cache_locked(int dev) {
     while (std::fgets(buf, sizeof(buf), f)) {
         std::string line(buf);
         if (line.find("\"arch\": \"" + arch + "\"") == std::string::npos) continue;
+        if (json_int(line, "fft", 0) == 1) {
+            const int32_t P[4] = {json_int(line, "P0", 0), json_int(line, "P1", 0), json_int(line, "P2", 0),
+                                  json_int(line, "P3", 0)};
+            const int fs = json_int(line, "sched", -1), d = json_int(line, "d", 0);
+            if (d >= 1 && d <= 4 && fs >= 0 && fs < FFT_SCHEDULES) fft_cache_entry(dev, d, P, fs);
+            continue;
+        }
         LaunchKey k{dev, json_int(line, "kind", -1), json_int(line, "d", 0), json_int(line, "r", 0),
-                    json_int(line, "N", 0), 0};
+                    json_int(line, "N", 0), json_int(line, "crit", 0)};
         RowLaunch rl{json_int(line, "variant", 0), json_int(line, "grid", 0)};
         if (k.kind >= 0 && rl.variant >= 0 && rl.variant < ROW_VARIANTS) g_launch[k] = rl;
     }
@@ -302,11 +312,47 @@ RowLaunch launch_for(int kind, int d, int r, int N, int crit = 0) {
     return RowLaunch{mom ? 4 : 3, 0};
 }
 
-void set_launch(int kind, int d, int r, int N, RowLaunch rl) {
+void set_launch(int kind, int d, int r, int N, RowLaunch rl, int crit = 0) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     std::lock_guard<std::mutex> lk(g_launch_mu);
-    g_launch[LaunchKey{dev, kind, d, r, N, 0}] = rl;
+    g_launch[LaunchKey{dev, kind, d, r, N, crit}] = rl;
+}
+
+// FFT-stage schedule of the count transform per device and grid shape (d, P)
+struct FftKey {
+    int dev, d, P[4];
+    bool operator<(const FftKey& o) const {
+        return std::tie(dev, d, P[0], P[1], P[2], P[3]) < std::tie(o.dev, o.d, o.P[0], o.P[1], o.P[2], o.P[3]);
+    }
+};
+std::map<FftKey, int> g_fft;
+
+FftKey fft_key(int dev, int d, const int32_t* P) {
+    FftKey k{dev, d, {0, 0, 0, 0}};
+    for (int i = 0; i < d; ++i) k.P[i] = P[i];
+    return k;
+}
+
+int fft_sched_for(const kdefft_grid& g) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_launch_mu);
+    load_cache_locked(dev);
+    auto it = g_fft.find(fft_key(dev, g.d, g.P));
+    return it == g_fft.end() ? 0 : it->second;
+}
+
+void fft_cache_entry(int dev, int d, const int32_t* P, int fs) { g_fft[fft_key(dev, d, P)] = fs; }
+
+void set_fft_sched(int d, const int32_t* P, int fs) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_launch_mu);
+    if (fs < 0)
+        g_fft.erase(fft_key(dev, d, P));
+    else
+        g_fft[fft_key(dev, d, P)] = fs;
 }
 
 void clear_launch(int kind, int d, int r, int N) {
@@ -466,6 +512,12 @@ int plan_bytes(const kdefft_grid& g, int op, int r, int64_t batch, Arena& a) {
             a.take<double>(TUNE_B * q);
             a.take<double>(TUNE_B);
             a.take<double>(TUNE_B * q);
+            a.take<double>(TUNE_PSI_OUT);
+            // the psi_4 timings carve their own scratch from the start of the
+            // workspace: at least that much
+            Arena ap(nullptr, 0, true);
+            carve_batch(ap, g, FUN_PSI, 4, 1);
+            if (ap.off > a.off) a.off = ap.off;
             return KDEFFT_OK;
         }
         default: return fail(KDEFFT_E_ARG, "unknown op %d", op);
@@ -540,8 +592,9 @@ int prepare_into(const double* X, int64_t n, const kdefft_grid& g, const double*
         HIPCHK(launch_ds_header(h, s), "dataset header");
         HIPCHK(launch_linbin_xcd(X, n, g, p.copies, L.n_out, s, nullptr, false), "linbin");
     }
-    HIPCHK(fft_prepare_nd(p.copies, XCD_COPIES, L.counts, L.spec, L.wmix, g, s), "count transform");
-    HIPCHK(fft_autocorr_nd(L.wmix, L.alag, g, s), "count autocorrelation");
+    const int fs = fft_sched_for(g);
+    HIPCHK(fft_prepare_nd(p.copies, XCD_COPIES, L.counts, L.spec, L.wmix, g, s, fs), "count transform");
+    HIPCHK(fft_autocorr_nd(L.wmix, L.alag, g, s, fs), "count autocorrelation");
     return KDEFFT_OK;
 }
 
@@ -1076,8 +1129,16 @@ int kdefft_dataset_grid(const kdefft_dataset* ds, kdefft_grid* out, void* stream
     return KDEFFT_OK;
 }
 
+static int psi_batch_common(const kdefft_dataset* ds, int n_ds, const double* G_host, int r, double* psi, void* ws,
+                            size_t ws_bytes, void* stream, const RowLaunch* force);
+
 int kdefft_psi_batch(const kdefft_dataset* ds, int n_ds, const double* G_host, int r, double* psi, void* ws,
                      size_t ws_bytes, void* stream) {
+    return psi_batch_common(ds, n_ds, G_host, r, psi, ws, ws_bytes, stream, nullptr);
+}
+
+static int psi_batch_common(const kdefft_dataset* ds, int n_ds, const double* G_host, int r, double* psi, void* ws,
+                            size_t ws_bytes, void* stream, const RowLaunch* force) {
     int rc = check_batch_ds(ds, n_ds, KDEFFT_MAX_PSI_DS);
     if (rc) return rc;
     const kdefft_grid& g = ds[0].grid;
@@ -1103,7 +1164,7 @@ int kdefft_psi_batch(const kdefft_dataset* ds, int n_ds, const double* G_host, i
     for (int j = 0; j < n_ds; ++j) recs[j] = static_cast<const DsDev*>(ds[j].rec);
     PsiBatchArgs args = psi_args(g, r, n_ds, recs.data(), Gs.data());
     hipStream_t s = S(stream);
-    const RowLaunch rl = launch_for(FUN_PSI, d, r, g.P[d - 1]);
+    const RowLaunch rl = force ? *force : launch_for(FUN_PSI, d, r, g.P[d - 1]);
     const int nu = (int)binom(d + r - 1, r);
     const RowGeom geo = make_geom(g, FUN_PSI, r, n_ds, rl.variant);
     args.fin = fin_psi(rl, geo, nu, b.counters, psi, nullptr);
@@ -1475,6 +1536,35 @@ int kdefft_set_row_launch(int kind, int d, int r, int N, int variant, int grid_b
     return KDEFFT_OK;
 }
 
+static int check_fft_shape(int d, const int32_t* P) {
+    if (d < 1 || d > KDEFFT_MAX_D) return fail(KDEFFT_E_ARG, "d=%d outside [1,4]", d);
+    if (!P) return fail(KDEFFT_E_ARG, "P_host is NULL");
+    for (int k = 0; k < d; ++k)
+        if (P[k] < 4 || P[k] > KDEFFT_MAX_P || (P[k] & (P[k] - 1)))
+            return fail(KDEFFT_E_ARG, "P[%d]=%d is not a power of two in [4, %d]", k, P[k], KDEFFT_MAX_P);
+    return KDEFFT_OK;
+}
+
+int kdefft_set_fft_schedule(int d, const int32_t* P_host, int sched) {
+    const int rc = check_fft_shape(d, P_host);
+    if (rc) return rc;
+    if (sched < -1 || sched >= FFT_SCHEDULES) return fail(KDEFFT_E_ARG, "sched=%d", sched);
+    set_fft_sched(d, P_host, sched);
+    return KDEFFT_OK;
+}
+
+int kdefft_get_fft_schedule(int d, const int32_t* P_host, int* sched) {
+    const int rc = check_fft_shape(d, P_host);
+    if (rc) return rc;
+    if (!sched) return fail(KDEFFT_E_ARG, "NULL output");
+    kdefft_grid g;
+    std::memset(&g, 0, sizeof(g));
+    g.d = d;
+    for (int k = 0; k < d; ++k) g.P[k] = P_host[k];
+    *sched = fft_sched_for(g);
+    return KDEFFT_OK;
+}
+
 int kdefft_get_row_launch(int kind, int d, int r, int N, int* variant, int* grid_blocks) {
     if (kind < 0 || kind > FUN_ETA2) return fail(KDEFFT_E_ARG, "kind=%d", kind);
     if (!variant || !grid_blocks) return fail(KDEFFT_E_ARG, "NULL output");
@@ -1483,6 +1573,60 @@ int kdefft_get_row_launch(int kind, int d, int r, int N, int* variant, int* grid
     *grid_blocks = rl.grid_blocks;
     return KDEFFT_OK;
 }
+
+extern "C++" {
+namespace {
+
+// Timing of one launch choice: one untimed call, then the mean of 5 between
+// two events on the stream.
+template <class Fn>
+int time_choice(hipStream_t s, hipEvent_t e0, hipEvent_t e1, Fn&& fn, float* ms) {
+    int rc = fn();
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(e0, s), "event");
+    for (int rep = 0; rep < 5; ++rep) {
+        rc = fn();
+        if (rc) return rc;
+    }
+    HIPCHK(hipEventRecord(e1, s), "event");
+    HIPCHK(hipEventSynchronize(e1), "event sync");
+    HIPCHK(hipEventElapsedTime(ms, e0, e1), "elapsed");
+    *ms /= 5.f;
+    return KDEFFT_OK;
+}
+
+// The fastest of a family's launch choices; the default keeps its place unless
+// another is more than 3% faster, so that timing noise does not flip the
+// choice from run to run.
+struct Pick {
+    RowLaunch best{0, 0};
+    float best_ms = 1e30f, dflt_ms = -1.f;
+    void add(RowLaunch rl, float ms, RowLaunch dflt) {
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = rl;
+        }
+        if (rl.variant == dflt.variant && rl.grid_blocks == dflt.grid_blocks) dflt_ms = ms;
+    }
+    void settle(RowLaunch dflt) {
+        if (dflt_ms > 0.f && best_ms > 0.97f * dflt_ms) {
+            best = dflt;
+            best_ms = dflt_ms;
+        }
+    }
+};
+
+void append_line(std::string& lines, const char* fmt, ...) {
+    char buf[256];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    lines += buf;
+}
+
+}  // namespace
+}  // extern "C++"
 
 int kdefft_autotune(const kdefft_dataset* ds, void* ws, size_t ws_bytes, const char* cache_path, void* stream) {
     int rc = check_batch_ds(ds, 1, 1);
@@ -1495,6 +1639,7 @@ int kdefft_autotune(const kdefft_dataset* ds, void* ws, size_t ws_bytes, const c
     double* vech = a.take<double>(TUNE_B * q);
     double* obj = a.take<double>(TUNE_B);
     double* grad = a.take<double>(TUNE_B * q);
+    double* psi_out = a.take<double>(TUNE_PSI_OUT);
     rc = check_ws(a, ws_bytes);
     if (rc) return rc;
     // TUNE_B candidates H_b = s_b * Gpilot with s_b spread over [0.5, 8]
@@ -1514,66 +1659,160 @@ int kdefft_autotune(const kdefft_dataset* ds, void* ws, size_t ws_bytes, const c
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0), "event");
     HIPCHK(hipEventCreate(&e1), "event");
-    const int grids[2] = {0, -1};
-    RowLaunch best{0, 0};
-    float best_ms = 1e30f;
-    // The untuned default keeps its place unless another launch beats it by
-    // more than 3%, so that timing noise does not flip the choice run to run.
-    const RowLaunch dflt{4, 0};
-    float dflt_ms = -1.f;
-    std::string lines;
+    std::string lines, cache;
     const std::string arch = [] {
         int dev = 0;
         (void)hipGetDevice(&dev);
         return arch_name(dev);
     }();
-    for (int v = 0; v < ROW_VARIANTS; ++v) {
-        if (rows_per_iter(FUN_SCV_OBJGRAD, d, 2, N, v) < 1) continue;
-        for (int gi = 0; gi < 2; ++gi) {
-            const RowLaunch rl{v, grids[gi]};
-            rc = scv_common(ds, 1, off, vech, FUN_SCV_OBJGRAD, nullptr, obj, grad, nullptr, ws, ws_bytes, stream, &rl);
-            if (rc) break;
-            HIPCHK(hipEventRecord(e0, s), "event");
-            for (int rep = 0; rep < 5; ++rep) {
-                rc = scv_common(ds, 1, off, vech, FUN_SCV_OBJGRAD, nullptr, obj, grad, nullptr, ws, ws_bytes, stream,
-                                &rl);
-                if (rc) break;
-            }
-            HIPCHK(hipEventRecord(e1, s), "event");
-            HIPCHK(hipEventSynchronize(e1), "event sync");
+    const int grids[2] = {0, -1};
+
+    // 1. FFT stage: the dataset's count transform and autocorrelation under
+    // every schedule (the dataset is left holding the chosen schedule's result)
+    int fbest = 0;
+    {
+        float fbest_ms = 1e30f, f0_ms = -1.f;
+        const kdefft_dataset* dsp = ds;
+        for (int fs = 0; fs < FFT_SCHEDULES && !rc; ++fs) {
             float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1), "elapsed");
-            ms /= 5.f;
-            char buf[256];
-            snprintf(buf, sizeof(buf), "variant %d grid %d: %.1f us\n", v, rl.grid_blocks, ms * 1000.0);
-            lines += buf;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = rl;
+            rc = time_choice(s, e0, e1, [&]() -> int {
+                HIPCHK(fft_prepare_nd(dsp->counts, 0, nullptr, reinterpret_cast<double2*>(dsp->spec),
+                                      reinterpret_cast<double2*>(dsp->wmix), g, s, fs), "count transform");
+                HIPCHK(fft_autocorr_nd(reinterpret_cast<const double2*>(dsp->wmix), dsp->alag, g, s, fs),
+                       "count autocorrelation");
+                return KDEFFT_OK;
+            }, &ms);
+            if (rc) break;
+            append_line(lines, "fft schedule %d: %.1f us\n", fs, ms * 1000.0);
+            if (ms < fbest_ms) {
+                fbest_ms = ms;
+                fbest = fs;
             }
-            if (rl.variant == dflt.variant && rl.grid_blocks == dflt.grid_blocks) dflt_ms = ms;
+            if (fs == 0) f0_ms = ms;
+        }
+        if (!rc) {
+            if (f0_ms > 0.f && fbest_ms > 0.97f * f0_ms) {
+                fbest = 0;
+                fbest_ms = f0_ms;
+            }
+            set_fft_sched(d, g.P, fbest);
+            rc = fft_prepare_nd(ds->counts, 0, nullptr, reinterpret_cast<double2*>(ds->spec),
+                                reinterpret_cast<double2*>(ds->wmix), g, s, fbest) == hipSuccess &&
+                         fft_autocorr_nd(reinterpret_cast<const double2*>(ds->wmix), ds->alag, g, s, fbest) ==
+                             hipSuccess
+                     ? KDEFFT_OK
+                     : fail(KDEFFT_E_HIP, "count transform");
+            append_line(lines, "fft best: schedule %d\n", fbest);
+            append_line(cache,
+                        "{\"arch\": \"%s\", \"fft\": 1, \"d\": %d, \"P0\": %d, \"P1\": %d, \"P2\": %d, \"P3\": %d, "
+                        "\"sched\": %d, \"us\": %.2f}\n",
+                        arch.c_str(), d, g.P[0], d > 1 ? g.P[1] : 0, d > 2 ? g.P[2] : 0, d > 3 ? g.P[3] : 0, fbest,
+                        fbest_ms * 1000.0);
+        }
+    }
+
+    // 2. SCV families (objective + gradient timed), then the same kernels
+    // serving LSCV (narrower Gaussians, their own choice)
+    const int crits[2] = {KDEFFT_CRIT_SCV, KDEFFT_CRIT_LSCV};
+    const RowLaunch dflt_mom{4, 0};
+    for (int ci = 0; ci < 2 && !rc; ++ci) {
+        const int crit = crits[ci];
+        Pick pk;
+        for (int v = 0; v < ROW_VARIANTS && !rc; ++v) {
+            if (rows_per_iter(FUN_SCV_OBJGRAD, d, 2, N, v) < 1) continue;
+            for (int gi = 0; gi < 2 && !rc; ++gi) {
+                const RowLaunch rl{v, grids[gi]};
+                float ms = 0.f;
+                rc = time_choice(s, e0, e1, [&] {
+                    return crit_common(ds, 1, off, vech, crit, 0, FUN_SCV_OBJGRAD, nullptr, obj, grad, nullptr, ws,
+                                       ws_bytes, stream, &rl);
+                }, &ms);
+                if (rc) break;
+                append_line(lines, crit == KDEFFT_CRIT_SCV ? "variant %d grid %d: %.1f us\n"
+                                                           : "lscv variant %d grid %d: %.1f us\n",
+                            v, rl.grid_blocks, ms * 1000.0);
+                pk.add(rl, ms, dflt_mom);
+            }
         }
         if (rc) break;
+        pk.settle(dflt_mom);
+        append_line(lines, crit == KDEFFT_CRIT_SCV ? "best: variant %d grid %d\n" : "lscv best: variant %d grid %d\n",
+                    pk.best.variant, pk.best.grid_blocks);
+        for (int kind = FUN_SCV_OBJ; kind <= FUN_SCV_GRAD; ++kind) {
+            if (rows_per_iter(kind, d, 2, N, pk.best.variant) < 1) continue;
+            set_launch(kind, d, 2, N, pk.best, crit == KDEFFT_CRIT_SCV ? 0 : KDEFFT_CRIT_LSCV);
+            append_line(cache,
+                        "{\"arch\": \"%s\", \"kind\": %d, \"crit\": %d, \"d\": %d, \"r\": 2, \"N\": %d, "
+                        "\"variant\": %d, \"grid\": %d, \"us\": %.2f}\n",
+                        arch.c_str(), kind, crit == KDEFFT_CRIT_SCV ? 0 : KDEFFT_CRIT_LSCV, d, N, pk.best.variant,
+                        pk.best.grid_blocks, pk.best_ms * 1000.0);
+        }
+    }
+
+    // 3. LSCV_4 (the scalar eta family, lag domain only): grid size
+    if (!rc && rows_per_iter(FUN_ETA2, d, 4, N, 3) >= 1) {
+        Pick pk;
+        const RowLaunch dflt{3, 0};
+        for (int gi = 0; gi < 2 && !rc; ++gi) {
+            const RowLaunch rl{3, grids[gi]};
+            float ms = 0.f;
+            rc = time_choice(s, e0, e1, [&] {
+                return crit_common(ds, 1, off, vech, KDEFFT_CRIT_LSCV, 4, FUN_ETA2, nullptr, obj, nullptr, nullptr, ws,
+                                   ws_bytes, stream, &rl);
+            }, &ms);
+            if (rc) break;
+            append_line(lines, "lscv4 grid %d: %.1f us\n", rl.grid_blocks, ms * 1000.0);
+            pk.add(rl, ms, dflt);
+        }
+        if (!rc) {
+            pk.settle(dflt);
+            set_launch(FUN_ETA2, d, 4, N, pk.best, KDEFFT_CRIT_LSCV);
+            append_line(lines, "lscv4 best: grid %d\n", pk.best.grid_blocks);
+            append_line(cache,
+                        "{\"arch\": \"%s\", \"kind\": %d, \"crit\": %d, \"d\": %d, \"r\": 4, \"N\": %d, "
+                        "\"variant\": 3, \"grid\": %d, \"us\": %.2f}\n",
+                        arch.c_str(), FUN_ETA2, KDEFFT_CRIT_LSCV, d, N, pk.best.grid_blocks, pk.best_ms * 1000.0);
+        }
+    }
+
+    // 4. psi_4 at the dataset's pilot (its workspace may overlap the candidates)
+    if (!rc && rows_per_iter(FUN_PSI, d, 4, N, 3) >= 1) {
+        double G16[16];
+        for (int i = 0; i < 16; ++i) G16[i] = 0.0;
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) G16[i * d + j] = ds->G[i * d + j];
+        Pick pk;
+        const RowLaunch dflt{3, 0};
+        for (int v = 0; v <= 3 && !rc; ++v) {
+            if (rows_per_iter(FUN_PSI, d, 4, N, v) < 1) continue;
+            for (int gi = 0; gi < 2 && !rc; ++gi) {
+                const RowLaunch rl{v, grids[gi]};
+                float ms = 0.f;
+                rc = time_choice(s, e0, e1, [&] {
+                    return psi_batch_common(ds, 1, G16, 4, psi_out, ws, ws_bytes, stream, &rl);
+                }, &ms);
+                if (rc) break;
+                append_line(lines, "psi4 variant %d grid %d: %.1f us\n", v, rl.grid_blocks, ms * 1000.0);
+                pk.add(rl, ms, dflt);
+            }
+        }
+        if (!rc) {
+            pk.settle(dflt);
+            set_launch(FUN_PSI, d, 4, N, pk.best);
+            append_line(lines, "psi4 best: variant %d grid %d\n", pk.best.variant, pk.best.grid_blocks);
+            append_line(cache,
+                        "{\"arch\": \"%s\", \"kind\": %d, \"d\": %d, \"r\": 4, \"N\": %d, \"variant\": %d, "
+                        "\"grid\": %d, \"us\": %.2f}\n",
+                        arch.c_str(), FUN_PSI, d, N, pk.best.variant, pk.best.grid_blocks, pk.best_ms * 1000.0);
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    if (dflt_ms > 0.f && best_ms > 0.97f * dflt_ms) best = dflt;
-    {
-        char buf[96];
-        snprintf(buf, sizeof(buf), "best: variant %d grid %d\n", best.variant, best.grid_blocks);
-        lines += buf;
-    }
-    for (int kind = FUN_SCV_OBJ; kind <= FUN_SCV_GRAD; ++kind)
-        if (rows_per_iter(kind, d, 2, N, best.variant) >= 1) set_launch(kind, d, 2, N, best);
     if (cache_path && *cache_path) {
         FILE* f = std::fopen(cache_path, "a");
         if (f) {
-            for (int kind = FUN_SCV_OBJ; kind <= FUN_SCV_GRAD; ++kind)
-                std::fprintf(f,
-                             "{\"arch\": \"%s\", \"kind\": %d, \"d\": %d, \"r\": 2, \"N\": %d, \"variant\": %d, "
-                             "\"grid\": %d, \"us\": %.2f}\n",
-                             arch.c_str(), kind, d, N, best.variant, best.grid_blocks, best_ms * 1000.0);
+            std::fputs(cache.c_str(), f);
             std::fclose(f);
         }
     }

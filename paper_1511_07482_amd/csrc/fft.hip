@@ -124,7 +124,7 @@ __device__ __forceinline__ int64_t flip_row(int64_t r, const RowFlip& f) {
 template <int N>
 constexpr int last_rows() { return (N / 2) >= 2048 ? 1 : 2048 / (N / 2); }
 
-template <int N, int NT, int ROWS>
+template <int N, int NT, int ROWS, int RADIX>
 __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, double2* __restrict__ out,
                                                  int64_t rows, const double2* __restrict__ tw, CountSrc cs) {
     constexpr int H = N / 2, Q = H + 1;
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
     }
     twc.store(twl, tw);
     __syncthreads();
-    fft_lds<H, ROWS, NT, -1, 0, N>(buf, PS, twl);
+    fft_lds<H, ROWS, NT, -1, RADIX, N>(buf, PS, twl);
     for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
         const int rr = e / Q, k = e - rr * Q;
         const int64_t row = r0 + rr;
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
     }
 }
 
-template <int N, int NT, int ROWS>
+template <int N, int NT, int ROWS, int RADIX>
 __global__ __launch_bounds__(NT) void k_c2r_last(const double2* __restrict__ in, double* __restrict__ out,
                                                  int64_t rows, const double2* __restrict__ tw, RowFlip fl) {
     constexpr int H = N / 2, Q = H + 1;
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(NT) void k_c2r_last(const double2* __restrict__ in,
         }
     }
     __syncthreads();
-    fft_lds<H, ROWS, NT, 1, 0, N>(buf, PS, twl);
+    fft_lds<H, ROWS, NT, 1, RADIX, N>(buf, PS, twl);
     double2* dst = reinterpret_cast<double2*>(out);
     for (int e = threadIdx.x; e < ROWS * H; e += NT) {
         const int rr = e / H, m = e - rr * H;
@@ -278,7 +278,7 @@ constexpr int tile_cols() {
 // MODE 0: in-place transform.  MODE 1: forward transform stored in place
 // (the finished count spectrum C), then |C|^2 transformed forward again and
 // stored to out2.
-template <int N, int NT, int DIR, int MODE, int T>
+template <int N, int NT, int DIR, int MODE, int T, int RADIX>
 __global__ __launch_bounds__(NT) void k_c2c_strided(double2* __restrict__ buf, double2* __restrict__ out2,
                                                     int64_t inner, int64_t tiles,
                                                     const double2* __restrict__ tw) {
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(NT) void k_c2c_strided(double2* __restrict__ buf, d
     }
     twc.store(twl, tw);
     __syncthreads();
-    fft_lds<N, T, NT, DIR, 0, N>(lds, PS, twl);
+    fft_lds<N, T, NT, DIR, RADIX, N>(lds, PS, twl);
     for (int e = threadIdx.x; e < N * T; e += NT) {
         const int t = e % T, p = e / T;
         if (i0 + t < inner) base[(int64_t)p * inner + t] = lds[t * PS + p];
@@ -308,7 +308,7 @@ __global__ __launch_bounds__(NT) void k_c2c_strided(double2* __restrict__ buf, d
             lds[t * PS + p] = make_double2(v.x * v.x + v.y * v.y, 0.0);
         }
         __syncthreads();
-        fft_lds<N, T, NT, -1, 0, N>(lds, PS, twl);
+        fft_lds<N, T, NT, -1, RADIX, N>(lds, PS, twl);
         double2* b2 = out2 + o * N * inner + i0;
         for (int e = threadIdx.x; e < N * T; e += NT) {
             const int t = e % T, p = e / T;
@@ -337,48 +337,84 @@ constexpr int64_t kMinBlocks = 512;
 template <int N>
 constexpr int small_rows() { return (N / 2) >= 512 ? 1 : ((512 / (N / 2)) > 16 ? 16 : 512 / (N / 2)); }
 
-template <int N>
-static hipError_t run_r2c_last(const double* in, double2* out, int64_t rows, const double2* tw, hipStream_t s,
-                               CountSrc cs) {
+// FFT-stage schedules (the tuner's choices, per grid shape):
+//   FS_AUTO    the shape rule above, radix-8 stages first;
+//   FS_RADIX4  the same shapes, radix-4 stages (one radix-8 or 2 when log2 is odd);
+//   FS_WIDE    256-thread blocks for every pass (ROWS rows, T-column tiles);
+//   FS_NARROW  one-wavefront blocks for every pass that has them (more blocks);
+//   FS_HALF    strided passes on T/2-column tiles (twice the blocks), last axis as FS_AUTO.
+enum { FS_AUTO = 0, FS_RADIX4 = 1, FS_WIDE = 2, FS_NARROW = 3, FS_HALF = 4 };
+
+template <int N, int RADIX>
+static void launch_r2c_shape(bool narrow, const double* in, double2* out, int64_t rows, const double2* tw,
+                             hipStream_t s, CountSrc cs) {
     constexpr int ROWS = last_rows<N>();
     constexpr int RS = small_rows<N>();
-    if ((rows + ROWS - 1) / ROWS < kMinBlocks && RS < ROWS) {
-        const int64_t blocks = (rows + RS - 1) / RS;
-        hipLaunchKernelGGL((k_r2c_last<N, 64, RS>), dim3((unsigned)blocks), dim3(64), 0, s, in, out, rows, tw, cs);
-    } else {
-        const int64_t blocks = (rows + ROWS - 1) / ROWS;
-        hipLaunchKernelGGL((k_r2c_last<N, 256, ROWS>), dim3((unsigned)blocks), dim3(256), 0, s, in, out, rows, tw,
-                           cs);
-    }
+    if (narrow && RS < ROWS)
+        hipLaunchKernelGGL((k_r2c_last<N, 64, RS, RADIX>), dim3((unsigned)((rows + RS - 1) / RS)), dim3(64), 0, s,
+                           in, out, rows, tw, cs);
+    else
+        hipLaunchKernelGGL((k_r2c_last<N, 256, ROWS, RADIX>), dim3((unsigned)((rows + ROWS - 1) / ROWS)), dim3(256),
+                           0, s, in, out, rows, tw, cs);
+}
+
+template <int N, int RADIX>
+static void launch_c2r_shape(bool narrow, const double2* in, double* out, int64_t rows, const double2* tw,
+                             hipStream_t s, RowFlip fl) {
+    constexpr int ROWS = last_rows<N>();
+    constexpr int RS = small_rows<N>();
+    if (narrow && RS < ROWS)
+        hipLaunchKernelGGL((k_c2r_last<N, 64, RS, RADIX>), dim3((unsigned)((rows + RS - 1) / RS)), dim3(64), 0, s,
+                           in, out, rows, tw, fl);
+    else
+        hipLaunchKernelGGL((k_c2r_last<N, 256, ROWS, RADIX>), dim3((unsigned)((rows + ROWS - 1) / ROWS)), dim3(256),
+                           0, s, in, out, rows, tw, fl);
+}
+
+// narrow (one-wavefront) last-axis blocks for schedule fs
+template <int N>
+static bool last_narrow(int64_t rows, int fs) {
+    constexpr int ROWS = last_rows<N>();
+    if (fs == FS_WIDE) return false;
+    if (fs == FS_NARROW) return true;
+    return (rows + ROWS - 1) / ROWS < kMinBlocks;
+}
+
+template <int N>
+static hipError_t run_r2c_last(const double* in, double2* out, int64_t rows, const double2* tw, hipStream_t s,
+                               CountSrc cs, int fs) {
+    const bool narrow = last_narrow<N>(rows, fs);
+    if (fs == FS_RADIX4)
+        launch_r2c_shape<N, 1>(narrow, in, out, rows, tw, s, cs);
+    else
+        launch_r2c_shape<N, 0>(narrow, in, out, rows, tw, s, cs);
     return hipGetLastError();
 }
 template <int N>
 static hipError_t run_c2r_last(const double2* in, double* out, int64_t rows, const double2* tw, hipStream_t s,
-                               RowFlip fl) {
-    constexpr int ROWS = last_rows<N>();
-    constexpr int RS = small_rows<N>();
-    if ((rows + ROWS - 1) / ROWS < kMinBlocks && RS < ROWS) {
-        const int64_t blocks = (rows + RS - 1) / RS;
-        hipLaunchKernelGGL((k_c2r_last<N, 64, RS>), dim3((unsigned)blocks), dim3(64), 0, s, in, out, rows, tw, fl);
-    } else {
-        const int64_t blocks = (rows + ROWS - 1) / ROWS;
-        hipLaunchKernelGGL((k_c2r_last<N, 256, ROWS>), dim3((unsigned)blocks), dim3(256), 0, s, in, out, rows, tw,
-                           fl);
-    }
+                               RowFlip fl, int fs) {
+    const bool narrow = last_narrow<N>(rows, fs);
+    if (fs == FS_RADIX4)
+        launch_c2r_shape<N, 1>(narrow, in, out, rows, tw, s, fl);
+    else
+        launch_c2r_shape<N, 0>(narrow, in, out, rows, tw, s, fl);
     return hipGetLastError();
 }
 
-template <int N, int NT, int T>
+template <int N, int NT, int T, int RADIX>
 static void launch_c2c_t(double2* buf, double2* out2, int64_t outer, int64_t inner, int dir, int mode,
                          const double2* tw, hipStream_t s) {
     const int64_t tiles = (inner + T - 1) / T;
     const dim3 grid((unsigned)(outer * tiles));
     if (mode == 1)
-        hipLaunchKernelGGL((k_c2c_strided<N, NT, -1, 1, T>), grid, dim3(NT), 0, s, buf, out2, inner, tiles, tw);
+        hipLaunchKernelGGL((k_c2c_strided<N, NT, -1, 1, T, RADIX>), grid, dim3(NT), 0, s, buf, out2, inner, tiles,
+                           tw);
     else if (dir < 0)
-        hipLaunchKernelGGL((k_c2c_strided<N, NT, -1, 0, T>), grid, dim3(NT), 0, s, buf, out2, inner, tiles, tw);
+        hipLaunchKernelGGL((k_c2c_strided<N, NT, -1, 0, T, RADIX>), grid, dim3(NT), 0, s, buf, out2, inner, tiles,
+                           tw);
     else
-        hipLaunchKernelGGL((k_c2c_strided<N, NT, 1, 0, T>), grid, dim3(NT), 0, s, buf, out2, inner, tiles, tw);
+        hipLaunchKernelGGL((k_c2c_strided<N, NT, 1, 0, T, RADIX>), grid, dim3(NT), 0, s, buf, out2, inner, tiles,
+                           tw);
 }
 
 // Slab tiles: when the axis is the last leading one its inner extent is the
@@ -389,27 +425,48 @@ static void launch_c2c_t(double2* buf, double2* out2, int64_t outer, int64_t inn
 template <int N, int Q>
 constexpr bool slab_fits() { return N >= 8 && Q * (N + 1) * 16 <= 81920; }
 
-template <int N>
-static hipError_t run_c2c(double2* buf, double2* out2, int64_t outer, int64_t inner, int dir, int mode,
-                          const double2* tw, hipStream_t s) {
+template <int N, int RADIX>
+static void run_c2c_r(double2* buf, double2* out2, int64_t outer, int64_t inner, int dir, int mode,
+                      const double2* tw, hipStream_t s, int fs) {
     constexpr int T = tile_cols<N>();
     constexpr int TS = N >= 64 ? 1 : (64 / N > 16 ? 16 : 64 / N);  // one radix pass per lane
-    if constexpr (slab_fits<N, 33>()) {
-        if (inner == 33 && outer >= kMinBlocks) {
-            launch_c2c_t<N, 256, 33>(buf, out2, outer, inner, dir, mode, tw, s);
-            return hipGetLastError();
+    constexpr int TH = T > 1 ? T / 2 : 1;
+    if (fs != FS_NARROW && fs != FS_HALF) {
+        if constexpr (slab_fits<N, 33>()) {
+            if (inner == 33 && (outer >= kMinBlocks || fs == FS_WIDE)) {
+                launch_c2c_t<N, 256, 33, RADIX>(buf, out2, outer, inner, dir, mode, tw, s);
+                return;
+            }
+        }
+        if constexpr (slab_fits<N, 17>()) {
+            if (inner == 17 && (outer >= kMinBlocks || fs == FS_WIDE)) {
+                launch_c2c_t<N, 256, 17, RADIX>(buf, out2, outer, inner, dir, mode, tw, s);
+                return;
+            }
         }
     }
-    if constexpr (slab_fits<N, 17>()) {
-        if (inner == 17 && outer >= kMinBlocks) {
-            launch_c2c_t<N, 256, 17>(buf, out2, outer, inner, dir, mode, tw, s);
-            return hipGetLastError();
+    const bool narrow = TS < T && (fs == FS_NARROW ||
+                                   (fs != FS_WIDE && outer * ((inner + T - 1) / T) < kMinBlocks));
+    if (narrow) {
+        launch_c2c_t<N, 64, TS, RADIX>(buf, out2, outer, inner, dir, mode, tw, s);
+        return;
+    }
+    if constexpr (RADIX == 0 && TH < T) {
+        if (fs == FS_HALF) {
+            launch_c2c_t<N, 256, TH, 0>(buf, out2, outer, inner, dir, mode, tw, s);
+            return;
         }
     }
-    if (outer * ((inner + T - 1) / T) < kMinBlocks && TS < T)
-        launch_c2c_t<N, 64, TS>(buf, out2, outer, inner, dir, mode, tw, s);
+    launch_c2c_t<N, 256, T, RADIX>(buf, out2, outer, inner, dir, mode, tw, s);
+}
+
+template <int N>
+static hipError_t run_c2c(double2* buf, double2* out2, int64_t outer, int64_t inner, int dir, int mode,
+                          const double2* tw, hipStream_t s, int fs) {
+    if (fs == FS_RADIX4)
+        run_c2c_r<N, 1>(buf, out2, outer, inner, dir, mode, tw, s, fs);
     else
-        launch_c2c_t<N, 256, T>(buf, out2, outer, inner, dir, mode, tw, s);
+        run_c2c_r<N, 0>(buf, out2, outer, inner, dir, mode, tw, s, fs);
     return hipGetLastError();
 }
 
@@ -431,22 +488,23 @@ static hipError_t run_c2c(double2* buf, double2* out2, int64_t outer, int64_t in
     }
 
 static hipError_t r2c_last(const double* in, double2* out, int64_t rows, int N, const double2* tw, hipStream_t s,
-                           CountSrc cs = CountSrc{nullptr, 0, {0, 0, 0, 0}, {0, 0, 0, 0}, 0, 0, nullptr}) {
-#define CALL(NN) run_r2c_last<NN>(in, out, rows, tw, s, cs)
+                           CountSrc cs = CountSrc{nullptr, 0, {0, 0, 0, 0}, {0, 0, 0, 0}, 0, 0, nullptr},
+                           int fs = FS_AUTO) {
+#define CALL(NN) run_r2c_last<NN>(in, out, rows, tw, s, cs, fs)
     if (N < 4) return hipErrorInvalidValue;
     KDEFFT_SWITCH_N(ilog2i(N), CALL)
 #undef CALL
 }
 static hipError_t c2r_last(const double2* in, double* out, int64_t rows, int N, const double2* tw, hipStream_t s,
-                           RowFlip fl = RowFlip{0, 0, {1, 1, 1}, 0}) {
-#define CALL(NN) run_c2r_last<NN>(in, out, rows, tw, s, fl)
+                           RowFlip fl = RowFlip{0, 0, {1, 1, 1}, 0}, int fs = FS_AUTO) {
+#define CALL(NN) run_c2r_last<NN>(in, out, rows, tw, s, fl, fs)
     if (N < 4) return hipErrorInvalidValue;
     KDEFFT_SWITCH_N(ilog2i(N), CALL)
 #undef CALL
 }
 static hipError_t c2c(double2* buf, double2* out2, int64_t outer, int N, int64_t inner, int dir, int mode,
-                      const double2* tw, hipStream_t s) {
-#define CALL(NN) run_c2c<NN>(buf, out2, outer, inner, dir, mode, tw, s)
+                      const double2* tw, hipStream_t s, int fs = FS_AUTO) {
+#define CALL(NN) run_c2c<NN>(buf, out2, outer, inner, dir, mode, tw, s, fs)
     KDEFFT_SWITCH_N(ilog2i(N), CALL)
 #undef CALL
 }
@@ -501,7 +559,8 @@ hipError_t fft_c2r_nd(double2* inout, double* out, const kdefft_grid& g, hipStre
 }
 
 hipError_t fft_prepare_nd(const int64_t* src, int ncopies, int64_t* counts, double2* spec, double2* wmix,
-                          const kdefft_grid& g, hipStream_t s) {
+                          const kdefft_grid& g, hipStream_t s, int fs) {
+    if (fs < 0 || fs >= FFT_SCHEDULES) return hipErrorInvalidValue;
     const double2* tw;
     hipError_t e = twiddles(&tw);
     if (e != hipSuccess) return e;
@@ -512,7 +571,7 @@ hipError_t fft_prepare_nd(const int64_t* src, int ncopies, int64_t* counts, doub
         cs.stride *= g.M[k];
     }
     if (ncopies > 0 && !counts) return hipErrorInvalidValue;
-    e = r2c_last(nullptr, spec, lead_count(g), g.P[g.d - 1], tw, s, cs);
+    e = r2c_last(nullptr, spec, lead_count(g), g.P[g.d - 1], tw, s, cs, fs);
     if (e != hipSuccess) return e;
     if (g.d == 1) {
         const int64_t cnt = g.P[0] / 2 + 1;
@@ -522,23 +581,24 @@ hipError_t fft_prepare_nd(const int64_t* src, int ncopies, int64_t* counts, doub
     for (int ax = g.d - 2; ax >= 1 && e == hipSuccess; --ax) {
         int64_t outer, inner;
         axis_shape(g, ax, &outer, &inner);
-        e = c2c(spec, nullptr, outer, g.P[ax], inner, -1, 0, tw, s);
+        e = c2c(spec, nullptr, outer, g.P[ax], inner, -1, 0, tw, s, fs);
     }
     if (e != hipSuccess) return e;
     {
         int64_t outer, inner;
         axis_shape(g, 0, &outer, &inner);
-        e = c2c(spec, wmix, outer, g.P[0], inner, -1, 1, tw, s);
+        e = c2c(spec, wmix, outer, g.P[0], inner, -1, 1, tw, s, fs);
     }
     for (int ax = 1; ax + 1 < g.d && e == hipSuccess; ++ax) {
         int64_t outer, inner;
         axis_shape(g, ax, &outer, &inner);
-        e = c2c(wmix, nullptr, outer, g.P[ax], inner, -1, 0, tw, s);
+        e = c2c(wmix, nullptr, outer, g.P[ax], inner, -1, 0, tw, s, fs);
     }
     return e;
 }
 
-hipError_t fft_autocorr_nd(const double2* wmix, double* alag, const kdefft_grid& g, hipStream_t s) {
+hipError_t fft_autocorr_nd(const double2* wmix, double* alag, const kdefft_grid& g, hipStream_t s, int fs) {
+    if (fs < 0 || fs >= FFT_SCHEDULES) return hipErrorInvalidValue;
     const double2* tw;
     hipError_t e = twiddles(&tw);
     if (e != hipSuccess) return e;
@@ -548,7 +608,7 @@ hipError_t fft_autocorr_nd(const double2* wmix, double* alag, const kdefft_grid&
     // occupy [0, M)) and are stored as exact zeros.
     RowFlip fl{g.d > 1 ? 1 : 0, g.d - 1, {1, 1, 1}, g.M[g.d - 1]};
     for (int k = 0; k + 1 < g.d; ++k) fl.P[k] = g.P[k];
-    return c2r_last(wmix, alag, lead_count(g), g.P[g.d - 1], tw, s, fl);
+    return c2r_last(wmix, alag, lead_count(g), g.P[g.d - 1], tw, s, fl, fs);
 }
 
 }  // namespace kdefft

@@ -163,15 +163,18 @@ hipError_t launch_fill_czp(const int64_t* counts, const kdefft_grid& g, double* 
 // Multi-dimensional transforms over the circular-layout arrays.
 hipError_t fft_r2c_nd(const double* in, double2* out, const kdefft_grid& g, hipStream_t s);
 hipError_t fft_c2r_nd(double2* inout, double* out, const kdefft_grid& g, hipStream_t s);
+// FFT-stage schedules of the count transform (launch shapes and radix order
+// of its passes; fft.hip FS_*): fs in [0, FFT_SCHEDULES), 0 the default.
+constexpr int FFT_SCHEDULES = 5;
 // Count spectrum of a prepared dataset: spec = R2C(czp); wmix = |spec|^2
 // transformed forward along the leading axes.  The first pass reads the int64
 // counts directly: src is the count grid itself (ncopies = 0) or ncopies grids
 // of prod M bins whose exact sum it also writes to counts.
 hipError_t fft_prepare_nd(const int64_t* src, int ncopies, int64_t* counts, double2* spec, double2* wmix,
-                          const kdefft_grid& g, hipStream_t s);
+                          const kdefft_grid& g, hipStream_t s, int fs);
 // alag = inverse transform of |C|^2 = prod P times the count autocorrelation,
 // computed from the mixed spectrum (rows at negated leading indices).
-hipError_t fft_autocorr_nd(const double2* wmix, double* alag, const kdefft_grid& g, hipStream_t s);
+hipError_t fft_autocorr_nd(const double2* wmix, double* alag, const kdefft_grid& g, hipStream_t s, int fs);
 
 // Paper-literal path, one grid per launch.
 hipError_t launch_kgrid_psi(double* out, const kdefft_grid& g, int r, const ParamBlock& prm,

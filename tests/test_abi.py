@@ -214,6 +214,29 @@ def test_criterion_entry_validation(kf):
     assert pb(2, 1, n0.ctypes.data, fake, off.ctypes.data, fake, fake, None, None, None) == L.E_ARG
 
 
+def test_fft_schedule_table(kf):
+    lib = kf._lib.load()
+    L = kf._lib
+    P = np.array([64, 128], dtype=np.int32)
+    out = C.c_int(-5)
+    assert lib.kdefft_get_fft_schedule(2, P.ctypes.data, C.byref(out)) == L.OK and out.value == 0
+    for sched in range(kf.FFT_SCHEDULES):
+        assert lib.kdefft_set_fft_schedule(2, P.ctypes.data, sched) == L.OK
+        assert lib.kdefft_get_fft_schedule(2, P.ctypes.data, C.byref(out)) == L.OK and out.value == sched
+    assert lib.kdefft_set_fft_schedule(2, P.ctypes.data, -1) == L.OK
+    assert lib.kdefft_get_fft_schedule(2, P.ctypes.data, C.byref(out)) == L.OK and out.value == 0
+    assert lib.kdefft_set_fft_schedule(2, P.ctypes.data, kf.FFT_SCHEDULES) == L.E_ARG
+    assert lib.kdefft_set_fft_schedule(2, P.ctypes.data, -2) == L.E_ARG
+    assert lib.kdefft_set_fft_schedule(5, P.ctypes.data, 0) == L.E_ARG
+    bad = np.array([64, 96], dtype=np.int32)
+    assert lib.kdefft_set_fft_schedule(2, bad.ctypes.data, 0) == L.E_ARG
+    assert lib.kdefft_set_fft_schedule(2, None, 0) == L.E_ARG
+    assert lib.kdefft_get_fft_schedule(2, P.ctypes.data, None) == L.E_ARG
+    with kf.fft_schedule([64, 128], 3):
+        assert kf.get_fft_schedule([64, 128]) == 3
+    assert kf.get_fft_schedule([64, 128]) == 0
+
+
 def test_minimize_entry_validation(kf):
     lib = kf._lib.load()
     L = kf._lib

@@ -127,13 +127,23 @@ def test_case4_default_launch_and_tuned(kf, gpu, case4):
     N = gold["grid"]["P"][1]
     kinds = (kf.FUN_SCV_OBJ, kf.FUN_SCV_OBJGRAD, kf.FUN_SCV_GRAD)
     saved = [(k, kf.get_row_launch(k, 2, 2, N)) for k in kinds]
+    P = gold["grid"]["P"]
+    saved_fft = kf.get_fft_schedule(P)
+    saved_psi = kf.get_row_launch(kf.FUN_PSI, 2, 4, N)
     try:
         log("[full] case4 autotune " + kf.autotune(ds).replace("\n", "; "))
         obj, g = kf.scv([ds], v)
         _check_scv(obj.cpu().numpy(), g.cpu().numpy(), gold["scv"], "case4 tuned launch")
+        # the tuner re-ran the dataset's transform under the chosen schedule;
+        # a dataset prepared afresh uses it too
+        for dd in (ds, kf.Dataset(torch.from_numpy(w.X[0]).to(gpu), w.G_pilot[0], M=w.M)):
+            got = kf.psi_batch([dd], [w.G_psi[0]], 4).cpu().numpy()[0]
+            assert_z16(got, gold["psi4"]["values"], gold["psi4"]["scales"], RTOL, what="case4 psi_4 tuned")
     finally:
         for k, (var, gb) in saved:
             kf.set_row_launch(k, 2, 2, N, var, gb)
+        kf.set_row_launch(kf.FUN_PSI, 2, 4, N, *saved_psi)
+        kf.set_fft_schedule(P, saved_fft)
 
 
 def test_case4_finite_differences(kf, gpu, case4):
