@@ -694,6 +694,9 @@ int scv_batch_ws_need(const kdefft_dataset* ds, int n_ds, const int64_t* off, si
     int rc = check_batch_ds(ds, n_ds, KDEFFT_MAX_BATCH_DS);
     if (rc) return rc;
     if (!off || !need) return fail(KDEFFT_E_ARG, "NULL h_offsets or size output");
+    if (off[0] != 0) return fail(KDEFFT_E_ARG, "h_offsets[0] must be 0");
+    for (int j = 0; j < n_ds; ++j)
+        if (off[j + 1] < off[j]) return fail(KDEFFT_E_ARG, "h_offsets must be non-decreasing");
     const int64_t B = off[n_ds];
     if (B < 1) return fail(KDEFFT_E_ARG, "no candidate bandwidths");
     if (B > (1LL << 24)) return fail(KDEFFT_E_ARG, "too many candidates in one call");
