@@ -154,6 +154,26 @@ def lscv_binned(A, n, g, H, exact=False, with_grad=True):
     return obj, _grad_from_hess(h2, h1, H, n, exact)
 
 
+def lscv_binned_scales(A, n, g, H, exact=False):
+    """Absolute-value scales of the binned LSCV (r = 0) and of each entry of its
+    vech gradient: the objective's |lag kernel| sum plus the diagonal term,
+    and for the gradient |D^2 phi_{2H}| and (a/2)|D^2 phi_H| summed against A
+    plus (b/2) phi_H(0) |H^-1|, carried through dLSCV/dL = lower(2 grad_H L)
+    with absolute values.  Used to judge entries that nearly cancel."""
+    d = g["d"]
+    a, b = _lscv_weights(n, exact)
+    phi0 = float(gauss.phi(np.zeros(d), H))
+    s_obj = lscv_abs_scale(A, n, g, H, 0, exact) + b * phi0
+    al = multiindex.unique_alphas(d, 2)
+    h2 = binned.vstat_abs(A, n, g, [(1.0, 2 * H)], al)
+    h1 = binned.vstat_abs(A, n, g, [(1.0, H)], al)
+    sH = (scv._hess_from_unique(h2, d) + 0.5 * a * scv._hess_from_unique(h1, d)
+          + 0.5 * b * phi0 * np.abs(np.linalg.inv(H)))
+    L = np.abs(np.linalg.cholesky(H))
+    sL = np.tril(2.0 * sH @ L)
+    return s_obj, np.concatenate([sL[j:, j] for j in range(d)])
+
+
 def lscv_direct(X, H, exact=False, with_grad=True, workers=None):
     """LSCV (r = 0) and its gradient, unbinned pairs."""
     X = np.asarray(X, dtype=np.float64)

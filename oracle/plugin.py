@@ -45,6 +45,24 @@ def objective(psi4_unique, n, H, with_grad=True):
     return obj, scv.vech_grad_from_matrix_grad(gH, H)
 
 
+def objective_scales(psi4_scale, n, H):
+    """Absolute-value scales of PI(H) and of each entry of its vech gradient,
+    from per-entry bounds psi4_scale >= |psi_4| (its absolute values, or the
+    absolute-value lag sums of an estimate): the first term's magnitude plus
+    1/4 sum |H_ij| |H_kl| psi4_scale_ijkl, and for the gradient
+    |d first term / dH| + 1/2 sum_kl psi4_scale_ijkl |H_kl|, carried through
+    dPI/dL = lower(2 grad_H L) with absolute values."""
+    H = np.asarray(H, dtype=np.float64)
+    d = H.shape[0]
+    T = psi4_tensor(np.abs(np.asarray(psi4_scale, dtype=np.float64)), d)
+    aH = np.abs(H)
+    s_obj = abs(scv.first_term(H, n)) + 0.25 * float(np.einsum("ijkl,ij,kl->", T, aH, aH))
+    sH = np.abs(scv.first_term_grad(H, n)) + 0.5 * np.einsum("ijkl,kl->ij", T, aH)
+    L = np.abs(np.linalg.cholesky(H))
+    sL = np.tril(2.0 * sH @ L)
+    return s_obj, np.concatenate([sL[j:, j] for j in range(d)])
+
+
 def normal_psi4(Sigma):
     """psi_4 of the normal density N(mu, Sigma), integrated exactly:
     int D^{(x)4} f(x) f(x) dx = D^{(x)4} phi_{2 Sigma}(0) (four integrations by

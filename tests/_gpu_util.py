@@ -6,7 +6,7 @@ import sys
 
 import numpy as np
 
-from oracle import binned, grid, linbin
+from oracle import binned, eta, grid, linbin, scv
 
 RTOL_PSI = 1e-11     # FFT route vs direct binned sum, relative
 
@@ -90,3 +90,30 @@ def assert_z16(got, want, scale, rtol=1e-11, what=""):
     log(f"  {what}: worst entry {k} rel err {err[k]:.2e} (bar {rtol:.0e})")
     assert err[k] <= rtol, (f"{what} entry {k}: got {np.ravel(got)[k]!r} want {np.ravel(want)[k]!r} "
                             f"rel err {err[k]:.3e}")
+
+
+def check_z16(got, want, scale, rtol=1e-11, what=""):
+    """As assert_z16, logging only on failure (for per-candidate loops)."""
+    err = z16_errors(got, want, scale)
+    k = int(np.argmax(err))
+    assert err[k] <= rtol, (f"{what} entry {k}: got {np.ravel(got)[k]!r} want {np.ravel(want)[k]!r} "
+                            f"rel err {err[k]:.3e}")
+
+
+def check_scv(obj_b, grad_b, A, n, g, H, G, rtol=1e-11, what=""):
+    """One candidate's SCV objective (and gradient, if given) against the
+    oracle's binned values, per entry under the near-zero rule."""
+    o, gr = scv.objective_binned(A, n, g, H, G, with_grad=grad_b is not None)
+    so, sg = scv.objective_binned_scales(A, n, g, H, G)
+    check_z16([obj_b], [o], [so], rtol, what + " objective")
+    if grad_b is not None:
+        check_z16(grad_b, gr, sg, rtol, what + " gradient")
+
+
+def check_lscv(obj_b, grad_b, A, n, g, H, exact=False, rtol=1e-11, what=""):
+    """One candidate's LSCV (r = 0) objective and gradient against the oracle."""
+    o, gr = eta.lscv_binned(A, n, g, H, exact, with_grad=grad_b is not None)
+    so, sg = eta.lscv_binned_scales(A, n, g, H, exact)
+    check_z16([obj_b], [o], [so], rtol, what + " objective")
+    if grad_b is not None:
+        check_z16(grad_b, gr, sg, rtol, what + " gradient")

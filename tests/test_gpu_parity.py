@@ -261,7 +261,7 @@ def test_psi_edge_cases(kf, gpu):
         g = kf.grid_plan([M, M], g_o["lo"], hi, P=P)
         for mode in ("plain", "fused"):
             got = kf.psi(_to_dev(X, gpu), G, 4, grid=g, mode=mode).cpu().numpy()
-            assert_psi_close(got, want, sabs, rtol=1e-10, what=f"M={M} P={P} {mode}")
+            assert_psi_close(got, want, sabs, what=f"M={M} P={P} {mode}")
 
 
 def test_psi_deterministic(kf, gpu):

@@ -206,3 +206,21 @@ def test_lscv_gradient_fd(exact):
     _, grd = eta.lscv_direct(X[:150], H, exact)
     fdd = _fd_richardson(lambda w: eta.lscv_direct(X[:150], _vech_to_H(w, 2), exact, with_grad=False)[0], v, 1e-4)
     np.testing.assert_allclose(grd, fdd, rtol=1e-7, atol=1e-9 * np.abs(grd).max())
+
+
+@pytest.mark.parametrize("exact", [False, True])
+def test_lscv_scales_bound_values(exact):
+    """lscv_binned_scales bounds |LSCV| and every |gradient entry|; the
+    objective's scale stays within two orders of magnitude of it, and the
+    gradient's (whose entries cancel strongly near the minimiser) within two
+    orders of the objective's scale over the smallest diagonal entry of L."""
+    X, G, g, A = _setup(400, 2, 24, 31)
+    n = X.shape[0]
+    for seed in range(4):
+        H = _spd(2, 20 + seed, 0.1)
+        o, gr = eta.lscv_binned(A, n, g, H, exact)
+        so, sg = eta.lscv_binned_scales(A, n, g, H, exact)
+        assert abs(o) <= so * (1 + 1e-13)
+        assert np.all(np.abs(gr) <= sg * (1 + 1e-13))
+        lmin = np.abs(np.diag(np.linalg.cholesky(H))).min()
+        assert so <= 100 * abs(o) and np.all(sg <= 100 * so / lmin)

@@ -90,3 +90,26 @@ def test_gradient_fd(d):
     _, g = plugin.objective(p4, n, H)
     fd = _fd_richardson(lambda w: plugin.objective(p4, n, _vech_to_H(w, d), with_grad=False)[0], v, 1e-4)
     np.testing.assert_allclose(g, fd, rtol=1e-7, atol=1e-9 * np.abs(g).max())
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_scales_bound_values(d):
+    """objective_scales bounds |PI| and every |gradient entry|; with diagonal
+    Sigma and H every term of the quadratic form is positive, so the objective's
+    scale equals the objective itself."""
+    n = 800
+    Sigma = _spd(d, 70 + d)
+    p4 = plugin.normal_psi4(Sigma)
+    for seed in range(4):
+        H = _spd(d, 80 + 7 * d + seed) * 0.1
+        o, g = plugin.objective(p4, n, H)
+        so, sg = plugin.objective_scales(p4, n, H)
+        assert abs(o) <= so * (1 + 1e-14)
+        assert np.all(np.abs(g) <= sg * (1 + 1e-14))
+        assert np.all(sg <= 100 * np.abs(g).max())
+    Sd = np.diag(np.linspace(0.5, 1.5, d))
+    Hd = np.diag(np.linspace(0.05, 0.2, d))
+    p4d = plugin.normal_psi4(Sd)
+    o, _ = plugin.objective(p4d, n, Hd)
+    so, _ = plugin.objective_scales(p4d, n, Hd)
+    assert so == pytest.approx(o, rel=1e-13)
