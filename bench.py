@@ -82,6 +82,14 @@ def moment_walk_layout(N):
     return run, seg
 
 
+def flops_per_run(N, d=2):
+    """FP64 flops of one run of the moment walk (see algorithmic_flops_per_candidate)."""
+    q = d * (d + 1) // 2
+    RL, SEG = moment_walk_layout(N)
+    return (RL * (2 * 8 + 1) + (3 + 25 * q) + 4 * d * (SEG - 1) / SEG
+            + 2 * (2 * d * d + 2 * d + 4 + 2 * EXP_FLOPS) / SEG)
+
+
 def algorithmic_flops_per_candidate(M, N, d=2, variant=0, rows=None):
     """FP64 flops of one candidate in the batched objective+gradient kernel
     over `rows` rows of the half lag set, N positions each (default M rows,
@@ -313,7 +321,15 @@ def main():
         torch.cuda.synchronize()
 
     # ---- roofline of the dominant kernel (batched SCV objective+gradient launch)
-    flops = algorithmic_flops_per_candidate(M, N, d, variant) * B
+    # work of the launch: the compacted walk (variants 5, 6) visits only the
+    # runs with a lag above 1e-30 of some Gaussian's peak, counted on the device
+    # for these candidates (and the constant term's pseudo-candidate); the
+    # other lag-domain variants walk every run of every row
+    RL = moment_walk_layout(N)[0]
+    all_runs = (B + 1) * M * (N // RL)
+    walked_runs = kf.scv_walk_runs([ds], vechL) if variant >= 5 else all_runs
+    flops = (walked_runs * flops_per_run(N, d) if variant >= 3
+             else algorithmic_flops_per_candidate(M, N, d, variant) * B)
     achieved = flops / (scv_ms * 1e-3)
     spec_flops = algorithmic_flops_per_candidate(M, N, d, spec_variant) * B
     traffic = None
@@ -327,13 +343,16 @@ def main():
             ent = rec.get("launches", {}).get(f"{variant},{grid_blocks}")
             if ent:
                 traffic = ent["hbm_bytes_per_launch"]
-    kname = (f"k_lag_mom<2,{N},ScvFun<2,1>,256,{moment_walk_layout(N)[0]},{'true' if variant == 4 else 'false'}>"
+    kname = (f"k_lag_mom<2,{N},ScvFun<2,1>,256,{RL},{'true' if variant in (4, 6) else 'false'},"
+             f"{'true' if variant >= 5 else 'false'}> variant {variant}"
              if variant >= 3 else f"k_rows<2,{N},ScvFun<2,1>> variant {variant}")
     kname += " (grid: one block per work item)" if grid_blocks < 0 else " (grid: resident blocks)"
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic,
                 "kernel": kname, "launch_ms": scv_ms, "call_ms": scv_call_ms,
                 "flops_per_launch": flops, "variant": variant,
+                "walk": {"runs_walked": walked_runs, "runs_all": all_runs, "lags_per_run": RL,
+                         "flops_per_run": flops_per_run(N, d)},
                 "direct_evaluation_equivalent": {
                     "flops_per_launch": direct_equivalent_flops_per_candidate(M, d) * B,
                     "rate_tflops": direct_equivalent_flops_per_candidate(M, d) * B / (scv_ms * 1e-3) / 1e12}}
@@ -344,6 +363,7 @@ def main():
 
     crit_out = criteria_section(kf, torch, ds, vechL, Gpsi, n, B)
     fftl_out = fftl_section(kf, torch, dev, X, Gpsi, g)
+    fft_stage = fft_stage_section(kf, torch, dev, stream)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -370,6 +390,7 @@ def main():
                         "kernel_times_from": "eager timed steps (library HIP events around each row-kernel launch)"},
         "roofline": roofline,
         "fft_route_batched": fft_route,
+        "fft_stage": fft_stage,
         "cpu_baseline": cpu,
         "row_kernels_in_timed_steps_ms": {"scv_objgrad_256": scv_ms, "psi4": float(np.mean(psi_k)),
                                           "scv_call_with_setup_final": scv_call_ms},
@@ -467,18 +488,48 @@ def fftl_section(kf, torch, dev, X, Gpsi, g):
     return res
 
 
-def fft_stage_bytes(P, d):
-    """HBM bytes of the count transform of one dataset: the last-axis R2C pass
-    reads the real grid and writes the half spectrum; each of the d-1 leading
-    passes reads and writes the half spectrum, the fused axis-0 pass writes it
-    twice (C and the mixed spectrum); the autocorrelation adds |C|^2 (read C,
-    write), d-1 inverse leading passes and the last-axis C2R (read half
-    spectrum, write real grid)."""
-    real = 8 * P ** d
+def fft_stage_bytes(P, M, d):
+    """Algorithmic HBM bytes of one dataset's count transform as the passes are
+    built (d >= 2): the last-axis R2C reads the int64 counts (prod M) and writes
+    the half spectrum (16 L Q bytes, L = prod of the leading P, Q = P/2 + 1);
+    the forward passes along axes d-2..1 read and write it; the axis-0 pass
+    reads it and writes C and the mixed spectrum |C|^2 transformed forward;
+    axes 1..d-2 of the mixed spectrum read and write it; the last-axis C2R
+    reads it and writes the real lag array (8 prod P)."""
     half = 16 * P ** (d - 1) * (P // 2 + 1)
-    fwd = (real + half) + (d - 1) * 2 * half + half + (d - 2) * 2 * half
-    auto = 2 * half + (d - 1) * 2 * half + (half + real)
-    return fwd + auto
+    return 8 * M ** d + 8 * P ** d + half * (5 + 4 * (d - 2))
+
+
+def fft_stage_section(kf, torch, dev, stream):
+    """The count transform alone at the case-5 dataset shape (d=4, M=32,
+    P=64: 418 MB touched per transform) over 4 datasets back to back (1.7 GB
+    cycled, well above the 256 MB last-level cache): algorithmic bytes per
+    transform over the HIP-event time per transform."""
+    import synth
+    w = synth.case5(n_datasets=4, B=1, n_lo=200_000, n_hi=200_000)
+    dss = [kf.Dataset(torch.from_numpy(X).to(dev), Gp, M=w.M) for X, Gp in zip(w.X, w.G_pilot)]
+    d, M, P = w.d, w.M, int(dss[0].shape_grid.P[0])
+    for ds in dss:
+        ds.transform()
+    torch.cuda.synchronize()
+    reps = 3
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        for ds in dss:
+            ds.transform()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / (reps * len(dss))
+    nbytes = fft_stage_bytes(P, M, d)
+    half = 16 * P ** (d - 1) * (P // 2 + 1)
+    touched = 8 * M ** d + 2 * half + 8 * P ** d
+    return {"workload": f"count transform of {len(dss)} case-5-shaped datasets back to back (d={d}, M={M}, "
+                        f"P={P}), re-run from their counts",
+            "bytes_per_transform": nbytes, "ms_per_transform": ms,
+            "achieved_GBps": nbytes / (ms * 1e-3) / 1e9, "peak_GBps": 8000.0,
+            "frac": nbytes / (ms * 1e-3) / 8e12, "touched_bytes_per_dataset": touched,
+            "cycled_bytes": touched * len(dss), "schedule": kf.get_fft_schedule([P] * d)}
 
 
 def main_case5(a):
@@ -533,7 +584,10 @@ def main_case5(a):
     roofline = None
     if variant >= 3:
         rows = M * (2 * M - 1) ** (d - 2)
-        flops = B * algorithmic_flops_per_candidate(M, P_last, d=d, variant=variant, rows=rows)
+        if variant >= 5:   # the compacted walk: the runs it visits, counted on the device
+            flops = kf.scv_walk_runs(dss, vech, per_ds=per) * flops_per_run(P_last, d)
+        else:
+            flops = B * algorithmic_flops_per_candidate(M, P_last, d=d, variant=variant, rows=rows)
         roofline = {"bound": "alu", "kernel": f"k_lag_mom<{d},{P_last},ScvFun<{d},1>> variant {variant}",
                     "launch_ms": lag_ms, "flops_per_launch": flops, "achieved": flops / (lag_ms * 1e-3) / 1e12,
                     "peak": 78.6, "unit": "TFLOP/s", "frac": flops / (lag_ms * 1e-3) / 1e12 / 78.6}
@@ -553,7 +607,7 @@ def main_case5(a):
            "prepare_all_ms": t_prep, "psi4_batch_ms": t_psi, "scv_objgrad_batch_ms": t_scv,
            "scv_evals_per_s": B / (t_scv * 1e-3), "psi4_evals_per_s": len(dss) / (t_psi * 1e-3),
            "largest_n": ns[big], "linbin_largest_ms": t_bin, "prepare_largest_ms": t_prep1,
-           "fft_stage_bytes_per_dataset": fft_stage_bytes(P, d), "scv_roofline": roofline, "tuned": tuned}
+           "fft_stage_bytes_per_dataset": fft_stage_bytes(P, M, d), "scv_roofline": roofline, "tuned": tuned}
     print(json.dumps(out))
 
 

@@ -243,6 +243,13 @@ int kdefft_dataset_prepare_auto(const double* X, int64_t n, int d, const int32_t
  * read back into *out (synchronizes `stream`). */
 int kdefft_dataset_grid(const kdefft_dataset* ds_host, kdefft_grid* out, void* stream);
 
+/* The count transform of a prepared dataset alone (Sec. 4, Eq. (19)-(22):
+ * C = R2C of the counts, |C|^2, and its inverse transform): recomputes spec,
+ * wmix and alag from the dataset's counts with the current FFT schedule of its
+ * grid shape (kdefft_set_fft_schedule).  Needs no workspace; returns without
+ * waiting. */
+int kdefft_dataset_transform(const kdefft_dataset* ds_host, void* stream);
+
 /* psi_r at bandwidth G_host + 16*j (row-major d x d) for each of n_ds prepared
  * datasets, one launch: the binned double sum of Eq. (13) as sum_l k(l) A(l)
  * over the prepared lag array (or, for the spectral launch variants, the
@@ -302,6 +309,16 @@ int kdefft_scv_adjoint(const kdefft_dataset* ds_host, int n_ds, const int64_t* h
 int kdefft_crit_batch(const kdefft_dataset* ds_host, int n_ds, const int64_t* h_offsets_host,
                       const double* vechL, int crit, int r, double* obj, double* grad,
                       int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/* Work of the compacted lag walk (row-kernel variants 5 and 6) for the SCV
+ * objective + gradient of these candidates (Sec. 4, Eq. (17)-(18) in the lag
+ * domain): the number of runs of kdefft_lag_layout(P_{d-1}, 1) positions that
+ * hold a lag whose Gaussians reach 1e-30 of their peak -- the runs the walk
+ * visits -- summed over all candidates and each dataset's constant term.
+ * *runs_host receives the sum.  Arguments and workspace as in
+ * kdefft_scv_batch.  Synchronizes `stream` (a measurement helper). */
+int kdefft_scv_walk_runs(const kdefft_dataset* ds_host, int n_ds, const int64_t* h_offsets_host,
+                         const double* vechL, int64_t* runs_host, void* ws, size_t ws_bytes, void* stream);
 
 /* Adjoint of kdefft_crit_batch for r = 0 and crit SCV / LSCV / LSCV_EXACT:
  * grad_vechL[b, :] = grad_out[b] * d crit(H_b) / d vechL_b.  Same workspace. */

@@ -30,7 +30,7 @@ __all__ = ["Grid", "Dataset", "KdefftError", "grid_plan", "grid_auto", "linbin",
            "CRIT_SCV", "CRIT_LSCV", "CRIT_LSCV_EXACT", "CRIT_QR", "fftl_plan", "psi_fftl",
            "get_row_launch", "row_launch", "lag_layout", "scv_batch_noalloc", "minimize", "CRIT_PI",
            "MIN_CONVERGED", "MIN_RUNNING", "MIN_STALLED", "MIN_BAD_START", "set_fft_schedule",
-           "get_fft_schedule", "fft_schedule", "FFT_SCHEDULES"]
+           "get_fft_schedule", "fft_schedule", "FFT_SCHEDULES", "scv_walk_runs"]
 
 
 def library_path():
@@ -251,6 +251,12 @@ class Dataset:
         start = self.desc.alag - self.mem.data_ptr()
         return self.mem[start:start + 8 * numel].view(torch.float64).view(shape).clone()
 
+    def transform(self):
+        """Recompute the count transform (spectrum, mixed spectrum, lag array)
+        from the counts with the current FFT schedule (kdefft_dataset_transform)."""
+        _lib.check(_L().kdefft_dataset_transform(C.byref(self.desc), _stream(self.device)),
+                   "kdefft_dataset_transform")
+
     def counts(self) -> torch.Tensor:
         """Copy of the int64 grid counts."""
         shape = tuple(self.shape_grid.M[:self.d])
@@ -413,6 +419,23 @@ def scv(datasets: Sequence[Dataset], vechL: torch.Tensor, per_ds=None, grad: boo
     if status:
         return obj, g, st
     return (obj, g) if grad else obj
+
+
+def scv_walk_runs(datasets: Sequence[Dataset], vechL: torch.Tensor, per_ds=None) -> int:
+    """Runs the compacted lag walk visits for the SCV objective + gradient of
+    these candidates (kdefft_scv_walk_runs; synchronizes)."""
+    datasets = list(datasets)
+    if len(datasets) > _lib.MAX_BATCH_DS:
+        raise ValueError(f"at most {_lib.MAX_BATCH_DS} datasets per call")
+    dev = datasets[0].device
+    vechL = vechL.to(device=dev, dtype=torch.float64).contiguous()
+    per_ds = _split_counts(datasets, vechL, per_ds)
+    off = _offsets(datasets, per_ds)
+    ws = _ws(datasets[0].shape_grid, _lib.OP_SCV_BATCH, 2, vechL.shape[0], dev)
+    out = C.c_int64()
+    _lib.check(_L().kdefft_scv_walk_runs(_ds_array(datasets), len(datasets), off.ctypes.data, _ptr(vechL),
+                                         C.byref(out), _ptr(ws), ws.numel(), _stream(dev)), "kdefft_scv_walk_runs")
+    return int(out.value)
 
 
 def scv_batch_noalloc(datasets: Sequence[Dataset], vechL: torch.Tensor, obj: torch.Tensor,

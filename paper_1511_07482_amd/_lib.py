@@ -91,6 +91,9 @@ EXPORTS = {
     "kdefft_minimize_ws_bytes": (C.c_int, [C.POINTER(Grid), C.c_int, C.c_int64, C.POINTER(C.c_size_t)]),
     "kdefft_set_fft_schedule": (C.c_int, [C.c_int, C.c_void_p, C.c_int]),
     "kdefft_get_fft_schedule": (C.c_int, [C.c_int, C.c_void_p, C.POINTER(C.c_int)]),
+    "kdefft_scv_walk_runs": (C.c_int, [C.POINTER(Dataset), C.c_int, C.c_void_p, C.c_void_p,
+                                       C.POINTER(C.c_int64), C.c_void_p, C.c_size_t, C.c_void_p]),
+    "kdefft_dataset_transform": (C.c_int, [C.POINTER(Dataset), C.c_void_p]),
     "kdefft_timing_start": (C.c_int, [C.c_int]),
     "kdefft_timing_stop": (C.c_int, [C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int)]),
 }

@@ -1110,6 +1110,19 @@ int kdefft_dataset_prepare_auto(const double* X, int64_t n, int d, const int32_t
     return KDEFFT_OK;
 }
 
+int kdefft_dataset_transform(const kdefft_dataset* ds, void* stream) {
+    const int rc = check_batch_ds(ds, 1, 1);
+    if (rc) return rc;
+    const kdefft_grid& g = ds->grid;
+    hipStream_t s = S(stream);
+    const int fs = fft_sched_for(g);
+    HIPCHK(fft_prepare_nd(ds->counts, 0, nullptr, reinterpret_cast<double2*>(ds->spec),
+                          reinterpret_cast<double2*>(ds->wmix), g, s, fs),
+           "count transform");
+    HIPCHK(fft_autocorr_nd(reinterpret_cast<const double2*>(ds->wmix), ds->alag, g, s, fs), "count autocorrelation");
+    return KDEFFT_OK;
+}
+
 int kdefft_dataset_grid(const kdefft_dataset* ds, kdefft_grid* out, void* stream) {
     if (!ds || !out || !ds->rec) return fail(KDEFFT_E_ARG, "NULL or unprepared dataset");
     int rc = check_grid_shape(&ds->grid);
@@ -1199,7 +1212,8 @@ static int crit_kind(int crit, int r, bool want_grad, bool adjoint) {
 
 static int crit_common(const kdefft_dataset* ds, int n_ds, const int64_t* off, const double* vechL, int crit,
                        int r, int kind, const double* grad_out, double* obj, double* grad, int32_t* status,
-                       void* ws, size_t ws_bytes, void* stream, const RowLaunch* force) {
+                       void* ws, size_t ws_bytes, void* stream, const RowLaunch* force,
+                       int64_t* walk_runs = nullptr) {
     int rc = check_batch_ds(ds, n_ds, KDEFFT_MAX_BATCH_DS);
     if (rc) return rc;
     if (crit < KDEFFT_CRIT_SCV || crit > KDEFFT_CRIT_QR) return fail(KDEFFT_E_ARG, "crit=%d", crit);
@@ -1248,6 +1262,17 @@ static int crit_common(const kdefft_dataset* ds, int n_ds, const int64_t* off, c
     // the criteria complete in their own kernel: fused into the row kernel the
     // assembly lengthens the dominant launch by about what the separate
     // launch costs in a replayed graph
+    if (walk_runs) {
+        // the live runs of every candidate (the compacted walk's work), summed
+        HIPCHK(launch_scv_setup(vechL, a, B, npseudo, b.prm, status, geo, b.wc, s, true), "criterion setup");
+        std::vector<int32_t> wc((size_t)nc);
+        HIPCHK(hipMemcpyAsync(wc.data(), b.wc, wc.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s), "readback");
+        HIPCHK(hipStreamSynchronize(s), "sync");
+        int64_t t = 0;
+        for (int32_t v : wc) t += v;
+        *walk_runs = t;
+        return KDEFFT_OK;
+    }
     HIPCHK(launch_scv_setup(vechL, a, B, npseudo, b.prm, status, geo, geo.nplan > 0 ? b.wc : nullptr, s),
            "criterion setup");
     HIPCHK(timed_rows(kind, g.d, kr, geo, b.prm, nc, b.partial, rl, s), "criterion rows");
@@ -1284,6 +1309,16 @@ int kdefft_crit_batch(const kdefft_dataset* ds, int n_ds, const int64_t* h_offse
         return fail(KDEFFT_E_UNSUPPORTED, "gradients exist for r = 0 SCV / LSCV criteria only");
     return crit_common(ds, n_ds, h_offsets_host, vechL, crit, r, crit_kind(crit, r, grad != nullptr, false),
                        nullptr, obj, grad, status, ws, ws_bytes, stream, nullptr);
+}
+
+int kdefft_scv_walk_runs(const kdefft_dataset* ds, int n_ds, const int64_t* h_offsets_host, const double* vechL,
+                         int64_t* runs_host, void* ws, size_t ws_bytes, void* stream) {
+    if (!runs_host) return fail(KDEFFT_E_ARG, "runs_host is NULL");
+    const int rc = check_batch_ds(ds, n_ds, KDEFFT_MAX_BATCH_DS);
+    if (rc) return rc;
+    const RowLaunch compact{5, 0};
+    return crit_common(ds, n_ds, h_offsets_host, vechL, KDEFFT_CRIT_SCV, 0, FUN_SCV_OBJGRAD, nullptr, nullptr,
+                       nullptr, nullptr, ws, ws_bytes, stream, &compact, runs_host);
 }
 
 int kdefft_crit_adjoint(const kdefft_dataset* ds, int n_ds, const int64_t* h_offsets_host, const double* vechL,

@@ -205,7 +205,7 @@ constexpr int ROW_VARIANTS = 7;
 // ncand real candidates, then npseudo constant-term candidates (SCV: one per
 // dataset); wc (may be NULL): live segment counts for the balanced plan.
 hipError_t launch_scv_setup(const double* vechL, const ScvBatchArgs& a, int64_t ncand, int npseudo, double* prm,
-                            int32_t* status, const RowGeom& geo, int32_t* wc, hipStream_t s);
+                            int32_t* status, const RowGeom& geo, int32_t* wc, hipStream_t s, bool count_runs = false);
 hipError_t launch_psi_setup(const PsiBatchArgs& a, double* prm, hipStream_t s);
 hipError_t launch_scv_final(int kind, const double* partial, const RowGeom& geo,
                             const double* prm, int64_t ncand, int npseudo, const double* grad_out,

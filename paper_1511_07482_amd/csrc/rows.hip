@@ -360,7 +360,8 @@ __device__ static void pseudo_params(const ScvBatchArgs& a, int j, double* __res
 // candidates): lane 0 writes the parameter block; with wc set, the wavefront
 // then counts the candidate's live segments over all rows of the half lag set
 // (row_live with the moment walk's run length rl and segment length seg) into
-// wc[c] for the balanced plan of the compacted walk.
+// wc[c] for the balanced plan of the compacted walk (with seg = 1: its live
+// runs, the work the compacted walk does).
 template <int D>
 __global__ __launch_bounds__(256) void k_scv_setup(const double* __restrict__ vechL, ScvBatchArgs a, int64_t ncand,
                                                    int npseudo, double* __restrict__ prm,
@@ -396,10 +397,11 @@ __global__ __launch_bounds__(256) void k_scv_setup(const double* __restrict__ ve
 }
 
 hipError_t launch_scv_setup(const double* vechL, const ScvBatchArgs& a, int64_t ncand, int npseudo, double* prm,
-                            int32_t* status, const RowGeom& geo, int32_t* wc, hipStream_t s) {
+                            int32_t* status, const RowGeom& geo, int32_t* wc, hipStream_t s, bool count_runs) {
     const int64_t blocks = (ncand + npseudo + 3) / 4;
     int rl = 1, seg = 1, rows = 1;
     if (wc && !lag_layout(geo.P[geo.d - 1], 1, &rl, &seg, &rows)) return hipErrorInvalidValue;
+    if (count_runs) seg = 1;   // one run per unit: wc counts the live runs
     switch (a.d) {
         case 1: hipLaunchKernelGGL(k_scv_setup<1>, dim3((unsigned)blocks), dim3(256), 0, s, vechL, a, ncand, npseudo, prm, status, geo, rl, seg, wc); break;
         case 2: hipLaunchKernelGGL(k_scv_setup<2>, dim3((unsigned)blocks), dim3(256), 0, s, vechL, a, ncand, npseudo, prm, status, geo, rl, seg, wc); break;

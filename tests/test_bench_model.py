@@ -49,11 +49,14 @@ def test_lag_layout_rejects_bad_length():
 
 
 def test_fft_stage_bytes():
-    # case 5 (P = 64, d = 4): real grid 8 P^4, half spectrum 16 P^3 (P/2 + 1)
-    real, half = 8 * 64 ** 4, 16 * 64 ** 3 * 33
-    fwd = real + half + 3 * 2 * half + half + 2 * 2 * half
-    auto = 2 * half + 3 * 2 * half + half + real
-    assert bench.fft_stage_bytes(64, 4) == fwd + auto == 3_175_088_128
-    # d = 2 (P = 512): no middle passes
-    real, half = 8 * 512 ** 2, 16 * 512 * 257
-    assert bench.fft_stage_bytes(512, 2) == (real + half) + 2 * half + half + 2 * half + 2 * half + half + real
+    # case 5 (M = 32, P = 64, d = 4): int64 counts 8 M^4 read by the R2C pass,
+    # half spectrum 16 P^3 (P/2 + 1) per pass, real lag array 8 P^4 written by
+    # the C2R pass.  Passes: R2C (counts -> half), axes 2, 1 forward (2 half
+    # each), axis 0 (read half, write C and the mixed spectrum: 3 half),
+    # axes 1, 2 of the mixed spectrum (2 half each), C2R (half -> real).
+    counts, real, half = 8 * 32 ** 4, 8 * 64 ** 4, 16 * 64 ** 3 * 33
+    want = (counts + half) + 2 * 2 * half + 3 * half + 2 * 2 * half + (half + real)
+    assert bench.fft_stage_bytes(64, 32, 4) == want == 1_941_962_752
+    # d = 2 (M = 256, P = 512): no middle passes
+    counts, real, half = 8 * 256 ** 2, 8 * 512 ** 2, 16 * 512 * 257
+    assert bench.fft_stage_bytes(512, 256, 2) == (counts + half) + 3 * half + (half + real)

@@ -401,3 +401,21 @@ def test_timing_hook_records_row_launches(kf, gpu):
     kf.scv([ds], v)
     kf.scv([ds], v)
     assert len(kf.timing_stop()) == 1
+
+
+def test_walk_runs_count(kf, gpu):
+    """kdefft_scv_walk_runs: the compacted walk's live runs -- at least one per
+    candidate and row band around lag 0, at most every run of every row, and
+    more for wider bandwidths (longer live intervals)."""
+    d, X, Gp, M, H, _ = _setup("d2", gpu)
+    ds = kf.Dataset(torch.from_numpy(X).to(gpu), Gp, M=M)
+    N = ds.grid.P[d - 1]
+    RL = kf.lag_layout(N, True)[0]
+    B = H.shape[0]
+    v = torch.from_numpy(_vech(H)).to(gpu)
+    runs = kf.scv_walk_runs([ds], v)
+    log(f"[walk runs] d=2 M={M} N={N}: {runs} of {(B + 1) * M * (N // RL)} runs")
+    assert B + 1 <= runs <= (B + 1) * M * (N // RL)
+    wide = kf.scv_walk_runs([ds], torch.from_numpy(_vech(4.0 * H)).to(gpu))
+    narrow = kf.scv_walk_runs([ds], torch.from_numpy(_vech(0.25 * H)).to(gpu))
+    assert narrow <= runs <= wide and narrow < wide
