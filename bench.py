@@ -35,7 +35,8 @@ import numpy as np  # noqa: E402
 METRIC = "psi_r evals/s and SCV objective+grad evals/s, batched+adjoint vs plain, FP64"
 PEAK_FP64_VECTOR = 78.6e12          # MI355X FP64 vector FLOP/s (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
 EXP_FLOPS = 20                      # flops charged per exp (the device exp is ~13 FMA + 4 other FP64 ops)
-ROW_KERNEL_SOURCES = ["rows_impl.h", "dev_kernels.h", "dev_common.h", "finish.h", "rows_dispatch.h", "rows_d2.hip"]
+ROW_KERNEL_SOURCES = ["rows_impl.h", "dev_kernels.h", "dev_common.h", "finish.h", "rows_dispatch.h", "rows_d2.hip",
+                      "rows.hip", "params.h"]
 
 
 def parse():
