@@ -1273,8 +1273,21 @@ static int crit_common(const kdefft_dataset* ds, int n_ds, const int64_t* off, c
         *walk_runs = t;
         return KDEFFT_OK;
     }
-    HIPCHK(launch_scv_setup(vechL, a, B, npseudo, b.prm, status, geo, geo.nplan > 0 ? b.wc : nullptr, s),
-           "criterion setup");
+    // the compacted lag walk (variant 5) computes its parameter blocks itself
+    // unless the balanced plan needs the set-up kernel's counts
+    const bool mom = kind == FUN_SCV_OBJ || kind == FUN_SCV_OBJGRAD || kind == FUN_SCV_GRAD;
+    if (mom && rl.variant == 5 && geo.nplan == 0) {
+        geo.setup.on = 1;
+        geo.setup.npseudo = npseudo;
+        geo.setup.ncand = B;
+        geo.setup.vechL = vechL;
+        geo.setup.status = status;
+        geo.setup.prm_out = b.prm;
+        geo.setup.a = a;
+    } else {
+        HIPCHK(launch_scv_setup(vechL, a, B, npseudo, b.prm, status, geo, geo.nplan > 0 ? b.wc : nullptr, s),
+               "criterion setup");
+    }
     HIPCHK(timed_rows(kind, g.d, kr, geo, b.prm, nc, b.partial, rl, s), "criterion rows");
     HIPCHK(launch_scv_final(kind, b.partial, geo, b.prm, B, npseudo, grad_out, obj, grad, s), "criterion final");
     return KDEFFT_OK;

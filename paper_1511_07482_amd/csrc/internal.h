@@ -85,6 +85,20 @@ struct ParamBlock {
     double v[64];
 };
 
+// Parameter set-up done by the lag kernel itself (the SCV families on the lag
+// launches): each work item's block computes its candidate's parameter block
+// in LDS from vechL and the dataset records, and the block of the candidate's
+// first item also stores it to prm_out (for the final kernel) and its status.
+struct ScvSetup {
+    int on;
+    int npseudo;
+    int64_t ncand;
+    const double* vechL;
+    int32_t* status;
+    double* prm_out;
+    ScvBatchArgs a;
+};
+
 // Geometry of the row decomposition of the lag grid used by the batched kernels.
 struct RowGeom {
     int d;
@@ -101,6 +115,7 @@ struct RowGeom {
     int nplan;
     const int32_t* wc;
     int32_t* item_off;
+    ScvSetup setup;    // setup.on: the SCV lag kernel computes its parameter blocks
 };
 
 // Kinds of kernel families generated on the lag grid.

@@ -33,6 +33,7 @@
 #include "dev_kernels.h"
 #include "finish.h"
 #include "internal.h"
+#include "params.h"
 
 namespace kdefft {
 
@@ -782,6 +783,24 @@ __global__ __launch_bounds__(NT, D <= 2 ? (COMPACT ? 3 : 1) : 2) void k_lag_mom(
             ch = item - h * geo.nchunks;
         }
         const double* pr = prm + h * PRM;
+        if (COMPACT && !SCALED && geo.setup.on) {
+            // the candidate's parameter block, computed here by thread 0 into
+            // LDS; the block of its first item also stores it for the final kernel
+            __shared__ double s_prm[PRM];
+            __syncthreads();   // the previous item's readers of s_prm are done
+            if (threadIdx.x == 0) {
+                const bool first = (COMPACT && geo.nplan > 0) ? part == 0 : ch == 0;
+                if (h < geo.setup.ncand)
+                    scv_params<D>(geo.setup.vechL, geo.setup.a, h, geo.setup.ncand, geo.setup.npseudo, s_prm,
+                                  first ? geo.setup.status : nullptr);
+                else
+                    pseudo_params<D>(geo.setup.a, (int)(h - geo.setup.ncand), s_prm);
+                if (first)
+                    for (int i = 0; i < PRM; ++i) geo.setup.prm_out[h * PRM + i] = s_prm[i];
+            }
+            __syncthreads();
+            pr = s_prm;
+        }
         Fun f;
         f.load(pr);
         double delta[D];
