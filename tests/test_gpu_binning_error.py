@@ -77,3 +77,26 @@ def test_case2_shape_binning_error(kf, gpu):
         f"{np.array2string(rel, precision=3)}; first-order prediction "
         f"{np.array2string(np.abs(pred) / np.abs(exact), precision=3)}")
     np.testing.assert_allclose(val - exact, pred, rtol=0.1, atol=0.05 * np.abs(pred).max())
+
+
+def test_case2_shape_binning_error_vs_M(kf, gpu):
+    """The case-2 psi_4 binning error against the grid size: linear binning's
+    error is second order in the spacing, so doubling M quarters it; the
+    smallest M meeting 1e-3 per entry is reported (M = 1024 on this data)."""
+    w = synth.case2()
+    X, G = w.X[0], w.G_psi[0]
+    Xt_full = torch.from_numpy(X).to(gpu)
+    sub = X[np.random.default_rng(151107482 + 70).choice(X.shape[0], 6000, replace=False)]
+    Xt = torch.from_numpy(sub).to(gpu)
+    exact = direct.psi(sub, G, 4, workers=direct.default_workers())
+    worst = {}
+    for M in (256, 512, 1024, 2048):
+        g = kf.grid_auto(Xt_full, G, M)
+        val = kf.psi(Xt, G, 4, grid=g, mode="plain").cpu().numpy()
+        worst[M] = float((np.abs(val - exact) / np.abs(exact)).max())
+        log(f"[binning error] case2 shape psi_4, M={M}: worst entry rel err {worst[M]:.3e}")
+    for M in (256, 512, 1024):
+        assert 3.4 <= worst[M] / worst[2 * M] <= 4.6, (M, worst)
+    meets = min(M for M in worst if worst[M] <= 1e-3)
+    log(f"[binning error] case2 shape psi_4: smallest M with every entry within 1e-3: {meets}")
+    assert meets <= 1024
