@@ -405,13 +405,15 @@ int kdefft_scv_plain(const kdefft_dataset* ds_host, const double* H_host, double
  * instead: sum_l k(l) A(l) against the prepared count autocorrelation
  * (identical sums, no per-candidate transform); for the SCV families, runs of
  * lags that start below 1e-290 and rise are evaluated lag by lag (3) or
- * walked with values scaled by e^600 (4, the untuned default); the psi and eta
- * families treat 3 and 4 alike and have no spectral variants for eta.
- * Variants 5 and 6 are 3 and 4 with the work compacted: each row's lags whose
- * Gaussians all stay below 1e-30 of their peak are bounded analytically and
- * skipped, and only the remaining runs are dealt to the threads (the dropped
- * terms are far below float64 rounding of the result; the psi and eta
- * families treat 5 and 6 as 3).
+ * walked with values scaled by e^600 (4); the psi and eta families treat 3 and
+ * 4 alike and have no spectral variants for eta.  Variants 5 and 6 are 3 and 4
+ * with the work compacted: each row's lags whose Gaussians all stay below
+ * 1e-30 of their peak are bounded analytically and skipped, and only the
+ * remaining runs are dealt to the threads (the dropped terms are far below
+ * float64 rounding of the result; the psi and eta families treat 5 and 6 as
+ * 3); variant 5 with one block per work item (the untuned default of the SCV
+ * families) also builds the candidates' parameter blocks inside the launch.
+ * The untuned default of the other families is variant 3, grid 0.
  * variant = -1 drops the pinned (or tuned) choice of that key, so the untuned
  * default applies again.  Used by kdefft_autotune and by tests that cover
  * every variant.  Host only. */
@@ -480,8 +482,9 @@ int kdefft_get_fft_schedule(int d, const int32_t* P_host, int* sched);
  *     H = s G (s spread over [0.5, 8], G the dataset's matrix);
  *   LSCV_4 (the scalar eta family: grid size) on the same candidates;
  *   psi_4 at the dataset's pilot (variants 0-3, grid size).
- * Each default (FFT schedule 0; variant 4 grid 0 for SCV / LSCV; variant 3
- * grid 0 otherwise) is kept unless another choice is more than 3% faster.
+ * Each default (FFT schedule 0; variant 5 with one block per work item for
+ * SCV / LSCV; variant 3 grid 0 otherwise) is kept unless another choice is
+ * more than 3% faster.
  * kdefft_last_error_detail() returns the timings afterwards.  Workspace:
  * KDEFFT_OP_AUTOTUNE.  Synchronizes `stream`. */
 int kdefft_autotune(const kdefft_dataset* ds_host, void* ws, size_t ws_bytes,

@@ -306,10 +306,11 @@ RowLaunch launch_for(int kind, int d, int r, int N, int crit = 0) {
     load_cache_locked(dev);
     auto it = g_launch.find(LaunchKey{dev, kind, d, r, N, crit});
     if (it != g_launch.end()) return it->second;
-    // untuned default: the lag-domain evaluation (fewest operations, no LDS),
-    // with the scaled walk for the SCV families (robust to narrow kernels)
+    // untuned default: the lag-domain evaluation (fewest operations, no LDS);
+    // for the SCV families the compacted walk, one block per work item (it
+    // builds its own parameter blocks)
     const bool mom = kind == FUN_SCV_OBJ || kind == FUN_SCV_OBJGRAD || kind == FUN_SCV_GRAD;
-    return RowLaunch{mom ? 4 : 3, 0};
+    return mom ? RowLaunch{5, -1} : RowLaunch{3, 0};
 }
 
 void set_launch(int kind, int d, int r, int N, RowLaunch rl, int crit = 0) {
@@ -1765,7 +1766,7 @@ int kdefft_autotune(const kdefft_dataset* ds, void* ws, size_t ws_bytes, const c
     // 2. SCV families (objective + gradient timed), then the same kernels
     // serving LSCV (narrower Gaussians, their own choice)
     const int crits[2] = {KDEFFT_CRIT_SCV, KDEFFT_CRIT_LSCV};
-    const RowLaunch dflt_mom{4, 0};
+    const RowLaunch dflt_mom{5, -1};
     for (int ci = 0; ci < 2 && !rc; ++ci) {
         const int crit = crits[ci];
         Pick pk;

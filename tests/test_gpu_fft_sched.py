@@ -5,7 +5,8 @@ the count transform, against the oracle:
   counts (1e-12 of its largest entry; exact zeros beyond the last-axis
   support) on small grids d = 1..4 (ragged M, one-wavefront and 256-thread
   shapes, P from 16 to 2048);
-* the counts are bit-identical under every schedule;
+* the counts are bit-identical under every schedule, and re-running a dataset's
+  transform from its counts reproduces its arrays bit for bit;
 * at the benchmark shapes -- d=2, n=1e5, P=512 and the d=4, n=2e5, P=64 case-5
   dataset -- psi_4 of the dataset prepared under each schedule against the
   values the oracle wrote (tests/golden), 1e-11 per entry (near-zero rule).
@@ -71,6 +72,10 @@ def test_every_schedule_lag_array(kf, gpu, name):
             ds = kf.Dataset(Xd, G, grid=g)
             al = ds.lag_array().cpu().numpy()
             shas.add(_sha(ds.counts()))
+            # the count transform re-run from the counts (kdefft_dataset_transform)
+            # reproduces the prepared arrays bit for bit
+            ds.transform()
+            assert np.array_equal(ds.lag_array().cpu().numpy(), al)
         got = al[np.ix_(*idx)] / float(np.prod(P))
         np.testing.assert_allclose(got, A, rtol=0, atol=1e-12 * np.abs(A).max(), err_msg=f"schedule {sched}")
         assert np.all(al[..., zero] == 0.0)
