@@ -1274,10 +1274,11 @@ static int crit_common(const kdefft_dataset* ds, int n_ds, const int64_t* off, c
         *walk_runs = t;
         return KDEFFT_OK;
     }
-    // the compacted lag walk (variant 5) computes its parameter blocks itself
-    // unless the balanced plan needs the set-up kernel's counts
+    // the compacted lag walk (variant 5) with one block per work item computes
+    // its parameter blocks itself (the balanced plan needs the set-up kernel's
+    // counts; a resident grid takes several items per block)
     const bool mom = kind == FUN_SCV_OBJ || kind == FUN_SCV_OBJGRAD || kind == FUN_SCV_GRAD;
-    if (mom && rl.variant == 5 && geo.nplan == 0) {
+    if (mom && rl.variant == 5 && rl.grid_blocks == -1 && geo.nplan == 0) {
         geo.setup.on = 1;
         geo.setup.npseudo = npseudo;
         geo.setup.ncand = B;

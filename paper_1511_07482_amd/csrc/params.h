@@ -70,7 +70,9 @@ __device__ __forceinline__ static void psi_params(const double* gv, const DsDev&
 //   Q_r:          S1 = H (the candidate matrix itself), no first or constant term;
 // their inverses and normal constants, grid spacing, n and the scale of the
 // lag sums.  status 1 = singular candidate.
-template <int D>
+// ETA = false: the caller serves r = 0 only (the moment kernels), where the
+// diagonal term's eta_r(0; H) / phi_H(0) is 1, and the eta_r code is left out.
+template <int D, bool ETA = true>
 __device__ static void scv_params(const double* __restrict__ vechL, const ScvBatchArgs& a, int64_t h, int64_t ncand,
                                   int npseudo, double* __restrict__ p, int32_t* __restrict__ status) {
     // dataset of candidate h: the last j with off[j] <= h (a binary search with
@@ -153,11 +155,15 @@ __device__ static void scv_params(const double* __restrict__ vechL, const ScvBat
         const bool exact = crit == KDEFFT_CRIT_LSCV_EXACT;
         const double b = exact ? 2.0 / (n - 1.0) : 2.0 / n;
         // eta_r(0; H) = phi_H(0) Y_r(kappa at x = 0); phi_H(0) = c2 before weighting
-        double P2[D * D], T2[ETA_RMAX + 1], z0[D];
-        for (int i = 0; i < D * D; ++i) P2[i] = p[S_P2 + (i / D) * 4 + (i % D)];
-        for (int i = 0; i < D; ++i) z0[i] = 0.0;
-        eta_traces<D>(P2, T2);
-        p[S_FIRST] = sgn * b * p[S_C2] * eta_ratio<D>(z0, P2, T2, r);
+        double ratio = 1.0;
+        if constexpr (ETA) {
+            double P2[D * D], T2[ETA_RMAX + 1], z0[D];
+            for (int i = 0; i < D * D; ++i) P2[i] = p[S_P2 + (i / D) * 4 + (i % D)];
+            for (int i = 0; i < D; ++i) z0[i] = 0.0;
+            eta_traces<D>(P2, T2);
+            ratio = eta_ratio<D>(z0, P2, T2, r);
+        }
+        p[S_FIRST] = sgn * b * p[S_C2] * ratio;
         if (exact) p[S_C2] *= n / (n - 1.0);
         p[S_SIGN] = sgn;
     }

@@ -45,6 +45,15 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A value that is the same in every lane (read from LDS at a uniform address),
+// moved to scalar registers so that it takes no vector register.
+__device__ __forceinline__ double wave_uniform(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // Position of element e of a pencil in LDS: the low four index bits are XORed
 // with a function of the next bits, so that 16 consecutive lanes hit 16
 // different 16-byte bank groups for contiguous reads, stride-8 writes (first
@@ -763,6 +772,26 @@ __global__ __launch_bounds__(NT, D <= 2 ? (COMPACT ? 3 : 1) : 2) void k_lag_mom(
     if constexpr (COMPACT) {
         if (geo.nplan > 0) nit = balanced_plan<NT>(geo, (int)gridDim.x, s_off, s_pw);
     }
+    // parameter blocks built in the launch (one block per work item, no plan):
+    // thread 0 computes the block's candidate's parameters into LDS before
+    // anything else is live, and the block of the candidate's first item also
+    // stores them for the final kernel
+    __shared__ double s_prm[COMPACT && !SCALED ? PRM : 1];
+    if constexpr (COMPACT && !SCALED) {
+        if (geo.setup.on) {
+            const int64_t h0 = blockIdx.x / geo.nchunks, ch0 = blockIdx.x - h0 * geo.nchunks;
+            if (threadIdx.x == 0) {
+                if (h0 < geo.setup.ncand)
+                    scv_params<D, false>(geo.setup.vechL, geo.setup.a, h0, geo.setup.ncand, geo.setup.npseudo, s_prm,
+                                         ch0 == 0 ? geo.setup.status : nullptr);
+                else
+                    pseudo_params<D>(geo.setup.a, (int)(h0 - geo.setup.ncand), s_prm);
+                if (ch0 == 0)
+                    for (int i = 0; i < PRM; ++i) geo.setup.prm_out[h0 * PRM + i] = s_prm[i];
+            }
+            __syncthreads();
+        }
+    }
     for (int64_t item = blockIdx.x; item < nit; item += gridDim.x) {
         int64_t h, ch = 0;
         int part = 0, parts = 1;
@@ -782,25 +811,18 @@ __global__ __launch_bounds__(NT, D <= 2 ? (COMPACT ? 3 : 1) : 2) void k_lag_mom(
             h = item / geo.nchunks;
             ch = item - h * geo.nchunks;
         }
-        const double* pr = prm + h * PRM;
+        // the parameter block, uniform over the block: loaded from the
+        // parameter array (scalar loads), or taken from LDS into scalar
+        // registers when the launch built it
+        double pv[PRM];
         if (COMPACT && !SCALED && geo.setup.on) {
-            // the candidate's parameter block, computed here by thread 0 into
-            // LDS; the block of its first item also stores it for the final kernel
-            __shared__ double s_prm[PRM];
-            __syncthreads();   // the previous item's readers of s_prm are done
-            if (threadIdx.x == 0) {
-                const bool first = (COMPACT && geo.nplan > 0) ? part == 0 : ch == 0;
-                if (h < geo.setup.ncand)
-                    scv_params<D>(geo.setup.vechL, geo.setup.a, h, geo.setup.ncand, geo.setup.npseudo, s_prm,
-                                  first ? geo.setup.status : nullptr);
-                else
-                    pseudo_params<D>(geo.setup.a, (int)(h - geo.setup.ncand), s_prm);
-                if (first)
-                    for (int i = 0; i < PRM; ++i) geo.setup.prm_out[h * PRM + i] = s_prm[i];
-            }
-            __syncthreads();
-            pr = s_prm;
+#pragma unroll
+            for (int i = 0; i < PRM; ++i) pv[i] = wave_uniform(s_prm[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < PRM; ++i) pv[i] = prm[h * PRM + i];
         }
+        const double* pr = pv;
         Fun f;
         f.load(pr);
         double delta[D];
