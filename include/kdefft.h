@@ -456,17 +456,20 @@ int kdefft_timing_stop(float* ms_out, int32_t* tag_out, int cap, int* count_out)
 /* FFT-stage schedule of the count transform (Sec. 4, Eq. (19)-(23): the
  * R2C, leading-axis and C2R passes of dataset preparation) for grids of shape
  * (d, P_host[0..d-1]) on the current device, for the rest of the process:
- *   0 (default) one-wavefront blocks when the 256-thread shape would give
- *     fewer than 512 blocks, else 256-thread blocks of ~2048 values; radix-8
- *     Stockham stages first (radix 4 or 2 for the remainder);
+ *   0 (default) 256-thread blocks of ~2048 values, or, when that shape would
+ *     give fewer than 512 blocks, 256-thread blocks of a few pencils (half of
+ *     what one wavefront takes, at least one: more blocks, more lanes per
+ *     pencil for the loads); radix-8 Stockham stages first (radix 4 or 2 for
+ *     the remainder);
  *   1 the same shapes with radix-4 stages (one radix-8 or 2 when log2 P is odd);
- *   2 256-thread blocks for every pass (strided passes on 16-column tiles, or
- *     whole [P][Q] slabs for Q = 17, 33);
+ *   2 256-thread blocks of ~2048 values for every pass (strided passes on
+ *     16-column tiles, or whole [P][Q] slabs for Q = 17, 33);
  *   3 one-wavefront blocks for every pass that has them;
- *   4 strided passes on half-width tiles (twice the blocks).
+ *   4 strided passes on half-width tiles (twice the blocks);
+ *   5 the small problems' 256-thread shape of schedule 0 for every pass.
  * All schedules compute the same transform (they differ in rounding order
  * only).  sched = -1 drops the pinned or tuned choice.  Host only. */
-#define KDEFFT_FFT_SCHEDULES 5
+#define KDEFFT_FFT_SCHEDULES 6
 int kdefft_set_fft_schedule(int d, const int32_t* P_host, int sched);
 int kdefft_get_fft_schedule(int d, const int32_t* P_host, int* sched);
 

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkdefft.so")
 
 OK = 0
-FFT_SCHEDULES = 5
+FFT_SCHEDULES = 6
 E_ARG, E_NOT_SPD, E_ODD_R, E_OUT_OF_GRID, E_OVERFLOW, E_WORKSPACE, E_HIP, E_UNSUPPORTED = range(-1, -9, -1)
 OP_GRID_AUTO, OP_PSI_PLAIN, OP_PSI_FUSED, OP_PREPARE, OP_PSI_BATCH, OP_SCV_BATCH, OP_SCV_PLAIN, OP_AUTOTUNE, \
     OP_PSI_FFTL, OP_PREPARE_AUTO = range(1, 11)

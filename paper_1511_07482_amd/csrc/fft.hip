@@ -330,74 +330,94 @@ __global__ void k_abs2(const double2* __restrict__ in, double2* __restrict__ out
 static int ilog2i(int n) { int k = 0; while ((1 << k) < n) ++k; return k; }
 
 // Launch shapes.  Default: ~2048 complex values per block (256 threads).
-// Small problems (fewer than ~512 blocks at the default shape) use one
-// wavefront per block with one or two pencils, so more CUs take part.
+// Small problems (fewer than ~512 blocks at the default shape) take one or a
+// few pencils per block instead, so more CUs take part: the pencils of one
+// wavefront's shape on 256 threads, whose extra lanes shorten the loads and
+// stores that bound these passes (part of them idle in the stages).
 constexpr int64_t kMinBlocks = 512;
 
+// pencils of one wavefront (at most 16, ~512 values), and half of them (at
+// least one) for the 256-thread small shape
 template <int N>
 constexpr int small_rows() { return (N / 2) >= 512 ? 1 : ((512 / (N / 2)) > 16 ? 16 : 512 / (N / 2)); }
+template <int N>
+constexpr int deep_rows() { return small_rows<N>() > 1 ? small_rows<N>() / 2 : 1; }
 
 // FFT-stage schedules (the tuner's choices, per grid shape):
 //   FS_AUTO    the shape rule above, radix-8 stages first;
 //   FS_RADIX4  the same shapes, radix-4 stages (one radix-8 or 2 when log2 is odd);
-//   FS_WIDE    256-thread blocks for every pass (ROWS rows, T-column tiles);
-//   FS_NARROW  one-wavefront blocks for every pass that has them (more blocks);
-//   FS_HALF    strided passes on T/2-column tiles (twice the blocks), last axis as FS_AUTO.
-enum { FS_AUTO = 0, FS_RADIX4 = 1, FS_WIDE = 2, FS_NARROW = 3, FS_HALF = 4 };
+//   FS_WIDE    256-thread blocks of the default shape for every pass;
+//   FS_NARROW  one-wavefront blocks for every pass that has them;
+//   FS_HALF    strided passes on T/2-column tiles (twice the blocks), last axis as FS_AUTO;
+//   FS_DEEP    the small problems' 256-thread shapes for every pass that has them.
+enum { FS_AUTO = 0, FS_RADIX4 = 1, FS_WIDE = 2, FS_NARROW = 3, FS_HALF = 4, FS_DEEP = 5 };
+
+// Last-axis launch shapes: ROWS rows on 256 threads, small_rows on one
+// wavefront, deep_rows on 256 threads.
+enum { SH_WIDE = 0, SH_NARROW = 1, SH_DEEP = 2 };
 
 template <int N, int RADIX>
-static void launch_r2c_shape(bool narrow, const double* in, double2* out, int64_t rows, const double2* tw,
+static void launch_r2c_shape(int sh, const double* in, double2* out, int64_t rows, const double2* tw,
                              hipStream_t s, CountSrc cs) {
     constexpr int ROWS = last_rows<N>();
     constexpr int RS = small_rows<N>();
-    if (narrow && RS < ROWS)
+    constexpr int RD = deep_rows<N>();
+    if (sh == SH_NARROW && RS < ROWS)
         hipLaunchKernelGGL((k_r2c_last<N, 64, RS, RADIX>), dim3((unsigned)((rows + RS - 1) / RS)), dim3(64), 0, s,
                            in, out, rows, tw, cs);
+    else if (sh == SH_DEEP && RS < ROWS)
+        hipLaunchKernelGGL((k_r2c_last<N, 256, RD, RADIX>), dim3((unsigned)((rows + RD - 1) / RD)), dim3(256), 0,
+                           s, in, out, rows, tw, cs);
     else
         hipLaunchKernelGGL((k_r2c_last<N, 256, ROWS, RADIX>), dim3((unsigned)((rows + ROWS - 1) / ROWS)), dim3(256),
                            0, s, in, out, rows, tw, cs);
 }
 
 template <int N, int RADIX>
-static void launch_c2r_shape(bool narrow, const double2* in, double* out, int64_t rows, const double2* tw,
+static void launch_c2r_shape(int sh, const double2* in, double* out, int64_t rows, const double2* tw,
                              hipStream_t s, RowFlip fl) {
     constexpr int ROWS = last_rows<N>();
     constexpr int RS = small_rows<N>();
-    if (narrow && RS < ROWS)
+    constexpr int RD = deep_rows<N>();
+    if (sh == SH_NARROW && RS < ROWS)
         hipLaunchKernelGGL((k_c2r_last<N, 64, RS, RADIX>), dim3((unsigned)((rows + RS - 1) / RS)), dim3(64), 0, s,
                            in, out, rows, tw, fl);
+    else if (sh == SH_DEEP && RS < ROWS)
+        hipLaunchKernelGGL((k_c2r_last<N, 256, RD, RADIX>), dim3((unsigned)((rows + RD - 1) / RD)), dim3(256), 0,
+                           s, in, out, rows, tw, fl);
     else
         hipLaunchKernelGGL((k_c2r_last<N, 256, ROWS, RADIX>), dim3((unsigned)((rows + ROWS - 1) / ROWS)), dim3(256),
                            0, s, in, out, rows, tw, fl);
 }
 
-// narrow (one-wavefront) last-axis blocks for schedule fs
+// last-axis launch shape for schedule fs
 template <int N>
-static bool last_narrow(int64_t rows, int fs) {
+static int last_shape(int64_t rows, int fs) {
     constexpr int ROWS = last_rows<N>();
-    if (fs == FS_WIDE) return false;
-    if (fs == FS_NARROW) return true;
-    return (rows + ROWS - 1) / ROWS < kMinBlocks;
+    if (fs == FS_WIDE) return SH_WIDE;
+    if (fs == FS_NARROW) return SH_NARROW;
+    if (fs == FS_DEEP) return SH_DEEP;
+    return (rows + ROWS - 1) / ROWS < kMinBlocks ? SH_DEEP : SH_WIDE;
 }
 
 template <int N>
 static hipError_t run_r2c_last(const double* in, double2* out, int64_t rows, const double2* tw, hipStream_t s,
                                CountSrc cs, int fs) {
-    const bool narrow = last_narrow<N>(rows, fs);
+    const int sh = last_shape<N>(rows, fs);
     if (fs == FS_RADIX4)
-        launch_r2c_shape<N, 1>(narrow, in, out, rows, tw, s, cs);
+        launch_r2c_shape<N, 1>(sh, in, out, rows, tw, s, cs);
     else
-        launch_r2c_shape<N, 0>(narrow, in, out, rows, tw, s, cs);
+        launch_r2c_shape<N, 0>(sh, in, out, rows, tw, s, cs);
     return hipGetLastError();
 }
 template <int N>
 static hipError_t run_c2r_last(const double2* in, double* out, int64_t rows, const double2* tw, hipStream_t s,
                                RowFlip fl, int fs) {
-    const bool narrow = last_narrow<N>(rows, fs);
+    const int sh = last_shape<N>(rows, fs);
     if (fs == FS_RADIX4)
-        launch_c2r_shape<N, 1>(narrow, in, out, rows, tw, s, fl);
+        launch_c2r_shape<N, 1>(sh, in, out, rows, tw, s, fl);
     else
-        launch_c2r_shape<N, 0>(narrow, in, out, rows, tw, s, fl);
+        launch_c2r_shape<N, 0>(sh, in, out, rows, tw, s, fl);
     return hipGetLastError();
 }
 
@@ -431,7 +451,8 @@ static void run_c2c_r(double2* buf, double2* out2, int64_t outer, int64_t inner,
     constexpr int T = tile_cols<N>();
     constexpr int TS = N >= 64 ? 1 : (64 / N > 16 ? 16 : 64 / N);  // one radix pass per lane
     constexpr int TH = T > 1 ? T / 2 : 1;
-    if (fs != FS_NARROW && fs != FS_HALF) {
+    const bool small = outer * ((inner + T - 1) / T) < kMinBlocks;
+    if (fs != FS_NARROW && fs != FS_HALF && fs != FS_DEEP) {
         if constexpr (slab_fits<N, 33>()) {
             if (inner == 33 && (outer >= kMinBlocks || fs == FS_WIDE)) {
                 launch_c2c_t<N, 256, 33, RADIX>(buf, out2, outer, inner, dir, mode, tw, s);
@@ -445,11 +466,16 @@ static void run_c2c_r(double2* buf, double2* out2, int64_t outer, int64_t inner,
             }
         }
     }
-    const bool narrow = TS < T && (fs == FS_NARROW ||
-                                   (fs != FS_WIDE && outer * ((inner + T - 1) / T) < kMinBlocks));
-    if (narrow) {
-        launch_c2c_t<N, 64, TS, RADIX>(buf, out2, outer, inner, dir, mode, tw, s);
-        return;
+    if constexpr (TS < T) {
+        // one-wavefront blocks (FS_NARROW), or the same tiles on 256 threads
+        if (fs == FS_NARROW) {
+            launch_c2c_t<N, 64, TS, RADIX>(buf, out2, outer, inner, dir, mode, tw, s);
+            return;
+        }
+        if (fs == FS_DEEP || (fs != FS_WIDE && small)) {
+            launch_c2c_t<N, 256, TS, RADIX>(buf, out2, outer, inner, dir, mode, tw, s);
+            return;
+        }
     }
     if constexpr (RADIX == 0 && TH < T) {
         if (fs == FS_HALF) {

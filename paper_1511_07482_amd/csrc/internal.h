@@ -180,7 +180,7 @@ hipError_t fft_r2c_nd(const double* in, double2* out, const kdefft_grid& g, hipS
 hipError_t fft_c2r_nd(double2* inout, double* out, const kdefft_grid& g, hipStream_t s);
 // FFT-stage schedules of the count transform (launch shapes and radix order
 // of its passes; fft.hip FS_*): fs in [0, FFT_SCHEDULES), 0 the default.
-constexpr int FFT_SCHEDULES = 5;
+constexpr int FFT_SCHEDULES = 6;
 // Count spectrum of a prepared dataset: spec = R2C(czp); wmix = |spec|^2
 // transformed forward along the leading axes.  The first pass reads the int64
 // counts directly: src is the count grid itself (ncopies = 0) or ncopies grids
