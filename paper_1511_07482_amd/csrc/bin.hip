@@ -31,6 +31,8 @@ __global__ __launch_bounds__(256) void k_bounds(const double* __restrict__ X, in
         mn[k] = INFINITY;
         mx[k] = -INFINITY;
     }
+    // unrolled so that a thread's loads are in flight together
+#pragma unroll 4
     for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += stride) {
 #pragma unroll
         for (int k = 0; k < D; ++k) {

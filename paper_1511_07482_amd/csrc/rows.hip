@@ -141,6 +141,11 @@ RowGeom make_geom(const kdefft_grid& g, int kind, int r, int64_t ncand, int vari
         // resident blocks; the same row chunks serve the launch without a plan
         const int64_t slots = (int64_t)compact_slots(g.d);
         int64_t per = (slots + ncand - 1) / ncand;
+        // more items than resident slots by more than an eighth of them would
+        // start a large second round of blocks: one round of fewer, larger
+        // items instead (a small overflow is absorbed by the blocks that
+        // finish early)
+        if (per > 1 && ncand * per > slots + slots / 8) per = slots / ncand > 1 ? slots / ncand : 1;
         if (per > nrows) per = nrows;
         const int64_t chunk = (nrows + per - 1) / per;
         geo.chunk = chunk;

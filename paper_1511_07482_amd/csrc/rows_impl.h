@@ -596,15 +596,15 @@ __device__ __forceinline__ void write_units(uint32_t* s_unit, int row, const Liv
 constexpr int UNIT_CAP = 4096;
 constexpr int MAX_PLAN = 1024;
 
-// Compacted dealing of an item's rows [rbeg, rend): the rows are taken RB at a
-// time; thread t finds row t's live runs (row_live), a block scan numbers their
-// segments, the segments are listed in LDS (rows in order, runs in order within
-// a row, so neighbouring lanes read neighbouring blocks of the
-// autocorrelation), and the threads walk segments t, t + NT, ... of the list
-// with seg_walk(ri, first run, runs).
+// Compacted dealing of an item's rows row0, row0 + rstride, ... (count rows):
+// the rows are taken RB at a time; thread t finds row t's live runs
+// (row_live), a block scan numbers their segments, the segments are listed in
+// LDS (rows in order, runs in order within a row, so neighbouring lanes read
+// neighbouring blocks of the autocorrelation), and the threads walk segments
+// t, t + NT, ... of the list with seg_walk(ri, first run, runs).
 template <int D, int N, int RL, int SEG, int NT, class Fun, class Walk>
-__device__ __forceinline__ void live_segments(const Fun& f, const RowGeom& geo, int64_t rbeg, int64_t rend,
-                                              const double* delta, Walk&& seg_walk) {
+__device__ __forceinline__ void live_segments(const Fun& f, const RowGeom& geo, int64_t row0, int64_t rstride,
+                                              int64_t count, const double* delta, Walk&& seg_walk) {
     constexpr int NRUN = N / RL;                               // runs per row
     constexpr int UPR = 2 * ((NRUN / 2 + SEG - 1) / SEG);     // segments per row, at most (both sides)
     constexpr int RB = NT < UNIT_CAP / UPR ? NT : UNIT_CAP / UPR;   // rows per pass
@@ -612,18 +612,20 @@ __device__ __forceinline__ void live_segments(const Fun& f, const RowGeom& geo, 
     __shared__ uint32_t s_unit[RB * UPR];
     __shared__ int s_wsum[NT / 64];
     const int M_last = geo.M[D - 1];
-    for (int64_t rb = rbeg; rb < rend; rb += RB) {
-        const int nb = rend - rb < RB ? (int)(rend - rb) : RB;
+    for (int64_t jb = 0; jb < count; jb += RB) {
+        const int nb = count - jb < RB ? (int)(count - jb) : RB;
         LiveRuns lr{0, 0, 0, 0};
         if ((int)threadIdx.x < nb)
-            lr = row_live<D>(f, row_info<D>(rb + threadIdx.x, rend, geo, delta, nullptr), M_last, N, RL, delta[D - 1]);
+            lr = row_live<D>(f, row_info<D>(row0 + (jb + threadIdx.x) * rstride, geo.nrows, geo, delta, nullptr),
+                             M_last, N, RL, delta[D - 1]);
         int total = 0;
         const int first = block_scan_excl<NT>(live_units<SEG>(lr), s_wsum, &total);
         if ((int)threadIdx.x < nb) write_units<SEG>(s_unit, (int)threadIdx.x, lr, first, 0, total);
         __syncthreads();
         for (int k = threadIdx.x; k < total; k += NT) {
             const uint32_t u = s_unit[k];
-            seg_walk(row_info<D>(rb + (u >> 16), rend, geo, delta, nullptr), (int)((u >> 8) & 255u), (int)(u & 255u));
+            seg_walk(row_info<D>(row0 + (jb + (u >> 16)) * rstride, geo.nrows, geo, delta, nullptr),
+                     (int)((u >> 8) & 255u), (int)(u & 255u));
         }
         __syncthreads();
     }
@@ -1048,8 +1050,10 @@ __global__ __launch_bounds__(NT, D <= 2 ? (COMPACT ? 3 : 1) : 2) void k_lag_mom(
         } else {
             if (geo.nplan > 0)
                 live_window<D, N, RL, SEG, NT>(f, geo, part, parts, delta, seg_walk);
-            else
-                live_segments<D, N, RL, SEG, NT>(f, geo, rbeg, rend, delta, seg_walk);
+            else   // the item's rows interleaved with its candidate's other items' (ch, ch + nchunks, ...):
+                   // every item gets a like share of the rows near the kernels' peaks
+                live_segments<D, N, RL, SEG, NT>(f, geo, ch, geo.nchunks, (geo.nrows - ch + geo.nchunks - 1) / geo.nchunks,
+                                                 delta, seg_walk);
         }
         double outv[NG];
         block_sum<NG, NT>(acc, red, outv);
