@@ -491,14 +491,18 @@ def fftl_section(kf, torch, dev, X, Gpsi, g):
 
 def fft_stage_bytes(P, M, d):
     """Algorithmic HBM bytes of one dataset's count transform as the passes are
-    built (d >= 2): the last-axis R2C reads the int64 counts (prod M) and writes
-    the half spectrum (16 L Q bytes, L = prod of the leading P, Q = P/2 + 1);
-    the forward passes along axes d-2..1 read and write it; the axis-0 pass
-    reads it and writes C and the mixed spectrum |C|^2 transformed forward;
+    built (d >= 2, f = M/P the live fraction of a leading axis): the last-axis
+    R2C reads the int64 counts (prod M) and writes the rows of the half
+    spectrum that can be nonzero (a fraction f^(d-1) of its 16 L Q bytes, L =
+    prod of the leading P, Q = P/2 + 1); the forward pass along axis a
+    (a = d-2..1) reads the fraction f^(a+1) of it and writes f^a; the axis-0
+    pass reads f and writes C and the mixed spectrum |C|^2 transformed forward;
     axes 1..d-2 of the mixed spectrum read and write it; the last-axis C2R
     reads it and writes the real lag array (8 prod P)."""
     half = 16 * P ** (d - 1) * (P // 2 + 1)
-    return 8 * M ** d + 8 * P ** d + half * (5 + 4 * (d - 2))
+    f = M / P
+    fwd = f ** (d - 1) + sum(f ** (a + 1) + f ** a for a in range(1, d - 1)) + f + 2
+    return int(round(8 * M ** d + 8 * P ** d + half * (fwd + 2 * (d - 2) + 1)))
 
 
 def fft_stage_section(kf, torch, dev, stream):

@@ -90,6 +90,7 @@ struct CountSrc {
     int ncopies;            // > 0: counts holds ncopies grids of `stride` bins, summed here
     int64_t stride;
     int64_t* sum_out;       // the summed grid, written when ncopies > 0
+    int prune;              // rows of the zero padding are not written (the next pass never reads them)
 };
 
 // Count of bin i (flat index into the M^d grid); sums the copies exactly
@@ -163,6 +164,7 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
         bool any = false;
         for (int rr = 0; rr < ROWS; ++rr) any = any || rbase[rr] >= 0;
         if (!any) {
+            if (cs.prune) return;
             for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
                 const int64_t row = r0 + e / Q;
                 if (row < rows) out[row * Q + (e % Q)] = make_double2(0.0, 0.0);
@@ -190,10 +192,23 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
     twc.store(twl, tw);
     __syncthreads();
     fft_lds<H, ROWS, NT, -1, RADIX, N>(buf, PS, twl);
+    __shared__ bool rskip[ROWS];   // zero rows left unwritten (pruned passes)
+    for (int rr = threadIdx.x; rr < ROWS; rr += NT) {
+        bool skip = false;
+        if (cs.counts && cs.prune) {
+            int64_t rem = r0 + rr;
+            for (int k = cs.d - 2; k >= 0; --k) {
+                skip = skip || (int)(rem % cs.P[k]) >= cs.M[k];
+                rem /= cs.P[k];
+            }
+        }
+        rskip[rr] = skip;
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
         const int rr = e / Q, k = e - rr * Q;
         const int64_t row = r0 + rr;
-        if (row >= rows) continue;
+        if (row >= rows || rskip[rr]) continue;
         const double2 zk = buf[rr * PS + (k == H ? 0 : k)];
         const double2 zc = c_conj(buf[rr * PS + (k == 0 ? 0 : H - k)]);
         const double2 E = c_scale(c_add(zk, zc), 0.5);
@@ -275,24 +290,47 @@ constexpr int tile_cols() {
          : 4096 / (N + 1) >= 2 ? 2 : 1;
 }
 
+// Zero structure of a forward count-transform pass along axis a (pruning):
+// the counts fill [0, M)^d of the padded P^d grid, so before the pass a
+// column (outer index i_0..i_{a-1} over the axes before a) can be nonzero only
+// if every i_k < M_k, and within it only its first M_a entries.  Dead columns
+// are skipped (nothing is read or written: the next pass, along a - 1, reads
+// only live columns' outputs), and only the first nlive entries of a live
+// column are read.  na = 0, nlive = N: the dense transform.
+struct Prune {
+    int na;       // axes before the pass's axis
+    int P[3];     // their extents (outer index digits, major first)
+    int M[3];     // their count extents
+    int nlive;    // entries of a live column that can be nonzero
+};
+
 // MODE 0: in-place transform.  MODE 1: forward transform stored in place
 // (the finished count spectrum C), then |C|^2 transformed forward again and
 // stored to out2.
 template <int N, int NT, int DIR, int MODE, int T, int RADIX>
 __global__ __launch_bounds__(NT) void k_c2c_strided(double2* __restrict__ buf, double2* __restrict__ out2,
                                                     int64_t inner, int64_t tiles,
-                                                    const double2* __restrict__ tw) {
+                                                    const double2* __restrict__ tw, Prune pr) {
     constexpr int PS = T > 1 ? N + 1 : N;
     __shared__ double2 lds[T * PS];
     __shared__ double2 twl[N];
+    const int64_t o = blockIdx.x / tiles;
+    if (pr.na > 0) {   // block-uniform
+        int64_t rem = o;
+        bool dead = false;
+        for (int k = pr.na - 1; k >= 0; --k) {
+            dead = dead || (int)(rem % pr.P[k]) >= pr.M[k];
+            rem /= pr.P[k];
+        }
+        if (dead) return;
+    }
     TwiddleCopy<N, NT> twc;
     twc.fetch(tw);
-    const int64_t o = blockIdx.x / tiles;
     const int64_t i0 = (blockIdx.x - o * tiles) * T;
     double2* base = buf + o * N * inner + i0;
     for (int e = threadIdx.x; e < N * T; e += NT) {
         const int t = e % T, p = e / T;
-        lds[t * PS + p] = (i0 + t < inner) ? base[(int64_t)p * inner + t] : make_double2(0.0, 0.0);
+        lds[t * PS + p] = (i0 + t < inner && p < pr.nlive) ? base[(int64_t)p * inner + t] : make_double2(0.0, 0.0);
     }
     twc.store(twl, tw);
     __syncthreads();
@@ -423,18 +461,18 @@ static hipError_t run_c2r_last(const double2* in, double* out, int64_t rows, con
 
 template <int N, int NT, int T, int RADIX>
 static void launch_c2c_t(double2* buf, double2* out2, int64_t outer, int64_t inner, int dir, int mode,
-                         const double2* tw, hipStream_t s) {
+                         const double2* tw, hipStream_t s, const Prune& pr) {
     const int64_t tiles = (inner + T - 1) / T;
     const dim3 grid((unsigned)(outer * tiles));
     if (mode == 1)
         hipLaunchKernelGGL((k_c2c_strided<N, NT, -1, 1, T, RADIX>), grid, dim3(NT), 0, s, buf, out2, inner, tiles,
-                           tw);
+                           tw, pr);
     else if (dir < 0)
         hipLaunchKernelGGL((k_c2c_strided<N, NT, -1, 0, T, RADIX>), grid, dim3(NT), 0, s, buf, out2, inner, tiles,
-                           tw);
+                           tw, pr);
     else
         hipLaunchKernelGGL((k_c2c_strided<N, NT, 1, 0, T, RADIX>), grid, dim3(NT), 0, s, buf, out2, inner, tiles,
-                           tw);
+                           tw, pr);
 }
 
 // Slab tiles: when the axis is the last leading one its inner extent is the
@@ -447,7 +485,7 @@ constexpr bool slab_fits() { return N >= 8 && Q * (N + 1) * 16 <= 81920; }
 
 template <int N, int RADIX>
 static void run_c2c_r(double2* buf, double2* out2, int64_t outer, int64_t inner, int dir, int mode,
-                      const double2* tw, hipStream_t s, int fs) {
+                      const double2* tw, hipStream_t s, int fs, const Prune& pr) {
     constexpr int T = tile_cols<N>();
     constexpr int TS = N >= 64 ? 1 : (64 / N > 16 ? 16 : 64 / N);  // one radix pass per lane
     constexpr int TH = T > 1 ? T / 2 : 1;
@@ -455,13 +493,13 @@ static void run_c2c_r(double2* buf, double2* out2, int64_t outer, int64_t inner,
     if (fs != FS_NARROW && fs != FS_HALF && fs != FS_DEEP) {
         if constexpr (slab_fits<N, 33>()) {
             if (inner == 33 && (outer >= kMinBlocks || fs == FS_WIDE)) {
-                launch_c2c_t<N, 256, 33, RADIX>(buf, out2, outer, inner, dir, mode, tw, s);
+                launch_c2c_t<N, 256, 33, RADIX>(buf, out2, outer, inner, dir, mode, tw, s, pr);
                 return;
             }
         }
         if constexpr (slab_fits<N, 17>()) {
             if (inner == 17 && (outer >= kMinBlocks || fs == FS_WIDE)) {
-                launch_c2c_t<N, 256, 17, RADIX>(buf, out2, outer, inner, dir, mode, tw, s);
+                launch_c2c_t<N, 256, 17, RADIX>(buf, out2, outer, inner, dir, mode, tw, s, pr);
                 return;
             }
         }
@@ -469,30 +507,30 @@ static void run_c2c_r(double2* buf, double2* out2, int64_t outer, int64_t inner,
     if constexpr (TS < T) {
         // one-wavefront blocks (FS_NARROW), or the same tiles on 256 threads
         if (fs == FS_NARROW) {
-            launch_c2c_t<N, 64, TS, RADIX>(buf, out2, outer, inner, dir, mode, tw, s);
+            launch_c2c_t<N, 64, TS, RADIX>(buf, out2, outer, inner, dir, mode, tw, s, pr);
             return;
         }
         if (fs == FS_DEEP || (fs != FS_WIDE && small)) {
-            launch_c2c_t<N, 256, TS, RADIX>(buf, out2, outer, inner, dir, mode, tw, s);
+            launch_c2c_t<N, 256, TS, RADIX>(buf, out2, outer, inner, dir, mode, tw, s, pr);
             return;
         }
     }
     if constexpr (RADIX == 0 && TH < T) {
         if (fs == FS_HALF) {
-            launch_c2c_t<N, 256, TH, 0>(buf, out2, outer, inner, dir, mode, tw, s);
+            launch_c2c_t<N, 256, TH, 0>(buf, out2, outer, inner, dir, mode, tw, s, pr);
             return;
         }
     }
-    launch_c2c_t<N, 256, T, RADIX>(buf, out2, outer, inner, dir, mode, tw, s);
+    launch_c2c_t<N, 256, T, RADIX>(buf, out2, outer, inner, dir, mode, tw, s, pr);
 }
 
 template <int N>
 static hipError_t run_c2c(double2* buf, double2* out2, int64_t outer, int64_t inner, int dir, int mode,
-                          const double2* tw, hipStream_t s, int fs) {
+                          const double2* tw, hipStream_t s, int fs, const Prune& pr) {
     if (fs == FS_RADIX4)
-        run_c2c_r<N, 1>(buf, out2, outer, inner, dir, mode, tw, s, fs);
+        run_c2c_r<N, 1>(buf, out2, outer, inner, dir, mode, tw, s, fs, pr);
     else
-        run_c2c_r<N, 0>(buf, out2, outer, inner, dir, mode, tw, s, fs);
+        run_c2c_r<N, 0>(buf, out2, outer, inner, dir, mode, tw, s, fs, pr);
     return hipGetLastError();
 }
 
@@ -514,7 +552,7 @@ static hipError_t run_c2c(double2* buf, double2* out2, int64_t outer, int64_t in
     }
 
 static hipError_t r2c_last(const double* in, double2* out, int64_t rows, int N, const double2* tw, hipStream_t s,
-                           CountSrc cs = CountSrc{nullptr, 0, {0, 0, 0, 0}, {0, 0, 0, 0}, 0, 0, nullptr},
+                           CountSrc cs = CountSrc{nullptr, 0, {0, 0, 0, 0}, {0, 0, 0, 0}, 0, 0, nullptr, 0},
                            int fs = FS_AUTO) {
 #define CALL(NN) run_r2c_last<NN>(in, out, rows, tw, s, cs, fs)
     if (N < 4) return hipErrorInvalidValue;
@@ -529,8 +567,9 @@ static hipError_t c2r_last(const double2* in, double* out, int64_t rows, int N, 
 #undef CALL
 }
 static hipError_t c2c(double2* buf, double2* out2, int64_t outer, int N, int64_t inner, int dir, int mode,
-                      const double2* tw, hipStream_t s, int fs = FS_AUTO) {
-#define CALL(NN) run_c2c<NN>(buf, out2, outer, inner, dir, mode, tw, s, fs)
+                      const double2* tw, hipStream_t s, int fs = FS_AUTO, Prune pr = Prune{0, {1, 1, 1}, {1, 1, 1}, 0}) {
+    if (pr.nlive <= 0 || pr.nlive > N) pr.nlive = N;
+#define CALL(NN) run_c2c<NN>(buf, out2, outer, inner, dir, mode, tw, s, fs, pr)
     KDEFFT_SWITCH_N(ilog2i(N), CALL)
 #undef CALL
 }
@@ -590,7 +629,7 @@ hipError_t fft_prepare_nd(const int64_t* src, int ncopies, int64_t* counts, doub
     const double2* tw;
     hipError_t e = twiddles(&tw);
     if (e != hipSuccess) return e;
-    CountSrc cs{src, g.d, {1, 1, 1, 1}, {1, 1, 1, 1}, ncopies, 1, counts};
+    CountSrc cs{src, g.d, {1, 1, 1, 1}, {1, 1, 1, 1}, ncopies, 1, counts, 1};
     for (int k = 0; k < g.d; ++k) {
         cs.M[k] = g.M[k];
         cs.P[k] = g.P[k];
@@ -604,16 +643,24 @@ hipError_t fft_prepare_nd(const int64_t* src, int ncopies, int64_t* counts, doub
         hipLaunchKernelGGL(k_abs2, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, spec, wmix, cnt);
         return hipGetLastError();
     }
+    // forward passes over the counts' spectrum, pruned: before the pass along
+    // axis a only columns with i_k < M_k (k < a) are nonzero, and only their
+    // first M_a entries
     for (int ax = g.d - 2; ax >= 1 && e == hipSuccess; --ax) {
         int64_t outer, inner;
         axis_shape(g, ax, &outer, &inner);
-        e = c2c(spec, nullptr, outer, g.P[ax], inner, -1, 0, tw, s, fs);
+        Prune pr{ax, {1, 1, 1}, {1, 1, 1}, g.M[ax]};
+        for (int k = 0; k < ax; ++k) {
+            pr.P[k] = g.P[k];
+            pr.M[k] = g.M[k];
+        }
+        e = c2c(spec, nullptr, outer, g.P[ax], inner, -1, 0, tw, s, fs, pr);
     }
     if (e != hipSuccess) return e;
     {
         int64_t outer, inner;
         axis_shape(g, 0, &outer, &inner);
-        e = c2c(spec, wmix, outer, g.P[0], inner, -1, 1, tw, s, fs);
+        e = c2c(spec, wmix, outer, g.P[0], inner, -1, 1, tw, s, fs, Prune{0, {1, 1, 1}, {1, 1, 1}, g.M[0]});
     }
     for (int ax = 1; ax + 1 < g.d && e == hipSuccess; ++ax) {
         int64_t outer, inner;

@@ -50,13 +50,17 @@ def test_lag_layout_rejects_bad_length():
 
 def test_fft_stage_bytes():
     # case 5 (M = 32, P = 64, d = 4): int64 counts 8 M^4 read by the R2C pass,
-    # half spectrum 16 P^3 (P/2 + 1) per pass, real lag array 8 P^4 written by
-    # the C2R pass.  Passes: R2C (counts -> half), axes 2, 1 forward (2 half
-    # each), axis 0 (read half, write C and the mixed spectrum: 3 half),
-    # axes 1, 2 of the mixed spectrum (2 half each), C2R (half -> real).
+    # half spectrum 16 P^3 (P/2 + 1), real lag array 8 P^4 written by the C2R
+    # pass.  The counts fill [0, 32)^4 of the 64^4 grid, so the forward passes
+    # touch only the part that can be nonzero: R2C writes the rows with all
+    # three leading indices < 32 (1/8 of half); the axis-2 pass reads those
+    # (1/8) and writes columns with i0, i1 < 32 (1/4); axis 1 reads 1/4 and
+    # writes 1/2; axis 0 reads 1/2 and writes C and the mixed spectrum (2 half);
+    # axes 1, 2 of the mixed spectrum are dense (2 half each); C2R reads half.
     counts, real, half = 8 * 32 ** 4, 8 * 64 ** 4, 16 * 64 ** 3 * 33
-    want = (counts + half) + 2 * 2 * half + 3 * half + 2 * 2 * half + (half + real)
-    assert bench.fft_stage_bytes(64, 32, 4) == want == 1_941_962_752
-    # d = 2 (M = 256, P = 512): no middle passes
+    want = (counts + half // 8) + (half // 8 + half // 4) + (half // 4 + half // 2) + (half // 2 + 2 * half) \
+        + 2 * 2 * half + (half + real)
+    assert bench.fft_stage_bytes(64, 32, 4) == want == 1_353_711_616
+    # d = 2 (M = 256, P = 512): R2C writes half the rows, axis 0 reads them
     counts, real, half = 8 * 256 ** 2, 8 * 512 ** 2, 16 * 512 * 257
-    assert bench.fft_stage_bytes(512, 256, 2) == (counts + half) + 3 * half + (half + real)
+    assert bench.fft_stage_bytes(512, 256, 2) == (counts + half // 2) + (half // 2 + 2 * half) + (half + real)
