@@ -90,7 +90,9 @@ struct CountSrc {
     int ncopies;            // > 0: counts holds ncopies grids of `stride` bins, summed here
     int64_t stride;
     int64_t* sum_out;       // the summed grid, written when ncopies > 0
-    int prune;              // rows of the zero padding are not written (the next pass never reads them)
+    int prune;              // only the rows inside the counts' box: row r of the launch is the counts'
+                            // row r (leading indices over M), stored at its place in the padded grid;
+                            // the padding's zero rows are not written (the next pass never reads them)
 };
 
 // Count of bin i (flat index into the M^d grid); sums the copies exactly
@@ -145,7 +147,9 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
         for (int rr = threadIdx.x; rr < ROWS; rr += NT) {
             const int64_t row = r0 + rr;
             int64_t base = -1;
-            if (row < rows) {
+            if (cs.prune) {
+                if (row < rows) base = row * Ml;
+            } else if (row < rows) {
                 int64_t rem = row, cf = 0, mul = 1;
                 bool ok = true;
                 for (int k = cs.d - 2; k >= 0; --k) {
@@ -164,7 +168,6 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
         bool any = false;
         for (int rr = 0; rr < ROWS; ++rr) any = any || rbase[rr] >= 0;
         if (!any) {
-            if (cs.prune) return;
             for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
                 const int64_t row = r0 + e / Q;
                 if (row < rows) out[row * Q + (e % Q)] = make_double2(0.0, 0.0);
@@ -192,23 +195,25 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
     twc.store(twl, tw);
     __syncthreads();
     fft_lds<H, ROWS, NT, -1, RADIX, N>(buf, PS, twl);
-    __shared__ bool rskip[ROWS];   // zero rows left unwritten (pruned passes)
+    __shared__ int64_t rout[ROWS];   // output row of each row: its place in the padded grid when pruned
     for (int rr = threadIdx.x; rr < ROWS; rr += NT) {
-        bool skip = false;
+        int64_t row = r0 + rr;
         if (cs.counts && cs.prune) {
-            int64_t rem = r0 + rr;
+            int64_t rem = row, mul = 1;
+            row = 0;
             for (int k = cs.d - 2; k >= 0; --k) {
-                skip = skip || (int)(rem % cs.P[k]) >= cs.M[k];
-                rem /= cs.P[k];
+                row += (rem % cs.M[k]) * mul;
+                rem /= cs.M[k];
+                mul *= cs.P[k];
             }
         }
-        rskip[rr] = skip;
+        rout[rr] = row;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
         const int rr = e / Q, k = e - rr * Q;
-        const int64_t row = r0 + rr;
-        if (row >= rows || rskip[rr]) continue;
+        if (r0 + rr >= rows) continue;
+        const int64_t row = rout[rr];
         const double2 zk = buf[rr * PS + (k == H ? 0 : k)];
         const double2 zc = c_conj(buf[rr * PS + (k == 0 ? 0 : H - k)]);
         const double2 E = c_scale(c_add(zk, zc), 0.5);
@@ -293,10 +298,12 @@ constexpr int tile_cols() {
 // Zero structure of a forward count-transform pass along axis a (pruning):
 // the counts fill [0, M)^d of the padded P^d grid, so before the pass a
 // column (outer index i_0..i_{a-1} over the axes before a) can be nonzero only
-// if every i_k < M_k, and within it only its first M_a entries.  Dead columns
-// are skipped (nothing is read or written: the next pass, along a - 1, reads
-// only live columns' outputs), and only the first nlive entries of a live
-// column are read.  na = 0, nlive = N: the dense transform.
+// if every i_k < M_k, and within it only its first M_a entries.  The launch
+// covers the live columns only (its outer index runs over the M_k extents and
+// is placed in the P_k-extent buffer; the dead columns are neither read nor
+// written: the next pass, along a - 1, reads only live columns' outputs), and
+// only the first nlive entries of a column are read.  na = 0, nlive = N: the
+// dense transform.
 struct Prune {
     int na;       // axes before the pass's axis
     int P[3];     // their extents (outer index digits, major first)
@@ -314,19 +321,20 @@ __global__ __launch_bounds__(NT) void k_c2c_strided(double2* __restrict__ buf, d
     constexpr int PS = T > 1 ? N + 1 : N;
     __shared__ double2 lds[T * PS];
     __shared__ double2 twl[N];
-    const int64_t o = blockIdx.x / tiles;
-    if (pr.na > 0) {   // block-uniform
-        int64_t rem = o;
-        bool dead = false;
-        for (int k = pr.na - 1; k >= 0; --k) {
-            dead = dead || (int)(rem % pr.P[k]) >= pr.M[k];
-            rem /= pr.P[k];
-        }
-        if (dead) return;
-    }
     TwiddleCopy<N, NT> twc;
     twc.fetch(tw);
-    const int64_t i0 = (blockIdx.x - o * tiles) * T;
+    const int64_t ol = blockIdx.x / tiles;
+    int64_t o = ol;
+    if (pr.na > 0) {   // live column ol (extents M) -> its outer index in the buffer (extents P)
+        int64_t rem = ol, mul = 1;
+        o = 0;
+        for (int k = pr.na - 1; k >= 0; --k) {
+            o += (rem % pr.M[k]) * mul;
+            rem /= pr.M[k];
+            mul *= pr.P[k];
+        }
+    }
+    const int64_t i0 = (blockIdx.x - ol * tiles) * T;
     double2* base = buf + o * N * inner + i0;
     for (int e = threadIdx.x; e < N * T; e += NT) {
         const int t = e % T, p = e / T;
@@ -569,6 +577,10 @@ static hipError_t c2r_last(const double2* in, double* out, int64_t rows, int N, 
 static hipError_t c2c(double2* buf, double2* out2, int64_t outer, int N, int64_t inner, int dir, int mode,
                       const double2* tw, hipStream_t s, int fs = FS_AUTO, Prune pr = Prune{0, {1, 1, 1}, {1, 1, 1}, 0}) {
     if (pr.nlive <= 0 || pr.nlive > N) pr.nlive = N;
+    if (pr.na > 0) {   // the launch covers the live columns only
+        outer = 1;
+        for (int k = 0; k < pr.na; ++k) outer *= pr.M[k];
+    }
 #define CALL(NN) run_c2c<NN>(buf, out2, outer, inner, dir, mode, tw, s, fs, pr)
     KDEFFT_SWITCH_N(ilog2i(N), CALL)
 #undef CALL
@@ -636,7 +648,10 @@ hipError_t fft_prepare_nd(const int64_t* src, int ncopies, int64_t* counts, doub
         cs.stride *= g.M[k];
     }
     if (ncopies > 0 && !counts) return hipErrorInvalidValue;
-    e = r2c_last(nullptr, spec, lead_count(g), g.P[g.d - 1], tw, s, cs, fs);
+    // the R2C covers the rows inside the counts' box only (prod of the leading M)
+    int64_t rows_live = 1;
+    for (int k = 0; k + 1 < g.d; ++k) rows_live *= g.M[k];
+    e = r2c_last(nullptr, spec, rows_live, g.P[g.d - 1], tw, s, cs, fs);
     if (e != hipSuccess) return e;
     if (g.d == 1) {
         const int64_t cnt = g.P[0] / 2 + 1;
