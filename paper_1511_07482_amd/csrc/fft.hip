@@ -174,22 +174,34 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
             }
             return;
         }
-        for (int e = threadIdx.x; e < ROWS * H; e += NT) {
-            const int rr = e / H, m = e - rr * H;
-            const int64_t base = rbase[rr];
-            double2 v = make_double2(0.0, 0.0);
-            if (base >= 0) {
-                const int p0 = 2 * m, p1 = 2 * m + 1;
-                if (p0 < Ml) v.x = (double)load_count(cs, base + p0) * quantum;
-                if (p1 < Ml) v.y = (double)load_count(cs, base + p1) * quantum;
+        // a thread's elements in an unrolled loop, so that their loads are in
+        // flight together (these passes are bound by load latency)
+        constexpr int PE = (ROWS * H + NT - 1) / NT;
+#pragma unroll
+        for (int u = 0; u < PE; ++u) {
+            const int e = threadIdx.x + u * NT;
+            if ((ROWS * H) % NT == 0 || e < ROWS * H) {
+                const int rr = e / H, m = e - rr * H;
+                const int64_t base = rbase[rr];
+                double2 v = make_double2(0.0, 0.0);
+                if (base >= 0) {
+                    const int p0 = 2 * m, p1 = 2 * m + 1;
+                    if (p0 < Ml) v.x = (double)load_count(cs, base + p0) * quantum;
+                    if (p1 < Ml) v.y = (double)load_count(cs, base + p1) * quantum;
+                }
+                buf[rr * PS + m] = v;
             }
-            buf[rr * PS + m] = v;
         }
     } else {
-        for (int e = threadIdx.x; e < ROWS * H; e += NT) {
-            const int rr = e / H, m = e - rr * H;
-            const int64_t row = r0 + rr;
-            buf[rr * PS + m] = row < rows ? src[row * H + m] : make_double2(0.0, 0.0);
+        constexpr int PE = (ROWS * H + NT - 1) / NT;
+#pragma unroll
+        for (int u = 0; u < PE; ++u) {
+            const int e = threadIdx.x + u * NT;
+            if ((ROWS * H) % NT == 0 || e < ROWS * H) {
+                const int rr = e / H, m = e - rr * H;
+                const int64_t row = r0 + rr;
+                buf[rr * PS + m] = row < rows ? src[row * H + m] : make_double2(0.0, 0.0);
+            }
         }
     }
     twc.store(twl, tw);
@@ -239,10 +251,17 @@ __global__ __launch_bounds__(NT) void k_c2r_last(const double2* __restrict__ in,
         rsrc[rr] = row < rows ? (fl.on ? flip_row(row, fl) : row) : -1;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < ROWS * Q; e += NT) {
-        const int rr = e / Q, k = e - rr * Q;
-        const int64_t src_row = rsrc[rr];
-        buf[rr * PS + k] = src_row >= 0 ? in[src_row * Q + k] : make_double2(0.0, 0.0);
+    {
+        constexpr int PE = (ROWS * Q + NT - 1) / NT;   // unrolled: the loads in flight together
+#pragma unroll
+        for (int u = 0; u < PE; ++u) {
+            const int e = threadIdx.x + u * NT;
+            if ((ROWS * Q) % NT == 0 || e < ROWS * Q) {
+                const int rr = e / Q, k = e - rr * Q;
+                const int64_t src_row = rsrc[rr];
+                buf[rr * PS + k] = src_row >= 0 ? in[src_row * Q + k] : make_double2(0.0, 0.0);
+            }
+        }
     }
     twc.store(twl, tw);
     __syncthreads();
@@ -336,9 +355,17 @@ __global__ __launch_bounds__(NT) void k_c2c_strided(double2* __restrict__ buf, d
     }
     const int64_t i0 = (blockIdx.x - ol * tiles) * T;
     double2* base = buf + o * N * inner + i0;
-    for (int e = threadIdx.x; e < N * T; e += NT) {
-        const int t = e % T, p = e / T;
-        lds[t * PS + p] = (i0 + t < inner && p < pr.nlive) ? base[(int64_t)p * inner + t] : make_double2(0.0, 0.0);
+    {
+        constexpr int PE = (N * T + NT - 1) / NT;   // unrolled: the loads in flight together
+#pragma unroll
+        for (int u = 0; u < PE; ++u) {
+            const int e = threadIdx.x + u * NT;
+            if ((N * T) % NT == 0 || e < N * T) {
+                const int t = e % T, p = e / T;
+                lds[t * PS + p] =
+                    (i0 + t < inner && p < pr.nlive) ? base[(int64_t)p * inner + t] : make_double2(0.0, 0.0);
+            }
+        }
     }
     twc.store(twl, tw);
     __syncthreads();
