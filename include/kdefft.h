@@ -412,7 +412,8 @@ int kdefft_scv_plain(const kdefft_dataset* ds_host, const double* H_host, double
  * remaining runs are dealt to the threads (the dropped terms are far below
  * float64 rounding of the result; the psi and eta families treat 5 and 6 as
  * 3); variant 5 with one block per work item (the untuned default of the SCV
- * families) also builds the candidates' parameter blocks inside the launch.
+ * families) deals each candidate's rows round-robin over its items and also
+ * builds the candidates' parameter blocks inside the launch.
  * The untuned default of the other families is variant 3, grid 0.
  * variant = -1 drops the pinned (or tuned) choice of that key, so the untuned
  * default applies again.  Used by kdefft_autotune and by tests that cover

@@ -138,7 +138,8 @@ RowGeom make_geom(const kdefft_grid& g, int kind, int r, int64_t ncand, int vari
     if (variant >= 5 && mom && nrows <= 4096 && ncand <= 1024) {
         // compacted walk with a balanced plan (items numbered on the device,
         // at most one per resident block): candidates x nchunks covers the
-        // resident blocks; the same row chunks serve the launch without a plan
+        // resident blocks; the launch without a plan takes the same number of
+        // items per candidate, each with every nchunks-th row of its candidate
         const int64_t slots = (int64_t)compact_slots(g.d);
         int64_t per = (slots + ncand - 1) / ncand;
         // more items than resident slots by more than an eighth of them would
