@@ -112,13 +112,15 @@ struct RowFlip {
     int mlast;   // > 0: positions of the last axis with |lag| > mlast - 1 are written as exact zeros
 };
 
-__device__ __forceinline__ int64_t flip_row(int64_t r, const RowFlip& f) {
-    int64_t out = 0, mul = 1;
+// Row indices of the passes are below 2^31 (checked on the host), so rows
+// are decoded with 32-bit divisions.
+__device__ __forceinline__ int64_t flip_row(int64_t row, const RowFlip& f) {
+    uint32_t r = (uint32_t)row, out = 0, mul = 1;
     for (int k = f.nlead - 1; k >= 0; --k) {
-        const int64_t i = r % f.P[k];
-        r /= f.P[k];
-        out += ((f.P[k] - i) % f.P[k]) * mul;
-        mul *= f.P[k];
+        const uint32_t p = (uint32_t)f.P[k], i = r % p;
+        r /= p;
+        out += (i == 0 ? 0u : p - i) * mul;
+        mul *= p;
     }
     return out;
 }
@@ -150,16 +152,16 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
             if (cs.prune) {
                 if (row < rows) base = row * Ml;
             } else if (row < rows) {
-                int64_t rem = row, cf = 0, mul = 1;
+                uint32_t rem = (uint32_t)row, cf = 0, mul = 1;
                 bool ok = true;
                 for (int k = cs.d - 2; k >= 0; --k) {
-                    const int i = (int)(rem % cs.P[k]);
-                    rem /= cs.P[k];
-                    ok = ok && i < cs.M[k];
+                    const uint32_t p = (uint32_t)cs.P[k], i = rem % p;
+                    rem /= p;
+                    ok = ok && i < (uint32_t)cs.M[k];
                     cf += i * mul;
-                    mul *= cs.M[k];
+                    mul *= (uint32_t)cs.M[k];
                 }
-                if (ok) base = cf * Ml;
+                if (ok) base = (int64_t)cf * Ml;
             }
             rbase[rr] = base;
         }
@@ -211,13 +213,14 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
     for (int rr = threadIdx.x; rr < ROWS; rr += NT) {
         int64_t row = r0 + rr;
         if (cs.counts && cs.prune) {
-            int64_t rem = row, mul = 1;
-            row = 0;
+            uint32_t rem = (uint32_t)row, o = 0, mul = 1;
             for (int k = cs.d - 2; k >= 0; --k) {
-                row += (rem % cs.M[k]) * mul;
-                rem /= cs.M[k];
-                mul *= cs.P[k];
+                const uint32_t m = (uint32_t)cs.M[k];
+                o += (rem % m) * mul;
+                rem /= m;
+                mul *= (uint32_t)cs.P[k];
             }
+            row = o;
         }
         rout[rr] = row;
     }
@@ -342,19 +345,21 @@ __global__ __launch_bounds__(NT) void k_c2c_strided(double2* __restrict__ buf, d
     __shared__ double2 twl[N];
     TwiddleCopy<N, NT> twc;
     twc.fetch(tw);
-    const int64_t ol = blockIdx.x / tiles;
-    int64_t o = ol;
+    // block indices and outer indices are below 2^32: 32-bit divisions
+    const uint32_t ol = blockIdx.x / (uint32_t)tiles;
+    uint32_t o = ol;
     if (pr.na > 0) {   // live column ol (extents M) -> its outer index in the buffer (extents P)
-        int64_t rem = ol, mul = 1;
+        uint32_t rem = ol, mul = 1;
         o = 0;
         for (int k = pr.na - 1; k >= 0; --k) {
-            o += (rem % pr.M[k]) * mul;
-            rem /= pr.M[k];
-            mul *= pr.P[k];
+            const uint32_t m = (uint32_t)pr.M[k];
+            o += (rem % m) * mul;
+            rem /= m;
+            mul *= (uint32_t)pr.P[k];
         }
     }
-    const int64_t i0 = (blockIdx.x - ol * tiles) * T;
-    double2* base = buf + o * N * inner + i0;
+    const int64_t i0 = (int64_t)(blockIdx.x - ol * (uint32_t)tiles) * T;
+    double2* base = buf + (int64_t)o * N * inner + i0;
     {
         constexpr int PE = (N * T + NT - 1) / NT;   // unrolled: the loads in flight together
 #pragma unroll
@@ -382,7 +387,7 @@ __global__ __launch_bounds__(NT) void k_c2c_strided(double2* __restrict__ buf, d
         }
         __syncthreads();
         fft_lds<N, T, NT, -1, RADIX, N>(lds, PS, twl);
-        double2* b2 = out2 + o * N * inner + i0;
+        double2* b2 = out2 + (int64_t)o * N * inner + i0;
         for (int e = threadIdx.x; e < N * T; e += NT) {
             const int t = e % T, p = e / T;
             if (i0 + t < inner) b2[(int64_t)p * inner + t] = lds[t * PS + p];
@@ -619,6 +624,10 @@ static int64_t lead_count(const kdefft_grid& g) {
     for (int k = 0; k + 1 < g.d; ++k) r *= g.P[k];
     return r;
 }
+// the kernels decode row and column indices in 32 bits
+static bool shape_ok(const kdefft_grid& g) {
+    return g.d >= 1 && g.d <= 4 && lead_count(g) * (g.P[g.d - 1] / 2 + 1) < (int64_t(1) << 31);
+}
 static void axis_shape(const kdefft_grid& g, int axis, int64_t* outer, int64_t* inner) {
     int64_t o = 1, in = g.P[g.d - 1] / 2 + 1;
     for (int k = 0; k < axis; ++k) o *= g.P[k];
@@ -628,6 +637,7 @@ static void axis_shape(const kdefft_grid& g, int axis, int64_t* outer, int64_t* 
 }
 
 hipError_t fft_c2c_axis(double2* buf, const kdefft_grid& g, int axis, int dir, hipStream_t s) {
+    if (!shape_ok(g)) return hipErrorInvalidValue;
     const double2* tw;
     hipError_t e = twiddles(&tw);
     if (e != hipSuccess) return e;
@@ -637,6 +647,7 @@ hipError_t fft_c2c_axis(double2* buf, const kdefft_grid& g, int axis, int dir, h
 }
 
 hipError_t fft_r2c_nd(const double* in, double2* out, const kdefft_grid& g, hipStream_t s) {
+    if (!shape_ok(g)) return hipErrorInvalidValue;
     const double2* tw;
     hipError_t e = twiddles(&tw);
     if (e != hipSuccess) return e;
@@ -650,6 +661,7 @@ hipError_t fft_r2c_nd(const double* in, double2* out, const kdefft_grid& g, hipS
 }
 
 hipError_t fft_c2r_nd(double2* inout, double* out, const kdefft_grid& g, hipStream_t s) {
+    if (!shape_ok(g)) return hipErrorInvalidValue;
     const double2* tw;
     hipError_t e = twiddles(&tw);
     if (e != hipSuccess) return e;
@@ -664,7 +676,7 @@ hipError_t fft_c2r_nd(double2* inout, double* out, const kdefft_grid& g, hipStre
 
 hipError_t fft_prepare_nd(const int64_t* src, int ncopies, int64_t* counts, double2* spec, double2* wmix,
                           const kdefft_grid& g, hipStream_t s, int fs) {
-    if (fs < 0 || fs >= FFT_SCHEDULES) return hipErrorInvalidValue;
+    if (fs < 0 || fs >= FFT_SCHEDULES || !shape_ok(g)) return hipErrorInvalidValue;
     const double2* tw;
     hipError_t e = twiddles(&tw);
     if (e != hipSuccess) return e;
@@ -713,6 +725,7 @@ hipError_t fft_prepare_nd(const int64_t* src, int ncopies, int64_t* counts, doub
 }
 
 hipError_t fft_autocorr_nd(const double2* wmix, double* alag, const kdefft_grid& g, hipStream_t s, int fs) {
+    if (!shape_ok(g)) return hipErrorInvalidValue;
     if (fs < 0 || fs >= FFT_SCHEDULES) return hipErrorInvalidValue;
     const double2* tw;
     hipError_t e = twiddles(&tw);
