@@ -263,7 +263,7 @@ def main():
     binning = {"call_ms": t_bin * 1e3, "points_per_s": n / t_bin, "lane_atomics_per_s": n * 2 ** d / t_bin,
                "x_read_GB_per_s": n * d * 8 / t_bin / 1e9,
                "what": "kdefft_linbin on the case-4 grid: fill of the 256^2 int64 grid plus binning of the "
-                       "1e5 points (the step's own binning adds into per-XCD copies cleared by the bounds pass)"}
+                       "1e5 points (the step's own binning adds into corner slots cleared by the bounds pass)"}
 
     def autograd_step():
         v = vechL.clone().requires_grad_(True)

@@ -389,14 +389,14 @@ DsLayout carve_dataset(Arena& a, const kdefft_grid& g) {
 struct PrepScratch {
     double* prm;
     double* partial;
-    int64_t* copies;    // per-XCD count grids for the binning
+    int64_t* slots;     // corner slots of the binning (2^d int64 per cell)
     int32_t* counter;   // completion counter of the constant-term launch
 };
 PrepScratch carve_prepare(Arena& a, const kdefft_grid& g) {
     PrepScratch p;
     p.prm = a.take<double>(PRM);
     p.partial = a.take<double>(max_nchunks(g, FUN_PSI, 0, 1));
-    p.copies = a.take<int64_t>(XCD_COPIES * sizes_of(g).prodM);
+    p.slots = a.take<int64_t>(corner_slots(g.d) * sizes_of(g).prodM);
     p.counter = a.take<int32_t>(1);
     return p;
 }
@@ -587,14 +587,14 @@ int prepare_into(const double* X, int64_t n, const kdefft_grid& g, const double*
     (void)with_const;
     if (partial) {
         // grid from the bound partials and the header inside the binning launch
-        // (the bounds launch cleared the counter, the scalar block and the copies)
-        HIPCHK(launch_linbin_xcd(X, n, g, p.copies, L.n_out, s, nullptr, true, &h), "linbin");
+        // (the bounds launch cleared the counter, the scalar block and the slots)
+        HIPCHK(launch_linbin_slots(X, n, g, p.slots, L.n_out, s, nullptr, true, &h), "linbin");
     } else {
         HIPCHK(launch_ds_header(h, s), "dataset header");
-        HIPCHK(launch_linbin_xcd(X, n, g, p.copies, L.n_out, s, nullptr, false), "linbin");
+        HIPCHK(launch_linbin_slots(X, n, g, p.slots, L.n_out, s, nullptr, false), "linbin");
     }
     const int fs = fft_sched_for(g);
-    HIPCHK(fft_prepare_nd(p.copies, XCD_COPIES, L.counts, L.spec, L.wmix, g, s, fs), "count transform");
+    HIPCHK(fft_prepare_nd(p.slots, 1, L.counts, L.spec, L.wmix, g, s, fs), "count transform");
     HIPCHK(fft_autocorr_nd(L.wmix, L.alag, g, s, fs), "count autocorrelation");
     return KDEFFT_OK;
 }
@@ -1090,8 +1090,8 @@ int kdefft_dataset_prepare_auto(const double* X, int64_t n, int d, const int32_t
         volatile double pk = pad_sd * sd;   // the same product as kdefft_grid_auto
         pad[k] = pk;
     }
-    HIPCHK(launch_bounds_partial(X, n, d, partial, (int)nb, s, p.copies,
-                                 (size_t)(XCD_COPIES * sizes_of(g).prodM) * sizeof(int64_t), dl.n_out, dl.scal),
+    HIPCHK(launch_bounds_partial(X, n, d, partial, (int)nb, s, p.slots,
+                                 (size_t)(corner_slots(g.d) * sizes_of(g).prodM) * sizeof(int64_t), dl.n_out, dl.scal),
            "bounds");
     rc = prepare_into(X, n, g, Gpilot_host, dl, p, true, s, partial, (int)nb, pad);
     if (rc) return rc;

@@ -128,24 +128,20 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
 //   the largest corner (lowest number on ties) takes 2^40 - sum of the others.
 // Floating-point contraction is disabled so that every step is one IEEE
 // operation, as on the host.
-// Index of the accelerator complex die (XCD) the wavefront runs on.
-__device__ __forceinline__ unsigned xcd_id() {
-    unsigned v;
-    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(v));
-    return v;
-}
-
-// copy_stride > 0: the counts are accumulated into XCD_COPIES grids of
-// copy_stride bins, one per XCD (chosen by the die the block runs on), so the
-// atomics of different dies never meet; the count transform's first pass adds
-// them (exactly, in integers) while it reads them.
+// slots != 0: the increments go to the corner slots (a record of 2^D int64 per
+// cell, slot c of the record of the point's lowest corner), so that a point's
+// 2^D increments fall in one contiguous record; the count transform's first
+// pass gathers the counts from the slots (exactly, in integers) while it reads
+// them.  slots == 0: straight into the count grid.
 //
 // Scattered 64-bit atomics cost one memory-side request per distinct cache
 // line per instruction, so after the per-point arithmetic the wavefront's
 // 64 x 2^D corner increments are re-dealt through LDS: instruction `it` gives
 // lane l the increment number it * 64 + l, i.e. point (it * 64 + l) / 2^D and
 // corner (it * 64 + l) % 2^D in an order whose consecutive corners differ in
-// the last (contiguous) axis, so neighbouring lanes add to adjacent bins.
+// the last (contiguous) axis, so neighbouring lanes add to adjacent bins of
+// the grid (2^(D-1) cache lines per point), or, with the corner slots, to one
+// record (one cache line per point for D <= 3, two for D = 4).
 // Grid origin and spacing from the data bounds (per-block partials of the
 // bounds kernel), by the same IEEE steps and order as the host planner:
 // lo = min - pad, hi = max + pad, hi = lo + 1 for a degenerate axis,
@@ -186,12 +182,11 @@ template <int D>
 __global__ __launch_bounds__(256) void k_linbin(const double* __restrict__ X, int64_t n, kdefft_grid g,
                                                 const double* __restrict__ gdev,
                                                 unsigned long long* __restrict__ counts,
-                                                int32_t* __restrict__ n_out, int64_t copy_stride, HeaderArgs hdr) {
+                                                int32_t* __restrict__ n_out, int slots, HeaderArgs hdr) {
 #pragma clang fp contract(off)
     constexpr int NC = 1 << D;
     __shared__ long long qs[256 * NC];   // increments, per wavefront in issue order
     __shared__ int64_t fbs[256];         // flat index of each point's lowest corner
-    if (copy_stride > 0) counts += (int64_t)(xcd_id() % XCD_COPIES) * copy_stride;
     if (gdev) {   // origin and spacing computed on the device
 #pragma unroll
         for (int k = 0; k < D; ++k) {
@@ -279,35 +274,39 @@ __global__ __launch_bounds__(256) void k_linbin(const double* __restrict__ X, in
             const int pnt = a / NC, c = a % NC;
             const long long v = qs[w0ff * NC + a];
             if (v != 0) {
-                int64_t off = 0;
+                if (slots) {
+                    atomicAdd(counts + fbs[w0ff + pnt] * NC + c, (unsigned long long)v);
+                } else {
+                    int64_t off = 0;
 #pragma unroll
-                for (int k = 0; k < D; ++k) off += ((c >> (D - 1 - k)) & 1) * stride[k];
-                atomicAdd(counts + fbs[w0ff + pnt] + off, (unsigned long long)v);
+                    for (int k = 0; k < D; ++k) off += ((c >> (D - 1 - k)) & 1) * stride[k];
+                    atomicAdd(counts + fbs[w0ff + pnt] + off, (unsigned long long)v);
+                }
             }
         }
         __syncthreads();
     }
 }
 
-hipError_t launch_linbin_xcd(const double* X, int64_t n, const kdefft_grid& g, int64_t* copies, int32_t* n_out,
-                             hipStream_t s, const double* gdev, bool copies_zeroed, const HeaderArgs* hdr) {
+hipError_t launch_linbin_slots(const double* X, int64_t n, const kdefft_grid& g, int64_t* slots, int32_t* n_out,
+                               hipStream_t s, const double* gdev, bool slots_zeroed, const HeaderArgs* hdr) {
     int64_t prodM = 1;
     for (int k = 0; k < g.d; ++k) prodM *= g.M[k];
     hipError_t e = hipSuccess;
-    if (!copies_zeroed) {
-        e = launch_zero(copies, (size_t)(XCD_COPIES * prodM) * sizeof(int64_t), s);
+    if (!slots_zeroed) {
+        e = launch_zero(slots, (size_t)(corner_slots(g.d) * prodM) * sizeof(int64_t), s);
         if (e != hipSuccess) return e;
     }
     int64_t blocks = (n + 255) / 256;
     if (blocks > 16384) blocks = 16384;
-    auto* c = reinterpret_cast<unsigned long long*>(copies);
+    auto* c = reinterpret_cast<unsigned long long*>(slots);
     HeaderArgs h{};
     if (hdr) h = *hdr;
     switch (g.d) {
-        case 1: hipLaunchKernelGGL(k_linbin<1>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, prodM, h); break;
-        case 2: hipLaunchKernelGGL(k_linbin<2>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, prodM, h); break;
-        case 3: hipLaunchKernelGGL(k_linbin<3>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, prodM, h); break;
-        case 4: hipLaunchKernelGGL(k_linbin<4>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, prodM, h); break;
+        case 1: hipLaunchKernelGGL(k_linbin<1>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, 1, h); break;
+        case 2: hipLaunchKernelGGL(k_linbin<2>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, 1, h); break;
+        case 3: hipLaunchKernelGGL(k_linbin<3>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, 1, h); break;
+        case 4: hipLaunchKernelGGL(k_linbin<4>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, 1, h); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -321,10 +320,10 @@ hipError_t launch_linbin(const double* X, int64_t n, const kdefft_grid& g, int64
     auto* c = reinterpret_cast<unsigned long long*>(counts);
     const HeaderArgs h{};
     switch (g.d) {
-        case 1: hipLaunchKernelGGL(k_linbin<1>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, (int64_t)0, h); break;
-        case 2: hipLaunchKernelGGL(k_linbin<2>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, (int64_t)0, h); break;
-        case 3: hipLaunchKernelGGL(k_linbin<3>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, (int64_t)0, h); break;
-        case 4: hipLaunchKernelGGL(k_linbin<4>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, (int64_t)0, h); break;
+        case 1: hipLaunchKernelGGL(k_linbin<1>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, 0, h); break;
+        case 2: hipLaunchKernelGGL(k_linbin<2>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, 0, h); break;
+        case 3: hipLaunchKernelGGL(k_linbin<3>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, 0, h); break;
+        case 4: hipLaunchKernelGGL(k_linbin<4>, dim3((unsigned)blocks), dim3(256), 0, s, X, n, g, gdev, c, n_out, 0, h); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -87,21 +87,52 @@ struct CountSrc {
     int d;
     int M[4];
     int P[4];
-    int ncopies;            // > 0: counts holds ncopies grids of `stride` bins, summed here
-    int64_t stride;
-    int64_t* sum_out;       // the summed grid, written when ncopies > 0
+    int slots;              // counts holds the binning's corner slots, gathered here
+    int64_t* sum_out;       // the gathered counts, written when slots is set
     int prune;              // only the rows inside the counts' box: row r of the launch is the counts'
                             // row r (leading indices over M), stored at its place in the padded grid;
                             // the padding's zero rows are not written (the next pass never reads them)
 };
 
-// Count of bin i (flat index into the M^d grid); sums the copies exactly
-// (unsigned 64-bit) and stores the sum when there are several.
-__device__ __forceinline__ int64_t load_count(const CountSrc& cs, int64_t i) {
-    if (cs.ncopies <= 0) return cs.counts[i];
+// Count of cell i (flat over the M^D box, last-axis index p, leading axes
+// with index >= 1 marked in lmask) gathered from the corner slots: slot c of
+// the record of cell i - e(c) for every corner c whose lower cell exists
+// (e(c) = 1 along the axes of c's set bits, bit 0 the last axis).  Exact
+// (unsigned 64-bit sums).
+template <int D>
+__device__ __forceinline__ uint64_t gather_slots(const int64_t* __restrict__ sl, int64_t i, int p, int lmask,
+                                                 const int* M) {
+    constexpr int NC = 1 << D;
     uint64_t t = 0;
-#pragma unroll 8
-    for (int c = 0; c < cs.ncopies; ++c) t += static_cast<uint64_t>(cs.counts[c * cs.stride + i]);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        int64_t off = 0, stride = 1;
+        bool ok = true;
+#pragma unroll
+        for (int k = D - 1; k >= 0; --k) {
+            if ((c >> (D - 1 - k)) & 1) {
+                off += stride;
+                ok = ok && (k == D - 1 ? p >= 1 : ((lmask >> k) & 1) != 0);
+            }
+            stride *= M[k];
+        }
+        if (ok) t += static_cast<uint64_t>(sl[(i - off) * NC + c]);
+    }
+    return t;
+}
+
+// Count of cell base + p (base: the cell of the row's first position); from
+// the corner slots it is gathered and also stored to sum_out.
+__device__ __forceinline__ int64_t load_count(const CountSrc& cs, int64_t base, int p, int lmask) {
+    const int64_t i = base + p;
+    if (!cs.slots) return cs.counts[i];
+    uint64_t t = 0;
+    switch (cs.d) {
+        case 1: t = gather_slots<1>(cs.counts, i, p, lmask, cs.M); break;
+        case 2: t = gather_slots<2>(cs.counts, i, p, lmask, cs.M); break;
+        case 3: t = gather_slots<3>(cs.counts, i, p, lmask, cs.M); break;
+        default: t = gather_slots<4>(cs.counts, i, p, lmask, cs.M); break;
+    }
     cs.sum_out[i] = static_cast<int64_t>(t);
     return static_cast<int64_t>(t);
 }
@@ -146,24 +177,28 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
         // offset of each row's counts (-1: a zero row of the padding), decoded
         // once per row
         __shared__ int64_t rbase[ROWS];
+        __shared__ int rmask[ROWS];   // leading axes whose index is >= 1 (bit k: axis k)
         for (int rr = threadIdx.x; rr < ROWS; rr += NT) {
             const int64_t row = r0 + rr;
             int64_t base = -1;
-            if (cs.prune) {
-                if (row < rows) base = row * Ml;
-            } else if (row < rows) {
+            int mask = 0;
+            if (row < rows) {
+                // the row's leading indices: digits over M (pruned launches
+                // run over the counts' rows) or over P (others)
                 uint32_t rem = (uint32_t)row, cf = 0, mul = 1;
                 bool ok = true;
                 for (int k = cs.d - 2; k >= 0; --k) {
-                    const uint32_t p = (uint32_t)cs.P[k], i = rem % p;
+                    const uint32_t p = (uint32_t)(cs.prune ? cs.M[k] : cs.P[k]), i = rem % p;
                     rem /= p;
                     ok = ok && i < (uint32_t)cs.M[k];
+                    mask |= (i >= 1 ? 1 : 0) << k;
                     cf += i * mul;
                     mul *= (uint32_t)cs.M[k];
                 }
                 if (ok) base = (int64_t)cf * Ml;
             }
             rbase[rr] = base;
+            rmask[rr] = mask;
         }
         __syncthreads();
         // a block of zero rows only (the padding): its spectrum is zero
@@ -187,9 +222,9 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
                 const int64_t base = rbase[rr];
                 double2 v = make_double2(0.0, 0.0);
                 if (base >= 0) {
-                    const int p0 = 2 * m, p1 = 2 * m + 1;
-                    if (p0 < Ml) v.x = (double)load_count(cs, base + p0) * quantum;
-                    if (p1 < Ml) v.y = (double)load_count(cs, base + p1) * quantum;
+                    const int p0 = 2 * m, p1 = 2 * m + 1, lm = rmask[rr];
+                    if (p0 < Ml) v.x = (double)load_count(cs, base, p0, lm) * quantum;
+                    if (p1 < Ml) v.y = (double)load_count(cs, base, p1, lm) * quantum;
                 }
                 buf[rr * PS + m] = v;
             }
@@ -592,7 +627,7 @@ static hipError_t run_c2c(double2* buf, double2* out2, int64_t outer, int64_t in
     }
 
 static hipError_t r2c_last(const double* in, double2* out, int64_t rows, int N, const double2* tw, hipStream_t s,
-                           CountSrc cs = CountSrc{nullptr, 0, {0, 0, 0, 0}, {0, 0, 0, 0}, 0, 0, nullptr, 0},
+                           CountSrc cs = CountSrc{nullptr, 0, {0, 0, 0, 0}, {0, 0, 0, 0}, 0, nullptr, 0},
                            int fs = FS_AUTO) {
 #define CALL(NN) run_r2c_last<NN>(in, out, rows, tw, s, cs, fs)
     if (N < 4) return hipErrorInvalidValue;
@@ -674,19 +709,18 @@ hipError_t fft_c2r_nd(double2* inout, double* out, const kdefft_grid& g, hipStre
     return c2r_last(inout, out, lead_count(g), g.P[g.d - 1], tw, s);
 }
 
-hipError_t fft_prepare_nd(const int64_t* src, int ncopies, int64_t* counts, double2* spec, double2* wmix,
+hipError_t fft_prepare_nd(const int64_t* src, int slots, int64_t* counts, double2* spec, double2* wmix,
                           const kdefft_grid& g, hipStream_t s, int fs) {
     if (fs < 0 || fs >= FFT_SCHEDULES || !shape_ok(g)) return hipErrorInvalidValue;
     const double2* tw;
     hipError_t e = twiddles(&tw);
     if (e != hipSuccess) return e;
-    CountSrc cs{src, g.d, {1, 1, 1, 1}, {1, 1, 1, 1}, ncopies, 1, counts, 1};
+    CountSrc cs{src, g.d, {1, 1, 1, 1}, {1, 1, 1, 1}, slots ? 1 : 0, counts, 1};
     for (int k = 0; k < g.d; ++k) {
         cs.M[k] = g.M[k];
         cs.P[k] = g.P[k];
-        cs.stride *= g.M[k];
     }
-    if (ncopies > 0 && !counts) return hipErrorInvalidValue;
+    if (slots && !counts) return hipErrorInvalidValue;
     // the R2C covers the rows inside the counts' box only (prod of the leading M)
     int64_t rows_live = 1;
     for (int k = 0; k + 1 < g.d; ++k) rows_live *= g.M[k];

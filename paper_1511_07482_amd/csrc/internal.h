@@ -141,15 +141,20 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // gdev: if not NULL, 8 device doubles (lo[4], delta[4]) that replace g's
 hipError_t launch_linbin(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts,
                          int32_t* n_out, hipStream_t s, const double* gdev = nullptr);
-// Binning into XCD_COPIES private copies of the count grid (one per XCD);
-// copies: XCD_COPIES * prod M int64 (cleared here unless copies_zeroed).  The
-// count transform (fft_prepare_nd) sums them exactly.
-constexpr int XCD_COPIES = 8;
+// Binning into corner slots: a record of 2^d int64 per cell of the count grid
+// (slots: 2^d * prod M int64, cleared here unless slots_zeroed), slot c of
+// record j summing the weights that points whose lowest corner is cell j give
+// their corner c (bit d-1-k of c set: the upper node along axis k, so bit 0
+// is the last axis).  A point's 2^d increments go to one contiguous record.
+// The count transform (fft_prepare_nd) gathers the counts from the slots
+// exactly: count(i) = sum over c of slot c of record i - e(c), e(c) the
+// corner's offset.
+__host__ __device__ constexpr int corner_slots(int d) { return 1 << d; }
 struct HeaderArgs;
 // hdr (may be NULL): with hdr->partial set, the binning launch also computes
 // the grid from the bound partials and writes the dataset header (block 0).
-hipError_t launch_linbin_xcd(const double* X, int64_t n, const kdefft_grid& g, int64_t* copies, int32_t* n_out,
-                             hipStream_t s, const double* gdev, bool copies_zeroed, const HeaderArgs* hdr = nullptr);
+hipError_t launch_linbin_slots(const double* X, int64_t n, const kdefft_grid& g, int64_t* slots, int32_t* n_out,
+                               hipStream_t s, const double* gdev, bool slots_zeroed, const HeaderArgs* hdr = nullptr);
 
 // One small launch at the start of a dataset's preparation: the record (with
 // the grid origin and spacing from the data bounds when `partial` is set --
@@ -183,9 +188,10 @@ hipError_t fft_c2r_nd(double2* inout, double* out, const kdefft_grid& g, hipStre
 constexpr int FFT_SCHEDULES = 6;
 // Count spectrum of a prepared dataset: spec = R2C(czp); wmix = |spec|^2
 // transformed forward along the leading axes.  The first pass reads the int64
-// counts directly: src is the count grid itself (ncopies = 0) or ncopies grids
-// of prod M bins whose exact sum it also writes to counts.
-hipError_t fft_prepare_nd(const int64_t* src, int ncopies, int64_t* counts, double2* spec, double2* wmix,
+// counts directly: src is the count grid itself (slots = 0) or the corner
+// slots of the binning (slots = 1), from which it gathers the counts exactly
+// and also writes them to counts.
+hipError_t fft_prepare_nd(const int64_t* src, int slots, int64_t* counts, double2* spec, double2* wmix,
                           const kdefft_grid& g, hipStream_t s, int fs);
 // alag = inverse transform of |C|^2 = prod P times the count autocorrelation,
 // computed from the mixed spectrum (rows at negated leading indices).
