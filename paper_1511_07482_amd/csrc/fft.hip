@@ -94,48 +94,30 @@ struct CountSrc {
                             // the padding's zero rows are not written (the next pass never reads them)
 };
 
-// Count of cell i (flat over the M^D box, last-axis index p, leading axes
-// with index >= 1 marked in lmask) gathered from the corner slots: slot c of
-// the record of cell i - e(c) for every corner c whose lower cell exists
-// (e(c) = 1 along the axes of c's set bits, bit 0 the last axis).  Exact
-// (unsigned 64-bit sums).
-template <int D>
-__device__ __forceinline__ uint64_t gather_slots(const int64_t* __restrict__ sl, int64_t i, int p, int lmask,
-                                                 const int* M) {
-    constexpr int NC = 1 << D;
-    uint64_t t = 0;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        int64_t off = 0, stride = 1;
-        bool ok = true;
-#pragma unroll
-        for (int k = D - 1; k >= 0; --k) {
-            if ((c >> (D - 1 - k)) & 1) {
-                off += stride;
-                ok = ok && (k == D - 1 ? p >= 1 : ((lmask >> k) & 1) != 0);
-            }
-            stride *= M[k];
-        }
-        if (ok) t += static_cast<uint64_t>(sl[(i - off) * NC + c]);
-    }
-    return t;
-}
-
-// Count of cell base + p (base: the cell of the row's first position); from
-// the corner slots it is gathered and also stored to sum_out.
-__device__ __forceinline__ int64_t load_count(const CountSrc& cs, int64_t base, int p, int lmask) {
+// Count of cell base + p (base: the cell of the row's first position, p the
+// last-axis index, up2: the row's index along axis d-2 is >= 1) gathered from
+// the corner slots of the last two axes: slot s of the record of cell
+// i - e(s), e(s) = (bit 0 of s) along the last axis + (bit 1) along axis d-2,
+// for the slots whose lower cell exists.  Exact (unsigned 64-bit sums); the
+// count is also stored to sum_out.
+__device__ __forceinline__ int64_t load_count(const CountSrc& cs, int64_t base, int p, bool up2) {
     const int64_t i = base + p;
     if (!cs.slots) return cs.counts[i];
-    uint64_t t = 0;
-    switch (cs.d) {
-        case 1: t = gather_slots<1>(cs.counts, i, p, lmask, cs.M); break;
-        case 2: t = gather_slots<2>(cs.counts, i, p, lmask, cs.M); break;
-        case 3: t = gather_slots<3>(cs.counts, i, p, lmask, cs.M); break;
-        default: t = gather_slots<4>(cs.counts, i, p, lmask, cs.M); break;
+    const int ml = cs.M[cs.d - 1];
+    uint64_t t;
+    if (cs.d == 1) {   // records of 2 slots
+        t = static_cast<uint64_t>(cs.counts[i * 2]);
+        if (p >= 1) t += static_cast<uint64_t>(cs.counts[(i - 1) * 2 + 1]);
+    } else {
+        t = static_cast<uint64_t>(cs.counts[i * 4]);
+        if (p >= 1) t += static_cast<uint64_t>(cs.counts[(i - 1) * 4 + 1]);
+        if (up2) t += static_cast<uint64_t>(cs.counts[(i - ml) * 4 + 2]);
+        if (up2 && p >= 1) t += static_cast<uint64_t>(cs.counts[(i - ml - 1) * 4 + 3]);
     }
     cs.sum_out[i] = static_cast<int64_t>(t);
     return static_cast<int64_t>(t);
 }
+
 struct RowFlip {
     int on;
     int nlead;
@@ -177,7 +159,7 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
         // offset of each row's counts (-1: a zero row of the padding), decoded
         // once per row
         __shared__ int64_t rbase[ROWS];
-        __shared__ int rmask[ROWS];   // leading axes whose index is >= 1 (bit k: axis k)
+        __shared__ int rmask[ROWS];   // the row's index along axis d-2 is >= 1
         for (int rr = threadIdx.x; rr < ROWS; rr += NT) {
             const int64_t row = r0 + rr;
             int64_t base = -1;
@@ -191,7 +173,7 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
                     const uint32_t p = (uint32_t)(cs.prune ? cs.M[k] : cs.P[k]), i = rem % p;
                     rem /= p;
                     ok = ok && i < (uint32_t)cs.M[k];
-                    mask |= (i >= 1 ? 1 : 0) << k;
+                    if (k == cs.d - 2) mask = i >= 1 ? 1 : 0;
                     cf += i * mul;
                     mul *= (uint32_t)cs.M[k];
                 }
@@ -222,7 +204,8 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
                 const int64_t base = rbase[rr];
                 double2 v = make_double2(0.0, 0.0);
                 if (base >= 0) {
-                    const int p0 = 2 * m, p1 = 2 * m + 1, lm = rmask[rr];
+                    const int p0 = 2 * m, p1 = 2 * m + 1;
+                    const bool lm = rmask[rr] != 0;
                     if (p0 < Ml) v.x = (double)load_count(cs, base, p0, lm) * quantum;
                     if (p1 < Ml) v.y = (double)load_count(cs, base, p1, lm) * quantum;
                 }

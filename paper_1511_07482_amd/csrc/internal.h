@@ -141,15 +141,18 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // gdev: if not NULL, 8 device doubles (lo[4], delta[4]) that replace g's
 hipError_t launch_linbin(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts,
                          int32_t* n_out, hipStream_t s, const double* gdev = nullptr);
-// Binning into corner slots: a record of 2^d int64 per cell of the count grid
-// (slots: 2^d * prod M int64, cleared here unless slots_zeroed), slot c of
-// record j summing the weights that points whose lowest corner is cell j give
-// their corner c (bit d-1-k of c set: the upper node along axis k, so bit 0
-// is the last axis).  A point's 2^d increments go to one contiguous record.
-// The count transform (fft_prepare_nd) gathers the counts from the slots
-// exactly: count(i) = sum over c of slot c of record i - e(c), e(c) the
-// corner's offset.
-__host__ __device__ constexpr int corner_slots(int d) { return 1 << d; }
+// Binning into corner slots over the last two axes: a record of S = 4 int64
+// per cell of the count grid (S = 2 for d = 1; slots: S * prod M int64,
+// cleared here unless slots_zeroed).  A point adds its 2^d corner weights to
+// 2^(d-2) records, one per corner of the leading axes (the cell of the lowest
+// corner moved to the upper node along the leading axes of that corner), slot
+// s of a record taking the corner's nodes along the last two axes (bit 0 of s:
+// upper along the last axis, bit 1: upper along axis d-2).  A point's
+// increments thus fall in 2^(d-2) contiguous 32-byte records instead of
+// 2^(d-1) pairs of grid cells.  The count transform's first pass (fft_prepare_nd
+// with slots) gathers each count exactly from its S nearby slots:
+// count(i) = sum over s of slot s of record i - e(s).
+__host__ __device__ constexpr int corner_slots(int d) { return d >= 2 ? 4 : 2; }
 struct HeaderArgs;
 // hdr (may be NULL): with hdr->partial set, the binning launch also computes
 // the grid from the bound partials and writes the dataset header (block 0).
