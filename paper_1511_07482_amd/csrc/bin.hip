@@ -128,11 +128,11 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
 //   the largest corner (lowest number on ties) takes 2^40 - sum of the others.
 // Floating-point contraction is disabled so that every step is one IEEE
 // operation, as on the host.
-// slots != 0: the increments go to the corner slots of the last two axes (a
-// record of 4 int64 per cell; 2 for D = 1), so that a point's 2^D increments
-// fall in 2^(D-2) contiguous records; the count transform's first pass gathers
-// the counts from the slots (exactly, in integers) while it reads them.
-// slots == 0: straight into the count grid.
+// slots != 0: the increments go to the corner slots of the last min(D, 3)
+// axes (a record of 2^min(D, 3) int64 per cell), so that a point's 2^D
+// increments fall in 2^max(D-3, 0) contiguous records; the count transform's
+// first pass gathers the counts from the slots (exactly, in integers) while
+// it reads them.  slots == 0: straight into the count grid.
 //
 // Scattered 64-bit atomics cost one memory-side request per distinct cache
 // line per instruction, so after the per-point arithmetic the wavefront's
@@ -141,7 +141,7 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
 // corner (it * 64 + l) % 2^D in an order whose consecutive corners differ in
 // the last (contiguous) axis, so neighbouring lanes add to adjacent bins of
 // the grid (2^(D-1) cache lines per point), or, with the corner slots, to one
-// 32-byte record per four lanes (2^(D-2) records per point).
+// record per 2^min(D, 3) lanes (one cache line per point, two for D = 4).
 // Grid origin and spacing from the data bounds (per-block partials of the
 // bounds kernel), by the same IEEE steps and order as the host planner:
 // lo = min - pad, hi = max + pad, hi = lo + 1 for a degenerate axis,
@@ -275,12 +275,12 @@ __global__ __launch_bounds__(256) void k_linbin(const double* __restrict__ X, in
             const long long v = qs[w0ff * NC + a];
             if (v != 0) {
                 if (slots) {
-                    // record: the lowest corner moved along the leading axes
-                    // of corner c (bits D-1..2 of c); slot: c's last two bits
+                    // record: the lowest corner moved along the unslotted
+                    // leading axes of corner c; slot: c's bits of the slotted axes
+                    constexpr int NSA = slot_axes(D), NS = corner_slots(D);
                     int64_t off = 0;
 #pragma unroll
-                    for (int k = 0; k + 2 < D; ++k) off += ((c >> (D - 1 - k)) & 1) * stride[k];
-                    constexpr int NS = corner_slots(D);
+                    for (int k = 0; k + NSA < D; ++k) off += ((c >> (D - 1 - k)) & 1) * stride[k];
                     atomicAdd(counts + (fbs[w0ff + pnt] + off) * NS + (c & (NS - 1)), (unsigned long long)v);
                 } else {
                     int64_t off = 0;

@@ -94,26 +94,40 @@ struct CountSrc {
                             // the padding's zero rows are not written (the next pass never reads them)
 };
 
-// Count of cell base + p (base: the cell of the row's first position, p the
-// last-axis index, up2: the row's index along axis d-2 is >= 1) gathered from
-// the corner slots of the last two axes: slot s of the record of cell
-// i - e(s), e(s) = (bit 0 of s) along the last axis + (bit 1) along axis d-2,
-// for the slots whose lower cell exists.  Exact (unsigned 64-bit sums); the
-// count is also stored to sum_out.
-__device__ __forceinline__ int64_t load_count(const CountSrc& cs, int64_t base, int p, bool up2) {
+// Count of cell i = base + p (base: the cell of the row's first position, p
+// the last-axis index; bit j - 1 of lmask: the row's index along axis d-1-j
+// is >= 1) gathered from the corner slots of the last NSA axes: slot s of the
+// record of cell i - e(s), e(s) = the sum over the set bits j of s of the
+// stride of axis d-1-j, for the slots whose lower cell exists.  Exact
+// (unsigned 64-bit sums).
+template <int NSA>
+__device__ __forceinline__ uint64_t gather_slots(const int64_t* __restrict__ sl, int64_t i, int p, int lmask,
+                                                 const int* M, int d) {
+    constexpr int NS = 1 << NSA;
+    const int64_t st1 = NSA > 1 ? M[d - 1] : 0;
+    const int64_t st2 = NSA > 2 ? st1 * M[d - 2] : 0;
+    uint64_t t = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const bool ok = (!(s & 1) || p >= 1) && (!(s & 2) || (lmask & 1)) && (!(s & 4) || (lmask & 2));
+        const int64_t off = (s & 1 ? 1 : 0) + (s & 2 ? st1 : 0) + (s & 4 ? st2 : 0);
+        if (ok) t += static_cast<uint64_t>(sl[(i - off) * NS + s]);
+    }
+    return t;
+}
+
+// Count of cell base + p: read directly, or gathered from the corner slots
+// (then also stored to sum_out).
+__device__ __forceinline__ int64_t load_count(const CountSrc& cs, int64_t base, int p, int lmask) {
     const int64_t i = base + p;
     if (!cs.slots) return cs.counts[i];
-    const int ml = cs.M[cs.d - 1];
     uint64_t t;
-    if (cs.d == 1) {   // records of 2 slots
-        t = static_cast<uint64_t>(cs.counts[i * 2]);
-        if (p >= 1) t += static_cast<uint64_t>(cs.counts[(i - 1) * 2 + 1]);
-    } else {
-        t = static_cast<uint64_t>(cs.counts[i * 4]);
-        if (p >= 1) t += static_cast<uint64_t>(cs.counts[(i - 1) * 4 + 1]);
-        if (up2) t += static_cast<uint64_t>(cs.counts[(i - ml) * 4 + 2]);
-        if (up2 && p >= 1) t += static_cast<uint64_t>(cs.counts[(i - ml - 1) * 4 + 3]);
-    }
+    if (cs.d == 1)
+        t = gather_slots<1>(cs.counts, i, p, lmask, cs.M, cs.d);
+    else if (cs.d == 2)
+        t = gather_slots<2>(cs.counts, i, p, lmask, cs.M, cs.d);
+    else
+        t = gather_slots<3>(cs.counts, i, p, lmask, cs.M, cs.d);
     cs.sum_out[i] = static_cast<int64_t>(t);
     return static_cast<int64_t>(t);
 }
@@ -159,7 +173,7 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
         // offset of each row's counts (-1: a zero row of the padding), decoded
         // once per row
         __shared__ int64_t rbase[ROWS];
-        __shared__ int rmask[ROWS];   // the row's index along axis d-2 is >= 1
+        __shared__ int rmask[ROWS];   // bit 0: the row's index along axis d-2 is >= 1; bit 1: along d-3
         for (int rr = threadIdx.x; rr < ROWS; rr += NT) {
             const int64_t row = r0 + rr;
             int64_t base = -1;
@@ -173,7 +187,8 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
                     const uint32_t p = (uint32_t)(cs.prune ? cs.M[k] : cs.P[k]), i = rem % p;
                     rem /= p;
                     ok = ok && i < (uint32_t)cs.M[k];
-                    if (k == cs.d - 2) mask = i >= 1 ? 1 : 0;
+                    if (k == cs.d - 2 && i >= 1) mask |= 1;
+                    if (k == cs.d - 3 && i >= 1) mask |= 2;
                     cf += i * mul;
                     mul *= (uint32_t)cs.M[k];
                 }
@@ -204,8 +219,7 @@ __global__ __launch_bounds__(NT) void k_r2c_last(const double* __restrict__ in, 
                 const int64_t base = rbase[rr];
                 double2 v = make_double2(0.0, 0.0);
                 if (base >= 0) {
-                    const int p0 = 2 * m, p1 = 2 * m + 1;
-                    const bool lm = rmask[rr] != 0;
+                    const int p0 = 2 * m, p1 = 2 * m + 1, lm = rmask[rr];
                     if (p0 < Ml) v.x = (double)load_count(cs, base, p0, lm) * quantum;
                     if (p1 < Ml) v.y = (double)load_count(cs, base, p1, lm) * quantum;
                 }

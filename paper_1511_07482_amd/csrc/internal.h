@@ -141,18 +141,19 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // gdev: if not NULL, 8 device doubles (lo[4], delta[4]) that replace g's
 hipError_t launch_linbin(const double* X, int64_t n, const kdefft_grid& g, int64_t* counts,
                          int32_t* n_out, hipStream_t s, const double* gdev = nullptr);
-// Binning into corner slots over the last two axes: a record of S = 4 int64
-// per cell of the count grid (S = 2 for d = 1; slots: S * prod M int64,
+// Binning into corner slots over the last min(d, 3) axes: a record of
+// S = 2^min(d, 3) int64 per cell of the count grid (slots: S * prod M int64,
 // cleared here unless slots_zeroed).  A point adds its 2^d corner weights to
-// 2^(d-2) records, one per corner of the leading axes (the cell of the lowest
-// corner moved to the upper node along the leading axes of that corner), slot
-// s of a record taking the corner's nodes along the last two axes (bit 0 of s:
-// upper along the last axis, bit 1: upper along axis d-2).  A point's
-// increments thus fall in 2^(d-2) contiguous 32-byte records instead of
-// 2^(d-1) pairs of grid cells.  The count transform's first pass (fft_prepare_nd
-// with slots) gathers each count exactly from its S nearby slots:
+// 2^(d-3) records for d = 4 (one per node of axis 0: the cell of the lowest
+// corner moved along axis 0 for the upper one), to one record otherwise,
+// slot s of a record taking the corner's nodes along the slotted axes (bit j
+// of s: upper along axis d-1-j).  A point's increments thus fall in
+// 2^max(d-3, 0) contiguous records (one cache line each) instead of 2^(d-1)
+// pairs of grid cells.  The count transform's first pass (fft_prepare_nd with
+// slots) gathers each count exactly from S nearby slots:
 // count(i) = sum over s of slot s of record i - e(s).
-__host__ __device__ constexpr int corner_slots(int d) { return d >= 2 ? 4 : 2; }
+__host__ __device__ constexpr int slot_axes(int d) { return d < 3 ? d : 3; }
+__host__ __device__ constexpr int corner_slots(int d) { return 1 << slot_axes(d); }
 struct HeaderArgs;
 // hdr (may be NULL): with hdr->partial set, the binning launch also computes
 // the grid from the bound partials and writes the dataset header (block 0).
