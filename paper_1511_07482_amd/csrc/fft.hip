@@ -77,9 +77,10 @@ hipError_t twiddles(const double2** out) {
 
 // ------------------------------------------------------------------ last axis
 // Optional input maps of the last-axis passes.
-//  * CountSrc: the R2C input row is read straight from the int64 grid counts
-//    (c = count 2^-40 at [0, M)^d of the circular layout, zero elsewhere), so
-//    the zero-padded real array is never materialised.
+//  * CountSrc: the R2C input row is read straight from the int64 grid counts,
+//    or gathered from the binning's corner slots (c = count 2^-40 at [0, M)^d
+//    of the circular layout, zero elsewhere), so the zero-padded real array is
+//    never materialised.
 //  * RowFlip: the C2R pass reads input row -l' (each leading index negated
 //    modulo P) for output row l'.
 struct CountSrc {
