@@ -364,7 +364,7 @@ def main():
 
     crit_out = criteria_section(kf, torch, ds, vechL, Gpsi, n, B)
     fftl_out = fftl_section(kf, torch, dev, X, Gpsi, g)
-    fft_stage = fft_stage_section(kf, torch, dev, stream)
+    fft_stage = fft_stage_section(kf, torch, dev, stream, tune=not a.no_tune)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -505,15 +505,19 @@ def fft_stage_bytes(P, M, d):
     return int(round(8 * M ** d + 8 * P ** d + half * (fwd + 2 * (d - 2) + 1)))
 
 
-def fft_stage_section(kf, torch, dev, stream):
+def fft_stage_section(kf, torch, dev, stream, tune=True):
     """The count transform alone at the case-5 dataset shape (d=4, M=32,
     P=64: 418 MB touched per transform) over 4 datasets back to back (1.7 GB
-    cycled, well above the 256 MB last-level cache): algorithmic bytes per
-    transform over the HIP-event time per transform."""
+    cycled, well above the 256 MB last-level cache), under the FFT schedule
+    the tuner picks for that shape (kdefft_autotune on the first dataset, as
+    the case-5 line does): algorithmic bytes per transform over the HIP-event
+    time per transform."""
     import synth
     w = synth.case5(n_datasets=4, B=1, n_lo=200_000, n_hi=200_000)
     dss = [kf.Dataset(torch.from_numpy(X).to(dev), Gp, M=w.M) for X, Gp in zip(w.X, w.G_pilot)]
     d, M, P = w.d, w.M, int(dss[0].shape_grid.P[0])
+    if tune:
+        kf.autotune(dss[0])
     for ds in dss:
         ds.transform()
     torch.cuda.synchronize()
@@ -534,7 +538,8 @@ def fft_stage_section(kf, torch, dev, stream):
             "bytes_per_transform": nbytes, "ms_per_transform": ms,
             "achieved_GBps": nbytes / (ms * 1e-3) / 1e9, "peak_GBps": 8000.0,
             "frac": nbytes / (ms * 1e-3) / 8e12, "touched_bytes_per_dataset": touched,
-            "cycled_bytes": touched * len(dss), "schedule": kf.get_fft_schedule([P] * d)}
+            "cycled_bytes": touched * len(dss), "schedule": kf.get_fft_schedule([P] * d),
+            "schedule_from": "kdefft_autotune" if tune else "untuned default"}
 
 
 def main_case5(a):
