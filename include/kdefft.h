@@ -461,7 +461,7 @@ int kdefft_timing_stop(float* ms_out, int32_t* tag_out, int cap, int* count_out)
  *     give fewer than 512 blocks, 256-thread blocks of a few pencils (half of
  *     what one wavefront takes, at least one: more blocks, more lanes per
  *     pencil for the loads); radix-8 Stockham stages first (radix 4 or 2 for
- *     the remainder);
+ *     the remainder), radix-4 stages for 64-point passes;
  *   1 the same shapes with radix-4 stages (one radix-8 or 2 when log2 P is odd);
  *   2 256-thread blocks of ~2048 values for every pass (strided passes on
  *     16-column tiles, or whole [P][Q] slabs for Q = 17, 33);
